@@ -1,0 +1,279 @@
+/*
+ * libshaken -- shaken dynamics on MI355X (gfx950).
+ *
+ * Shaken dynamics (Apollonio, D'Autilia, Scoppola, Scoppola, Troiani,
+ * arXiv:1904.06257) is a parallel Markov chain for an Ising system
+ *
+ *     H(sigma) = - sum_{{x,y} in E} J_xy sigma_x sigma_y - 2 sum_x lambda_x sigma_x
+ *
+ * (section 2, equation ham1).  Every undirected edge is given an orientation;
+ * the oriented edge set E^o splits the neighbourhood of each site into an
+ * in-half {y : (y,x) in E^o} and an out-half {y : (x,y) in E^o} (section 2,
+ * construction of the doubling graph from G^o).  One full step is two
+ * half-steps (section 2, kernels P^{1->2}, P^{2->1} and P^sh):
+ *
+ *   half-step 1: every spin is redrawn at once, P(+1) = 1/(1 + exp(-2 beta h)),
+ *                h_x = sum_{in-half} J_yx sigma_y + q sigma_x + lambda_x
+ *   half-step 2: the same with the out-half, read from the result of step 1.
+ *
+ * On the L x L torus E^o = {(x, x_up), (x, x_right)}: half-step 1 reads the
+ * down and left neighbours (P^dl), half-step 2 the up and right ones (P^ur)
+ * (section 3, equations hur, hdl, pasymm, pasymm1).  Torus sites are stored
+ * row-major, site (row, col) at row*L + col, "up" = row+1, "right" = col+1.
+ *
+ * Randomness and thresholds (the paper fixes none; the library's contract,
+ * identical on every code path and reproduced bit for bit by an independent
+ * CPU implementation):
+ *   Philox4x32-10 with key (lo32(seed), hi32(seed)).  A site's new spin is +1
+ *   iff u < T, where T in [0, 2^32] is the threshold of its local field
+ *       h = ((double)S + q*sigma) + lambda,  e = exp(-((2 beta)|h|)),
+ *       t = floor(e/(1+e) * 2^32),  T = (h >= 0) ? 2^32 - t : t,
+ *   computed in IEEE double on the host, and u is a 32-bit uniform:
+ *     torus:  word w = row*ceil(L/32) + (col>>5), bit b = col & 31,
+ *             R_k = word (k&3) of Philox((w, s, replica, k>>2)),
+ *             u = sum_k ((R_k >> b) & 1) 2^(31-k)            (bit-sliced)
+ *     graph:  u = word (v&3) of Philox((v>>2, s, replica, 0x80000000))
+ *   with s the half-step index (0, 1, 2, ... ; even = half-step 1).
+ *   A random initial state uses s = 0xFFFFFFFF: torus site +1 iff bit b of
+ *   R_0; graph vertex +1 iff bit 31 of its u.
+ *
+ * Conventions for every call:
+ *   - Return codes only; nothing is thrown across the ABI.  On failure the
+ *     thread-local message of shaken_last_error() says why.
+ *   - Host arrays passed in are copied before the call returns; the caller
+ *     keeps ownership.  Device memory belongs to the context until
+ *     shaken_free().
+ *   - Work is enqueued on the context's HIP stream.  Calls that hand data back
+ *     to the host synchronise that stream; the others return as soon as the
+ *     work is enqueued.
+ *   - A context is not thread-safe.  Distinct contexts are independent.
+ */
+#ifndef SHAKEN_H
+#define SHAKEN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SHAKEN_VERSION_MAJOR 0
+#define SHAKEN_VERSION_MINOR 1
+
+typedef enum shaken_status {
+    SHAKEN_OK = 0,
+    SHAKEN_EINVAL = 1,   /* invalid argument (message says which)          */
+    SHAKEN_ENOMEM = 2,   /* host or device allocation failed               */
+    SHAKEN_EDEVICE = 3,  /* HIP runtime error (message carries its string) */
+    SHAKEN_ESTATE = 4    /* call not valid in the context's current state  */
+} shaken_status;
+
+/* ------------------------------------------------------------------ inputs */
+
+typedef enum shaken_graph_kind {
+    SHAKEN_TORUS = 0,   /* L x L periodic square lattice, E^o = up/right edges */
+    SHAKEN_EDGES = 1    /* arbitrary simple graph given as oriented edges      */
+} shaken_graph_kind;
+
+/* The interaction graph with its orientation (Definition 2.1).
+ *   kind == SHAKEN_TORUS: L is the side, 3 <= L <= 32768; n, m, src, dst unused.
+ *   kind == SHAKEN_EDGES: n vertices (1 <= n < 2^31), m oriented edges; edge e
+ *     is (src[e], dst[e]) in E^o, i.e. dst[e] reads src[e] in half-step 1 and
+ *     src[e] reads dst[e] in half-step 2.  Host arrays of m int32 each.
+ *     Self-loops, out-of-range ids and an edge given twice (in either
+ *     direction) are rejected with SHAKEN_EINVAL. */
+typedef struct shaken_graph {
+    int32_t kind;
+    int32_t L;
+    int32_t n;
+    int64_t m;
+    const int32_t *src;
+    const int32_t *dst;
+} shaken_graph;
+
+/* External field lambda as a small table of values (section 2, lambda_x).
+ *   n_classes in [1, 256]; value[c] = lambda of class c (host doubles);
+ *   class_of_vertex: host uint8 per vertex (n entries), or NULL = all class 0.
+ *   The torus takes a uniform field only (n_classes == 1, class_of_vertex NULL).
+ *   Passing NULL for the whole struct means lambda = 0 everywhere.
+ *   lambda enters h with weight 1 and H(sigma) with weight 2 (equations ham1,
+ *   hur, hdl). */
+typedef struct shaken_field {
+    int32_t n_classes;
+    const double *value;
+    const uint8_t *class_of_vertex;
+} shaken_field;
+
+enum {
+    SHAKEN_FMT_AUTO = 0,       /* torus: bit-packed; graph: int8              */
+    SHAKEN_FMT_INT8 = 1,       /* one int8 (+1 / -1) per site                 */
+    SHAKEN_FMT_BITPACKED = 2   /* torus only: uint32[L][ceil(L/32)], bit = +1 */
+};
+
+enum {
+    SHAKEN_INIT_RANDOM = 0,    /* from Philox at s = 0xFFFFFFFF (see above)   */
+    SHAKEN_INIT_ALL_UP = 1,
+    SHAKEN_INIT_ALL_DOWN = 2,
+    SHAKEN_INIT_USER = 3       /* init_spins: host int8, +1/-1, n or L*L      */
+};
+
+typedef struct shaken_opts {
+    int32_t format;            /* SHAKEN_FMT_*                                */
+    int32_t init;              /* SHAKEN_INIT_*                               */
+    const int8_t *init_spins;  /* SHAKEN_INIT_USER only                       */
+    uint32_t replica;          /* third Philox counter word                   */
+    int32_t device;            /* HIP device ordinal; -1 = current device     */
+    void *stream;              /* hipStream_t; NULL = the null stream         */
+} shaken_opts;
+
+typedef struct shaken_ctx shaken_ctx;
+
+/* ------------------------------------------------------------ single chain */
+
+/* Create a chain: graph g with couplings J and field lambda, self-interaction
+ * q >= 0 (Definition 2.2 takes q > 0; q = 0 is accepted) and inverse
+ * temperature beta >= 0 (both finite), Philox key `seed`.
+ *   J: host int8 per oriented edge (m entries), or NULL = all +1.  For the
+ *      torus J is per oriented edge too (2*L*L entries: index 2x is the edge
+ *      (x, x_up), 2x+1 is (x, x_right)) and must currently be uniform; NULL
+ *      means +1.
+ *   opts: NULL = defaults (AUTO format, random init, replica 0, current
+ *      device, null stream).
+ * The threshold table covers every local field the graph can produce; its
+ * size is (2*Smax+1) * 2 * n_classes entries with Smax the largest sum of
+ * |J| over a half-neighbourhood; more than 2^24 entries is SHAKEN_EINVAL.
+ * Errors: SHAKEN_EINVAL (bad graph, q/beta negative or not finite, torus with
+ * a non-uniform J or field), SHAKEN_ENOMEM, SHAKEN_EDEVICE. */
+shaken_status shaken_init(shaken_ctx **out, const shaken_graph *g, const int8_t *J,
+                          const shaken_field *lambda, double q, double beta,
+                          uint64_t seed, const shaken_opts *opts);
+
+/* Release every device and host resource of the context (NULL is a no-op). */
+shaken_status shaken_free(shaken_ctx *ctx);
+
+/* Advance n >= 0 half-steps (section 2, P^{1->2} then P^{2->1} alternately).
+ * The parity of the context's half-step counter s selects the half: even =
+ * half-step 1 (in-half, torus dl), odd = half-step 2 (out-half, torus ur).
+ * Asynchronous. */
+shaken_status shaken_half_step(shaken_ctx *ctx, int64_t n);
+
+/* Advance n_full >= 0 full steps (P^sh = P^{1->2} P^{2->1}, section 2).
+ * If H_out / M_out are non-NULL they receive n_full+1 host int64 values:
+ * H(sigma_t) and M(sigma_t) = sum_x sigma_x for t = 0..n_full (t = 0 is the
+ * configuration before the call).  H_out requires every 2*lambda to be an
+ * integer (else SHAKEN_EINVAL), so that H is exact.  The counter s must be
+ * even (else SHAKEN_ESTATE).  Synchronises the stream when logs are asked
+ * for. */
+shaken_status shaken_sweep(shaken_ctx *ctx, int64_t n_full, int64_t *H_out, int64_t *M_out);
+
+/* Observables of the current configuration. */
+typedef struct shaken_obs {
+    int64_t half_step;   /* the counter s                                    */
+    int64_t n_sites;
+    int64_t M;           /* sum_x sigma_x                                    */
+    int64_t E_J;         /* sum_{(x,y) in E^o} J_xy sigma_x sigma_y           */
+    int64_t E_lambda2;   /* sum_x 2 lambda_x sigma_x, valid iff flags & 1     */
+    double H;            /* -E_J - sum_x 2 lambda_x sigma_x (double)         */
+    int32_t flags;       /* bit 0: every 2*lambda is an integer              */
+    int32_t reserved;
+} shaken_obs;
+
+/* Synchronises the stream. */
+shaken_status shaken_observables(shaken_ctx *ctx, shaken_obs *out);
+
+/* Change beta and q (rebuilds the threshold table; same validation as init). */
+shaken_status shaken_set_params(shaken_ctx *ctx, double beta, double q);
+
+/* Copy the current configuration to / from host int8 (+1/-1), n or L*L
+ * entries, row-major for the torus.  get synchronises; set validates
+ * entries (SHAKEN_EINVAL unless every value is +1 or -1). */
+shaken_status shaken_get_spins(shaken_ctx *ctx, int8_t *out);
+shaken_status shaken_set_spins(shaken_ctx *ctx, const int8_t *in);
+
+/* Set the half-step counter s (checkpoint restore); s < 2^32 - 1. */
+shaken_status shaken_set_half_step(shaken_ctx *ctx, int64_t s);
+
+/* Copy the threshold table: entry index ((S + Smax)*2 + (sigma > 0)) *
+ * n_classes + class holds T (33 bits in a uint64).  If out is NULL only *n
+ * is set; otherwise *n must hold the capacity on entry and receives the
+ * entry count.  *smax receives Smax when non-NULL. */
+shaken_status shaken_get_lut(const shaken_ctx *ctx, uint64_t *out, size_t *n, int32_t *smax);
+
+/* Borrow the device pointer of the current configuration (valid until the
+ * next call on the context) and its format (SHAKEN_FMT_INT8 / BITPACKED). */
+shaken_status shaken_spins_device(shaken_ctx *ctx, void **ptr, int32_t *format);
+
+/* Block until the context's stream is idle. */
+shaken_status shaken_synchronize(shaken_ctx *ctx);
+
+/* ------------------------------------------------------------------ batches */
+
+/* A batch runs many independent chains (each its own graph, J, lambda, beta,
+ * q, seed and replica -- the paper's dynamics per chain, unchanged) with
+ * fused launches.  Strategies:
+ *   SHAKEN_BATCH_GRID:       one launch per half-step covering every chain
+ *                            (any size); optionally replayed from a HIP graph.
+ *   SHAKEN_BATCH_PERSISTENT: one launch per call; each workgroup takes whole
+ *                            chains from a device queue (longest first) and
+ *                            keeps their spins in LDS for all the steps.  Tori
+ *                            need L <= 256 and graphs n <= 65536 with at most
+ *                            32 neighbours per half.
+ *   SHAKEN_BATCH_AUTO:       persistent when every chain fits, else grid. */
+enum { SHAKEN_BATCH_AUTO = 0, SHAKEN_BATCH_GRID = 1, SHAKEN_BATCH_PERSISTENT = 2 };
+
+typedef struct shaken_batch_opts {
+    int32_t strategy;      /* SHAKEN_BATCH_*                                  */
+    int32_t use_hipgraph;  /* grid strategy: capture the half-step launches   */
+    int32_t autotune;      /* 0: fixed launch shapes; 1: measure candidates
+                              on the first call and keep the fastest         */
+    int32_t record;        /* log H and M of every chain at every full step  */
+    void *stream;          /* hipStream_t; NULL = the first chain's stream   */
+} shaken_batch_opts;
+
+typedef struct shaken_batch shaken_batch;
+
+/* Group n >= 1 contexts into a batch.  Every context must be on the same
+ * device and have the same half-step counter s (even).  The contexts stay
+ * owned by the caller and must outlive the batch; the batch never frees
+ * them.  Errors: SHAKEN_EINVAL, SHAKEN_ESTATE (counters differ or odd),
+ * SHAKEN_ENOMEM, SHAKEN_EDEVICE. */
+shaken_status shaken_batch_create(shaken_batch **out, shaken_ctx *const *ctx, int32_t n,
+                                  const shaken_batch_opts *opts);
+
+/* Advance every chain of the batch by n_full full steps.  With record set,
+ * each chain's H/M log of this call (n_full+1 entries) can then be read with
+ * shaken_batch_get_log.  Asynchronous. */
+shaken_status shaken_batch_sweep(shaken_batch *b, int64_t n_full);
+
+/* Copy chain i's log of the last shaken_batch_sweep (requires record and
+ * integer 2*lambda for H).  cap = capacity of H_out / M_out in entries. */
+shaken_status shaken_batch_get_log(shaken_batch *b, int32_t i, int64_t *H_out, int64_t *M_out,
+                                   int64_t cap);
+
+/* Strategy the batch uses (after AUTO and autotuning), and the last call's
+ * device time in milliseconds measured with HIP events on the batch stream
+ * (synchronises). */
+shaken_status shaken_batch_info(shaken_batch *b, int32_t *strategy, double *last_ms);
+
+shaken_status shaken_batch_free(shaken_batch *b);
+
+/* One-call convenience: create a batch over ctx[0..n-1], run n_full full
+ * steps, optionally copy each chain's final H into H_final (n entries),
+ * free the batch.  Synchronises. */
+shaken_status shaken_batch_run(shaken_ctx *const *ctx, int32_t n, int64_t n_full,
+                               const shaken_batch_opts *opts, int64_t *H_final);
+
+/* -------------------------------------------------------------- diagnostics */
+
+const char *shaken_strerror(shaken_status s);
+/* Message of the last failing call on this thread ("" if none). */
+const char *shaken_last_error(void);
+/* (major << 16) | minor */
+int32_t shaken_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SHAKEN_H */

@@ -1,0 +1,352 @@
+"""Python binding of libshaken: shaken dynamics (arXiv:1904.06257) on MI355X.
+
+Argument marshalling only.  Every half-step, observable and batch runs in the
+HIP kernels of ``libshaken.so`` behind the C ABI declared in
+``include/shaken.h``; this module converts numpy arrays and torch streams to
+the plain pointers and sizes of that ABI.  There is no Python or CPU fallback:
+importing the package fails if the library has not been built.
+
+The functions keep the C names (``shaken_init``, ``shaken_half_step``,
+``shaken_sweep``, ``shaken_observables``, ``shaken_batch_run`` ...).  The
+classes ``Chain`` and ``Batch`` wrap a context / batch handle with the same
+calls as methods.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libshaken.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libshaken.so is not built (run __graft_entry__.build() or "
+                      "python paper_1904_06257_amd/build.py); there is no fallback")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+SHAKEN_OK, SHAKEN_EINVAL, SHAKEN_ENOMEM, SHAKEN_EDEVICE, SHAKEN_ESTATE = range(5)
+SHAKEN_TORUS, SHAKEN_EDGES = 0, 1
+SHAKEN_FMT_AUTO, SHAKEN_FMT_INT8, SHAKEN_FMT_BITPACKED = 0, 1, 2
+SHAKEN_INIT_RANDOM, SHAKEN_INIT_ALL_UP, SHAKEN_INIT_ALL_DOWN, SHAKEN_INIT_USER = 0, 1, 2, 3
+SHAKEN_BATCH_AUTO, SHAKEN_BATCH_GRID, SHAKEN_BATCH_PERSISTENT = 0, 1, 2
+
+_INIT = {"random": SHAKEN_INIT_RANDOM, "all_up": SHAKEN_INIT_ALL_UP,
+         "all_down": SHAKEN_INIT_ALL_DOWN, "user": SHAKEN_INIT_USER}
+_FMT = {"auto": SHAKEN_FMT_AUTO, "int8": SHAKEN_FMT_INT8, "bitpacked": SHAKEN_FMT_BITPACKED}
+_STRAT = {"auto": SHAKEN_BATCH_AUTO, "grid": SHAKEN_BATCH_GRID,
+          "persistent": SHAKEN_BATCH_PERSISTENT}
+
+
+class shaken_graph(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("L", ctypes.c_int32), ("n", ctypes.c_int32),
+                ("m", ctypes.c_int64), ("src", ctypes.POINTER(ctypes.c_int32)),
+                ("dst", ctypes.POINTER(ctypes.c_int32))]
+
+
+class shaken_field(ctypes.Structure):
+    _fields_ = [("n_classes", ctypes.c_int32), ("value", ctypes.POINTER(ctypes.c_double)),
+                ("class_of_vertex", ctypes.POINTER(ctypes.c_uint8))]
+
+
+class shaken_opts(ctypes.Structure):
+    _fields_ = [("format", ctypes.c_int32), ("init", ctypes.c_int32),
+                ("init_spins", ctypes.POINTER(ctypes.c_int8)), ("replica", ctypes.c_uint32),
+                ("device", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+
+
+class shaken_obs(ctypes.Structure):
+    _fields_ = [("half_step", ctypes.c_int64), ("n_sites", ctypes.c_int64),
+                ("M", ctypes.c_int64), ("E_J", ctypes.c_int64), ("E_lambda2", ctypes.c_int64),
+                ("H", ctypes.c_double), ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class shaken_batch_opts(ctypes.Structure):
+    _fields_ = [("strategy", ctypes.c_int32), ("use_hipgraph", ctypes.c_int32),
+                ("autotune", ctypes.c_int32), ("record", ctypes.c_int32),
+                ("stream", ctypes.c_void_p)]
+
+
+_vp = ctypes.c_void_p
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_i8p = ctypes.POINTER(ctypes.c_int8)
+
+_SIGS = {
+    "shaken_init": [ctypes.POINTER(_vp), ctypes.POINTER(shaken_graph), _i8p,
+                    ctypes.POINTER(shaken_field), ctypes.c_double, ctypes.c_double,
+                    ctypes.c_uint64, ctypes.POINTER(shaken_opts)],
+    "shaken_free": [_vp],
+    "shaken_half_step": [_vp, ctypes.c_int64],
+    "shaken_sweep": [_vp, ctypes.c_int64, _i64p, _i64p],
+    "shaken_observables": [_vp, ctypes.POINTER(shaken_obs)],
+    "shaken_set_params": [_vp, ctypes.c_double, ctypes.c_double],
+    "shaken_get_spins": [_vp, _i8p],
+    "shaken_set_spins": [_vp, _i8p],
+    "shaken_set_half_step": [_vp, ctypes.c_int64],
+    "shaken_get_lut": [_vp, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_size_t),
+                       ctypes.POINTER(ctypes.c_int32)],
+    "shaken_spins_device": [_vp, ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_int32)],
+    "shaken_synchronize": [_vp],
+    "shaken_batch_create": [ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.c_int32,
+                            ctypes.POINTER(shaken_batch_opts)],
+    "shaken_batch_sweep": [_vp, ctypes.c_int64],
+    "shaken_batch_get_log": [_vp, ctypes.c_int32, _i64p, _i64p, ctypes.c_int64],
+    "shaken_batch_info": [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)],
+    "shaken_batch_free": [_vp],
+    "shaken_batch_run": [ctypes.POINTER(_vp), ctypes.c_int32, ctypes.c_int64,
+                         ctypes.POINTER(shaken_batch_opts), _i64p],
+}
+for _name, _args in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = ctypes.c_int
+_lib.shaken_strerror.argtypes = [ctypes.c_int]
+_lib.shaken_strerror.restype = ctypes.c_char_p
+_lib.shaken_last_error.argtypes = []
+_lib.shaken_last_error.restype = ctypes.c_char_p
+_lib.shaken_version.argtypes = []
+_lib.shaken_version.restype = ctypes.c_int32
+
+EXPORTED = sorted(list(_SIGS) + ["shaken_strerror", "shaken_last_error", "shaken_version"])
+
+
+class ShakenError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (_lib.shaken_strerror(status).decode(), msg))
+        self.status = status
+
+
+def _check(st):
+    if st != SHAKEN_OK:
+        raise ShakenError(st, _lib.shaken_last_error().decode())
+
+
+def _ptr(a, t):
+    return None if a is None else a.ctypes.data_as(ctypes.POINTER(t))
+
+
+def _stream_handle(stream):
+    """torch stream, raw handle (int) or None -> void*"""
+    if stream is None:
+        return None
+    if hasattr(stream, "cuda_stream"):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+# ------------------------------------------------------------- raw functions
+
+def shaken_version():
+    return int(_lib.shaken_version())
+
+
+def shaken_init(graph, J, lam, q, beta, seed, opts):
+    """Returns a context handle (c_void_p).  graph, lam, opts are the ctypes
+    structs above (lam may be None); J a contiguous int8 array or None."""
+    h = _vp()
+    _check(_lib.shaken_init(ctypes.byref(h), ctypes.byref(graph), _ptr(J, ctypes.c_int8),
+                            None if lam is None else ctypes.byref(lam), float(q), float(beta),
+                            ctypes.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), ctypes.byref(opts)))
+    return h
+
+
+def shaken_free(ctx):
+    _check(_lib.shaken_free(ctx))
+
+
+def shaken_half_step(ctx, n):
+    _check(_lib.shaken_half_step(ctx, int(n)))
+
+
+def shaken_sweep(ctx, n_full, H_out=None, M_out=None):
+    _check(_lib.shaken_sweep(ctx, int(n_full), _ptr(H_out, ctypes.c_int64), _ptr(M_out, ctypes.c_int64)))
+
+
+def shaken_observables(ctx):
+    o = shaken_obs()
+    _check(_lib.shaken_observables(ctx, ctypes.byref(o)))
+    return o
+
+
+def shaken_batch_run(ctxs, n_full, opts, H_final=None):
+    arr = (_vp * len(ctxs))(*[c.value for c in ctxs])
+    _check(_lib.shaken_batch_run(arr, len(ctxs), int(n_full), ctypes.byref(opts),
+                                 _ptr(H_final, ctypes.c_int64)))
+
+
+# ------------------------------------------------------------------ classes
+
+class Chain:
+    """One shaken-dynamics chain (a libshaken context)."""
+
+    def __init__(self, kind, *, L=0, n=0, src=None, dst=None, J=None, lam_values=None,
+                 lam_class=None, q=1.0, beta=1.0, seed=0, replica=0, init="random",
+                 init_spins=None, fmt="auto", device=-1, stream=None):
+        g = shaken_graph()
+        self._keep = []
+        if kind == "torus":
+            g.kind, g.L = SHAKEN_TORUS, int(L)
+            self.shape = (int(L), int(L))
+            self.n = int(L) * int(L)
+        elif kind == "graph":
+            src = np.ascontiguousarray(src, dtype=np.int32)
+            dst = np.ascontiguousarray(dst, dtype=np.int32)
+            self._keep += [src, dst]
+            g.kind, g.n, g.m = SHAKEN_EDGES, int(n), int(src.shape[0])
+            g.src, g.dst = _ptr(src, ctypes.c_int32), _ptr(dst, ctypes.c_int32)
+            self.shape = (int(n),)
+            self.n = int(n)
+        else:
+            raise ValueError("kind must be 'torus' or 'graph'")
+        Jarr = None if J is None else np.ascontiguousarray(J, dtype=np.int8)
+        field = None
+        if lam_values is not None:
+            lv = np.ascontiguousarray(np.atleast_1d(lam_values), dtype=np.float64)
+            lc = None if lam_class is None else np.ascontiguousarray(lam_class, dtype=np.uint8)
+            self._keep += [lv, lc]
+            field = shaken_field(len(lv), _ptr(lv, ctypes.c_double), _ptr(lc, ctypes.c_uint8))
+            self.lam_values = lv
+            self.lam_class = lc
+        else:
+            self.lam_values = np.zeros(1)
+            self.lam_class = None
+        o = shaken_opts()
+        o.format = _FMT[fmt]
+        o.init = _INIT[init]
+        sp = None
+        if init_spins is not None:
+            sp = np.ascontiguousarray(init_spins, dtype=np.int8).reshape(-1)
+            o.init = SHAKEN_INIT_USER
+            o.init_spins = _ptr(sp, ctypes.c_int8)
+        o.replica = int(replica)
+        o.device = int(device)
+        o.stream = _stream_handle(stream)
+        self.kind = kind
+        self.handle = shaken_init(g, Jarr, field, q, beta, seed, o)
+        self._keep = None
+
+    @classmethod
+    def torus(cls, L, **kw):
+        return cls("torus", L=L, **kw)
+
+    @classmethod
+    def graph(cls, n, src, dst, **kw):
+        return cls("graph", n=n, src=src, dst=dst, **kw)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            shaken_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def half_step(self, n=1):
+        shaken_half_step(self.handle, n)
+
+    def sweep(self, n_full, log=False):
+        if not log:
+            shaken_sweep(self.handle, n_full)
+            return None
+        H = np.zeros(n_full + 1, dtype=np.int64)
+        M = np.zeros(n_full + 1, dtype=np.int64)
+        shaken_sweep(self.handle, n_full, H, M)
+        return H, M
+
+    def sweep_m(self, n_full):
+        """magnetisation log only (works for any lambda)"""
+        M = np.zeros(n_full + 1, dtype=np.int64)
+        shaken_sweep(self.handle, n_full, None, M)
+        return M
+
+    def observables(self):
+        return shaken_observables(self.handle)
+
+    def set_params(self, beta, q):
+        _check(_lib.shaken_set_params(self.handle, float(beta), float(q)))
+
+    def spins(self):
+        out = np.zeros(self.n, dtype=np.int8)
+        _check(_lib.shaken_get_spins(self.handle, _ptr(out, ctypes.c_int8)))
+        return out.reshape(self.shape)
+
+    def set_spins(self, sp):
+        a = np.ascontiguousarray(sp, dtype=np.int8).reshape(-1)
+        if a.shape[0] != self.n:
+            raise ValueError("wrong number of spins")
+        _check(_lib.shaken_set_spins(self.handle, _ptr(a, ctypes.c_int8)))
+
+    def set_half_step(self, s):
+        _check(_lib.shaken_set_half_step(self.handle, int(s)))
+
+    @property
+    def half_step_index(self):
+        return int(self.observables().half_step)
+
+    def lut(self):
+        n = ctypes.c_size_t(0)
+        smax = ctypes.c_int32(0)
+        _check(_lib.shaken_get_lut(self.handle, None, ctypes.byref(n), ctypes.byref(smax)))
+        out = np.zeros(n.value, dtype=np.uint64)
+        _check(_lib.shaken_get_lut(self.handle, _ptr(out, ctypes.c_uint64), ctypes.byref(n),
+                                   ctypes.byref(smax)))
+        return out, int(smax.value)
+
+    def device_spins(self):
+        p = _vp()
+        f = ctypes.c_int32()
+        _check(_lib.shaken_spins_device(self.handle, ctypes.byref(p), ctypes.byref(f)))
+        return p.value, int(f.value)
+
+    def synchronize(self):
+        _check(_lib.shaken_synchronize(self.handle))
+
+
+class Batch:
+    """A batch of chains advanced by fused launches (libshaken batch)."""
+
+    def __init__(self, chains, strategy="auto", use_hipgraph=False, autotune=False,
+                 record=False, stream=None):
+        self.chains = list(chains)
+        o = shaken_batch_opts(_STRAT[strategy], int(use_hipgraph), int(autotune), int(record),
+                              _stream_handle(stream))
+        arr = (_vp * len(self.chains))(*[c.handle.value for c in self.chains])
+        h = _vp()
+        _check(_lib.shaken_batch_create(ctypes.byref(h), arr, len(self.chains), ctypes.byref(o)))
+        self.handle = h
+        self.record = bool(record)
+        self._last = None
+
+    def sweep(self, n_full):
+        _check(_lib.shaken_batch_sweep(self.handle, int(n_full)))
+        self._last = int(n_full)
+
+    def log(self, i, with_H=True):
+        n = self._last + 1
+        H = np.zeros(n, dtype=np.int64) if with_H else None
+        M = np.zeros(n, dtype=np.int64)
+        _check(_lib.shaken_batch_get_log(self.handle, int(i), _ptr(H, ctypes.c_int64),
+                                         _ptr(M, ctypes.c_int64), n))
+        return H, M
+
+    def info(self):
+        st = ctypes.c_int32()
+        ms = ctypes.c_double()
+        _check(_lib.shaken_batch_info(self.handle, ctypes.byref(st), ctypes.byref(ms)))
+        return int(st.value), float(ms.value)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            _check(_lib.shaken_batch_free(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

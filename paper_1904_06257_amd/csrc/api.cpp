@@ -1,0 +1,1121 @@
+// Host runtime and C ABI of libshaken: argument validation, the layout of the
+// oriented graph (in-half and out-half CSR), the threshold tables, chain
+// contexts and the batch executor.  Every half-step runs in the HIP kernels of
+// kernels.hip; this file only prepares data and enqueues launches.
+#include "shaken.h"
+#include "shaken_internal.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace shaken;
+
+namespace {
+
+thread_local std::string g_err;
+
+shaken_status fail(shaken_status s, const std::string &msg) {
+    g_err = msg;
+    return s;
+}
+
+#define HIPCHK(expr)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(e_ == hipErrorOutOfMemory ? SHAKEN_ENOMEM : SHAKEN_EDEVICE,           \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));                   \
+    } while (0)
+
+#define CHK(expr)                                                                             \
+    do {                                                                                      \
+        shaken_status s_ = (expr);                                                            \
+        if (s_ != SHAKEN_OK) return s_;                                                       \
+    } while (0)
+
+// Make the context's device current for the duration of a call.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (dev >= 0 && dev != prev) ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+template <class T>
+shaken_status dalloc(T **p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void **)p, count * sizeof(T));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(e == hipErrorOutOfMemory ? SHAKEN_ENOMEM : SHAKEN_EDEVICE,
+                    std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    return SHAKEN_OK;
+}
+
+template <class T>
+void dfree(T *&p) {
+    if (p) (void)hipFree((void *)p);
+    p = nullptr;
+}
+
+// ---------------------------------------------------------------- thresholds
+
+// Local field h = S + q sigma + lambda, evaluated left to right in double.
+double field_h(int64_t S, int sigma, double q, double lam) {
+    double h = (double)S;
+    h = h + q * (double)sigma;
+    h = h + lam;
+    return h;
+}
+
+// T in [0, 2^32] with P(+1) = T / 2^32 ~ 1 / (1 + exp(-2 beta h)) (the
+// heat-bath factor exp(beta h s') / (2 cosh(beta h)) of section 2).  The small
+// tail e/(1+e) is rounded down and mirrored, so T(h) + T(-h) = 2^32 exactly.
+uint64_t threshold_T(double h, double beta) {
+    const double e = std::exp(-((2.0 * beta) * std::fabs(h)));
+    const double p = e / (1.0 + e);
+    const uint64_t t = (uint64_t)std::floor(p * 4294967296.0);
+    return (h >= 0.0) ? ((uint64_t)1 << 32) - t : t;
+}
+
+bool finite_nonneg(double x) { return std::isfinite(x) && x >= 0.0; }
+
+}  // namespace
+
+// ------------------------------------------------------------------ context
+
+struct shaken_ctx {
+    int device = -1;
+    hipStream_t stream = nullptr;
+    int kind = KIND_TORUS;
+    int format = FMT_BITPACKED;
+    int L = 0, W = 0, n = 0;
+    int64_t m = 0;
+    double q = 0, beta = 0;
+    uint64_t seed = 0;
+    uint32_t replica = 0;
+    int J = 1;  // uniform torus coupling
+    std::vector<double> lam;
+    std::vector<int64_t> class_size;
+    bool lam2_int = true;
+    std::vector<int64_t> lam2;  // 2*lambda as integers (valid iff lam2_int)
+    int smax = 0;
+    int maxdeg = 0;
+    std::vector<uint64_t> lut;
+    uint32_t s = 0;  // half-step counter; configuration at s is in spin[s & 1]
+    void *spin[2] = {nullptr, nullptr};
+    uint64_t *lut_dev = nullptr;
+    int32_t *rp[2] = {nullptr, nullptr};
+    int32_t *col[2] = {nullptr, nullptr};
+    int8_t *jw[2] = {nullptr, nullptr};
+    uint8_t *cls_dev = nullptr;
+    int64_t *log_dev = nullptr;
+    int64_t log_cap = 0;  // slots
+    int64_t *obs_dev = nullptr;
+    ChainDesc hd{};
+    ChainDesc *dd = nullptr;
+    int block = 256;
+
+    size_t spin_bytes() const {
+        if (kind == KIND_TORUS && format == FMT_BITPACKED) return (size_t)L * W * 4;
+        return (size_t)n;
+    }
+    int64_t stride() const { return 1 + (int64_t)lam.size(); }
+};
+
+namespace {
+
+void release(shaken_ctx *c) {
+    dfree(c->spin[0]);
+    dfree(c->spin[1]);
+    dfree(c->lut_dev);
+    for (int h = 0; h < 2; ++h) {
+        dfree(c->rp[h]);
+        dfree(c->col[h]);
+        dfree(c->jw[h]);
+    }
+    dfree(c->cls_dev);
+    dfree(c->log_dev);
+    dfree(c->obs_dev);
+    dfree(c->dd);
+}
+
+// Build the host threshold table and the bit-packed torus class tables.
+void build_tables(shaken_ctx *c) {
+    const int ncls = (int)c->lam.size();
+    const int nS = 2 * c->smax + 1;
+    c->lut.assign((size_t)nS * 2 * ncls, 0);
+    for (int S = -c->smax; S <= c->smax; ++S)
+        for (int sb = 0; sb < 2; ++sb)
+            for (int k = 0; k < ncls; ++k) {
+                const double h = field_h(S, sb ? 1 : -1, c->q, c->lam[k]);
+                c->lut[((size_t)(S + c->smax) * 2 + sb) * ncls + k] = threshold_T(h, c->beta);
+            }
+    if (c->kind == KIND_TORUS) {
+        uint32_t sgn = 0;
+        for (int j = 0; j < 6; ++j) {
+            const int nplus = j % 3, cb = j / 3;
+            const int64_t S = (int64_t)c->J * (2 * nplus - 2);
+            const double h = field_h(S, cb ? 1 : -1, c->q, c->lam[0]);
+            const uint64_t T = threshold_T(h, c->beta);
+            const uint64_t t = (h >= 0.0) ? ((uint64_t)1 << 32) - T : T;
+            c->hd.tsmall[j] = (uint32_t)t;
+            if (h >= 0.0) sgn |= 1u << j;
+        }
+        c->hd.sgn = sgn;
+        const uint32_t *t = c->hd.tsmall;
+        c->hd.fold3 = (t[0] == t[5] && t[2] == t[3] && t[1] == t[4]) ? 1 : 0;
+    }
+}
+
+shaken_status upload_tables(shaken_ctx *c) {
+    HIPCHK(hipMemcpyAsync(c->lut_dev, c->lut.data(), c->lut.size() * sizeof(uint64_t),
+                          hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->dd, &c->hd, sizeof(ChainDesc), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return SHAKEN_OK;
+}
+
+void refresh_desc_spins(shaken_ctx *c) {
+    c->hd.spin[0] = c->spin[0];
+    c->hd.spin[1] = c->spin[1];
+    c->hd.log = c->log_dev;
+}
+
+shaken_status ensure_log(shaken_ctx *c, int64_t slots) {
+    if (slots <= c->log_cap) return SHAKEN_OK;
+    dfree(c->log_dev);
+    c->log_cap = 0;
+    CHK(dalloc(&c->log_dev, (size_t)(slots * c->stride())));
+    c->log_cap = slots;
+    refresh_desc_spins(c);
+    HIPCHK(hipMemcpyAsync(c->dd, &c->hd, sizeof(ChainDesc), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return SHAKEN_OK;
+}
+
+// pack / unpack host int8 <-> bit-packed torus
+void pack_torus(const int8_t *in, int L, int W, std::vector<uint32_t> &out) {
+    out.assign((size_t)L * W, 0u);
+    for (int r = 0; r < L; ++r)
+        for (int c = 0; c < L; ++c)
+            if (in[(size_t)r * L + c] > 0) out[(size_t)r * W + (c >> 5)] |= 1u << (c & 31);
+}
+
+void unpack_torus(const std::vector<uint32_t> &in, int L, int W, int8_t *out) {
+    for (int r = 0; r < L; ++r)
+        for (int c = 0; c < L; ++c)
+            out[(size_t)r * L + c] = ((in[(size_t)r * W + (c >> 5)] >> (c & 31)) & 1u) ? 1 : -1;
+}
+
+// Convert a device log (slots x stride) to H and M per slot.
+void convert_log(const shaken_ctx *c, const std::vector<int64_t> &raw, int64_t slots,
+                 int64_t *H, int64_t *M) {
+    const int64_t st = c->stride();
+    for (int64_t t = 0; t < slots; ++t) {
+        const int64_t EJ = raw[t * st];
+        int64_t m = 0, l2 = 0;
+        for (size_t k = 0; k < c->lam.size(); ++k) {
+            const int64_t mk = 2 * raw[t * st + 1 + k] - c->class_size[k];
+            m += mk;
+            if (c->lam2_int) l2 += c->lam2[k] * mk;
+        }
+        if (H) H[t] = -EJ - l2;
+        if (M) M[t] = m;
+    }
+}
+
+// Validate and lay out an oriented graph as in-half and out-half CSR.
+shaken_status build_graph(shaken_ctx *c, const shaken_graph *g, const int8_t *J,
+                          std::vector<int32_t> rp[2], std::vector<int32_t> col[2],
+                          std::vector<int8_t> jw[2]) {
+    const int n = g->n;
+    const int64_t m = g->m;
+    if (n < 1) return fail(SHAKEN_EINVAL, "graph: n must be >= 1");
+    if (m < 0 || m > (int64_t)std::numeric_limits<int32_t>::max())
+        return fail(SHAKEN_EINVAL, "graph: m out of range");
+    if (m > 0 && (!g->src || !g->dst)) return fail(SHAKEN_EINVAL, "graph: src/dst are NULL");
+    std::vector<int64_t> key((size_t)m);
+    for (int64_t e = 0; e < m; ++e) {
+        const int32_t a = g->src[e], b = g->dst[e];
+        if (a < 0 || a >= n || b < 0 || b >= n)
+            return fail(SHAKEN_EINVAL, "graph: vertex id out of range at edge " + std::to_string(e));
+        if (a == b) return fail(SHAKEN_EINVAL, "graph: self-loop at edge " + std::to_string(e));
+        key[e] = (int64_t)std::min(a, b) * n + std::max(a, b);
+    }
+    std::sort(key.begin(), key.end());
+    for (int64_t e = 1; e < m; ++e)
+        if (key[e] == key[e - 1])
+            return fail(SHAKEN_EINVAL, "graph: an edge is given twice (the graph must be simple)");
+    // half 0: in-half (row = head dst, entries = tails src); half 1: out-half
+    for (int h = 0; h < 2; ++h) {
+        rp[h].assign((size_t)n + 1, 0);
+        const int32_t *row = (h == 0) ? g->dst : g->src;
+        const int32_t *other = (h == 0) ? g->src : g->dst;
+        for (int64_t e = 0; e < m; ++e) rp[h][row[e] + 1]++;
+        for (int v = 0; v < n; ++v) rp[h][v + 1] += rp[h][v];
+        col[h].assign((size_t)m, 0);
+        jw[h].assign((size_t)m, 1);
+        std::vector<int32_t> pos(rp[h].begin(), rp[h].end() - 1);
+        for (int64_t e = 0; e < m; ++e) {
+            const int32_t p = pos[row[e]]++;
+            col[h][p] = other[e];
+            jw[h][p] = J ? J[e] : (int8_t)1;
+        }
+    }
+    int64_t smax = 0;
+    int maxdeg = 0;
+    for (int h = 0; h < 2; ++h)
+        for (int v = 0; v < n; ++v) {
+            int64_t a = 0;
+            for (int32_t e = rp[h][v]; e < rp[h][v + 1]; ++e) a += std::abs((int)jw[h][e]);
+            smax = std::max(smax, a);
+            maxdeg = std::max(maxdeg, rp[h][v + 1] - rp[h][v]);
+        }
+    if (smax > (1 << 22)) return fail(SHAKEN_EINVAL, "graph: coupling sums too large for the threshold table");
+    c->smax = (int)smax;
+    c->maxdeg = maxdeg;
+    return SHAKEN_OK;
+}
+
+struct HostLayout {
+    std::vector<uint8_t> cls_host;
+    std::vector<int32_t> rp[2], col[2];
+    std::vector<int8_t> jw[2];
+};
+
+// Host phase of shaken_init: validation, layout and tables; touches no device.
+shaken_status init_host(shaken_ctx *c, const shaken_graph *g, const int8_t *J,
+                        const shaken_field *lambda, const shaken_opts *o, HostLayout &hl) {
+    std::vector<uint8_t> &cls_host = hl.cls_host;
+    std::vector<int32_t> *rp = hl.rp, *col = hl.col;
+    std::vector<int8_t> *jw = hl.jw;
+    // field
+    if (lambda) {
+        if (lambda->n_classes < 1 || lambda->n_classes > 256 || !lambda->value)
+            return fail(SHAKEN_EINVAL, "field: n_classes must be in [1, 256] with values");
+        c->lam.assign(lambda->value, lambda->value + lambda->n_classes);
+        for (double v : c->lam)
+            if (!std::isfinite(v)) return fail(SHAKEN_EINVAL, "field: non-finite lambda");
+    } else {
+        c->lam.assign(1, 0.0);
+    }
+    c->lam2.assign(c->lam.size(), 0);
+    c->lam2_int = true;
+    for (size_t k = 0; k < c->lam.size(); ++k) {
+        const double v2 = 2.0 * c->lam[k];
+        if (v2 != std::floor(v2) || std::fabs(v2) > 1e15)
+            c->lam2_int = false;
+        else
+            c->lam2[k] = (int64_t)v2;
+    }
+    if (g->kind == SHAKEN_TORUS) {
+        if (g->L < 3 || g->L > 32768) return fail(SHAKEN_EINVAL, "torus: L must be in [3, 32768]");
+        if (lambda && (lambda->n_classes != 1 || lambda->class_of_vertex))
+            return fail(SHAKEN_EINVAL, "torus: the field must be uniform (one class, no class map)");
+        c->kind = KIND_TORUS;
+        c->L = g->L;
+        c->W = (g->L + 31) / 32;
+        c->n = g->L * g->L;
+        c->m = 2 * (int64_t)c->n;
+        c->J = 1;
+        if (J) {
+            for (int64_t e = 1; e < c->m; ++e)
+                if (J[e] != J[0])
+                    return fail(SHAKEN_EINVAL, "torus: couplings must be uniform (pass a non-uniform torus as SHAKEN_EDGES)");
+            c->J = J[0];
+        }
+        c->smax = 2 * std::abs(c->J);
+        c->maxdeg = 2;
+        if (o->format == SHAKEN_FMT_INT8)
+            c->format = FMT_INT8;
+        else if (o->format == SHAKEN_FMT_AUTO || o->format == SHAKEN_FMT_BITPACKED)
+            c->format = FMT_BITPACKED;
+        else
+            return fail(SHAKEN_EINVAL, "unknown format");
+        c->class_size.assign(1, c->n);
+    } else if (g->kind == SHAKEN_EDGES) {
+        c->kind = KIND_GRAPH;
+        c->n = g->n;
+        c->m = g->m;
+        if (o->format == SHAKEN_FMT_BITPACKED)
+            return fail(SHAKEN_EINVAL, "graph: only the int8 format is available");
+        if (o->format != SHAKEN_FMT_AUTO && o->format != SHAKEN_FMT_INT8)
+            return fail(SHAKEN_EINVAL, "unknown format");
+        c->format = FMT_INT8;
+        CHK(build_graph(c, g, J, rp, col, jw));
+        cls_host.assign((size_t)c->n, 0);
+        if (lambda && lambda->class_of_vertex) {
+            for (int v = 0; v < c->n; ++v) {
+                if (lambda->class_of_vertex[v] >= lambda->n_classes)
+                    return fail(SHAKEN_EINVAL, "field: class id out of range");
+                cls_host[v] = lambda->class_of_vertex[v];
+            }
+        }
+        c->class_size.assign(c->lam.size(), 0);
+        for (int v = 0; v < c->n; ++v) c->class_size[cls_host[v]]++;
+    } else {
+        return fail(SHAKEN_EINVAL, "unknown graph kind");
+    }
+    const size_t lut_entries = (size_t)(2 * c->smax + 1) * 2 * c->lam.size();
+    if (lut_entries > ((size_t)1 << 24))
+        return fail(SHAKEN_EINVAL, "threshold table would exceed 2^24 entries");
+    if (o->init == SHAKEN_INIT_USER) {
+        if (!o->init_spins) return fail(SHAKEN_EINVAL, "init: SHAKEN_INIT_USER needs init_spins");
+        for (int64_t i = 0; i < c->n; ++i)
+            if (o->init_spins[i] != 1 && o->init_spins[i] != -1)
+                return fail(SHAKEN_EINVAL, "init: spins must be +1 or -1");
+    } else if (o->init != SHAKEN_INIT_RANDOM && o->init != SHAKEN_INIT_ALL_UP &&
+               o->init != SHAKEN_INIT_ALL_DOWN) {
+        return fail(SHAKEN_EINVAL, "unknown init mode");
+    }
+    return SHAKEN_OK;
+}
+
+// Device phase of shaken_init: buffers, uploads, descriptor, initial state.
+shaken_status init_device(shaken_ctx *c, const shaken_opts *o, HostLayout &hl) {
+    std::vector<uint8_t> &cls_host = hl.cls_host;
+    std::vector<int32_t> *rp = hl.rp, *col = hl.col;
+    std::vector<int8_t> *jw = hl.jw;
+    const size_t lut_entries = (size_t)(2 * c->smax + 1) * 2 * c->lam.size();
+
+    // device buffers
+    CHK(dalloc((uint8_t **)&c->spin[0], c->spin_bytes()));
+    CHK(dalloc((uint8_t **)&c->spin[1], c->spin_bytes()));
+    CHK(dalloc(&c->lut_dev, lut_entries));
+    CHK(dalloc(&c->obs_dev, (size_t)c->stride()));
+    CHK(dalloc(&c->dd, 1));
+    if (c->kind == KIND_GRAPH) {
+        for (int h = 0; h < 2; ++h) {
+            CHK(dalloc(&c->rp[h], rp[h].size()));
+            CHK(dalloc(&c->col[h], col[h].size()));
+            CHK(dalloc(&c->jw[h], jw[h].size()));
+            HIPCHK(hipMemcpyAsync(c->rp[h], rp[h].data(), rp[h].size() * 4, hipMemcpyHostToDevice, c->stream));
+            if (c->m > 0) {
+                HIPCHK(hipMemcpyAsync(c->col[h], col[h].data(), col[h].size() * 4, hipMemcpyHostToDevice, c->stream));
+                HIPCHK(hipMemcpyAsync(c->jw[h], jw[h].data(), jw[h].size(), hipMemcpyHostToDevice, c->stream));
+            }
+        }
+        CHK(dalloc(&c->cls_dev, (size_t)c->n));
+        HIPCHK(hipMemcpyAsync(c->cls_dev, cls_host.data(), (size_t)c->n, hipMemcpyHostToDevice, c->stream));
+    }
+
+    // descriptor
+    ChainDesc &d = c->hd;
+    std::memset(&d, 0, sizeof(d));
+    d.seed = c->seed;
+    d.replica = c->replica;
+    d.kind = c->kind;
+    d.format = c->format;
+    d.L = c->L;
+    d.W = c->W;
+    d.n = c->n;
+    d.J = c->J;
+    d.lut = c->lut_dev;
+    d.smax = c->smax;
+    d.ncls = (int32_t)c->lam.size();
+    for (int h = 0; h < 2; ++h) {
+        d.rowptr[h] = c->rp[h];
+        d.col[h] = c->col[h];
+        d.jw[h] = c->jw[h];
+    }
+    d.cls = c->cls_dev;
+    d.maxdeg = c->maxdeg;
+    d.log_stride = c->stride();
+    refresh_desc_spins(c);
+    build_tables(c);
+    CHK(upload_tables(c));
+
+    // initial state into spin[0] (s = 0)
+    switch (o->init) {
+    case SHAKEN_INIT_RANDOM:
+    case SHAKEN_INIT_ALL_UP:
+    case SHAKEN_INIT_ALL_DOWN: {
+        const int mode = o->init == SHAKEN_INIT_RANDOM ? 0 : (o->init == SHAKEN_INIT_ALL_UP ? 1 : 2);
+        HIPCHK(launch_init(c->hd, c->spin[0], mode, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        break;
+    }
+    default:
+        CHK(shaken_set_spins(c, o->init_spins));
+        break;
+    }
+    return SHAKEN_OK;
+}
+
+// one half-step at the context's counter
+shaken_status half_step_once(shaken_ctx *c, int log_on, uint32_t s_log0) {
+    if (c->s >= kInitStep - 1) return fail(SHAKEN_ESTATE, "half-step counter exhausted");
+    HIPCHK(launch_half_step_grid(c->dd, &c->hd, 1, nullptr, c->s, s_log0, log_on,
+                                 (c->s & 1u) == 0, c->block, c->stream));
+    c->s += 1;
+    return SHAKEN_OK;
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+
+extern "C" {
+
+shaken_status shaken_init(shaken_ctx **out, const shaken_graph *g, const int8_t *J,
+                          const shaken_field *lambda, double q, double beta, uint64_t seed,
+                          const shaken_opts *opts) {
+    g_err.clear();
+    if (!out || !g) return fail(SHAKEN_EINVAL, "out and g must be non-NULL");
+    *out = nullptr;
+    if (!finite_nonneg(q)) return fail(SHAKEN_EINVAL, "q must be finite and >= 0");
+    if (!finite_nonneg(beta)) return fail(SHAKEN_EINVAL, "beta must be finite and >= 0");
+    shaken_opts o{};
+    o.format = SHAKEN_FMT_AUTO;
+    o.init = SHAKEN_INIT_RANDOM;
+    o.device = -1;
+    if (opts) o = *opts;
+    shaken_ctx *c = new (std::nothrow) shaken_ctx();
+    if (!c) return fail(SHAKEN_ENOMEM, "host allocation failed");
+    c->stream = (hipStream_t)o.stream;
+    c->q = q;
+    c->beta = beta;
+    c->seed = seed;
+    c->replica = o.replica;
+    shaken_status st;
+    HostLayout hl;
+    try {
+        st = init_host(c, g, J, lambda, &o, hl);
+    } catch (const std::bad_alloc &) {
+        st = fail(SHAKEN_ENOMEM, "host allocation failed");
+    }
+    if (st != SHAKEN_OK) {
+        delete c;
+        return st;
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+        (void)hipGetLastError();
+        delete c;
+        return fail(SHAKEN_EDEVICE, "no HIP device");
+    }
+    if (o.device >= ndev) {
+        delete c;
+        return fail(SHAKEN_EINVAL, "device ordinal out of range");
+    }
+    if (o.device >= 0) {
+        c->device = o.device;
+    } else if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return fail(SHAKEN_EDEVICE, "no current HIP device");
+    }
+    DeviceGuard guard(c->device);
+    try {
+        st = init_device(c, &o, hl);
+    } catch (const std::bad_alloc &) {
+        st = fail(SHAKEN_ENOMEM, "host allocation failed");
+    }
+    if (st != SHAKEN_OK) {
+        release(c);
+        delete c;
+        return st;
+    }
+    *out = c;
+    return SHAKEN_OK;
+}
+
+shaken_status shaken_free(shaken_ctx *ctx) {
+    if (!ctx) return SHAKEN_OK;
+    DeviceGuard guard(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    release(ctx);
+    delete ctx;
+    return SHAKEN_OK;
+}
+
+shaken_status shaken_half_step(shaken_ctx *ctx, int64_t n) {
+    if (!ctx) return fail(SHAKEN_EINVAL, "ctx is NULL");
+    if (n < 0) return fail(SHAKEN_EINVAL, "n must be >= 0");
+    DeviceGuard guard(ctx->device);
+    if ((int64_t)ctx->s + n >= (int64_t)kInitStep) return fail(SHAKEN_ESTATE, "half-step counter would overflow");
+    for (int64_t i = 0; i < n; ++i) CHK(half_step_once(ctx, 0, 0));
+    return SHAKEN_OK;
+}
+
+shaken_status shaken_sweep(shaken_ctx *ctx, int64_t n_full, int64_t *H_out, int64_t *M_out) {
+    if (!ctx) return fail(SHAKEN_EINVAL, "ctx is NULL");
+    if (n_full < 0) return fail(SHAKEN_EINVAL, "n_full must be >= 0");
+    if (ctx->s & 1u) return fail(SHAKEN_ESTATE, "shaken_sweep needs an even half-step counter");
+    if (H_out && !ctx->lam2_int) return fail(SHAKEN_EINVAL, "H_out needs every 2*lambda to be an integer");
+    if ((int64_t)ctx->s + 2 * n_full >= (int64_t)kInitStep) return fail(SHAKEN_ESTATE, "half-step counter would overflow");
+    DeviceGuard guard(ctx->device);
+    const bool logs = H_out || M_out;
+    const uint32_t s0 = ctx->s;
+    if (logs) {
+        CHK(ensure_log(ctx, n_full + 1));
+        HIPCHK(launch_fill_i64(ctx->log_dev, (n_full + 1) * ctx->stride(), 0, ctx->stream));
+    }
+    for (int64_t t = 0; t < n_full; ++t) {
+        CHK(half_step_once(ctx, logs ? 1 : 0, s0));
+        CHK(half_step_once(ctx, 0, s0));
+    }
+    if (logs) {
+        HIPCHK(launch_observe(ctx->dd, &ctx->hd, 1, (int)(ctx->s & 1u), (int)n_full, ctx->stream));
+        std::vector<int64_t> raw((size_t)((n_full + 1) * ctx->stride()));
+        HIPCHK(hipMemcpyAsync(raw.data(), ctx->log_dev, raw.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        convert_log(ctx, raw, n_full + 1, H_out, M_out);
+    }
+    return SHAKEN_OK;
+}
+
+shaken_status shaken_observables(shaken_ctx *ctx, shaken_obs *out) {
+    if (!ctx || !out) return fail(SHAKEN_EINVAL, "ctx and out must be non-NULL");
+    DeviceGuard guard(ctx->device);
+    // the observe kernel writes slot `slot` of d.log: point a temporary desc at obs_dev
+    ChainDesc d = ctx->hd;
+    d.log = ctx->obs_dev;
+    ChainDesc *dtmp = nullptr;
+    CHK(dalloc(&dtmp, 1));
+    shaken_status st = SHAKEN_OK;
+    std::vector<int64_t> raw((size_t)ctx->stride());
+    do {
+        hipError_t e;
+        if ((e = hipMemcpyAsync(dtmp, &d, sizeof(d), hipMemcpyHostToDevice, ctx->stream)) != hipSuccess ||
+            (e = launch_fill_i64(ctx->obs_dev, ctx->stride(), 0, ctx->stream)) != hipSuccess ||
+            (e = launch_observe(dtmp, &d, 1, (int)(ctx->s & 1u), 0, ctx->stream)) != hipSuccess ||
+            (e = hipMemcpyAsync(raw.data(), ctx->obs_dev, raw.size() * 8, hipMemcpyDeviceToHost, ctx->stream)) != hipSuccess ||
+            (e = hipStreamSynchronize(ctx->stream)) != hipSuccess) {
+            st = fail(SHAKEN_EDEVICE, std::string("observables: ") + hipGetErrorString(e));
+        }
+    } while (0);
+    dfree(dtmp);
+    if (st != SHAKEN_OK) return st;
+    out->half_step = ctx->s;
+    out->n_sites = ctx->n;
+    out->E_J = raw[0];
+    int64_t m = 0, l2 = 0;
+    double l2d = 0;
+    for (size_t k = 0; k < ctx->lam.size(); ++k) {
+        const int64_t mk = 2 * raw[1 + k] - ctx->class_size[k];
+        m += mk;
+        l2 += ctx->lam2[k] * mk;
+        l2d += 2.0 * ctx->lam[k] * (double)mk;
+    }
+    out->M = m;
+    out->E_lambda2 = ctx->lam2_int ? l2 : 0;
+    out->H = ctx->lam2_int ? (double)(-raw[0] - l2) : -(double)raw[0] - l2d;
+    out->flags = ctx->lam2_int ? 1 : 0;
+    out->reserved = 0;
+    return SHAKEN_OK;
+}
+
+shaken_status shaken_set_params(shaken_ctx *ctx, double beta, double q) {
+    if (!ctx) return fail(SHAKEN_EINVAL, "ctx is NULL");
+    if (!finite_nonneg(q)) return fail(SHAKEN_EINVAL, "q must be finite and >= 0");
+    if (!finite_nonneg(beta)) return fail(SHAKEN_EINVAL, "beta must be finite and >= 0");
+    DeviceGuard guard(ctx->device);
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    ctx->beta = beta;
+    ctx->q = q;
+    build_tables(ctx);
+    return upload_tables(ctx);
+}
+
+shaken_status shaken_get_spins(shaken_ctx *ctx, int8_t *out) {
+    if (!ctx || !out) return fail(SHAKEN_EINVAL, "ctx and out must be non-NULL");
+    DeviceGuard guard(ctx->device);
+    const void *src = ctx->spin[ctx->s & 1u];
+    if (ctx->kind == KIND_TORUS && ctx->format == FMT_BITPACKED) {
+        std::vector<uint32_t> w((size_t)ctx->L * ctx->W);
+        HIPCHK(hipMemcpyAsync(w.data(), src, w.size() * 4, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        unpack_torus(w, ctx->L, ctx->W, out);
+    } else {
+        HIPCHK(hipMemcpyAsync(out, src, (size_t)ctx->n, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+    }
+    return SHAKEN_OK;
+}
+
+shaken_status shaken_set_spins(shaken_ctx *ctx, const int8_t *in) {
+    if (!ctx || !in) return fail(SHAKEN_EINVAL, "ctx and in must be non-NULL");
+    for (int64_t i = 0; i < ctx->n; ++i)
+        if (in[i] != 1 && in[i] != -1) return fail(SHAKEN_EINVAL, "spins must be +1 or -1");
+    DeviceGuard guard(ctx->device);
+    void *dst = ctx->spin[ctx->s & 1u];
+    if (ctx->kind == KIND_TORUS && ctx->format == FMT_BITPACKED) {
+        std::vector<uint32_t> w;
+        pack_torus(in, ctx->L, ctx->W, w);
+        HIPCHK(hipMemcpyAsync(dst, w.data(), w.size() * 4, hipMemcpyHostToDevice, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+    } else {
+        HIPCHK(hipMemcpyAsync(dst, in, (size_t)ctx->n, hipMemcpyHostToDevice, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+    }
+    return SHAKEN_OK;
+}
+
+shaken_status shaken_set_half_step(shaken_ctx *ctx, int64_t s) {
+    if (!ctx) return fail(SHAKEN_EINVAL, "ctx is NULL");
+    if (s < 0 || s >= (int64_t)kInitStep) return fail(SHAKEN_EINVAL, "s out of range");
+    DeviceGuard guard(ctx->device);
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (((uint32_t)s & 1u) != (ctx->s & 1u)) {
+        // keep the configuration where the new parity expects it
+        std::swap(ctx->spin[0], ctx->spin[1]);
+        refresh_desc_spins(ctx);
+        HIPCHK(hipMemcpyAsync(ctx->dd, &ctx->hd, sizeof(ChainDesc), hipMemcpyHostToDevice, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+    }
+    ctx->s = (uint32_t)s;
+    return SHAKEN_OK;
+}
+
+shaken_status shaken_get_lut(const shaken_ctx *ctx, uint64_t *out, size_t *n, int32_t *smax) {
+    if (!ctx || !n) return fail(SHAKEN_EINVAL, "ctx and n must be non-NULL");
+    if (smax) *smax = ctx->smax;
+    if (!out) {
+        *n = ctx->lut.size();
+        return SHAKEN_OK;
+    }
+    if (*n < ctx->lut.size()) return fail(SHAKEN_EINVAL, "capacity too small");
+    std::memcpy(out, ctx->lut.data(), ctx->lut.size() * sizeof(uint64_t));
+    *n = ctx->lut.size();
+    return SHAKEN_OK;
+}
+
+shaken_status shaken_spins_device(shaken_ctx *ctx, void **ptr, int32_t *format) {
+    if (!ctx || !ptr) return fail(SHAKEN_EINVAL, "ctx and ptr must be non-NULL");
+    *ptr = ctx->spin[ctx->s & 1u];
+    if (format) *format = ctx->format == FMT_BITPACKED ? SHAKEN_FMT_BITPACKED : SHAKEN_FMT_INT8;
+    return SHAKEN_OK;
+}
+
+shaken_status shaken_synchronize(shaken_ctx *ctx) {
+    if (!ctx) return fail(SHAKEN_EINVAL, "ctx is NULL");
+    DeviceGuard guard(ctx->device);
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return SHAKEN_OK;
+}
+
+const char *shaken_strerror(shaken_status s) {
+    switch (s) {
+    case SHAKEN_OK: return "ok";
+    case SHAKEN_EINVAL: return "invalid argument";
+    case SHAKEN_ENOMEM: return "out of memory";
+    case SHAKEN_EDEVICE: return "device error";
+    case SHAKEN_ESTATE: return "invalid state";
+    }
+    return "unknown status";
+}
+
+const char *shaken_last_error(void) { return g_err.c_str(); }
+
+int32_t shaken_version(void) { return (SHAKEN_VERSION_MAJOR << 16) | SHAKEN_VERSION_MINOR; }
+
+}  // extern "C"
+
+// ====================================================================== batches
+
+namespace {
+
+struct Group {
+    int kind = 0, format = 0;
+    std::vector<int> members;  // indices into the batch's contexts
+    std::vector<ChainDesc> hd;
+    ChainDesc *dd = nullptr;
+    int block = 256;
+};
+
+}  // namespace
+
+struct shaken_batch {
+    std::vector<shaken_ctx *> ctx;
+    int device = -1;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int strategy = SHAKEN_BATCH_GRID;
+    int use_graph = 0;
+    int autotune = 0;
+    bool tuned = false;
+    int record = 0;
+    std::vector<Group> groups;
+    uint32_t *dstate = nullptr;  // [0] half-step base, [1] log base
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    int chunk = 0;          // full steps per graph replay
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    bool timed = false;
+    int64_t last_n_full = -1;
+    // persistent strategy
+    ChainDesc *pdescs = nullptr;
+    std::vector<ChainDesc> phd;
+    int32_t *order = nullptr;
+    int32_t *counter = nullptr;
+    int pblock = 256, pgrid = 0;
+};
+
+namespace {
+
+void batch_release(shaken_batch *b) {
+    for (auto &g : b->groups) dfree(g.dd);
+    dfree(b->dstate);
+    dfree(b->pdescs);
+    dfree(b->order);
+    dfree(b->counter);
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->ev0) (void)hipEventDestroy(b->ev0);
+    if (b->ev1) (void)hipEventDestroy(b->ev1);
+    if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+}
+
+// refresh every group's device descriptors from the contexts (spin and log
+// pointers may have changed)
+shaken_status batch_upload(shaken_batch *b) {
+    for (auto &g : b->groups) {
+        for (size_t i = 0; i < g.members.size(); ++i) {
+            shaken_ctx *c = b->ctx[g.members[i]];
+            refresh_desc_spins(c);
+            g.hd[i] = c->hd;
+        }
+        HIPCHK(hipMemcpyAsync(g.dd, g.hd.data(), g.hd.size() * sizeof(ChainDesc),
+                              hipMemcpyHostToDevice, b->stream));
+    }
+    if (b->pdescs) {
+        for (size_t i = 0; i < b->ctx.size(); ++i) {
+            refresh_desc_spins(b->ctx[i]);
+            b->phd[i] = b->ctx[i]->hd;
+        }
+        HIPCHK(hipMemcpyAsync(b->pdescs, b->phd.data(), b->phd.size() * sizeof(ChainDesc),
+                              hipMemcpyHostToDevice, b->stream));
+    }
+    HIPCHK(hipStreamSynchronize(b->stream));
+    return SHAKEN_OK;
+}
+
+// all groups, one half-step at s (explicit) or dstate[0] + s_add
+shaken_status batch_half(shaken_batch *b, const uint32_t *dstate, uint32_t s_add, uint32_t s_log0,
+                         bool even) {
+    for (auto &g : b->groups)
+        HIPCHK(launch_half_step_grid(g.dd, g.hd.data(), (int)g.hd.size(), dstate, s_add, s_log0,
+                                     b->record, even, g.block, b->stream));
+    return SHAKEN_OK;
+}
+
+// time `reps` repeated launches of the same half-step (idempotent: same input,
+// same output buffer) for one group and block size
+shaken_status time_group(shaken_batch *b, Group &g, int block, uint32_t s, float *ms) {
+    const int reps = 5;
+    HIPCHK(launch_half_step_grid(g.dd, g.hd.data(), (int)g.hd.size(), nullptr, s, s, 0, (s & 1u) == 0,
+                                 block, b->stream));
+    HIPCHK(hipEventRecord(b->ev0, b->stream));
+    for (int i = 0; i < reps; ++i)
+        HIPCHK(launch_half_step_grid(g.dd, g.hd.data(), (int)g.hd.size(), nullptr, s, s, 0,
+                                     (s & 1u) == 0, block, b->stream));
+    HIPCHK(hipEventRecord(b->ev1, b->stream));
+    HIPCHK(hipEventSynchronize(b->ev1));
+    HIPCHK(hipEventElapsedTime(ms, b->ev0, b->ev1));
+    return SHAKEN_OK;
+}
+
+shaken_status batch_autotune(shaken_batch *b) {
+    const uint32_t s = b->ctx[0]->s;
+    for (auto &g : b->groups) {
+        const int cands[3] = {64, 128, 256};
+        float best = 1e30f;
+        int best_b = g.block;
+        for (int cb : cands) {
+            float ms = 0;
+            CHK(time_group(b, g, cb, s, &ms));
+            if (ms < best) {
+                best = ms;
+                best_b = cb;
+            }
+        }
+        g.block = best_b;
+    }
+    b->tuned = true;
+    return SHAKEN_OK;
+}
+
+shaken_status batch_build_graph(shaken_batch *b, int chunk) {
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->gexec = nullptr;
+    b->graph = nullptr;
+    HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    shaken_status st = SHAKEN_OK;
+    for (int k = 0; k < 2 * chunk && st == SHAKEN_OK; ++k)
+        st = batch_half(b, b->dstate, (uint32_t)k, 0, (k & 1) == 0);
+    if (st == SHAKEN_OK) {
+        hipError_t e = launch_advance(b->dstate, (uint32_t)(2 * chunk), b->stream);
+        if (e != hipSuccess) st = fail(SHAKEN_EDEVICE, hipGetErrorString(e));
+    }
+    hipGraph_t gr = nullptr;
+    hipError_t e = hipStreamEndCapture(b->stream, &gr);
+    if (st != SHAKEN_OK) {
+        if (gr) (void)hipGraphDestroy(gr);
+        return st;
+    }
+    if (e != hipSuccess) return fail(SHAKEN_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    b->graph = gr;
+    HIPCHK(hipGraphInstantiate(&b->gexec, gr, nullptr, nullptr, 0));
+    b->chunk = chunk;
+    return SHAKEN_OK;
+}
+
+shaken_status batch_sweep_grid(shaken_batch *b, int64_t n_full) {
+    const uint32_t s0 = b->ctx[0]->s;
+    if (b->use_graph && n_full > 0) {
+        const int chunk = (int)std::min<int64_t>(n_full, 16);
+        if (!b->gexec || b->chunk != chunk) CHK(batch_build_graph(b, chunk));
+        HIPCHK(launch_set_state(b->dstate, s0, s0, b->stream));
+        const int64_t reps = n_full / chunk;
+        for (int64_t r = 0; r < reps; ++r) HIPCHK(hipGraphLaunch(b->gexec, b->stream));
+        uint32_t s = s0 + (uint32_t)(2 * chunk * reps);
+        for (int64_t t = reps * chunk; t < n_full; ++t) {
+            CHK(batch_half(b, nullptr, s, s0, true));
+            CHK(batch_half(b, nullptr, s + 1, s0, false));
+            s += 2;
+        }
+    } else {
+        uint32_t s = s0;
+        for (int64_t t = 0; t < n_full; ++t) {
+            CHK(batch_half(b, nullptr, s, s0, true));
+            CHK(batch_half(b, nullptr, s + 1, s0, false));
+            s += 2;
+        }
+    }
+    return SHAKEN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+shaken_status shaken_batch_create(shaken_batch **out, shaken_ctx *const *ctx, int32_t n,
+                                  const shaken_batch_opts *opts) {
+    g_err.clear();
+    if (!out || !ctx || n < 1) return fail(SHAKEN_EINVAL, "need out, ctx and n >= 1");
+    *out = nullptr;
+    shaken_batch_opts o{};
+    if (opts) o = *opts;
+    for (int i = 0; i < n; ++i) {
+        if (!ctx[i]) return fail(SHAKEN_EINVAL, "ctx[" + std::to_string(i) + "] is NULL");
+        if (ctx[i]->device != ctx[0]->device) return fail(SHAKEN_EINVAL, "contexts on different devices");
+        if (ctx[i]->s != ctx[0]->s) return fail(SHAKEN_ESTATE, "contexts have different half-step counters");
+        for (int j = 0; j < i; ++j)
+            if (ctx[j] == ctx[i]) return fail(SHAKEN_EINVAL, "a context appears twice");
+    }
+    if (ctx[0]->s & 1u) return fail(SHAKEN_ESTATE, "batches need an even half-step counter");
+    if (o.strategy < SHAKEN_BATCH_AUTO || o.strategy > SHAKEN_BATCH_PERSISTENT)
+        return fail(SHAKEN_EINVAL, "unknown batch strategy");
+    shaken_batch *b = new (std::nothrow) shaken_batch();
+    if (!b) return fail(SHAKEN_ENOMEM, "host allocation failed");
+    b->ctx.assign(ctx, ctx + n);
+    b->device = ctx[0]->device;
+    DeviceGuard guard(b->device);
+    b->use_graph = o.use_hipgraph;
+    b->autotune = o.autotune;
+    b->record = o.record;
+    b->stream = o.stream ? (hipStream_t)o.stream : ctx[0]->stream;
+    shaken_status st = SHAKEN_OK;
+    auto bail = [&](shaken_status s) {
+        batch_release(b);
+        delete b;
+        return s;
+    };
+    if (!b->stream && b->use_graph) {
+        if (hipStreamCreate(&b->stream) != hipSuccess) return bail(fail(SHAKEN_EDEVICE, "hipStreamCreate failed"));
+        b->own_stream = true;
+    }
+    // work queued on the chains' own streams must finish first
+    for (int i = 0; i < n; ++i)
+        if (hipStreamSynchronize(ctx[i]->stream) != hipSuccess) return bail(fail(SHAKEN_EDEVICE, "stream sync failed"));
+    if (hipEventCreate(&b->ev0) != hipSuccess || hipEventCreate(&b->ev1) != hipSuccess)
+        return bail(fail(SHAKEN_EDEVICE, "hipEventCreate failed"));
+    bool all_fit = true;
+    for (int i = 0; i < n; ++i) all_fit = all_fit && persistent_fits(ctx[i]->hd);
+    int strat = o.strategy;
+    if (strat == SHAKEN_BATCH_AUTO) strat = all_fit ? SHAKEN_BATCH_PERSISTENT : SHAKEN_BATCH_GRID;
+    if (strat == SHAKEN_BATCH_PERSISTENT && !all_fit)
+        return bail(fail(SHAKEN_EINVAL, "a chain does not fit the persistent strategy"));
+    b->strategy = strat;
+    if ((st = dalloc(&b->dstate, 2)) != SHAKEN_OK) return bail(st);
+    if (strat == SHAKEN_BATCH_GRID) {
+        // group by (kind, format): one launch per group and half-step
+        for (int i = 0; i < n; ++i) {
+            Group *g = nullptr;
+            for (auto &x : b->groups)
+                if (x.kind == ctx[i]->kind && x.format == ctx[i]->format) g = &x;
+            if (!g) {
+                b->groups.emplace_back();
+                g = &b->groups.back();
+                g->kind = ctx[i]->kind;
+                g->format = ctx[i]->format;
+            }
+            g->members.push_back(i);
+            g->hd.push_back(ctx[i]->hd);
+        }
+        for (auto &g : b->groups)
+            if ((st = dalloc(&g.dd, g.hd.size())) != SHAKEN_OK) return bail(st);
+    } else {
+        b->phd.resize(n);
+        if ((st = dalloc(&b->pdescs, (size_t)n)) != SHAKEN_OK) return bail(st);
+        if ((st = dalloc(&b->order, (size_t)n)) != SHAKEN_OK) return bail(st);
+        if ((st = dalloc(&b->counter, 2)) != SHAKEN_OK) return bail(st);
+        // longest first: cost ~ sites (tori) or sites + edges (graphs)
+        std::vector<std::pair<double, int>> cost;
+        for (int i = 0; i < n; ++i) {
+            const shaken_ctx *c = ctx[i];
+            const double w = c->kind == KIND_TORUS ? (double)c->n : 3.0 * (double)(c->n + c->m);
+            cost.push_back({-w, i});
+        }
+        std::sort(cost.begin(), cost.end());
+        std::vector<int32_t> ord;
+        for (auto &p : cost) ord.push_back(p.second);
+        if (hipMemcpy(b->order, ord.data(), ord.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
+            return bail(fail(SHAKEN_EDEVICE, "order upload failed"));
+        int ncu = 256;
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, b->device) == hipSuccess) ncu = prop.multiProcessorCount;
+        b->pgrid = std::min(n, 4 * ncu);
+    }
+    if ((st = batch_upload(b)) != SHAKEN_OK) return bail(st);
+    *out = b;
+    return SHAKEN_OK;
+}
+
+shaken_status shaken_batch_sweep(shaken_batch *b, int64_t n_full) {
+    if (!b) return fail(SHAKEN_EINVAL, "batch is NULL");
+    if (n_full < 0) return fail(SHAKEN_EINVAL, "n_full must be >= 0");
+    DeviceGuard guard(b->device);
+    const uint32_t s0 = b->ctx[0]->s;
+    if ((int64_t)s0 + 2 * n_full >= (int64_t)kInitStep) return fail(SHAKEN_ESTATE, "half-step counter would overflow");
+    for (auto *c : b->ctx)
+        if (c->s != s0) return fail(SHAKEN_ESTATE, "a context of the batch was stepped on its own");
+    if (b->record) {
+        bool changed = false;
+        for (auto *c : b->ctx) {
+            int64_t *before = c->log_dev;
+            CHK(ensure_log(c, n_full + 1));
+            changed |= before != c->log_dev;
+            HIPCHK(launch_fill_i64(c->log_dev, (n_full + 1) * c->stride(), 0, b->stream));
+        }
+        if (changed) {
+            CHK(batch_upload(b));
+            if (b->gexec) {
+                (void)hipGraphExecDestroy(b->gexec);
+                b->gexec = nullptr;
+            }
+        }
+    }
+    if (b->strategy == SHAKEN_BATCH_GRID && b->autotune && !b->tuned) {
+        CHK(batch_autotune(b));
+        if (b->gexec) {
+            (void)hipGraphExecDestroy(b->gexec);
+            b->gexec = nullptr;
+        }
+    }
+    HIPCHK(hipEventRecord(b->ev0, b->stream));
+    if (b->strategy == SHAKEN_BATCH_GRID) {
+        CHK(batch_sweep_grid(b, n_full));
+    } else {
+        HIPCHK(launch_set_state((uint32_t *)b->counter, 0u, 0u, b->stream));
+        HIPCHK(launch_persistent(b->pdescs, (int)b->ctx.size(), b->order, b->counter, s0, n_full,
+                                 b->record, b->pblock, b->pgrid, b->stream));
+    }
+    const uint32_t s1 = s0 + (uint32_t)(2 * n_full);
+    if (b->record) {
+        // observables of the final configuration (spin[s1 & 1]) into slot n_full
+        if (b->strategy == SHAKEN_BATCH_GRID) {
+            for (auto &g : b->groups)
+                HIPCHK(launch_observe(g.dd, g.hd.data(), (int)g.hd.size(), (int)(s1 & 1u), (int)n_full, b->stream));
+        } else {
+            HIPCHK(launch_observe(b->pdescs, b->phd.data(), (int)b->phd.size(), (int)(s1 & 1u), (int)n_full, b->stream));
+        }
+    }
+    HIPCHK(hipEventRecord(b->ev1, b->stream));
+    b->timed = true;
+    for (auto *c : b->ctx) c->s = s1;
+    b->last_n_full = n_full;
+    return SHAKEN_OK;
+}
+
+shaken_status shaken_batch_get_log(shaken_batch *b, int32_t i, int64_t *H_out, int64_t *M_out,
+                                   int64_t cap) {
+    if (!b || i < 0 || i >= (int32_t)b->ctx.size()) return fail(SHAKEN_EINVAL, "bad batch or index");
+    if (!b->record || b->last_n_full < 0) return fail(SHAKEN_ESTATE, "no recorded sweep");
+    shaken_ctx *c = b->ctx[i];
+    if (H_out && !c->lam2_int) return fail(SHAKEN_EINVAL, "H_out needs every 2*lambda to be an integer");
+    const int64_t slots = b->last_n_full + 1;
+    if (cap < slots) return fail(SHAKEN_EINVAL, "capacity too small");
+    DeviceGuard guard(b->device);
+    std::vector<int64_t> raw((size_t)(slots * c->stride()));
+    HIPCHK(hipMemcpyAsync(raw.data(), c->log_dev, raw.size() * 8, hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    convert_log(c, raw, slots, H_out, M_out);
+    return SHAKEN_OK;
+}
+
+shaken_status shaken_batch_info(shaken_batch *b, int32_t *strategy, double *last_ms) {
+    if (!b) return fail(SHAKEN_EINVAL, "batch is NULL");
+    if (strategy) *strategy = b->strategy;
+    if (last_ms) {
+        *last_ms = 0;
+        if (b->timed) {
+            DeviceGuard guard(b->device);
+            float ms = 0;
+            HIPCHK(hipEventSynchronize(b->ev1));
+            HIPCHK(hipEventElapsedTime(&ms, b->ev0, b->ev1));
+            *last_ms = ms;
+        }
+    }
+    return SHAKEN_OK;
+}
+
+shaken_status shaken_batch_free(shaken_batch *b) {
+    if (!b) return SHAKEN_OK;
+    DeviceGuard guard(b->device);
+    (void)hipStreamSynchronize(b->stream);
+    batch_release(b);
+    delete b;
+    return SHAKEN_OK;
+}
+
+shaken_status shaken_batch_run(shaken_ctx *const *ctx, int32_t n, int64_t n_full,
+                               const shaken_batch_opts *opts, int64_t *H_final) {
+    shaken_batch *b = nullptr;
+    CHK(shaken_batch_create(&b, ctx, n, opts));
+    shaken_status st = shaken_batch_sweep(b, n_full);
+    if (st == SHAKEN_OK) {
+        DeviceGuard guard(b->device);
+        if (hipStreamSynchronize(b->stream) != hipSuccess) st = fail(SHAKEN_EDEVICE, "stream sync failed");
+    }
+    shaken_batch_free(b);
+    if (st != SHAKEN_OK) return st;
+    if (H_final) {
+        for (int i = 0; i < n; ++i) {
+            shaken_obs ob;
+            CHK(shaken_observables(ctx[i], &ob));
+            if (!(ob.flags & 1)) return fail(SHAKEN_EINVAL, "H_final needs every 2*lambda to be an integer");
+            H_final[i] = (int64_t)ob.H;
+        }
+    }
+    return SHAKEN_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,542 @@
+// HIP kernels of libshaken for gfx950 (MI355X).
+//
+// The half-steps of shaken dynamics (arXiv:1904.06257, section 2: kernels
+// P^{1->2} and P^{2->1}; section 3: P^dl and P^ur on the torus).  Every kernel
+// reads one configuration and writes the other buffer: a half-step is a
+// parallel update, never an in-place one.
+//
+// Bit-packed torus ("multi-spin coding"): one lane owns one 32-site word.
+// The neighbour words of the half (down/left for dl, up/right for ur) give
+// three bit-planes a, b, c (two neighbours and the site itself).  With a
+// uniform coupling the field is h = J(2 n_plus - 2) + q sigma + lambda, so a
+// site belongs to one of six classes j = n_plus + 3 c.  The comparison
+// u < T is done bit-serially from the most significant level, 32 sites at a
+// time: level k of the 32 uniforms is one Philox output word (the bit-sliced
+// uniform of the contract), the matching threshold bit-plane is assembled from
+// the class masks, and a site drops out of the comparison as soon as its
+// uniform bit differs from its threshold bit.  Thresholds are folded by the
+// sign of h (u < 2^32 - t  <=>  not(~u < t)), so only t <= 2^31 is compared.
+#include "shaken_internal.hpp"
+
+namespace shaken {
+
+// ------------------------------------------------------------------ Philox
+
+struct U4 {
+    uint32_t x, y, z, w;
+};
+
+// Philox4x32 with ten rounds (Salmon et al., SC'11).
+__device__ __forceinline__ U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                       uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int i = 0; i < 10; ++i) {
+        const uint64_t a = (uint64_t)c0 * 0xD2511F53u;
+        const uint64_t b = (uint64_t)c2 * 0xCD9E8D57u;
+        const uint32_t n0 = (uint32_t)(b >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(a >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)b;
+        c3 = (uint32_t)a;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return U4{c0, c1, c2, c3};
+}
+
+__device__ __forceinline__ uint32_t bfi(uint32_t m, uint32_t x, uint32_t y) {
+    return (m & x) | (~m & y);
+}
+
+// all-ones if bit `sh` of v is set, else zero
+__device__ __forceinline__ uint32_t bitmask(uint32_t v, int sh) {
+    return 0u - ((v >> sh) & 1u);
+}
+
+// ------------------------------------------------------------ reductions
+
+__device__ __forceinline__ int wave_sum(int v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// block-level sum of two ints into log[0] and log[1] (one atomic per block)
+__device__ __forceinline__ void block_accumulate2(int e, int p, int64_t *log) {
+    __shared__ int sh_e[16], sh_p[16];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    e = wave_sum(e);
+    p = wave_sum(p);
+    if (lane == 0) {
+        sh_e[wv] = e;
+        sh_p[wv] = p;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long se = 0, sp = 0;
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int i = 0; i < nw; ++i) {
+            se += sh_e[i];
+            sp += sh_p[i];
+        }
+        if (se) atomicAdd((unsigned long long *)&log[0], (unsigned long long)se);
+        if (sp) atomicAdd((unsigned long long *)&log[1], (unsigned long long)sp);
+    }
+}
+
+// XCD-aware block order: the hardware deals consecutive workgroups round-robin
+// over the 8 XCDs; give each XCD a contiguous run of tiles so that rows shared
+// as halos stay in one L2.
+__device__ __forceinline__ int xcd_block(int bx, int nb) {
+    if ((nb & 7) != 0) return bx;
+    return (bx & 7) * (nb >> 3) + (bx >> 3);
+}
+
+// ------------------------------------------------------ bit-packed torus
+
+// New word of 32 sites.  a, b: bit-planes of the two neighbours of the half,
+// c: the sites themselves, vm: valid bits, w: RNG word, s: half-step index.
+template <bool FOLD3>
+__device__ __forceinline__ uint32_t bp_word(uint32_t a, uint32_t b, uint32_t c, uint32_t vm,
+                                            uint32_t w, uint32_t s, uint32_t rep, uint32_t k0,
+                                            uint32_t k1, const uint32_t *__restrict__ ts,
+                                            uint32_t sgn) {
+    const uint32_t both = a & b;   // n_plus = 2
+    const uint32_t one = a ^ b;    // n_plus = 1
+    // sign of h per site (class j = n_plus + 3 c)
+    const uint32_t slo = bfi(both, bitmask(sgn, 2), bfi(one, bitmask(sgn, 1), bitmask(sgn, 0)));
+    const uint32_t shi = bfi(both, bitmask(sgn, 5), bfi(one, bitmask(sgn, 4), bitmask(sgn, 3)));
+    const uint32_t smask = bfi(c, shi, slo);
+    // sign-folded classes: aligned (0,0)/(2,1), anti (2,0)/(0,1), one (1,*)
+    const uint32_t al = ~(a ^ c) & ~one;
+    const uint32_t t0 = ts[0], t1 = ts[1], t2 = ts[2], t3 = ts[3], t4 = ts[4], t5 = ts[5];
+    uint32_t und = vm, res = 0;
+
+#define SHAKEN_LEVEL(K, R)                                                                  \
+    {                                                                                       \
+        const int sh_ = 31 - (K);                                                           \
+        uint32_t t_;                                                                        \
+        if (FOLD3) {                                                                        \
+            t_ = bfi(one, bitmask(t1, sh_), bfi(al, bitmask(t5, sh_), bitmask(t2, sh_)));   \
+        } else {                                                                            \
+            const uint32_t lo_ = bfi(both, bitmask(t2, sh_),                                \
+                                     bfi(one, bitmask(t1, sh_), bitmask(t0, sh_)));         \
+            const uint32_t hi_ = bfi(both, bitmask(t5, sh_),                                \
+                                     bfi(one, bitmask(t4, sh_), bitmask(t3, sh_)));         \
+            t_ = bfi(c, hi_, lo_);                                                          \
+        }                                                                                   \
+        const uint32_t d_ = (R) ^ smask ^ t_;                                               \
+        res |= und & d_ & t_;                                                               \
+        und &= ~d_;                                                                         \
+    }
+
+#pragma unroll
+    for (int g = 0; g < 8; ++g) {
+        const U4 r = philox10(w, s, rep, (uint32_t)g, k0, k1);
+        SHAKEN_LEVEL(4 * g + 0, r.x)
+        SHAKEN_LEVEL(4 * g + 1, r.y)
+        SHAKEN_LEVEL(4 * g + 2, r.z)
+        SHAKEN_LEVEL(4 * g + 3, r.w)
+        if (und == 0) break;
+    }
+#undef SHAKEN_LEVEL
+    // res: v < t with v = u ^ sign; the new spin is that bit flipped where h >= 0
+    return (res ^ smask) & vm;
+}
+
+// neighbour bit-planes of word (r, wd) for half `phase` (0 = down/left,
+// 1 = up/right) on an L x L torus with W words per row
+__device__ __forceinline__ void bp_neighbours(const uint32_t *__restrict__ sp, int L, int W, int r,
+                                              int wd, int phase, uint32_t own, uint32_t &a,
+                                              uint32_t &b) {
+    const int lastbits = ((L - 1) & 31);  // bit index of column L-1 in the last word
+    if (phase == 0) {
+        const int rd = (r == 0) ? L - 1 : r - 1;
+        a = sp[rd * W + wd];
+        uint32_t carry;
+        if (wd > 0)
+            carry = sp[r * W + wd - 1] >> 31;
+        else
+            carry = (sp[r * W + W - 1] >> lastbits) & 1u;
+        b = (own << 1) | carry;
+    } else {
+        const int ru = (r == L - 1) ? 0 : r + 1;
+        a = sp[ru * W + wd];
+        if (wd < W - 1)
+            b = (own >> 1) | (sp[r * W + wd + 1] << 31);
+        else
+            b = (own >> 1) | ((sp[r * W] & 1u) << lastbits);
+    }
+}
+
+__device__ __forceinline__ uint32_t bp_valid(int L, int W, int wd) {
+    const int rem = L & 31;
+    return (wd == W - 1 && rem) ? ((1u << rem) - 1u) : 0xFFFFFFFFu;
+}
+
+// Half-step index and log slot of a launch.  The index is dstate[0] + s_add
+// when the launch reads it from device memory (replayable HIP graphs), else
+// s_add; the configuration at half-step s lives in spin[s & 1].  Observables
+// of the configuration read at an even s go to slot (s - base) / 2.
+struct StepArgs {
+    const uint32_t *dstate;  // [0] = half-step base, [1] = log base (or null)
+    uint32_t s_add;
+    uint32_t s_log0;
+    int log_on;
+};
+
+__device__ __forceinline__ uint32_t step_s(const StepArgs &a) {
+    return (a.dstate ? a.dstate[0] : 0u) + a.s_add;
+}
+__device__ __forceinline__ int step_slot(const StepArgs &a, uint32_t s) {
+    return (int)((s - (a.dstate ? a.dstate[1] : a.s_log0)) >> 1);
+}
+
+template <bool OBS, bool FOLD3>
+__global__ __launch_bounds__(256) void k_torus_bp(const ChainDesc *__restrict__ descs, StepArgs sa) {
+    const ChainDesc &d = descs[blockIdx.y];
+    const uint32_t s = step_s(sa);
+    const int in_idx = (int)(s & 1u);
+    const int slot = OBS ? step_slot(sa, s) : 0;
+    const int L = d.L, W = d.W;
+    const int total = L * W;
+    const int bx = xcd_block(blockIdx.x, gridDim.x);
+    const int gid = bx * blockDim.x + threadIdx.x;
+    const uint32_t *__restrict__ in = (const uint32_t *)d.spin[in_idx];
+    uint32_t *__restrict__ out = (uint32_t *)d.spin[in_idx ^ 1];
+    int e_acc = 0, p_acc = 0;
+    if (gid < total) {
+        const int r = gid / W, wd = gid - r * W;
+        const uint32_t own = in[gid];
+        uint32_t a, b;
+        bp_neighbours(in, L, W, r, wd, (int)(s & 1u), own, a, b);
+        const uint32_t vm = bp_valid(L, W, wd);
+        out[gid] = bp_word<FOLD3>(a, b, own, vm, (uint32_t)gid, s, d.replica, (uint32_t)d.seed,
+                                  (uint32_t)(d.seed >> 32), d.tsmall, d.sgn);
+        if (OBS) {
+            const int nb = __popc(vm);
+            e_acc = d.J * (2 * nb - 2 * __popc((own ^ a) & vm) - 2 * __popc((own ^ b) & vm));
+            p_acc = __popc(own & vm);
+        }
+    }
+    if (OBS && bx * (int)blockDim.x < total)
+        block_accumulate2(e_acc, p_acc, d.log + (int64_t)slot * d.log_stride);
+}
+
+// ------------------------------------------------------------- int8 torus
+
+// u < T for the bit-sliced uniform of bit b of RNG word w, decided from the
+// most significant level down
+__device__ __forceinline__ bool sliced_less(uint64_t T, uint32_t w, int b, uint32_t s,
+                                            uint32_t rep, uint32_t k0, uint32_t k1) {
+    if (T >> 32) return true;  // T = 2^32
+    const uint32_t t = (uint32_t)T;
+    for (int g = 0; g < 8; ++g) {
+        const U4 r = philox10(w, s, rep, (uint32_t)g, k0, k1);
+        const uint32_t rr[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int k = 4 * g + j;
+            const uint32_t ub = (rr[j] >> b) & 1u;
+            const uint32_t tb = (t >> (31 - k)) & 1u;
+            if (ub != tb) return ub < tb;
+        }
+    }
+    return false;  // u == t
+}
+
+template <bool OBS>
+__global__ __launch_bounds__(256) void k_torus_i8(const ChainDesc *__restrict__ descs, StepArgs sa) {
+    const ChainDesc &d = descs[blockIdx.y];
+    const uint32_t s = step_s(sa);
+    const int in_idx = (int)(s & 1u);
+    const int slot = OBS ? step_slot(sa, s) : 0;
+    const int L = d.L, n = d.n;
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int8_t *__restrict__ in = (const int8_t *)d.spin[in_idx];
+    int8_t *__restrict__ out = (int8_t *)d.spin[in_idx ^ 1];
+    int e_acc = 0, p_acc = 0;
+    if (gid < n) {
+        const int r = gid / L, c = gid - r * L;
+        int n1, n2;
+        if ((s & 1u) == 0) {
+            n1 = in[(r == 0 ? L - 1 : r - 1) * L + c];
+            n2 = in[r * L + (c == 0 ? L - 1 : c - 1)];
+        } else {
+            n1 = in[(r == L - 1 ? 0 : r + 1) * L + c];
+            n2 = in[r * L + (c == L - 1 ? 0 : c + 1)];
+        }
+        const int own = in[gid];
+        const int S = d.J * (n1 + n2);
+        const uint64_t T = d.lut[((S + d.smax) * 2 + (own > 0)) * d.ncls];
+        const uint32_t w = (uint32_t)(r * d.W + (c >> 5));
+        const bool up = sliced_less(T, w, c & 31, s, d.replica, (uint32_t)d.seed,
+                                    (uint32_t)(d.seed >> 32));
+        out[gid] = up ? 1 : -1;
+        if (OBS) {
+            e_acc = own * S;
+            p_acc = own > 0;
+        }
+    }
+    if (OBS && blockIdx.x < (unsigned)((n + blockDim.x - 1) / blockDim.x))
+        block_accumulate2(e_acc, p_acc, d.log + (int64_t)slot * d.log_stride);
+}
+
+// ------------------------------------------------------------------ graph
+
+// Lane = 4 consecutive vertices = one Philox call.  S_v sums the CSR row of
+// the half (in-half for s even, out-half for s odd).
+template <bool OBS>
+__global__ __launch_bounds__(256) void k_graph(const ChainDesc *__restrict__ descs, StepArgs sa) {
+    const ChainDesc &d = descs[blockIdx.y];
+    const uint32_t s = step_s(sa);
+    const int in_idx = (int)(s & 1u);
+    const int slot = OBS ? step_slot(sa, s) : 0;
+    const int n = d.n;
+    const int half = (int)(s & 1u);
+    const int q4 = blockIdx.x * blockDim.x + threadIdx.x;
+    const int v0 = q4 * 4;
+    const int8_t *__restrict__ in = (const int8_t *)d.spin[in_idx];
+    int8_t *__restrict__ out = (int8_t *)d.spin[in_idx ^ 1];
+    const int32_t *__restrict__ rp = d.rowptr[half];
+    const int32_t *__restrict__ col = d.col[half];
+    const int8_t *__restrict__ jw = d.jw[half];
+    const uint8_t *__restrict__ cls = d.cls;
+    const int ncls = d.ncls, smax = d.smax;
+    int e_acc = 0;
+    extern __shared__ int sh_plus[];  // ncls counters (OBS only)
+    if (OBS) {
+        for (int i = threadIdx.x; i < ncls; i += blockDim.x) sh_plus[i] = 0;
+        __syncthreads();
+    }
+    if (v0 < n) {
+        const U4 r = philox10((uint32_t)q4, s, d.replica, kGraphStream, (uint32_t)d.seed,
+                              (uint32_t)(d.seed >> 32));
+        const uint32_t u[4] = {r.x, r.y, r.z, r.w};
+        int8_t nv[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int v = v0 + j;
+            if (v < n) {
+                int S = 0;
+                const int e1 = rp[v + 1];
+                for (int e = rp[v]; e < e1; ++e) S += jw[e] * in[col[e]];
+                const int own = in[v];
+                const int cl = cls[v];
+                const uint64_t T = d.lut[((S + smax) * 2 + (own > 0)) * ncls + cl];
+                nv[j] = ((uint64_t)u[j] < T) ? 1 : -1;
+                if (OBS) {
+                    e_acc += own * S;
+                    if (own > 0) atomicAdd(&sh_plus[cl], 1);
+                }
+            }
+        }
+        if (v0 + 3 < n) {
+            const uint32_t packed = (uint32_t)(uint8_t)nv[0] | ((uint32_t)(uint8_t)nv[1] << 8) |
+                                    ((uint32_t)(uint8_t)nv[2] << 16) |
+                                    ((uint32_t)(uint8_t)nv[3] << 24);
+            *(uint32_t *)(out + v0) = packed;
+        } else {
+            for (int j = 0; j < 4 && v0 + j < n; ++j) out[v0 + j] = nv[j];
+        }
+    }
+    if (OBS && blockIdx.x < (unsigned)((n + 4 * blockDim.x - 1) / (4 * blockDim.x))) {
+        int64_t *lg = d.log + (int64_t)slot * d.log_stride;
+        const int lane = threadIdx.x & 63;
+        e_acc = wave_sum(e_acc);
+        if (lane == 0 && e_acc) atomicAdd((unsigned long long *)&lg[0], (unsigned long long)(long long)e_acc);
+        __syncthreads();
+        for (int i = threadIdx.x; i < ncls; i += blockDim.x)
+            if (sh_plus[i]) atomicAdd((unsigned long long *)&lg[1 + i], (unsigned long long)sh_plus[i]);
+    }
+}
+
+// ------------------------------------------------------------ observables
+
+__global__ __launch_bounds__(256) void k_observe(const ChainDesc *__restrict__ descs, int idx,
+                                                 int slot) {
+    const ChainDesc &d = descs[blockIdx.y];
+    int64_t *lg = d.log + (int64_t)slot * d.log_stride;
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    int e_acc = 0, p_acc = 0;
+    bool active_block;
+    if (d.kind == KIND_TORUS && d.format == FMT_BITPACKED) {
+        const int total = d.L * d.W;
+        active_block = blockIdx.x * blockDim.x < (unsigned)total;
+        if (gid < total) {
+            const uint32_t *sp = (const uint32_t *)d.spin[idx];
+            const int r = gid / d.W, wd = gid - r * d.W;
+            const uint32_t own = sp[gid];
+            uint32_t a, b;
+            bp_neighbours(sp, d.L, d.W, r, wd, 0, own, a, b);
+            const uint32_t vm = bp_valid(d.L, d.W, wd);
+            e_acc = d.J * (2 * __popc(vm) - 2 * __popc((own ^ a) & vm) - 2 * __popc((own ^ b) & vm));
+            p_acc = __popc(own & vm);
+        }
+        if (active_block) block_accumulate2(e_acc, p_acc, lg);
+        return;
+    }
+    if (d.kind == KIND_TORUS) {
+        active_block = blockIdx.x * blockDim.x < (unsigned)d.n;
+        if (gid < d.n) {
+            const int8_t *sp = (const int8_t *)d.spin[idx];
+            const int L = d.L, r = gid / L, c = gid - r * L;
+            const int own = sp[gid];
+            e_acc = d.J * own * (sp[(r == 0 ? L - 1 : r - 1) * L + c] + sp[r * L + (c == 0 ? L - 1 : c - 1)]);
+            p_acc = own > 0;
+        }
+        if (active_block) block_accumulate2(e_acc, p_acc, lg);
+        return;
+    }
+    // graph: E_J via the in-half of every vertex, plus counts per class
+    if (blockIdx.x * blockDim.x >= (unsigned)d.n) return;
+    if (gid < d.n) {
+        const int8_t *sp = (const int8_t *)d.spin[idx];
+        int S = 0;
+        for (int e = d.rowptr[0][gid]; e < d.rowptr[0][gid + 1]; ++e) S += d.jw[0][e] * sp[d.col[0][e]];
+        const int own = sp[gid];
+        e_acc = own * S;
+        if (own > 0) atomicAdd((unsigned long long *)&lg[1 + d.cls[gid]], 1ull);
+    }
+    e_acc = wave_sum(e_acc);
+    if ((threadIdx.x & 63) == 0 && e_acc)
+        atomicAdd((unsigned long long *)&lg[0], (unsigned long long)(long long)e_acc);
+}
+
+// ---------------------------------------------------------------- helpers
+
+__global__ void k_fill_i64(int64_t *p, int64_t count, int64_t value) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = value;
+}
+
+// mode: 0 random, 1 all up, 2 all down
+__global__ void k_init(ChainDesc d, void *dst, int mode) {
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t k0 = (uint32_t)d.seed, k1 = (uint32_t)(d.seed >> 32);
+    if (d.kind == KIND_TORUS && d.format == FMT_BITPACKED) {
+        const int total = d.L * d.W;
+        if (gid >= total) return;
+        const uint32_t vm = bp_valid(d.L, d.W, gid % d.W);
+        uint32_t v;
+        if (mode == 0)
+            v = philox10((uint32_t)gid, kInitStep, d.replica, 0u, k0, k1).x;
+        else
+            v = (mode == 1) ? 0xFFFFFFFFu : 0u;
+        ((uint32_t *)dst)[gid] = v & vm;
+        return;
+    }
+    if (gid >= d.n) return;
+    int8_t v;
+    if (mode == 0) {
+        if (d.kind == KIND_TORUS) {
+            const int r = gid / d.L, c = gid - r * d.L;
+            const uint32_t x = philox10((uint32_t)(r * d.W + (c >> 5)), kInitStep, d.replica, 0u, k0, k1).x;
+            v = ((x >> (c & 31)) & 1u) ? 1 : -1;
+        } else {
+            const U4 r = philox10((uint32_t)(gid >> 2), kInitStep, d.replica, kGraphStream, k0, k1);
+            const uint32_t u[4] = {r.x, r.y, r.z, r.w};
+            v = (u[gid & 3] >> 31) ? 1 : -1;
+        }
+    } else {
+        v = (mode == 1) ? 1 : -1;
+    }
+    ((int8_t *)dst)[gid] = v;
+}
+
+// -------------------------------------------------------------- launchers
+
+hipError_t launch_fill_i64(int64_t *p, int64_t count, int64_t value, hipStream_t stream) {
+    if (count <= 0) return hipSuccess;
+    const int b = 256;
+    const int64_t g = (count + b - 1) / b;
+    hipLaunchKernelGGL(k_fill_i64, dim3((unsigned)g), dim3(b), 0, stream, p, count, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_init(const ChainDesc &d, void *dst, int mode, hipStream_t stream) {
+    const int total = (d.kind == KIND_TORUS && d.format == FMT_BITPACKED) ? d.L * d.W : d.n;
+    const int b = 256;
+    hipLaunchKernelGGL(k_init, dim3((total + b - 1) / b), dim3(b), 0, stream, d, dst, mode);
+    return hipGetLastError();
+}
+
+static int units_of(const ChainDesc &d) {
+    if (d.kind == KIND_TORUS) return d.format == FMT_BITPACKED ? d.L * d.W : d.n;
+    return (d.n + 3) / 4;
+}
+
+hipError_t launch_half_step_grid(const ChainDesc *dev_descs, const ChainDesc *host_descs,
+                                 int nchains, const uint32_t *dstate, uint32_t s_add,
+                                 uint32_t s_log0, int log_on, bool even, int block,
+                                 hipStream_t stream) {
+    if (nchains <= 0) return hipSuccess;
+    // the chains of one launch share a kind and a format (the runtime groups them)
+    const ChainDesc &h0 = host_descs[0];
+    int maxu = 0, fold = 1, maxcls = 1;
+    for (int i = 0; i < nchains; ++i) {
+        maxu = maxu > units_of(host_descs[i]) ? maxu : units_of(host_descs[i]);
+        fold &= host_descs[i].fold3;
+        maxcls = maxcls > host_descs[i].ncls ? maxcls : host_descs[i].ncls;
+    }
+    const bool obs = log_on && even;
+    const StepArgs sa{dstate, s_add, s_log0, log_on};
+    const int b = block > 0 ? block : 256;
+    const dim3 grid((maxu + b - 1) / b, nchains);
+    if (h0.kind == KIND_TORUS && h0.format == FMT_BITPACKED) {
+        if (obs) {
+            if (fold) hipLaunchKernelGGL((k_torus_bp<true, true>), grid, dim3(b), 0, stream, dev_descs, sa);
+            else hipLaunchKernelGGL((k_torus_bp<true, false>), grid, dim3(b), 0, stream, dev_descs, sa);
+        } else {
+            if (fold) hipLaunchKernelGGL((k_torus_bp<false, true>), grid, dim3(b), 0, stream, dev_descs, sa);
+            else hipLaunchKernelGGL((k_torus_bp<false, false>), grid, dim3(b), 0, stream, dev_descs, sa);
+        }
+    } else if (h0.kind == KIND_TORUS) {
+        if (obs) hipLaunchKernelGGL((k_torus_i8<true>), grid, dim3(b), 0, stream, dev_descs, sa);
+        else hipLaunchKernelGGL((k_torus_i8<false>), grid, dim3(b), 0, stream, dev_descs, sa);
+    } else {
+        const size_t shm = obs ? sizeof(int) * (size_t)maxcls : 0;
+        if (obs) hipLaunchKernelGGL((k_graph<true>), grid, dim3(b), shm, stream, dev_descs, sa);
+        else hipLaunchKernelGGL((k_graph<false>), grid, dim3(b), 0, stream, dev_descs, sa);
+    }
+    return hipGetLastError();
+}
+
+// advance the device half-step counter by `by` (end of a replayed graph)
+__global__ void k_advance(uint32_t *dstate, uint32_t by) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) dstate[0] += by;
+}
+
+__global__ void k_set_state(uint32_t *d, uint32_t a, uint32_t b) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        d[0] = a;
+        d[1] = b;
+    }
+}
+
+hipError_t launch_set_state(uint32_t *d, uint32_t a, uint32_t b, hipStream_t stream) {
+    hipLaunchKernelGGL(k_set_state, dim3(1), dim3(64), 0, stream, d, a, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_advance(uint32_t *dstate, uint32_t by, hipStream_t stream) {
+    hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, stream, dstate, by);
+    return hipGetLastError();
+}
+
+hipError_t launch_observe(const ChainDesc *dev_descs, const ChainDesc *host_descs, int nchains,
+                          int idx, int slot, hipStream_t stream) {
+    if (nchains <= 0) return hipSuccess;
+    int maxu = 0;
+    for (int i = 0; i < nchains; ++i) {
+        const ChainDesc &d = host_descs[i];
+        const int u = (d.kind == KIND_TORUS && d.format == FMT_BITPACKED) ? d.L * d.W : d.n;
+        maxu = maxu > u ? maxu : u;
+    }
+    const int b = 256;
+    hipLaunchKernelGGL(k_observe, dim3((maxu + b - 1) / b, nchains), dim3(b), 0, stream, dev_descs, idx, slot);
+    return hipGetLastError();
+}
+
+}  // namespace shaken

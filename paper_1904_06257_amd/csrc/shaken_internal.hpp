@@ -1,0 +1,90 @@
+// Internal declarations shared by the host runtime (api.cpp) and the HIP
+// kernels (kernels.hip) of libshaken.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace shaken {
+
+constexpr uint32_t kGraphStream = 0x80000000u;  // fourth counter word, graph uniforms
+constexpr uint32_t kInitStep = 0xFFFFFFFFu;     // half-step index of the random start
+
+enum Kind : int32_t { KIND_TORUS = 0, KIND_GRAPH = 1 };
+enum Format : int32_t { FMT_INT8 = 1, FMT_BITPACKED = 2 };
+
+// Everything a kernel needs to advance one chain.  Lives in device memory for
+// batches and is passed by value for single-chain launches.
+struct ChainDesc {
+    uint64_t seed;
+    uint32_t replica;
+    int32_t kind;
+    int32_t format;
+    int32_t L;        // torus side
+    int32_t W;        // torus words per row (ceil(L/32))
+    int32_t n;        // sites (L*L or graph vertices)
+    void *spin[2];    // spin[0] holds the configuration read at even offsets
+    // bit-packed torus: classes j = (#plus neighbours in the half) + 3*(own spin is +1)
+    uint32_t tsmall[6];  // t of the class: floor(p_small * 2^32), p_small = min(p, 1-p)
+    uint32_t sgn;        // bit j: field of class j is >= 0
+    int32_t fold3;       // tsmall depends on |h| only (3 classes after sign folding)
+    int32_t J;           // uniform torus coupling
+    // generic threshold table (int8 torus, graph): ((S+smax)*2 + (sigma>0))*ncls + cls
+    const uint64_t *lut;
+    int32_t smax;
+    int32_t ncls;
+    // graph: CSR per half (0 = in-half, read in half-step 1; 1 = out-half)
+    const int32_t *rowptr[2];
+    const int32_t *col[2];
+    const int8_t *jw[2];     // coupling per CSR entry
+    const uint8_t *cls;      // field class per vertex (never NULL on device)
+    int32_t maxdeg;          // largest half-degree
+    int32_t pad0;
+    // observables log: slot t holds [E_J, plus_0 .. plus_{ncls-1}] (int64)
+    int64_t *log;
+    int64_t log_stride;      // 1 + ncls
+};
+
+// ---------------------------------------------------------------- launchers
+// All launchers enqueue on `stream` and return the hipError_t of the launch.
+
+// random / constant initial state of one chain into buffer `dst`
+hipError_t launch_init(const ChainDesc &d, void *dst, int mode, hipStream_t stream);
+
+// One half-step of every chain in dev_descs[0..nchains) (device array, all of
+// one kind and format; host_descs mirrors it for launch shapes).  The
+// half-step index is s = dstate[0] + s_add if dstate is non-null, else s_add;
+// `even` must equal (s % 2 == 0).  Chain configurations at half-step s live in
+// spin[s & 1].  With log_on, the observables of a configuration read at an
+// even s are accumulated into log slot (s - base) / 2, base = dstate[1] or
+// s_log0.
+hipError_t launch_half_step_grid(const ChainDesc *dev_descs, const ChainDesc *host_descs,
+                                 int nchains, const uint32_t *dstate, uint32_t s_add,
+                                 uint32_t s_log0, int log_on, bool even, int block,
+                                 hipStream_t stream);
+
+// d[0] = a, d[1] = b (two uint32 words)
+hipError_t launch_set_state(uint32_t *d, uint32_t a, uint32_t b, hipStream_t stream);
+
+// dstate[0] += by
+hipError_t launch_advance(uint32_t *dstate, uint32_t by, hipStream_t stream);
+
+// observables of spin[idx] of every chain into log slot `slot`
+hipError_t launch_observe(const ChainDesc *dev_descs, const ChainDesc *host_descs, int nchains,
+                          int idx, int slot, hipStream_t stream);
+
+// zero `count` int64 at p
+hipError_t launch_fill_i64(int64_t *p, int64_t count, int64_t value, hipStream_t stream);
+
+// persistent batch: run n_full full steps of every chain, starting at
+// half-step s0 with the configuration in spin[0]; chains are taken from a
+// device queue in the order given by `order`; counter must be zero on entry.
+// Writes the final configuration back into spin[0].
+hipError_t launch_persistent(const ChainDesc *dev_descs, int nchains, const int32_t *order,
+                             int32_t *counter, uint32_t s0, int64_t n_full, int record,
+                             int block, int grid, hipStream_t stream);
+
+// can chain d run in the persistent kernel?
+bool persistent_fits(const ChainDesc &d);
+
+}  // namespace shaken

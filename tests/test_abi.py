@@ -1,0 +1,72 @@
+"""The C-ABI library loads, exports every symbol include/shaken.h declares,
+and rejects invalid arguments before touching a device.  CPU only."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "shaken.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:shaken_status|const char \*|int32_t)\s*\*?\s*(shaken_\w+)\s*\(",
+                                 txt, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_1904_06257_amd as sk
+    lib = ctypes.CDLL(sk.LIB_PATH)
+    names = _declared()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(sk.EXPORTED)
+
+
+def test_version_and_strings():
+    import paper_1904_06257_amd as sk
+    assert sk.shaken_version() == (0 << 16) | 1
+    assert sk._lib.shaken_strerror(1) == b"invalid argument"
+
+
+def _init_status(**kw):
+    import paper_1904_06257_amd as sk
+    try:
+        sk.Chain(**kw)
+    except sk.ShakenError as e:
+        return e.status, str(e)
+    return 0, ""
+
+
+@pytest.mark.parametrize("kw,frag", [
+    (dict(kind="torus", L=2), "L must be"),
+    (dict(kind="torus", L=8, q=-1.0), "q must be"),
+    (dict(kind="torus", L=8, beta=float("nan")), "beta must be"),
+    (dict(kind="torus", L=8, lam_values=[0.1, 0.2]), "uniform"),
+    (dict(kind="torus", L=4, J=np.r_[np.ones(31), -np.ones(1)]), "uniform"),
+    (dict(kind="graph", n=4, src=[0, 1], dst=[1, 1]), "self-loop"),
+    (dict(kind="graph", n=4, src=[0, 1], dst=[1, 0]), "twice"),
+    (dict(kind="graph", n=4, src=[0, 5], dst=[1, 2]), "out of range"),
+    (dict(kind="graph", n=0, src=[], dst=[]), "n must be"),
+    (dict(kind="graph", n=3, src=[0], dst=[1], fmt="bitpacked"), "int8"),
+    (dict(kind="graph", n=3, src=[0], dst=[1], lam_values=[0.0], lam_class=[0, 1, 0]), "class id"),
+    (dict(kind="torus", L=3, init_spins=np.zeros(9)), "+1 or -1"),
+])
+def test_invalid_arguments_rejected_on_host(kw, frag):
+    import paper_1904_06257_amd as sk
+    st, msg = _init_status(**kw)
+    assert st == sk.SHAKEN_EINVAL, msg
+    assert frag in msg
+
+
+def test_valid_arguments_reach_the_device_check():
+    """With no GPU here a valid call fails only at the device step."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    import paper_1904_06257_amd as sk
+    st, msg = _init_status(kind="torus", L=8)
+    assert st == sk.SHAKEN_EDEVICE

@@ -1,0 +1,303 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Bit-exact on every integer output: final configurations, per-step H and M,
+threshold tables.  Sizes span several tiles and ragged tails; the full-size
+workloads are checked on sampled sites, or over a short prefix the oracle can
+run.  All tests need an MI355X.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sk():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    import paper_1904_06257_amd as m
+    return m
+
+
+def _print_case(*a):
+    print("case:", *a, flush=True)
+
+
+# --------------------------------------------------------------- torus
+
+@pytest.mark.parametrize("fmt", ["bitpacked", "int8"])
+def test_torus_64_full_config(sk, fmt):
+    """64 x 64, J=1, lambda=0, q=1, beta=0.4, 1000 full steps, Philox seed 1:
+    final spins and the H, M logs of every step equal the oracle's."""
+    L, q, beta, seed, T = 64, 1.0, 0.40, 1, 1000
+    _print_case("torus64", fmt)
+    init = oracle.torus_init_random(L, seed)
+    want, ej, mm = oracle.torus_run(init, 1, 0.0, q, beta, seed, 0, T)
+    ch = sk.Chain.torus(L, q=q, beta=beta, seed=seed, fmt=fmt)
+    assert np.array_equal(ch.spins(), init)
+    H, M = ch.sweep(T, log=True)
+    assert np.array_equal(ch.spins(), want)
+    assert np.array_equal(H, -ej)
+    assert np.array_equal(M, mm)
+    ob = ch.observables()
+    assert ob.half_step == 2 * T and ob.H == -ej[-1] and ob.M == mm[-1]
+
+
+@pytest.mark.parametrize("L,fmt,lam,q,beta,J", [
+    (3, "bitpacked", 0.0, 1.0, 0.4, 1),
+    (5, "int8", 0.15, 0.1, 1.3, 1),
+    (31, "bitpacked", 0.15, 0.1, 2.3, 1),
+    (33, "bitpacked", -0.3, 0.7, 0.9, 2),
+    (37, "int8", 0.0, 0.0, 0.6, 1),
+    (64, "bitpacked", 0.25, 2.0, 0.44, -1),
+    (101, "bitpacked", 0.0, 0.5, 0.3, 1),
+    (101, "int8", 0.0, 0.5, 0.3, 1),
+    (200, "bitpacked", 0.05, 3.0, 0.5, 1),
+])
+def test_torus_ragged_and_parameters(sk, L, fmt, lam, q, beta, J):
+    """Ragged widths (L not a multiple of 32), fields that break the sign
+    symmetry, q = 0, antiferromagnetic J; M log and final spins bit-exact,
+    E_J through the observables."""
+    seed, T = 12345 + L, 40
+    _print_case("torus", L, fmt, lam, q, beta, J)
+    init = oracle.torus_init_random(L, seed, 3)
+    want, ej, mm = oracle.torus_run(init, J, lam, q, beta, seed, 3, T)
+    Jarr = np.full(2 * L * L, J, dtype=np.int8)
+    ch = sk.Chain.torus(L, J=Jarr, lam_values=[lam], q=q, beta=beta, seed=seed, replica=3, fmt=fmt)
+    M = ch.sweep_m(T)
+    assert np.array_equal(ch.spins(), want)
+    assert np.array_equal(M, mm)
+    ob = ch.observables()
+    assert ob.E_J == ej[-1]
+
+
+def test_torus_bitpacked_equals_int8(sk):
+    L, T = 77, 60
+    a = sk.Chain.torus(L, q=0.8, beta=0.5, seed=9, fmt="bitpacked", lam_values=[0.1])
+    b = sk.Chain.torus(L, q=0.8, beta=0.5, seed=9, fmt="int8", lam_values=[0.1])
+    a.sweep(T)
+    b.sweep(T)
+    assert np.array_equal(a.spins(), b.spins())
+
+
+def test_torus_half_steps_and_parity(sk):
+    """Odd numbers of half-steps, checkpoint restore of the counter."""
+    L, q, beta, seed = 40, 0.9, 0.45, 4
+    init = oracle.torus_init_random(L, seed)
+    x = init.copy()
+    for s in range(7):
+        x = oracle.torus_half_step(x, 1, 0.0, q, beta, seed, 0, s)
+    ch = sk.Chain.torus(L, q=q, beta=beta, seed=seed)
+    ch.half_step(3)
+    ch.half_step(4)
+    assert np.array_equal(ch.spins(), x)
+    # restore: set spins and counter, continue
+    y = oracle.torus_half_step(x, 1, 0.0, q, beta, seed, 0, 7)
+    c2 = sk.Chain.torus(L, q=q, beta=beta, seed=seed, init_spins=x)
+    c2.set_half_step(7)
+    c2.half_step(1)
+    assert np.array_equal(c2.spins(), y)
+    with pytest.raises(sk.ShakenError):
+        c2.set_half_step(7)
+        c2.sweep(1)
+
+
+def test_torus_zero_temperature_diagonal(sk):
+    """The printed zero-temperature growth (proof of Theorem 3.3) on the GPU."""
+    L, r0, c0 = 16, 5, 11
+    sp = -np.ones((L, L), dtype=np.int8)
+    sp[r0, c0] = 1
+    for fmt in ("bitpacked", "int8"):
+        ch = sk.Chain.torus(L, q=0.1, lam_values=[0.15], beta=1000.0, seed=1, init_spins=sp, fmt=fmt)
+        ch.half_step(1)
+        got = set(map(tuple, np.argwhere(ch.spins() > 0)))
+        assert got == {(r0 + 1, c0), (r0, c0 + 1)}
+        ch.half_step(2 * (L // 2) - 1)
+        got = set(map(tuple, np.argwhere(ch.spins() > 0)))
+        assert got == {(r, c) for r in range(L) for c in range(L) if (r + c - r0 - c0) % L == 0}
+
+
+def test_torus_lut_matches_oracle(sk):
+    for q, beta, lam, J in [(1.0, 0.4, 0.0, 1), (0.1, 2.3, 0.15, 1), (2.5, 0.9, -0.2, 3)]:
+        ch = sk.Chain.torus(8, J=np.full(128, J, dtype=np.int8), q=q, beta=beta, lam_values=[lam])
+        lut, smax = ch.lut()
+        assert smax == 2 * abs(J)
+        for S in range(-smax, smax + 1):
+            for sb in (0, 1):
+                want = oracle.threshold_of(S, 1 if sb else -1, q, lam, beta)
+                assert int(lut[(S + smax) * 2 + sb]) == want
+
+
+def test_torus_4096_sampled_sites(sk):
+    """Full size: one dl and one ur half-step of a 4096^2 bit-packed torus,
+    16384 sampled sites recomputed one by one by the oracle."""
+    L, q, beta, seed = 4096, 1.0, 0.44, 2
+    _print_case("torus4096 sampled")
+    ch = sk.Chain.torus(L, q=q, beta=beta, seed=seed, replica=5)
+    s0 = ch.spins()
+    init = oracle.torus_init_random(L, seed, 5)
+    rng = np.random.Generator(np.random.PCG64(3))
+    rows = rng.integers(0, L, 64)
+    assert np.array_equal(s0[rows], init[rows])
+    ch.half_step(1)
+    s1 = ch.spins()
+    ch.half_step(1)
+    s2 = ch.spins()
+    idx = rng.integers(0, L, size=(16384, 2))
+    idx[:64, 1] = 0
+    idx[64:128, 1] = L - 1
+    for (r, c) in idx[:8192]:
+        assert s1[r, c] == oracle.torus_site(s0, 1, 0.0, q, beta, seed, 5, 0, r, c)
+    for (r, c) in idx[8192:]:
+        assert s2[r, c] == oracle.torus_site(s1, 1, 0.0, q, beta, seed, 5, 1, r, c)
+
+
+def test_torus_256_long_prefix(sk):
+    L, q, beta, T = 256, 2.0, 0.5, 200
+    init = np.ones((L, L), dtype=np.int8)
+    want, ej, mm = oracle.torus_run(init, 1, 0.0, q, beta, 2, 0, T)
+    ch = sk.Chain.torus(L, q=q, beta=beta, seed=2, init="all_up")
+    H, M = ch.sweep(T, log=True)
+    assert np.array_equal(ch.spins(), want)
+    assert np.array_equal(H, -ej) and np.array_equal(M, mm)
+
+
+# ---------------------------------------------------------------- graph
+
+def _graph_case(n, seed, lam=(-0.5, 0.0, 0.5)):
+    inst = synth.oriented_instance(n, 3, seed, lam_values=lam, pm_j=True)
+    g = oracle.Graph(inst.n, inst.src, inst.dst, inst.J, inst.cls, inst.lam_values)
+    return inst, g
+
+
+def _h_from_plus(inst, ej, plus):
+    ncls = np.bincount(inst.cls, minlength=len(inst.lam_values))
+    lam2 = (2 * inst.lam_values).astype(np.int64)
+    return -ej - ((2 * plus - ncls[None, :]) * lam2[None, :]).sum(axis=1)
+
+
+@pytest.mark.parametrize("n", [4, 10, 1002, 4096])
+def test_graph_3regular(sk, n):
+    """3-regular +-J graph, coin orientation, lambda in {-1/2, 0, 1/2},
+    q = 1.5, beta = 0.8: spins and H, M logs bit-exact over 200 full steps."""
+    T = 200
+    _print_case("graph3reg", n)
+    inst, g = _graph_case(n, 100 + n)
+    sp0 = oracle.graph_init_random(n, 1)
+    want, ej, plus = oracle.graph_run(g, sp0, 1.5, 0.8, 1, 0, T)
+    ch = sk.Chain.graph(n, inst.src, inst.dst, J=inst.J, lam_values=inst.lam_values,
+                        lam_class=inst.cls, q=1.5, beta=0.8, seed=1)
+    assert np.array_equal(ch.spins(), sp0)
+    H, M = ch.sweep(T, log=True)
+    assert np.array_equal(ch.spins(), want)
+    assert np.array_equal(H, _h_from_plus(inst, ej, plus))
+    ncls = np.bincount(inst.cls, minlength=3)
+    assert np.array_equal(M, (2 * plus - ncls[None, :]).sum(axis=1))
+
+
+@pytest.mark.parametrize("n,p,jmax,ncls", [(1, 0.0, 1, 1), (7, 0.0, 1, 2), (333, 0.05, 3, 4),
+                                            (1001, 0.01, 5, 7)])
+def test_graph_general(sk, n, p, jmax, ncls):
+    """Erdos-Renyi graphs (no edges, isolated vertices, larger couplings, many
+    field classes, n not a multiple of 4)."""
+    T = 50
+    _print_case("graphER", n, p, jmax, ncls)
+    inst = synth.random_oriented_graph(n, p, 7 + n, jmax=jmax, n_classes=ncls, lam_scale=0.3)
+    g = oracle.Graph(inst.n, inst.src, inst.dst, inst.J, inst.cls, inst.lam_values)
+    sp0 = oracle.graph_init_random(n, 3, 2)
+    want, ej, plus = oracle.graph_run(g, sp0, 0.6, 0.7, 3, 2, T)
+    ch = sk.Chain.graph(n, inst.src, inst.dst, J=inst.J, lam_values=inst.lam_values,
+                        lam_class=inst.cls, q=0.6, beta=0.7, seed=3, replica=2)
+    M = ch.sweep_m(T)
+    assert np.array_equal(ch.spins(), want)
+    ncls_cnt = np.bincount(inst.cls, minlength=ncls)
+    assert np.array_equal(M, (2 * plus - ncls_cnt[None, :]).sum(axis=1))
+    assert ch.observables().E_J == ej[-1]
+
+
+def test_graph_full_size_prefix(sk):
+    """N = 2^20 3-regular +-J graph: 6 full steps bit-exact (whole configuration)."""
+    n, T = 1 << 20, 6
+    _print_case("graph 2^20")
+    inst, g = _graph_case(n, 3)
+    sp0 = oracle.graph_init_random(n, 1)
+    want, ej, plus = oracle.graph_run(g, sp0, 1.5, 0.8, 1, 0, T)
+    ch = sk.Chain.graph(n, inst.src, inst.dst, J=inst.J, lam_values=inst.lam_values,
+                        lam_class=inst.cls, q=1.5, beta=0.8, seed=1)
+    H, M = ch.sweep(T, log=True)
+    assert np.array_equal(ch.spins(), want)
+    assert np.array_equal(H, _h_from_plus(inst, ej, plus))
+
+
+def test_graph_lut_matches_oracle(sk):
+    inst, g = _graph_case(64, 8)
+    ch = sk.Chain.graph(64, inst.src, inst.dst, J=inst.J, lam_values=inst.lam_values,
+                        lam_class=inst.cls, q=1.5, beta=0.8, seed=1)
+    lut, smax = ch.lut()
+    nc = len(inst.lam_values)
+    for S in range(-smax, smax + 1):
+        for sb in (0, 1):
+            for k in range(nc):
+                want = oracle.threshold_of(S, 1 if sb else -1, 1.5, inst.lam_values[k], 0.8)
+                assert int(lut[((S + smax) * 2 + sb) * nc + k]) == want
+
+
+def test_set_params_changes_law(sk):
+    L, T = 48, 10
+    init = oracle.torus_init_random(L, 5)
+    x, _, _ = oracle.torus_run(init, 1, 0.0, 1.0, 0.4, 5, 0, T)
+    y, _, _ = oracle.torus_run(x, 1, 0.0, 2.0, 0.7, 5, 0, T, s0=2 * T)
+    ch = sk.Chain.torus(L, q=1.0, beta=0.4, seed=5)
+    ch.sweep(T)
+    ch.set_params(0.7, 2.0)
+    ch.sweep(T)
+    assert np.array_equal(ch.spins(), y)
+
+
+# ---------------------------------------------------------------- batches
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_batch_grid_mixed(sk, use_graph):
+    """A grid batch of tori (both formats, several sizes) and graphs, each
+    with its own beta, q, seed and replica, advanced together."""
+    T = 37
+    specs = []
+    chains = []
+    for i, (L, fmt) in enumerate([(64, "bitpacked"), (96, "bitpacked"), (50, "int8"), (33, "bitpacked")]):
+        q, b, seed = 0.5 + 0.3 * i, 0.3 + 0.1 * i, 1000 + i
+        init = oracle.torus_init_random(L, seed, i)
+        want, ej, mm = oracle.torus_run(init, 1, 0.0, q, b, seed, i, T)
+        specs.append(("t", want, -ej, mm))
+        chains.append(sk.Chain.torus(L, q=q, beta=b, seed=seed, replica=i, fmt=fmt))
+    for i, n in enumerate([500, 2048]):
+        inst, g = _graph_case(n, 50 + i)
+        sp0 = oracle.graph_init_random(n, 77 + i, i)
+        want, ej, plus = oracle.graph_run(g, sp0, 1.2, 0.6, 77 + i, i, T)
+        ncls = np.bincount(inst.cls, minlength=3)
+        specs.append(("g", want, _h_from_plus(inst, ej, plus), (2 * plus - ncls[None, :]).sum(axis=1)))
+        chains.append(sk.Chain.graph(n, inst.src, inst.dst, J=inst.J, lam_values=inst.lam_values,
+                                     lam_class=inst.cls, q=1.2, beta=0.6, seed=77 + i, replica=i))
+    b = sk.Batch(chains, strategy="grid", use_hipgraph=use_graph, record=True, autotune=True)
+    b.sweep(T)
+    for i, (kind, want, H, M) in enumerate(specs):
+        assert np.array_equal(chains[i].spins(), want), i
+        h, m = b.log(i)
+        assert np.array_equal(h, H), i
+        assert np.array_equal(m, M), i
+    # a second sweep continues the same chains
+    b.sweep(3)
+    st, ms = b.info()
+    assert st == sk.SHAKEN_BATCH_GRID and ms > 0
+
+
+def test_batch_rejects_mismatched_counters(sk):
+    a = sk.Chain.torus(16, seed=1)
+    c = sk.Chain.torus(16, seed=2)
+    c.half_step(2)
+    with pytest.raises(sk.ShakenError):
+        sk.Batch([a, c], strategy="grid")
