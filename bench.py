@@ -1,0 +1,200 @@
+"""Benchmark of the shaken-dynamics hot path on one MI355X.
+
+Default workload (the headline): the 24 runs of the 4096 x 4096 bit-packed
+torus -- q in {0.5, 1, 2} x beta in {0.30, 0.40, 0.44, 0.50} x initial state
+{all up, random} -- held as 24 chains of one grid batch.  One step is one full
+step (half-step dl with the fused observables of the configuration it reads,
+then half-step ur) of all 24 chains; it is replayed from a captured HIP
+graph.  Inputs are resident in device memory before the timed region.
+
+Other workloads (``--workload``): ``graph`` (3-regular +-J graph, n = 2^20,
+CSR, int8), ``batch`` (2048 mixed tori and 3-regular graphs, persistent
+launch), ``torus64`` (one 64 x 64 chain).
+
+Prints one JSON line: metric, value (site-updates/s), roofline of the
+dominant kernel (HIP-event time per launch, algorithmic work per launch) and
+the CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# --------------------------------------------------------------- constants
+# MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz = 39.3e12 full-rate 32-bit
+# VALU lane-cycles per second.
+VALU_PEAK = 256 * 64 * 2.4e9
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic ALU work of one bit-packed site-update, in VALU lane-cycles
+# (derivation in the design doc): per 32-site word, E[G] = 1.999 Philox4x32-10
+# calls (per-word early exit of the MSB-first compare, groups of 4 levels),
+# 100 lane-cycles per call (20 quarter-rate 32x32->64 multiplies + 20
+# three-input xors), 4 E[G] compare levels x 6 lane-cycles, 17 lane-cycles of
+# neighbour, class and sign planes: (199.9 + 48.0 + 17) / 32.
+BP_ALU_PER_SITE = (1.999 * 100 + 4 * 1.999 * 6 + 17) / 32.0
+BP_BYTES_PER_SITE = 0.25  # read 1 bit, write 1 bit
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "batch.hip", "shaken_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_1904_06257_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kernel_key):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None if the kernels changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("#") or "=" not in line:
+                continue
+            k, v = line.split("=", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("source_hash") != kernel_source_hash():
+        return None
+    v = vals.get(kernel_key + ".bytes_per_launch")
+    return float(v) if v else None
+
+
+def cpu_baseline_torus():
+    """The oracle as it stands: four full steps (eight half-steps) of one
+    4096^2 chain, single-threaded C."""
+    import oracle
+    L, steps = 4096, 4
+    sp = oracle.torus_init_random(L, 2)
+    t0 = time.perf_counter()
+    oracle.torus_run(sp, 1, 0.0, 1.0, 0.44, 2, 0, steps, log=False)
+    dt = time.perf_counter() - t0
+    n = 2 * L * L * steps
+    return {"value": n / dt, "unit": "site-updates/s", "cores": 1, "kind": "oracle",
+            "sample": "%d full steps of one 4096^2 torus chain (q=1, beta=0.44, random init), "
+                      "%.1f s on one host core" % (steps, dt)}
+
+
+def bench_torus4096(args, sk):
+    import synth
+    import torch
+    L = 4096
+    runs = synth.torus_runs()
+    chains = []
+    for i, r in enumerate(runs):
+        chains.append(sk.Chain.torus(L, q=r["q"], beta=r["beta"], seed=r["seed"], replica=i,
+                                     init=r["init"]))
+    batch = sk.Batch(chains, strategy="grid", use_hipgraph=True, record=True, autotune=True)
+    batch.sweep(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.sweep(args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    _, ev_ms = batch.info()   # HIP events on the batch stream around the sweep
+    n_chains = len(chains)
+    site_updates = 2.0 * n_chains * L * L * args.steps
+    value = site_updates / wall
+    # dominant kernel: the bit-packed half-step, 2 launches per step; the
+    # remaining launches per step (1/16 of a counter increment) are < 0.1 %
+    per_launch_s = ev_ms * 1e-3 / (2 * args.steps)
+    units_per_launch = n_chains * L * L
+    achieved_alu = units_per_launch * BP_ALU_PER_SITE / per_launch_s
+    traffic = read_traffic("k_torus_bp")
+    roof = {"bound": "alu", "achieved": achieved_alu / 1e12, "peak": VALU_PEAK / 1e12,
+            "unit": "T lane-cycles/s", "frac": achieved_alu / VALU_PEAK,
+            "traffic": traffic, "kernel": "k_torus_bp",
+            "launch_us": per_launch_s * 1e6,
+            "alg_bytes_GBs": units_per_launch * BP_BYTES_PER_SITE / per_launch_s / 1e9,
+            "hbm_frac": units_per_launch * BP_BYTES_PER_SITE / per_launch_s / 1e9 / HBM_PEAK_GBS}
+    for c in chains:
+        c.close()
+    batch.close()
+    cfg = {"workload": "4096x4096 bit-packed torus, 24 chains (q x beta x init) batched",
+           "L": L, "chains": n_chains, "J": 1, "lambda": 0.0, "q": [0.5, 1.0, 2.0],
+           "beta": [0.30, 0.40, 0.44, 0.50], "init": ["all_up", "random"],
+           "strategy": "grid + hipGraph", "observables": "fused, every full step"}
+    return value, wall, cfg, roof, "u1 (bit-packed spins)"
+
+
+def bench_graph(args, sk):
+    import numpy as np
+    import synth
+    import torch
+    n = 1 << 20
+    inst = synth.oriented_instance(n, 3, 3, lam_values=(-0.5, 0.0, 0.5), pm_j=True)
+    ch = sk.Chain.graph(n, inst.src, inst.dst, J=inst.J, lam_values=inst.lam_values,
+                        lam_class=inst.cls, q=1.5, beta=0.8, seed=1)
+    batch = sk.Batch([ch], strategy="grid", use_hipgraph=True, record=True, autotune=True)
+    batch.sweep(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.sweep(args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    _, ev_ms = batch.info()
+    value = 2.0 * n * args.steps / wall
+    per_launch_s = ev_ms * 1e-3 / (2 * args.steps)
+    m = inst.src.shape[0]
+    # algorithmic bytes per half-step: rowptr (n+1) + col + J (m) + own spin,
+    # gathered spins (m), field class, written spin
+    bytes_launch = 4 * (n + 1) + 5 * m + n + m + n + n
+    achieved = bytes_launch / per_launch_s / 1e9
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": read_traffic("k_graph"),
+            "kernel": "k_graph", "launch_us": per_launch_s * 1e6}
+    ch.close()
+    batch.close()
+    cfg = {"workload": "random 3-regular +-J graph, n=2^20, coin orientation, CSR int32, int8 spins",
+           "n": n, "q": 1.5, "beta": 0.8, "lambda": [-0.5, 0.0, 0.5]}
+    return value, wall, cfg, roof, "int8"
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="torus4096", choices=["torus4096", "graph"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(each chain is independent; see DESIGN.md for how the work would shard)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    torch.cuda.set_device(0)
+    import paper_1904_06257_amd as sk
+
+    if args.workload == "torus4096":
+        value, wall, cfg, roof, dtype = bench_torus4096(args, sk)
+        metric = "spin-site updates/s (4096^2 torus, batched)"
+        cpu = None if args.no_cpu_baseline else cpu_baseline_torus()
+    else:
+        value, wall, cfg, roof, dtype = bench_graph(args, sk)
+        metric = "vertex updates/s (3-regular graph, n=2^20)"
+        cpu = None
+    out = {"metric": metric, "value": value, "unit": "site-updates/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": wall * 1e3 / args.steps, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+           "config": cfg, "roofline": roof, "cpu_baseline": cpu}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

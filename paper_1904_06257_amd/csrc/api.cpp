@@ -135,7 +135,9 @@ struct shaken_ctx {
         if (kind == KIND_TORUS && format == FMT_BITPACKED) return (size_t)L * W * 4;
         return (size_t)n;
     }
-    int64_t stride() const { return 1 + (int64_t)lam.size(); }
+    int64_t nvals() const { return 1 + (int64_t)lam.size(); }               // values per slot
+    int64_t line() const { return (nvals() + 15) / 16 * 16; }                 // one partial line
+    int64_t stride() const { return (int64_t)kLogParts * line(); }            // int64 per slot
 };
 
 namespace {
@@ -226,12 +228,17 @@ void unpack_torus(const std::vector<uint32_t> &in, int L, int W, int8_t *out) {
 // Convert a device log (slots x stride) to H and M per slot.
 void convert_log(const shaken_ctx *c, const std::vector<int64_t> &raw, int64_t slots,
                  int64_t *H, int64_t *M) {
-    const int64_t st = c->stride();
+    const int64_t st = c->stride(), ln = c->line();
+    auto val = [&](int64_t t, int64_t v) {
+        int64_t a = 0;
+        for (int p = 0; p < kLogParts; ++p) a += raw[t * st + p * ln + v];
+        return a;
+    };
     for (int64_t t = 0; t < slots; ++t) {
-        const int64_t EJ = raw[t * st];
+        const int64_t EJ = val(t, 0);
         int64_t m = 0, l2 = 0;
         for (size_t k = 0; k < c->lam.size(); ++k) {
-            const int64_t mk = 2 * raw[t * st + 1 + k] - c->class_size[k];
+            const int64_t mk = 2 * val(t, 1 + (int64_t)k) - c->class_size[k];
             m += mk;
             if (c->lam2_int) l2 += c->lam2[k] * mk;
         }
@@ -436,6 +443,7 @@ shaken_status init_device(shaken_ctx *c, const shaken_opts *o, HostLayout &hl) {
     }
     d.cls = c->cls_dev;
     d.maxdeg = c->maxdeg;
+    d.log_line = c->line();
     d.log_stride = c->stride();
     refresh_desc_spins(c);
     build_tables(c);
@@ -602,20 +610,25 @@ shaken_status shaken_observables(shaken_ctx *ctx, shaken_obs *out) {
     } while (0);
     dfree(dtmp);
     if (st != SHAKEN_OK) return st;
+    auto val = [&](int64_t v) {
+        int64_t a = 0;
+        for (int p = 0; p < kLogParts; ++p) a += raw[p * ctx->line() + v];
+        return a;
+    };
     out->half_step = ctx->s;
     out->n_sites = ctx->n;
-    out->E_J = raw[0];
+    out->E_J = val(0);
     int64_t m = 0, l2 = 0;
     double l2d = 0;
     for (size_t k = 0; k < ctx->lam.size(); ++k) {
-        const int64_t mk = 2 * raw[1 + k] - ctx->class_size[k];
+        const int64_t mk = 2 * val(1 + (int64_t)k) - ctx->class_size[k];
         m += mk;
         l2 += ctx->lam2[k] * mk;
         l2d += 2.0 * ctx->lam[k] * (double)mk;
     }
     out->M = m;
     out->E_lambda2 = ctx->lam2_int ? l2 : 0;
-    out->H = ctx->lam2_int ? (double)(-raw[0] - l2) : -(double)raw[0] - l2d;
+    out->H = ctx->lam2_int ? (double)(-out->E_J - l2) : -(double)out->E_J - l2d;
     out->flags = ctx->lam2_int ? 1 : 0;
     out->reserved = 0;
     return SHAKEN_OK;

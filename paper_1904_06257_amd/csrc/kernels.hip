@@ -26,15 +26,16 @@ struct U4 {
     uint32_t x, y, z, w;
 };
 
-// Philox4x32 with ten rounds (Salmon et al., SC'11).
+// Philox4x32 with ten rounds (Salmon et al., SC'11).  The three-input xors
+// are single v_bitop3_b32 instructions (truth table 0x96).
 __device__ __forceinline__ U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                        uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int i = 0; i < 10; ++i) {
         const uint64_t a = (uint64_t)c0 * 0xD2511F53u;
         const uint64_t b = (uint64_t)c2 * 0xCD9E8D57u;
-        const uint32_t n0 = (uint32_t)(b >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(a >> 32) ^ c3 ^ k1;
+        const uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(b >> 32), c1, k0, 0x96);
+        const uint32_t n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(a >> 32), c3, k1, 0x96);
         c1 = (uint32_t)b;
         c3 = (uint32_t)a;
         c0 = n0;
@@ -60,6 +61,11 @@ __device__ __forceinline__ int wave_sum(int v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
+}
+
+// line of log slot `slot` that block `blk` adds into
+__device__ __forceinline__ int64_t *log_part(const ChainDesc &d, int slot, int blk) {
+    return d.log + (int64_t)slot * d.log_stride + (int64_t)(blk & (kLogParts - 1)) * d.log_line;
 }
 
 // block-level sum of two ints into log[0] and log[1] (one atomic per block)
@@ -193,35 +199,73 @@ __device__ __forceinline__ int step_slot(const StepArgs &a, uint32_t s) {
     return (int)((s - (a.dstate ? a.dstate[1] : a.s_log0)) >> 1);
 }
 
+// One lane owns a strip of kRows words of one word column: it loads the strip,
+// the halo row below (dl) or above (ur) and the adjacent words that supply
+// the wrap-around bit, then updates the kRows words one after the other.  The
+// vertical neighbour of a row is the strip's next or previous row, already in
+// registers.
 template <bool OBS, bool FOLD3>
 __global__ __launch_bounds__(256) void k_torus_bp(const ChainDesc *__restrict__ descs, StepArgs sa) {
     const ChainDesc &d = descs[blockIdx.y];
     const uint32_t s = step_s(sa);
-    const int in_idx = (int)(s & 1u);
+    const int phase = (int)(s & 1u);
     const int slot = OBS ? step_slot(sa, s) : 0;
     const int L = d.L, W = d.W;
-    const int total = L * W;
+    const int nrb = (L + kRows - 1) / kRows;
+    const int total = nrb * W;
     const int bx = xcd_block(blockIdx.x, gridDim.x);
     const int gid = bx * blockDim.x + threadIdx.x;
-    const uint32_t *__restrict__ in = (const uint32_t *)d.spin[in_idx];
-    uint32_t *__restrict__ out = (uint32_t *)d.spin[in_idx ^ 1];
+    const uint32_t *__restrict__ in = (const uint32_t *)d.spin[phase];
+    uint32_t *__restrict__ out = (uint32_t *)d.spin[phase ^ 1];
+    const uint32_t k0 = (uint32_t)d.seed, k1 = (uint32_t)(d.seed >> 32);
     int e_acc = 0, p_acc = 0;
     if (gid < total) {
-        const int r = gid / W, wd = gid - r * W;
-        const uint32_t own = in[gid];
-        uint32_t a, b;
-        bp_neighbours(in, L, W, r, wd, (int)(s & 1u), own, a, b);
+        const int rb = gid / W, wd = gid - rb * W;
+        const int r0 = rb * kRows;
+        const int nr = min(kRows, L - r0);
         const uint32_t vm = bp_valid(L, W, wd);
-        out[gid] = bp_word<FOLD3>(a, b, own, vm, (uint32_t)gid, s, d.replica, (uint32_t)d.seed,
-                                  (uint32_t)(d.seed >> 32), d.tsmall, d.sgn);
-        if (OBS) {
-            const int nb = __popc(vm);
-            e_acc = d.J * (2 * nb - 2 * __popc((own ^ a) & vm) - 2 * __popc((own ^ b) & vm));
-            p_acc = __popc(own & vm);
+        const int lastbits = (L - 1) & 31;
+        // adjacent word supplying the carry bit: left word (dl) / right word (ur)
+        const int wside = phase == 0 ? (wd > 0 ? wd - 1 : W - 1) : (wd < W - 1 ? wd + 1 : 0);
+        uint32_t own[kRows], side[kRows];
+#pragma unroll
+        for (int i = 0; i < kRows; ++i) {
+            if (i < nr) {
+                own[i] = in[(r0 + i) * W + wd];
+                side[i] = in[(r0 + i) * W + wside];
+            } else {
+                own[i] = 0u;
+                side[i] = 0u;
+            }
+        }
+        const int rh = phase == 0 ? (r0 == 0 ? L - 1 : r0 - 1) : (r0 + nr == L ? 0 : r0 + nr);
+        const uint32_t halo = in[rh * W + wd];
+#pragma unroll
+        for (int i = 0; i < kRows; ++i) {
+            if (i < nr) {
+                uint32_t a, b;
+                if (phase == 0) {
+                    a = (i == 0) ? halo : own[i > 0 ? i - 1 : 0];
+                    const uint32_t carry = wd > 0 ? (side[i] >> 31) : ((side[i] >> lastbits) & 1u);
+                    b = (own[i] << 1) | carry;
+                } else {
+                    a = (i == nr - 1) ? halo : own[i < kRows - 1 ? i + 1 : 0];
+                    b = wd < W - 1 ? ((own[i] >> 1) | (side[i] << 31))
+                                   : ((own[i] >> 1) | ((side[i] & 1u) << lastbits));
+                }
+                const int widx = (r0 + i) * W + wd;
+                out[widx] = bp_word<FOLD3>(a, b, own[i], vm, (uint32_t)widx, s, d.replica, k0, k1,
+                                           d.tsmall, d.sgn);
+                if (OBS) {
+                    e_acc += d.J * (2 * __popc(vm) - 2 * __popc((own[i] ^ a) & vm) -
+                                    2 * __popc((own[i] ^ b) & vm));
+                    p_acc += __popc(own[i] & vm);
+                }
+            }
         }
     }
     if (OBS && bx * (int)blockDim.x < total)
-        block_accumulate2(e_acc, p_acc, d.log + (int64_t)slot * d.log_stride);
+        block_accumulate2(e_acc, p_acc, log_part(d, slot, bx));
 }
 
 // ------------------------------------------------------------- int8 torus
@@ -280,25 +324,29 @@ __global__ __launch_bounds__(256) void k_torus_i8(const ChainDesc *__restrict__ 
         }
     }
     if (OBS && blockIdx.x < (unsigned)((n + blockDim.x - 1) / blockDim.x))
-        block_accumulate2(e_acc, p_acc, d.log + (int64_t)slot * d.log_stride);
+        block_accumulate2(e_acc, p_acc, log_part(d, slot, blockIdx.x));
 }
 
 // ------------------------------------------------------------------ graph
 
 // Lane = 4 consecutive vertices = one Philox call.  S_v sums the CSR row of
-// the half (in-half for s even, out-half for s odd).
+// the half (in-half for s even, out-half for s odd).  The rows of the four
+// vertices are contiguous in the CSR arrays, so the lane walks them as one
+// edge range in chunks of 8 whose loads are all issued before any is used;
+// an edge is attributed to its vertex by comparing with the row bounds.
+constexpr int kEdgeChunk = 8;
+
 template <bool OBS>
 __global__ __launch_bounds__(256) void k_graph(const ChainDesc *__restrict__ descs, StepArgs sa) {
     const ChainDesc &d = descs[blockIdx.y];
     const uint32_t s = step_s(sa);
-    const int in_idx = (int)(s & 1u);
+    const int half = (int)(s & 1u);
     const int slot = OBS ? step_slot(sa, s) : 0;
     const int n = d.n;
-    const int half = (int)(s & 1u);
     const int q4 = blockIdx.x * blockDim.x + threadIdx.x;
     const int v0 = q4 * 4;
-    const int8_t *__restrict__ in = (const int8_t *)d.spin[in_idx];
-    int8_t *__restrict__ out = (int8_t *)d.spin[in_idx ^ 1];
+    const int8_t *__restrict__ in = (const int8_t *)d.spin[half];
+    int8_t *__restrict__ out = (int8_t *)d.spin[half ^ 1];
     const int32_t *__restrict__ rp = d.rowptr[half];
     const int32_t *__restrict__ col = d.col[half];
     const int8_t *__restrict__ jw = d.jw[half];
@@ -311,42 +359,80 @@ __global__ __launch_bounds__(256) void k_graph(const ChainDesc *__restrict__ des
         __syncthreads();
     }
     if (v0 < n) {
-        const U4 r = philox10((uint32_t)q4, s, d.replica, kGraphStream, (uint32_t)d.seed,
-                              (uint32_t)(d.seed >> 32));
-        const uint32_t u[4] = {r.x, r.y, r.z, r.w};
-        int8_t nv[4];
+        const bool full = v0 + 3 < n;
+        int rpv[5];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int v = v0 + j;
-            if (v < n) {
-                int S = 0;
-                const int e1 = rp[v + 1];
-                for (int e = rp[v]; e < e1; ++e) S += jw[e] * in[col[e]];
-                const int own = in[v];
-                const int cl = cls[v];
-                const uint64_t T = d.lut[((S + smax) * 2 + (own > 0)) * ncls + cl];
-                nv[j] = ((uint64_t)u[j] < T) ? 1 : -1;
-                if (OBS) {
-                    e_acc += own * S;
-                    if (own > 0) atomicAdd(&sh_plus[cl], 1);
-                }
+        for (int j = 0; j < 5; ++j) rpv[j] = rp[min(v0 + j, n)];
+        int own[4], cl[4];
+        if (full) {
+            const uint32_t o4 = *(const uint32_t *)(in + v0);
+            const uint32_t c4 = *(const uint32_t *)(cls + v0);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                own[j] = (int)(int8_t)(o4 >> (8 * j));
+                cl[j] = (int)((c4 >> (8 * j)) & 0xFFu);
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                own[j] = v0 + j < n ? in[v0 + j] : 1;
+                cl[j] = v0 + j < n ? cls[v0 + j] : 0;
             }
         }
-        if (v0 + 3 < n) {
-            const uint32_t packed = (uint32_t)(uint8_t)nv[0] | ((uint32_t)(uint8_t)nv[1] << 8) |
-                                    ((uint32_t)(uint8_t)nv[2] << 16) |
-                                    ((uint32_t)(uint8_t)nv[3] << 24);
+        const U4 r = philox10((uint32_t)q4, s, d.replica, kGraphStream, (uint32_t)d.seed,
+                              (uint32_t)(d.seed >> 32));
+        int S0 = 0, S1 = 0, S2 = 0, S3 = 0;
+        for (int base = rpv[0]; base < rpv[4]; base += kEdgeChunk) {
+            int cc[kEdgeChunk], jj[kEdgeChunk], sv[kEdgeChunk];
+#pragma unroll
+            for (int k = 0; k < kEdgeChunk; ++k) {
+                const int e = base + k;
+                cc[k] = e < rpv[4] ? col[e] : 0;
+                jj[k] = e < rpv[4] ? (int)jw[e] : 0;
+            }
+#pragma unroll
+            for (int k = 0; k < kEdgeChunk; ++k) sv[k] = (int)in[cc[k]];
+#pragma unroll
+            for (int k = 0; k < kEdgeChunk; ++k) {
+                const int e = base + k;
+                const int t = jj[k] * sv[k];
+                S0 += e < rpv[1] ? t : 0;
+                S1 += (e >= rpv[1] && e < rpv[2]) ? t : 0;
+                S2 += (e >= rpv[2] && e < rpv[3]) ? t : 0;
+                S3 += (e >= rpv[3]) ? t : 0;
+            }
+        }
+        const int Sv[4] = {S0, S1, S2, S3};
+        const uint32_t u[4] = {r.x, r.y, r.z, r.w};
+        uint32_t packed = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint64_t T = d.lut[((Sv[j] + smax) * 2 + (own[j] > 0)) * ncls + cl[j]];
+            const uint32_t nv = ((uint64_t)u[j] < T) ? 0x01u : 0xFFu;
+            packed |= nv << (8 * j);
+            if (OBS && v0 + j < n) {
+                e_acc += own[j] * Sv[j];
+                if (own[j] > 0) atomicAdd(&sh_plus[cl[j]], 1);
+            }
+        }
+        if (full) {
             *(uint32_t *)(out + v0) = packed;
         } else {
-            for (int j = 0; j < 4 && v0 + j < n; ++j) out[v0 + j] = nv[j];
+            for (int j = 0; j < 4 && v0 + j < n; ++j) out[v0 + j] = (int8_t)(packed >> (8 * j));
         }
     }
     if (OBS && blockIdx.x < (unsigned)((n + 4 * blockDim.x - 1) / (4 * blockDim.x))) {
-        int64_t *lg = d.log + (int64_t)slot * d.log_stride;
-        const int lane = threadIdx.x & 63;
+        int64_t *lg = log_part(d, slot, blockIdx.x);
+        __shared__ int sh_e[16];
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
         e_acc = wave_sum(e_acc);
-        if (lane == 0 && e_acc) atomicAdd((unsigned long long *)&lg[0], (unsigned long long)(long long)e_acc);
+        if (lane == 0) sh_e[wv] = e_acc;
         __syncthreads();
+        if (threadIdx.x == 0) {
+            long long se = 0;
+            for (int i = 0; i < (int)((blockDim.x + 63) >> 6); ++i) se += sh_e[i];
+            if (se) atomicAdd((unsigned long long *)&lg[0], (unsigned long long)se);
+        }
         for (int i = threadIdx.x; i < ncls; i += blockDim.x)
             if (sh_plus[i]) atomicAdd((unsigned long long *)&lg[1 + i], (unsigned long long)sh_plus[i]);
     }
@@ -357,7 +443,7 @@ __global__ __launch_bounds__(256) void k_graph(const ChainDesc *__restrict__ des
 __global__ __launch_bounds__(256) void k_observe(const ChainDesc *__restrict__ descs, int idx,
                                                  int slot) {
     const ChainDesc &d = descs[blockIdx.y];
-    int64_t *lg = d.log + (int64_t)slot * d.log_stride;
+    int64_t *lg = log_part(d, slot, blockIdx.x);
     const int gid = blockIdx.x * blockDim.x + threadIdx.x;
     int e_acc = 0, p_acc = 0;
     bool active_block;
@@ -463,7 +549,8 @@ hipError_t launch_init(const ChainDesc &d, void *dst, int mode, hipStream_t stre
 }
 
 static int units_of(const ChainDesc &d) {
-    if (d.kind == KIND_TORUS) return d.format == FMT_BITPACKED ? d.L * d.W : d.n;
+    if (d.kind == KIND_TORUS)
+        return d.format == FMT_BITPACKED ? ((d.L + kRows - 1) / kRows) * d.W : d.n;
     return (d.n + 3) / 4;
 }
 

@@ -9,6 +9,8 @@ namespace shaken {
 
 constexpr uint32_t kGraphStream = 0x80000000u;  // fourth counter word, graph uniforms
 constexpr uint32_t kInitStep = 0xFFFFFFFFu;     // half-step index of the random start
+constexpr int kLogParts = 8;   // partial accumulators per logged value (spread atomics)
+constexpr int kRows = 8;       // rows of one word column per lane (bit-packed torus)
 
 enum Kind : int32_t { KIND_TORUS = 0, KIND_GRAPH = 1 };
 enum Format : int32_t { FMT_INT8 = 1, FMT_BITPACKED = 2 };
@@ -40,9 +42,13 @@ struct ChainDesc {
     const uint8_t *cls;      // field class per vertex (never NULL on device)
     int32_t maxdeg;          // largest half-degree
     int32_t pad0;
-    // observables log: slot t holds [E_J, plus_0 .. plus_{ncls-1}] (int64)
+    // observables log: slot t is kLogParts lines of log_line int64; line p holds
+    // partial sums [E_J, plus_0 .. plus_{ncls-1}] (a block adds into line
+    // blockIdx % kLogParts, so that thousands of blocks do not queue on one
+    // address); the host adds the lines.
     int64_t *log;
-    int64_t log_stride;      // 1 + ncls
+    int64_t log_line;        // 1 + ncls rounded up to 16 (one 128-byte line)
+    int64_t log_stride;      // kLogParts * log_line
 };
 
 // ---------------------------------------------------------------- launchers
