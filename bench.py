@@ -35,11 +35,13 @@ HBM_PEAK_GBS = 8000.0
 
 # Algorithmic ALU work of one bit-packed site-update, in VALU lane-cycles
 # (derivation in the design doc): per 32-site word, E[G] = 1.999 Philox4x32-10
-# calls (per-word early exit of the MSB-first compare, groups of 4 levels),
-# 100 lane-cycles per call (20 quarter-rate 32x32->64 multiplies + 20
-# three-input xors), 4 E[G] compare levels x 6 lane-cycles, 17 lane-cycles of
-# neighbour, class and sign planes: (199.9 + 48.0 + 17) / 32.
-BP_ALU_PER_SITE = (1.999 * 100 + 4 * 1.999 * 6 + 17) / 32.0
+# calls (the MSB-first compare stops once all 32 sites of the word are
+# decided; levels come in groups of 4), 40 lane-cycles per call (20
+# v_mad_u64_u32 + 20 three-input xors, both full rate on gfx950), 4 E[G]
+# compare levels x 6 lane-cycles, 15 lane-cycles of neighbour, class and sign
+# planes per word: (80.0 + 48.0 + 15) / 32 = 4.47.
+PHILOX_LC = 40.0
+BP_ALU_PER_SITE = (1.999 * PHILOX_LC + 4 * 1.999 * 6 + 15) / 32.0
 BP_BYTES_PER_SITE = 0.25  # read 1 bit, write 1 bit
 
 

@@ -217,8 +217,8 @@ shaken_status shaken_synchronize(shaken_ctx *ctx);
  *   SHAKEN_BATCH_PERSISTENT: one launch per call; each workgroup takes whole
  *                            chains from a device queue (longest first) and
  *                            keeps their spins in LDS for all the steps.  Tori
- *                            need L <= 256 and graphs n <= 65536 with at most
- *                            32 neighbours per half.
+ *                            need the bit-packed format and L <= 256; graphs
+ *                            n <= 65536 and at most 16 field classes.
  *   SHAKEN_BATCH_AUTO:       persistent when every chain fits, else grid. */
 enum { SHAKEN_BATCH_AUTO = 0, SHAKEN_BATCH_GRID = 1, SHAKEN_BATCH_PERSISTENT = 2 };
 

@@ -1005,7 +1005,8 @@ shaken_status shaken_batch_create(shaken_batch **out, shaken_ctx *const *ctx, in
         int ncu = 256;
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, b->device) == hipSuccess) ncu = prop.multiProcessorCount;
-        b->pgrid = std::min(n, 4 * ncu);
+        // 16 KiB of LDS and 4 waves per workgroup: 8 workgroups fit on a CU
+        b->pgrid = std::min(n, 8 * ncu);
     }
     if ((st = batch_upload(b)) != SHAKEN_OK) return bail(st);
     *out = b;
@@ -1054,11 +1055,10 @@ shaken_status shaken_batch_sweep(shaken_batch *b, int64_t n_full) {
     const uint32_t s1 = s0 + (uint32_t)(2 * n_full);
     if (b->record) {
         // observables of the final configuration (spin[s1 & 1]) into slot n_full
+        // (the persistent kernel records the final slot itself)
         if (b->strategy == SHAKEN_BATCH_GRID) {
             for (auto &g : b->groups)
                 HIPCHK(launch_observe(g.dd, g.hd.data(), (int)g.hd.size(), (int)(s1 & 1u), (int)n_full, b->stream));
-        } else {
-            HIPCHK(launch_observe(b->pdescs, b->phd.data(), (int)b->phd.size(), (int)(s1 & 1u), (int)n_full, b->stream));
         }
     }
     HIPCHK(hipEventRecord(b->ev1, b->stream));

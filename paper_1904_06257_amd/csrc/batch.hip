@@ -1,13 +1,278 @@
-// Persistent batch kernel of libshaken (one workgroup per chain, spins in LDS).
-#include "shaken_internal.hpp"
+// Persistent batch kernel of libshaken (gfx950).
+//
+// Many independent shaken-dynamics chains (arXiv:1904.06257; each chain is the
+// paper's dynamics with its own graph, beta, q and seed) in one launch.  A
+// workgroup takes a whole chain from a device queue (longest first), copies
+// its configuration into LDS as bits, runs every half-step of the call with
+// workgroup barriers only, and writes the configuration back.  Both halves of
+// the double buffer live in LDS (2 x 2048 words = 16 KiB): tori up to
+// 256 x 256 and graphs up to 65536 vertices.  The randomness and thresholds
+// are those of the grid kernels, so a chain gives the same trajectory either
+// way.  Adjacency (CSR) and the threshold table stay in global memory.
+#include "device.hpp"
 
 namespace shaken {
 
-bool persistent_fits(const ChainDesc &) { return false; }
+constexpr int kPBlock = 256;
+constexpr int kPWords = 2048;
+constexpr int kPClasses = 16;
 
-hipError_t launch_persistent(const ChainDesc *, int, const int32_t *, int32_t *, uint32_t, int64_t,
-                             int, int, int, hipStream_t) {
-    return hipErrorNotSupported;
+bool persistent_fits(const ChainDesc &d) {
+    if (d.kind == KIND_TORUS) return d.format == FMT_BITPACKED && d.L * d.W <= kPWords;
+    return d.n <= 32 * kPWords && d.ncls <= kPClasses;
+}
+
+// Sum e and p over the workgroup; the totals are valid in thread 0.
+__device__ __forceinline__ void block_sum2(int &e, int &p, int *sh) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    e = wave_sum(e);
+    p = wave_sum(p);
+    if (lane == 0) {
+        sh[2 * wv] = e;
+        sh[2 * wv + 1] = p;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < kPBlock / 64; ++i) {
+            e += sh[2 * i];
+            p += sh[2 * i + 1];
+        }
+    }
+    __syncthreads();
+}
+
+// ------------------------------------------------------------------- torus
+
+// One half-step (or, with dst == nullptr, only the observables of src) of an
+// L x L bit-packed torus held in LDS.
+template <bool FOLD3>
+__device__ void torus_lds_half(const ChainDesc &d, const uint32_t *src, uint32_t *dst, uint32_t s,
+                               bool obs, int *sh_red, int64_t *log_slot) {
+    const int L = d.L, W = d.W, nw = L * W;
+    const int phase = (int)(s & 1u);
+    const uint32_t k0 = (uint32_t)d.seed, k1 = (uint32_t)(d.seed >> 32);
+    int e_acc = 0, p_acc = 0;
+    for (int w = threadIdx.x; w < nw; w += kPBlock) {
+        const int r = w / W, wd = w - r * W;
+        const uint32_t own = src[w];
+        const uint32_t vm = bp_valid(L, W, wd);
+        uint32_t a, b;
+        if (obs || phase == 0) {
+            // down and left neighbours (the in-half)
+            const int lastbits = (L - 1) & 31;
+            a = src[(r == 0 ? L - 1 : r - 1) * W + wd];
+            const uint32_t carry = wd > 0 ? (src[r * W + wd - 1] >> 31)
+                                          : ((src[r * W + W - 1] >> lastbits) & 1u);
+            b = (own << 1) | carry;
+            if (obs) {
+                e_acc += d.J * (2 * __popc(vm) - 2 * __popc((own ^ a) & vm) - 2 * __popc((own ^ b) & vm));
+                p_acc += __popc(own & vm);
+            }
+        }
+        if (!dst) continue;
+        if (phase == 1) {
+            const int lastbits = (L - 1) & 31;
+            a = src[(r == L - 1 ? 0 : r + 1) * W + wd];
+            b = wd < W - 1 ? ((own >> 1) | (src[r * W + wd + 1] << 31))
+                           : ((own >> 1) | ((src[r * W] & 1u) << lastbits));
+        }
+        dst[w] = bp_word<FOLD3>(a, b, own, vm, (uint32_t)w, s, d.replica, k0, k1, d.tsmall, d.sgn);
+    }
+    if (obs) {
+        block_sum2(e_acc, p_acc, sh_red);
+        if (threadIdx.x == 0) {
+            log_slot[0] = e_acc;
+            log_slot[1] = p_acc;
+        }
+    }
+}
+
+template <bool FOLD3>
+__device__ void run_torus(const ChainDesc &d, uint32_t (*buf)[kPWords], uint32_t s0, int64_t n_full,
+                          int record, int *sh_red) {
+    const int nw = d.L * d.W;
+    const uint32_t *g = (const uint32_t *)d.spin[0];
+    for (int w = threadIdx.x; w < nw; w += kPBlock) buf[0][w] = g[w];
+    __syncthreads();
+    for (int64_t t = 0; t < n_full; ++t) {
+        const uint32_t s = s0 + 2u * (uint32_t)t;
+        int64_t *lg = record ? d.log + t * d.log_stride : nullptr;
+        torus_lds_half<FOLD3>(d, buf[0], buf[1], s, record != 0, sh_red, lg);
+        __syncthreads();
+        torus_lds_half<FOLD3>(d, buf[1], buf[0], s + 1u, false, sh_red, nullptr);
+        __syncthreads();
+    }
+    if (record) {
+        torus_lds_half<FOLD3>(d, buf[0], nullptr, s0, true, sh_red, d.log + n_full * d.log_stride);
+        __syncthreads();
+    }
+    uint32_t *go = (uint32_t *)d.spin[0];
+    for (int w = threadIdx.x; w < nw; w += kPBlock) go[w] = buf[0][w];
+}
+
+// ------------------------------------------------------------------- graph
+
+__device__ __forceinline__ int lds_spin(const uint32_t *bits, int v) {
+    return ((bits[v >> 5] >> (v & 31)) & 1u) ? 1 : -1;
+}
+
+// One half-step (or, with dst == nullptr, only the observables of src) of a
+// graph whose spins are bits in LDS.  A lane takes 4 consecutive vertices (one
+// Philox call); 8 consecutive lanes own one 32-vertex output word and merge
+// their 4-bit pieces with lane shuffles.
+__device__ void graph_lds_half(const ChainDesc &d, const uint32_t *src, uint32_t *dst, uint32_t s,
+                               bool obs, int *sh_red, int *sh_plus, int64_t *log_slot) {
+    const int n = d.n;
+    const int half = dst ? (int)(s & 1u) : 0;  // observables use the in-half
+    const int32_t *__restrict__ rp = d.rowptr[half];
+    const int32_t *__restrict__ col = d.col[half];
+    const int8_t *__restrict__ jw = d.jw[half];
+    const int ncls = d.ncls, smax = d.smax;
+    const uint32_t k0 = (uint32_t)d.seed, k1 = (uint32_t)(d.seed >> 32);
+    const int nq = (n + 3) / 4;
+    const int nq_pad = (nq + kPBlock - 1) / kPBlock * kPBlock;
+    if (obs) {
+        if (threadIdx.x < kPClasses) sh_plus[threadIdx.x] = 0;
+        __syncthreads();
+    }
+    int e_acc = 0;
+    for (int q4 = threadIdx.x; q4 < nq_pad; q4 += kPBlock) {
+        uint32_t bits = 0;
+        if (q4 < nq) {
+            const int v0 = 4 * q4;
+            int rpv[5];
+#pragma unroll
+            for (int j = 0; j < 5; ++j) rpv[j] = rp[min(v0 + j, n)];
+            int S0 = 0, S1 = 0, S2 = 0, S3 = 0;
+            for (int base = rpv[0]; base < rpv[4]; base += 8) {
+                int cc[8], jj[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const int e = base + k;
+                    cc[k] = e < rpv[4] ? col[e] : 0;
+                    jj[k] = e < rpv[4] ? (int)jw[e] : 0;
+                }
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const int e = base + k;
+                    const int t = jj[k] * lds_spin(src, cc[k]);
+                    S0 += e < rpv[1] ? t : 0;
+                    S1 += (e >= rpv[1] && e < rpv[2]) ? t : 0;
+                    S2 += (e >= rpv[2] && e < rpv[3]) ? t : 0;
+                    S3 += (e >= rpv[3]) ? t : 0;
+                }
+            }
+            const int Sv[4] = {S0, S1, S2, S3};
+            if (dst) {
+                const U4 r = philox10((uint32_t)q4, s, d.replica, kGraphStream, k0, k1);
+                const uint32_t u[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    if (v0 + j < n) {
+                        const int own = lds_spin(src, v0 + j);
+                        const uint64_t T = d.lut[((Sv[j] + smax) * 2 + (own > 0)) * ncls + d.cls[v0 + j]];
+                        if ((uint64_t)u[j] < T) bits |= 1u << j;
+                    }
+                }
+            }
+            if (obs) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    if (v0 + j < n) {
+                        const int own = lds_spin(src, v0 + j);
+                        e_acc += own * Sv[j];
+                        if (own > 0) atomicAdd(&sh_plus[d.cls[v0 + j]], 1);
+                    }
+                }
+            }
+        }
+        if (dst) {
+            uint32_t val = bits << (4 * (q4 & 7));
+            val |= __shfl_xor(val, 1, 64);
+            val |= __shfl_xor(val, 2, 64);
+            val |= __shfl_xor(val, 4, 64);
+            if ((q4 & 7) == 0 && q4 < nq) dst[q4 >> 3] = val;
+        }
+    }
+    if (obs) {
+        int dummy = 0;
+        block_sum2(e_acc, dummy, sh_red);
+        if (threadIdx.x == 0) log_slot[0] = e_acc;
+        if (threadIdx.x < ncls) log_slot[1 + threadIdx.x] = sh_plus[threadIdx.x];
+    }
+}
+
+__device__ void run_graph(const ChainDesc &d, uint32_t (*buf)[kPWords], uint32_t s0, int64_t n_full,
+                          int record, int *sh_red, int *sh_plus) {
+    const int n = d.n, nw = (n + 31) / 32;
+    const int8_t *g = (const int8_t *)d.spin[0];
+    for (int w = threadIdx.x; w < nw; w += kPBlock) {
+        uint32_t word = 0;
+        for (int b = 0; b < 32; ++b) {
+            const int v = 32 * w + b;
+            if (v < n && g[v] > 0) word |= 1u << b;
+        }
+        buf[0][w] = word;
+    }
+    __syncthreads();
+    for (int64_t t = 0; t < n_full; ++t) {
+        const uint32_t s = s0 + 2u * (uint32_t)t;
+        int64_t *lg = record ? d.log + t * d.log_stride : nullptr;
+        graph_lds_half(d, buf[0], buf[1], s, record != 0, sh_red, sh_plus, lg);
+        __syncthreads();
+        graph_lds_half(d, buf[1], buf[0], s + 1u, false, sh_red, sh_plus, nullptr);
+        __syncthreads();
+    }
+    if (record) {
+        graph_lds_half(d, buf[0], nullptr, s0, true, sh_red, sh_plus, d.log + n_full * d.log_stride);
+        __syncthreads();
+    }
+    int8_t *go = (int8_t *)d.spin[0];
+    for (int v = threadIdx.x; v < n; v += kPBlock) go[v] = (int8_t)lds_spin(buf[0], v);
+}
+
+// ------------------------------------------------------------------ kernel
+
+__global__ __launch_bounds__(kPBlock) void k_persistent(const ChainDesc *__restrict__ descs,
+                                                        int nchains,
+                                                        const int32_t *__restrict__ order,
+                                                        int32_t *counter, uint32_t s0,
+                                                        int64_t n_full, int record) {
+    __shared__ uint32_t buf[2][kPWords];
+    __shared__ int sh_item;
+    __shared__ int sh_red[2 * (kPBlock / 64)];
+    __shared__ int sh_plus[kPClasses];
+    for (;;) {
+        if (threadIdx.x == 0) {
+            const int k = atomicAdd(counter, 1);
+            sh_item = k < nchains ? order[k] : -1;
+        }
+        __syncthreads();
+        const int item = __builtin_amdgcn_readfirstlane(sh_item);
+        __syncthreads();
+        if (item < 0) break;  // queue drained: every wave of the block leaves
+        const ChainDesc &d = descs[item];
+        if (d.kind == KIND_TORUS) {
+            if (d.fold3)
+                run_torus<true>(d, buf, s0, n_full, record, sh_red);
+            else
+                run_torus<false>(d, buf, s0, n_full, record, sh_red);
+        } else {
+            run_graph(d, buf, s0, n_full, record, sh_red, sh_plus);
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_persistent(const ChainDesc *dev_descs, int nchains, const int32_t *order,
+                             int32_t *counter, uint32_t s0, int64_t n_full, int record, int block,
+                             int grid, hipStream_t stream) {
+    (void)block;
+    if (nchains <= 0) return hipSuccess;
+    const int g = grid > 0 ? grid : nchains;
+    hipLaunchKernelGGL(k_persistent, dim3(g), dim3(kPBlock), 0, stream, dev_descs, nchains, order,
+                       counter, s0, n_full, record);
+    return hipGetLastError();
 }
 
 }  // namespace shaken

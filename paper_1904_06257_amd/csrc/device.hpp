@@ -1,0 +1,145 @@
+// Device helpers shared by the HIP kernels of libshaken (gfx950): Philox,
+// bit-plane helpers, reductions and the 32-site bit-packed update.
+#pragma once
+
+#include "shaken_internal.hpp"
+
+namespace shaken {
+
+// ------------------------------------------------------------------ Philox
+
+struct U4 {
+    uint32_t x, y, z, w;
+};
+
+// Philox4x32 with ten rounds (Salmon et al., SC'11).  The three-input xors
+// are single v_bitop3_b32 instructions (truth table 0x96).
+__device__ __forceinline__ U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                       uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int i = 0; i < 10; ++i) {
+        const uint64_t a = (uint64_t)c0 * 0xD2511F53u;
+        const uint64_t b = (uint64_t)c2 * 0xCD9E8D57u;
+        const uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(b >> 32), c1, k0, 0x96);
+        const uint32_t n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(a >> 32), c3, k1, 0x96);
+        c1 = (uint32_t)b;
+        c3 = (uint32_t)a;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return U4{c0, c1, c2, c3};
+}
+
+__device__ __forceinline__ uint32_t bfi(uint32_t m, uint32_t x, uint32_t y) {
+    return (m & x) | (~m & y);
+}
+
+// all-ones if bit `sh` of v is set, else zero
+__device__ __forceinline__ uint32_t bitmask(uint32_t v, int sh) {
+    return 0u - ((v >> sh) & 1u);
+}
+
+// ------------------------------------------------------------ reductions
+
+__device__ __forceinline__ int wave_sum(int v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// line of log slot `slot` that block `blk` adds into
+__device__ __forceinline__ int64_t *log_part(const ChainDesc &d, int slot, int blk) {
+    return d.log + (int64_t)slot * d.log_stride + (int64_t)(blk & (kLogParts - 1)) * d.log_line;
+}
+
+// block-level sum of two ints into log[0] and log[1] (one atomic per block)
+__device__ __forceinline__ void block_accumulate2(int e, int p, int64_t *log) {
+    __shared__ int sh_e[16], sh_p[16];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    e = wave_sum(e);
+    p = wave_sum(p);
+    if (lane == 0) {
+        sh_e[wv] = e;
+        sh_p[wv] = p;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long se = 0, sp = 0;
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int i = 0; i < nw; ++i) {
+            se += sh_e[i];
+            sp += sh_p[i];
+        }
+        if (se) atomicAdd((unsigned long long *)&log[0], (unsigned long long)se);
+        if (sp) atomicAdd((unsigned long long *)&log[1], (unsigned long long)sp);
+    }
+}
+
+// XCD-aware block order: the hardware deals consecutive workgroups round-robin
+// over the 8 XCDs; give each XCD a contiguous run of tiles so that rows shared
+// as halos stay in one L2.
+__device__ __forceinline__ int xcd_block(int bx, int nb) {
+    if ((nb & 7) != 0) return bx;
+    return (bx & 7) * (nb >> 3) + (bx >> 3);
+}
+
+// ------------------------------------------------------ bit-packed torus
+
+// New word of 32 sites.  a, b: bit-planes of the two neighbours of the half,
+// c: the sites themselves, vm: valid bits, w: RNG word, s: half-step index.
+template <bool FOLD3>
+__device__ __forceinline__ uint32_t bp_word(uint32_t a, uint32_t b, uint32_t c, uint32_t vm,
+                                            uint32_t w, uint32_t s, uint32_t rep, uint32_t k0,
+                                            uint32_t k1, const uint32_t *__restrict__ ts,
+                                            uint32_t sgn) {
+    const uint32_t both = a & b;   // n_plus = 2
+    const uint32_t one = a ^ b;    // n_plus = 1
+    // sign of h per site (class j = n_plus + 3 c)
+    const uint32_t slo = bfi(both, bitmask(sgn, 2), bfi(one, bitmask(sgn, 1), bitmask(sgn, 0)));
+    const uint32_t shi = bfi(both, bitmask(sgn, 5), bfi(one, bitmask(sgn, 4), bitmask(sgn, 3)));
+    const uint32_t smask = bfi(c, shi, slo);
+    // sign-folded classes: aligned (0,0)/(2,1), anti (2,0)/(0,1), one (1,*)
+    const uint32_t al = ~(a ^ c) & ~one;
+    const uint32_t t0 = ts[0], t1 = ts[1], t2 = ts[2], t3 = ts[3], t4 = ts[4], t5 = ts[5];
+    uint32_t und = vm, res = 0;
+
+#define SHAKEN_LEVEL(K, R)                                                                  \
+    {                                                                                       \
+        const int sh_ = 31 - (K);                                                           \
+        uint32_t t_;                                                                        \
+        if (FOLD3) {                                                                        \
+            t_ = bfi(one, bitmask(t1, sh_), bfi(al, bitmask(t5, sh_), bitmask(t2, sh_)));   \
+        } else {                                                                            \
+            const uint32_t lo_ = bfi(both, bitmask(t2, sh_),                                \
+                                     bfi(one, bitmask(t1, sh_), bitmask(t0, sh_)));         \
+            const uint32_t hi_ = bfi(both, bitmask(t5, sh_),                                \
+                                     bfi(one, bitmask(t4, sh_), bitmask(t3, sh_)));         \
+            t_ = bfi(c, hi_, lo_);                                                          \
+        }                                                                                   \
+        const uint32_t d_ = (R) ^ smask ^ t_;                                               \
+        res |= und & d_ & t_;                                                               \
+        und &= ~d_;                                                                         \
+    }
+
+#pragma unroll
+    for (int g = 0; g < 8; ++g) {
+        const U4 r = philox10(w, s, rep, (uint32_t)g, k0, k1);
+        SHAKEN_LEVEL(4 * g + 0, r.x)
+        SHAKEN_LEVEL(4 * g + 1, r.y)
+        SHAKEN_LEVEL(4 * g + 2, r.z)
+        SHAKEN_LEVEL(4 * g + 3, r.w)
+        if (und == 0) break;
+    }
+#undef SHAKEN_LEVEL
+    // res: v < t with v = u ^ sign; the new spin is that bit flipped where h >= 0
+    return (res ^ smask) & vm;
+}
+
+__device__ __forceinline__ uint32_t bp_valid(int L, int W, int wd) {
+    const int rem = L & 31;
+    return (wd == W - 1 && rem) ? ((1u << rem) - 1u) : 0xFFFFFFFFu;
+}
+
+}  // namespace shaken

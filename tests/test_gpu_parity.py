@@ -301,3 +301,75 @@ def test_batch_rejects_mismatched_counters(sk):
     c.half_step(2)
     with pytest.raises(sk.ShakenError):
         sk.Batch([a, c], strategy="grid")
+
+
+def _mixed_specs(T, torus_sizes, graph_sizes, seed0=0):
+    specs = []
+    for i, L in enumerate(torus_sizes):
+        q, b, seed = 0.5 + 0.25 * i, 0.25 + 0.15 * i, 5000 + i + seed0
+        lam = 0.0 if i % 2 == 0 else 0.2
+        init = oracle.torus_init_random(L, seed, i)
+        want, ej, mm = oracle.torus_run(init, 1, lam, q, b, seed, i, T)
+        specs.append(dict(kind="torus", L=L, q=q, beta=b, seed=seed, rep=i, lam=lam,
+                          want=want, H=(-ej - (2 * lam * mm).round().astype(np.int64)) if lam == 0 else None,
+                          M=mm, EJ=ej))
+    for i, n in enumerate(graph_sizes):
+        inst, g = _graph_case(n, 900 + i + seed0)
+        seed = 7000 + i + seed0
+        sp0 = oracle.graph_init_random(n, seed, 40 + i)
+        want, ej, plus = oracle.graph_run(g, sp0, 1.1 + 0.3 * i, 0.5 + 0.2 * i, seed, 40 + i, T)
+        ncls = np.bincount(inst.cls, minlength=3)
+        specs.append(dict(kind="graph", inst=inst, n=n, q=1.1 + 0.3 * i, beta=0.5 + 0.2 * i,
+                          seed=seed, rep=40 + i, want=want, H=_h_from_plus(inst, ej, plus),
+                          M=(2 * plus - ncls[None, :]).sum(axis=1), EJ=ej))
+    return specs
+
+
+def _make(sk, sp):
+    if sp["kind"] == "torus":
+        return sk.Chain.torus(sp["L"], q=sp["q"], beta=sp["beta"], seed=sp["seed"], replica=sp["rep"],
+                              lam_values=[sp["lam"]])
+    inst = sp["inst"]
+    return sk.Chain.graph(sp["n"], inst.src, inst.dst, J=inst.J, lam_values=inst.lam_values,
+                          lam_class=inst.cls, q=sp["q"], beta=sp["beta"], seed=sp["seed"],
+                          replica=sp["rep"])
+
+
+def test_batch_persistent_mixed(sk):
+    """Persistent strategy: tori (ragged and full 256) and graphs (ragged, up to
+    65536 vertices), spins in LDS for all steps; every chain bit-exact, logs
+    included, and the same as the grid strategy."""
+    T = 30
+    _print_case("persistent mixed")
+    specs = _mixed_specs(T, [16, 48, 100, 256], [1024, 2050, 65536])
+    chains = [_make(sk, sp) for sp in specs]
+    b = sk.Batch(chains, strategy="auto", record=True)
+    st, _ = b.info()
+    assert st == sk.SHAKEN_BATCH_PERSISTENT
+    b.sweep(T)
+    for i, sp in enumerate(specs):
+        assert np.array_equal(chains[i].spins().reshape(sp["want"].shape), sp["want"]), i
+        h, m = b.log(i, with_H=sp["H"] is not None)
+        assert np.array_equal(m, sp["M"]), i
+        if sp["H"] is not None:
+            assert np.array_equal(h, sp["H"]), i
+        assert chains[i].observables().E_J == sp["EJ"][-1]
+    # the chains continue on their own from where the batch left them
+    sp = specs[0]
+    x, _, _ = oracle.torus_run(sp["want"], 1, sp["lam"], sp["q"], sp["beta"], sp["seed"], sp["rep"], 3, s0=2 * T)
+    chains[0].sweep(3)
+    assert np.array_equal(chains[0].spins(), x)
+
+
+def test_batch_persistent_equals_grid(sk):
+    T = 12
+    specs = _mixed_specs(T, [32, 80], [4096], seed0=3)
+    a = [_make(sk, sp) for sp in specs]
+    c = [_make(sk, sp) for sp in specs]
+    ba = sk.Batch(a, strategy="persistent")
+    bc = sk.Batch(c, strategy="grid", use_hipgraph=True)
+    ba.sweep(T)
+    bc.sweep(T)
+    for x, y, sp in zip(a, c, specs):
+        assert np.array_equal(x.spins(), y.spins())
+        assert np.array_equal(x.spins().reshape(sp["want"].shape), sp["want"])
