@@ -229,6 +229,12 @@ typedef struct shaken_batch_opts {
                               on the first call and keep the fastest         */
     int32_t record;        /* log H and M of every chain at every full step  */
     void *stream;          /* hipStream_t; NULL = the first chain's stream   */
+    int32_t track;         /* persistent strategy: keep, per chain, H of the
+                              last configuration and the lowest H (with its
+                              configuration) over the full-step
+                              configurations of each sweep call; needs every
+                              2*lambda to be an integer                      */
+    int32_t reserved;
 } shaken_batch_opts;
 
 typedef struct shaken_batch shaken_batch;
@@ -251,6 +257,23 @@ shaken_status shaken_batch_sweep(shaken_batch *b, int64_t n_full);
 shaken_status shaken_batch_get_log(shaken_batch *b, int32_t i, int64_t *H_out, int64_t *M_out,
                                    int64_t cap);
 
+/* Set beta[i] and q[i] (host arrays, one per chain) for the following sweeps
+ * of the batch: the thresholds are rebuilt on the host in double exactly as
+ * shaken_set_params does and uploaded.  This is how an annealing schedule
+ * (beta_t, q_t) drives the chains (section 6, Theorem 6.1: alternate dynamics
+ * as a minimiser).  Synchronises the batch stream.  SHAKEN_EINVAL on a
+ * negative or non-finite value. */
+shaken_status shaken_batch_set_params(shaken_batch *b, const double *beta, const double *q);
+
+/* After a sweep with opts.track: H_last[i] = H of chain i's configuration at
+ * the end of the call, H_best[i] = the lowest H over its full-step
+ * configurations of the call (the one it started from included).  best_spins
+ * (optional, host int8) receives, concatenated over the chains in batch
+ * order, the configuration that reached H_best (n or L*L entries each).
+ * Synchronises. */
+shaken_status shaken_batch_get_track(shaken_batch *b, int64_t *H_last, int64_t *H_best,
+                                     int8_t *best_spins);
+
 /* Strategy the batch uses (after AUTO and autotuning), and the last call's
  * device time in milliseconds measured with HIP events on the batch stream
  * (synchronises). */
@@ -263,6 +286,63 @@ shaken_status shaken_batch_free(shaken_batch *b);
  * free the batch.  Synchronises. */
 shaken_status shaken_batch_run(shaken_ctx *const *ctx, int32_t n, int64_t n_full,
                                const shaken_batch_opts *opts, int64_t *H_final);
+
+/* ------------------------------------------------- annealing schedule network
+ *
+ * A small multilayer perceptron that maps per-chain features (size, degree
+ * statistics, elapsed fraction of the schedule, current and best energy
+ * density, previous beta and q) to the next (log beta, log q) of an annealing
+ * schedule for the minimisation use of the dynamics (section 6).  The network
+ * is not part of the paper; it only chooses parameters, the sampler's
+ * arithmetic is unchanged.
+ *
+ * Shape: 16 inputs (features padded with zeros) -> 128 -> 128 -> 128 -> 16
+ * outputs (the first 2 are used), ReLU after each hidden layer.  Parameters
+ * are FP32 masters; every product uses their BF16 (round to nearest even)
+ * copies and BF16 activations, accumulated in FP32 on the matrix cores.
+ * Parameter vector layout (FP32, SHAKEN_MLP_NPARAM entries): W1[128][16],
+ * b1[128], W2[128][128], b2[128], W3[128][128], b3[128], W4[16][128], b4[16]
+ * (row-major, W[out][in]); rows 2..15 of W4 and b4[2..15] are kept at zero.
+ */
+#define SHAKEN_MLP_IN 16
+#define SHAKEN_MLP_HIDDEN 128
+#define SHAKEN_MLP_OUT 16
+#define SHAKEN_MLP_NPARAM (128 * 16 + 128 + 2 * (128 * 128 + 128) + 16 * 128 + 16)
+
+typedef struct shaken_mlp shaken_mlp;
+
+/* Allocate a network (parameters zero) on `device` (-1 = current) with work
+ * enqueued on `stream` (hipStream_t, NULL = null stream). */
+shaken_status shaken_mlp_create(shaken_mlp **out, int32_t device, void *stream);
+shaken_status shaken_mlp_free(shaken_mlp *m);
+
+/* Copy the FP32 parameter vector from / to the host (n = SHAKEN_MLP_NPARAM).
+ * Setting also refreshes the BF16 copies and zeroes the Adam moments. */
+shaken_status shaken_mlp_set_params(shaken_mlp *m, const float *host, size_t n);
+shaken_status shaken_mlp_get_params(shaken_mlp *m, float *host, size_t n);
+
+/* y[batch][16] = f(x[batch][16]); x and y are device FP32 row-major.  Keeps
+ * the activations for shaken_mlp_backward.  batch >= 1. */
+shaken_status shaken_mlp_forward(shaken_mlp *m, const float *x_dev, int32_t batch, float *y_dev);
+
+/* Gradient of sum_rows w_r * sum_{c<2} (y[r][c] - target[r][c])^2 / sum_r w_r
+ * at the last forward: writes the loss to *loss_host (synchronises) and the
+ * parameter gradient into the network's FP32 gradient buffer.  target and w
+ * are device FP32 ([batch][16] and [batch]; w may be NULL = all ones). */
+shaken_status shaken_mlp_loss_backward(shaken_mlp *m, const float *target_dev, const float *w_dev,
+                                       int32_t batch, float *loss_host);
+
+/* Backward pass for an arbitrary output gradient dy[batch][16] (device FP32)
+ * of the last forward; fills the FP32 gradient buffer. */
+shaken_status shaken_mlp_backward(shaken_mlp *m, const float *dy_dev, int32_t batch);
+
+/* Copy the gradient buffer to the host (n = SHAKEN_MLP_NPARAM). */
+shaken_status shaken_mlp_get_grads(shaken_mlp *m, float *host, size_t n);
+
+/* One Adam step on the FP32 masters from the gradient buffer (step t >= 1 for
+ * the bias corrections), then refresh the BF16 copies. */
+shaken_status shaken_mlp_adam(shaken_mlp *m, float lr, float beta1, float beta2, float eps,
+                              int32_t t);
 
 /* -------------------------------------------------------------- diagnostics */
 

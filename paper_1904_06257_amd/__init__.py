@@ -66,7 +66,8 @@ class shaken_obs(ctypes.Structure):
 class shaken_batch_opts(ctypes.Structure):
     _fields_ = [("strategy", ctypes.c_int32), ("use_hipgraph", ctypes.c_int32),
                 ("autotune", ctypes.c_int32), ("record", ctypes.c_int32),
-                ("stream", ctypes.c_void_p)]
+                ("stream", ctypes.c_void_p), ("track", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 _vp = ctypes.c_void_p
@@ -97,6 +98,18 @@ _SIGS = {
     "shaken_batch_free": [_vp],
     "shaken_batch_run": [ctypes.POINTER(_vp), ctypes.c_int32, ctypes.c_int64,
                          ctypes.POINTER(shaken_batch_opts), _i64p],
+    "shaken_batch_set_params": [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
+    "shaken_batch_get_track": [_vp, _i64p, _i64p, _i8p],
+    "shaken_mlp_create": [ctypes.POINTER(_vp), ctypes.c_int32, _vp],
+    "shaken_mlp_free": [_vp],
+    "shaken_mlp_set_params": [_vp, ctypes.POINTER(ctypes.c_float), ctypes.c_size_t],
+    "shaken_mlp_get_params": [_vp, ctypes.POINTER(ctypes.c_float), ctypes.c_size_t],
+    "shaken_mlp_forward": [_vp, _vp, ctypes.c_int32, _vp],
+    "shaken_mlp_loss_backward": [_vp, _vp, _vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_float)],
+    "shaken_mlp_backward": [_vp, _vp, ctypes.c_int32],
+    "shaken_mlp_get_grads": [_vp, ctypes.POINTER(ctypes.c_float), ctypes.c_size_t],
+    "shaken_mlp_adam": [_vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                        ctypes.c_int32],
 }
 for _name, _args in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -311,10 +324,10 @@ class Batch:
     """A batch of chains advanced by fused launches (libshaken batch)."""
 
     def __init__(self, chains, strategy="auto", use_hipgraph=False, autotune=False,
-                 record=False, stream=None):
+                 record=False, stream=None, track=False):
         self.chains = list(chains)
         o = shaken_batch_opts(_STRAT[strategy], int(use_hipgraph), int(autotune), int(record),
-                              _stream_handle(stream))
+                              _stream_handle(stream), int(track), 0)
         arr = (_vp * len(self.chains))(*[c.handle.value for c in self.chains])
         h = _vp()
         _check(_lib.shaken_batch_create(ctypes.byref(h), arr, len(self.chains), ctypes.byref(o)))
@@ -334,6 +347,24 @@ class Batch:
                                          _ptr(M, ctypes.c_int64), n))
         return H, M
 
+    def set_params(self, beta, q):
+        b = np.ascontiguousarray(beta, dtype=np.float64)
+        qq = np.ascontiguousarray(q, dtype=np.float64)
+        if b.shape[0] != len(self.chains) or qq.shape[0] != len(self.chains):
+            raise ValueError("one beta and one q per chain")
+        _check(_lib.shaken_batch_set_params(self.handle, _ptr(b, ctypes.c_double),
+                                            _ptr(qq, ctypes.c_double)))
+
+    def track(self, best_spins=False):
+        """(H_last, H_best[, best configurations concatenated]) of the last sweep"""
+        n = len(self.chains)
+        hl = np.zeros(n, dtype=np.int64)
+        hb = np.zeros(n, dtype=np.int64)
+        sp = np.zeros(sum(c.n for c in self.chains), dtype=np.int8) if best_spins else None
+        _check(_lib.shaken_batch_get_track(self.handle, _ptr(hl, ctypes.c_int64),
+                                           _ptr(hb, ctypes.c_int64), _ptr(sp, ctypes.c_int8)))
+        return (hl, hb, sp) if best_spins else (hl, hb)
+
     def info(self):
         st = ctypes.c_int32()
         ms = ctypes.c_double()
@@ -350,3 +381,68 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------- schedule network
+
+MLP_IN, MLP_HIDDEN, MLP_OUT = 16, 128, 16
+MLP_NPARAM = 128 * 16 + 128 + 2 * (128 * 128 + 128) + 16 * 128 + 16
+
+
+def _dptr(t):
+    """device pointer of a torch tensor (contiguous float32 on the GPU)"""
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous device tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class MLP:
+    """The annealing-schedule network (libshaken's BF16/FP32 MFMA kernels)."""
+
+    def __init__(self, device=-1, stream=None):
+        h = _vp()
+        _check(_lib.shaken_mlp_create(ctypes.byref(h), int(device), _stream_handle(stream)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            _check(_lib.shaken_mlp_free(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, p):
+        a = np.ascontiguousarray(p, dtype=np.float32)
+        _check(_lib.shaken_mlp_set_params(self.handle, _ptr(a, ctypes.c_float), a.shape[0]))
+
+    def params(self):
+        a = np.zeros(MLP_NPARAM, dtype=np.float32)
+        _check(_lib.shaken_mlp_get_params(self.handle, _ptr(a, ctypes.c_float), MLP_NPARAM))
+        return a
+
+    def grads(self):
+        a = np.zeros(MLP_NPARAM, dtype=np.float32)
+        _check(_lib.shaken_mlp_get_grads(self.handle, _ptr(a, ctypes.c_float), MLP_NPARAM))
+        return a
+
+    def forward(self, x, y):
+        """x, y: torch float32 device tensors [batch, 16]"""
+        _check(_lib.shaken_mlp_forward(self.handle, _dptr(x), x.shape[0], _dptr(y)))
+
+    def loss_backward(self, target, w=None):
+        loss = ctypes.c_float()
+        _check(_lib.shaken_mlp_loss_backward(self.handle, _dptr(target),
+                                             None if w is None else _dptr(w), target.shape[0],
+                                             ctypes.byref(loss)))
+        return float(loss.value)
+
+    def backward(self, dy):
+        _check(_lib.shaken_mlp_backward(self.handle, _dptr(dy), dy.shape[0]))
+
+    def adam(self, lr, t, beta1=0.9, beta2=0.999, eps=1e-8):
+        _check(_lib.shaken_mlp_adam(self.handle, float(lr), float(beta1), float(beta2),
+                                    float(eps), int(t)))

@@ -1,0 +1,203 @@
+"""Annealing schedules for the minimisation use of shaken dynamics.
+
+Section 6 of the paper (Theorem 6.1) uses the alternate dynamics as a parallel
+minimiser of H: at low temperature the pair law concentrates on the pair
+minimisers, which lie on the diagonal when q exceeds every half-neighbourhood
+coupling sum.  Here a schedule lowers the temperature and moves q over the run;
+the chains themselves are the library's (persistent batch, one workgroup per
+graph), with the lowest H of every chain tracked on the device.
+
+Policies map per-chain features to (beta, q) once per chunk of sweeps:
+  * ``GeometricPolicy`` -- beta from beta0 to beta1 geometrically, q constant;
+  * ``PerturbedPolicy`` -- a geometric base plus a random walk in (log beta,
+    log q) (the runs the schedule network is trained on);
+  * ``MLPPolicy``       -- the network of the library (BF16/FP32 MFMA kernels)
+    maps the features to (log beta, log q).
+
+This module only orchestrates: sampling, thresholds, tracking and the network
+all run in libshaken.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+from . import Batch, Chain, MLP
+
+NFEAT = 16
+LOG_BETA_RANGE = (np.log(0.05), np.log(20.0))
+LOG_Q_RANGE = (np.log(0.05), np.log(8.0))
+
+
+def graph_stats(inst):
+    """(log2 n / 16, mean degree / 4, std of in-degree minus out-degree / 2)"""
+    n = inst.n
+    deg_in = np.bincount(inst.dst, minlength=n)
+    deg_out = np.bincount(inst.src, minlength=n)
+    return (np.log2(n) / 16.0, (deg_in + deg_out).mean() / 4.0, (deg_in - deg_out).std() / 2.0)
+
+
+def features(stats, frac, e_cur, e_best, n, log_beta, log_q):
+    """Feature matrix [chains, 16]: graph statistics, elapsed fraction, current
+    and best energy density, previous log beta and log q, a constant 1."""
+    F = np.zeros((len(stats), NFEAT), dtype=np.float32)
+    F[:, 0:3] = np.asarray(stats, dtype=np.float32)
+    F[:, 3] = frac
+    F[:, 4] = e_cur / n
+    F[:, 5] = e_best / n
+    F[:, 6] = log_beta / 3.0
+    F[:, 7] = log_q / 3.0
+    F[:, 8] = 1.0
+    return F
+
+
+@dataclasses.dataclass
+class GeometricPolicy:
+    beta0: float
+    beta1: float
+    q: float
+
+    def __call__(self, F, c, n_chunks):
+        t = (c + 0.5) / n_chunks
+        lb = np.log(self.beta0) + t * (np.log(self.beta1) - np.log(self.beta0))
+        rows = F.shape[0]
+        return np.full(rows, lb), np.full(rows, np.log(self.q))
+
+
+class PerturbedPolicy:
+    """Geometric base with a per-chain random walk in (log beta, log q)."""
+
+    def __init__(self, base: GeometricPolicy, rows, n_chunks, seed, sigma_b=0.12, sigma_q=0.15,
+                 q_spread=0.6):
+        rng = np.random.Generator(np.random.PCG64(seed))
+        self.base = base
+        self.db = np.cumsum(rng.normal(0, sigma_b, (n_chunks, rows)), axis=0)
+        self.dq = np.log(base.q) + rng.uniform(-q_spread, q_spread, rows)[None, :] + \
+            np.cumsum(rng.normal(0, sigma_q, (n_chunks, rows)), axis=0)
+
+    def __call__(self, F, c, n_chunks):
+        lb, _ = self.base(F, c, n_chunks)
+        return lb + self.db[c], self.dq[c]
+
+
+class MLPPolicy:
+    def __init__(self, mlp: MLP, device="cuda"):
+        import torch
+        self.mlp = mlp
+        self.torch = torch
+        self.device = device
+
+    def __call__(self, F, c, n_chunks):
+        torch = self.torch
+        x = torch.from_numpy(np.ascontiguousarray(F)).to(self.device)
+        y = torch.empty((F.shape[0], NFEAT), dtype=torch.float32, device=self.device)
+        self.mlp.forward(x, y)
+        out = y[:, :2].double().cpu().numpy()
+        lb, lq = out[:, 0], out[:, 1]
+        bad = ~np.isfinite(lb) | ~np.isfinite(lq)
+        lb = np.clip(np.where(bad, 0.0, lb), *LOG_BETA_RANGE)
+        lq = np.clip(np.where(bad, 0.0, lq), *LOG_Q_RANGE)
+        return lb, lq
+
+
+@dataclasses.dataclass
+class RunResult:
+    best: np.ndarray          # lowest H per chain over the run (full-step configurations)
+    last: np.ndarray          # H of the final configuration
+    best_spins: list          # configuration that reached `best`, per chain
+    final_spins: list
+    feats: np.ndarray         # [chunks, chains, 16]
+    log_beta: np.ndarray      # [chunks, chains]
+    log_q: np.ndarray
+    seconds: float
+
+
+def run(instances, seeds, policy, sweeps, chunk, replica0=0, keep_spins=False):
+    """Anneal every instance (synth.Instance with lambda = 0) once under
+    `policy`; chains start from the random state of their seed."""
+    import time
+    n_chunks = sweeps // chunk
+    chains = []
+    for i, inst in enumerate(instances):
+        chains.append(Chain.graph(inst.n, inst.src, inst.dst, J=inst.J, q=1.0, beta=0.1,
+                                  seed=int(seeds[i]), replica=replica0 + i))
+    stats = [graph_stats(inst) for inst in instances]
+    ns = np.array([inst.n for inst in instances], dtype=np.float64)
+    batch = Batch(chains, strategy="persistent", track=True)
+    # energy (and configuration) of the starting state: a zero-step sweep
+    batch.sweep(0)
+    if keep_spins:
+        e_cur, e_best, sp = batch.track(best_spins=True)
+        offs = np.cumsum([0] + [ch.n for ch in chains])
+        best_spins = [sp[offs[i]:offs[i + 1]].copy() for i in range(len(chains))]
+    else:
+        e_cur, e_best = batch.track()
+        best_spins = []
+    e_cur = e_cur.astype(np.float64)
+    e_best = e_best.astype(np.float64)
+    lb_prev = np.zeros(len(chains))
+    lq_prev = np.zeros(len(chains))
+    feats, lbs, lqs = [], [], []
+    t0 = time.perf_counter()
+    for c in range(n_chunks):
+        F = features(stats, c / n_chunks, e_cur, e_best, ns, lb_prev, lq_prev)
+        lb, lq = policy(F, c, n_chunks)
+        lb = np.clip(lb, *LOG_BETA_RANGE)
+        lq = np.clip(lq, *LOG_Q_RANGE)
+        batch.set_params(np.exp(lb), np.exp(lq))
+        batch.sweep(chunk)
+        if keep_spins:
+            hl, hb, sp = batch.track(best_spins=True)
+            for i in np.nonzero(hb < e_best)[0]:
+                best_spins[i] = sp[offs[i]:offs[i + 1]].copy()
+        else:
+            hl, hb = batch.track()
+        e_best = np.minimum(e_best, hb)
+        e_cur = hl.astype(np.float64)
+        feats.append(F)
+        lbs.append(lb)
+        lqs.append(lq)
+        lb_prev, lq_prev = lb, lq
+    secs = time.perf_counter() - t0
+    final = [ch.spins() for ch in chains] if keep_spins else []
+    batch.close()
+    for ch in chains:
+        ch.close()
+    return RunResult(e_best, e_cur, best_spins, final, np.array(feats), np.array(lbs),
+                     np.array(lqs), secs)
+
+
+def train_mlp(mlp: MLP, X, Y, w, epochs, batch_rows, lr, seed=0, device="cuda", log=None):
+    """Weighted least squares of the network outputs (first two) onto targets,
+    Adam on the library's kernels; X [rows, 16], Y [rows, 2], w [rows]."""
+    import torch
+    rng = np.random.Generator(np.random.PCG64(seed))
+    rows = X.shape[0]
+    Xd = torch.from_numpy(np.ascontiguousarray(X, dtype=np.float32)).to(device)
+    T = np.zeros((rows, NFEAT), dtype=np.float32)
+    T[:, :2] = Y
+    Td = torch.from_numpy(T).to(device)
+    Wd = torch.from_numpy(np.ascontiguousarray(w, dtype=np.float32)).to(device)
+    yb = torch.empty((batch_rows, NFEAT), dtype=torch.float32, device=device)
+    step = 0
+    losses = []
+    for ep in range(epochs):
+        perm = torch.from_numpy(rng.permutation(rows)).to(device)
+        tot = 0.0
+        nb = 0
+        for s0 in range(0, rows - batch_rows + 1, batch_rows):
+            idx = perm[s0:s0 + batch_rows]
+            xb = Xd[idx].contiguous()
+            tb = Td[idx].contiguous()
+            wb = Wd[idx].contiguous()
+            mlp.forward(xb, yb)
+            loss = mlp.loss_backward(tb, wb)
+            step += 1
+            mlp.adam(lr, step)
+            tot += loss
+            nb += 1
+        losses.append(tot / max(nb, 1))
+        if log:
+            log("epoch %d loss %.5f" % (ep, losses[-1]))
+    return losses

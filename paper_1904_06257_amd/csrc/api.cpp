@@ -97,6 +97,13 @@ bool finite_nonneg(double x) { return std::isfinite(x) && x >= 0.0; }
 
 }  // namespace
 
+namespace shaken {
+shaken_status set_error(shaken_status s, const char *msg) {
+    g_err = msg ? msg : "";
+    return s;
+}
+}  // namespace shaken
+
 // ------------------------------------------------------------------ context
 
 struct shaken_ctx {
@@ -127,6 +134,7 @@ struct shaken_ctx {
     int64_t *log_dev = nullptr;
     int64_t log_cap = 0;  // slots
     int64_t *obs_dev = nullptr;
+    bool lut_stale = false;  // a batch changed beta/q: re-upload before a call of its own
     ChainDesc hd{};
     ChainDesc *dd = nullptr;
     int block = 256;
@@ -155,6 +163,11 @@ void release(shaken_ctx *c) {
     dfree(c->log_dev);
     dfree(c->obs_dev);
     dfree(c->dd);
+}
+
+size_t bit_words(const shaken_ctx *c) {
+    if (c->kind == KIND_TORUS) return (size_t)c->L * c->W;
+    return ((size_t)c->n + 31) / 32;
 }
 
 // Build the host threshold table and the bit-packed torus class tables.
@@ -191,6 +204,13 @@ shaken_status upload_tables(shaken_ctx *c) {
     HIPCHK(hipMemcpyAsync(c->dd, &c->hd, sizeof(ChainDesc), hipMemcpyHostToDevice, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     return SHAKEN_OK;
+}
+
+// refresh the device tables of a chain whose parameters a batch changed
+shaken_status refresh_if_stale(shaken_ctx *c) {
+    if (!c->lut_stale) return SHAKEN_OK;
+    c->lut_stale = false;
+    return upload_tables(c);
 }
 
 void refresh_desc_spins(shaken_ctx *c) {
@@ -445,6 +465,10 @@ shaken_status init_device(shaken_ctx *c, const shaken_opts *o, HostLayout &hl) {
     d.maxdeg = c->maxdeg;
     d.log_line = c->line();
     d.log_stride = c->stride();
+    for (size_t k = 0; k < c->lam.size() && k < 16; ++k) {
+        d.lam2[k] = c->lam2_int ? (int32_t)c->lam2[k] : 0;
+        d.csize[k] = (int32_t)c->class_size[k];
+    }
     refresh_desc_spins(c);
     build_tables(c);
     CHK(upload_tables(c));
@@ -469,6 +493,7 @@ shaken_status init_device(shaken_ctx *c, const shaken_opts *o, HostLayout &hl) {
 // one half-step at the context's counter
 shaken_status half_step_once(shaken_ctx *c, int log_on, uint32_t s_log0) {
     if (c->s >= kInitStep - 1) return fail(SHAKEN_ESTATE, "half-step counter exhausted");
+    CHK(refresh_if_stale(c));
     HIPCHK(launch_half_step_grid(c->dd, &c->hd, 1, nullptr, c->s, s_log0, log_on,
                                  (c->s & 1u) == 0, c->block, c->stream));
     c->s += 1;
@@ -764,7 +789,15 @@ struct shaken_batch {
     int autotune = 0;
     bool tuned = false;
     int record = 0;
+    int track = 0;
     std::vector<Group> groups;
+    // batch-wide pools: thresholds of every chain, tracking pairs, best configurations
+    uint64_t *lut_pool = nullptr;
+    std::vector<size_t> lut_off;
+    std::vector<uint64_t> lut_host;
+    int64_t *track_pool = nullptr;
+    uint32_t *best_pool = nullptr;
+    std::vector<size_t> best_off;
     uint32_t *dstate = nullptr;  // [0] half-step base, [1] log base
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
@@ -785,6 +818,9 @@ namespace {
 void batch_release(shaken_batch *b) {
     for (auto &g : b->groups) dfree(g.dd);
     dfree(b->dstate);
+    dfree(b->lut_pool);
+    dfree(b->track_pool);
+    dfree(b->best_pool);
     dfree(b->pdescs);
     dfree(b->order);
     dfree(b->counter);
@@ -797,21 +833,25 @@ void batch_release(shaken_batch *b) {
 
 // refresh every group's device descriptors from the contexts (spin and log
 // pointers may have changed)
+// the descriptor chain i uses inside the batch (pool pointers)
+ChainDesc batch_desc(shaken_batch *b, size_t i) {
+    shaken_ctx *c = b->ctx[i];
+    refresh_desc_spins(c);
+    ChainDesc d = c->hd;
+    d.lut = b->lut_pool + b->lut_off[i];
+    d.track = b->track_pool ? b->track_pool + 2 * i : nullptr;
+    d.best = b->best_pool ? b->best_pool + b->best_off[i] : nullptr;
+    return d;
+}
+
 shaken_status batch_upload(shaken_batch *b) {
     for (auto &g : b->groups) {
-        for (size_t i = 0; i < g.members.size(); ++i) {
-            shaken_ctx *c = b->ctx[g.members[i]];
-            refresh_desc_spins(c);
-            g.hd[i] = c->hd;
-        }
+        for (size_t i = 0; i < g.members.size(); ++i) g.hd[i] = batch_desc(b, g.members[i]);
         HIPCHK(hipMemcpyAsync(g.dd, g.hd.data(), g.hd.size() * sizeof(ChainDesc),
                               hipMemcpyHostToDevice, b->stream));
     }
     if (b->pdescs) {
-        for (size_t i = 0; i < b->ctx.size(); ++i) {
-            refresh_desc_spins(b->ctx[i]);
-            b->phd[i] = b->ctx[i]->hd;
-        }
+        for (size_t i = 0; i < b->ctx.size(); ++i) b->phd[i] = batch_desc(b, i);
         HIPCHK(hipMemcpyAsync(b->pdescs, b->phd.data(), b->phd.size() * sizeof(ChainDesc),
                               hipMemcpyHostToDevice, b->stream));
     }
@@ -944,6 +984,7 @@ shaken_status shaken_batch_create(shaken_batch **out, shaken_ctx *const *ctx, in
     b->use_graph = o.use_hipgraph;
     b->autotune = o.autotune;
     b->record = o.record;
+    b->track = o.track;
     b->stream = o.stream ? (hipStream_t)o.stream : ctx[0]->stream;
     shaken_status st = SHAKEN_OK;
     auto bail = [&](shaken_status s) {
@@ -966,7 +1007,33 @@ shaken_status shaken_batch_create(shaken_batch **out, shaken_ctx *const *ctx, in
     if (strat == SHAKEN_BATCH_AUTO) strat = all_fit ? SHAKEN_BATCH_PERSISTENT : SHAKEN_BATCH_GRID;
     if (strat == SHAKEN_BATCH_PERSISTENT && !all_fit)
         return bail(fail(SHAKEN_EINVAL, "a chain does not fit the persistent strategy"));
+    if (b->track && strat != SHAKEN_BATCH_PERSISTENT)
+        return bail(fail(SHAKEN_EINVAL, "tracking needs the persistent strategy"));
     b->strategy = strat;
+    // threshold pool (current tables of every chain)
+    {
+        size_t tot = 0;
+        for (int i = 0; i < n; ++i) {
+            b->lut_off.push_back(tot);
+            tot += ctx[i]->lut.size();
+        }
+        b->lut_host.resize(tot);
+        for (int i = 0; i < n; ++i)
+            std::copy(ctx[i]->lut.begin(), ctx[i]->lut.end(), b->lut_host.begin() + b->lut_off[i]);
+        if ((st = dalloc(&b->lut_pool, tot)) != SHAKEN_OK) return bail(st);
+        if (hipMemcpy(b->lut_pool, b->lut_host.data(), tot * 8, hipMemcpyHostToDevice) != hipSuccess)
+            return bail(fail(SHAKEN_EDEVICE, "threshold upload failed"));
+    }
+    if (b->track) {
+        size_t tot = 0;
+        for (int i = 0; i < n; ++i) {
+            if (!ctx[i]->lam2_int) return bail(fail(SHAKEN_EINVAL, "tracking needs every 2*lambda to be an integer"));
+            b->best_off.push_back(tot);
+            tot += bit_words(ctx[i]);
+        }
+        if ((st = dalloc(&b->track_pool, 2 * (size_t)n)) != SHAKEN_OK) return bail(st);
+        if ((st = dalloc(&b->best_pool, tot)) != SHAKEN_OK) return bail(st);
+    }
     if ((st = dalloc(&b->dstate, 2)) != SHAKEN_OK) return bail(st);
     if (strat == SHAKEN_BATCH_GRID) {
         // group by (kind, format): one launch per group and half-step
@@ -1050,7 +1117,7 @@ shaken_status shaken_batch_sweep(shaken_batch *b, int64_t n_full) {
     } else {
         HIPCHK(launch_set_state((uint32_t *)b->counter, 0u, 0u, b->stream));
         HIPCHK(launch_persistent(b->pdescs, (int)b->ctx.size(), b->order, b->counter, s0, n_full,
-                                 b->record, b->pblock, b->pgrid, b->stream));
+                                 b->record, b->track, b->pblock, b->pgrid, b->stream));
     }
     const uint32_t s1 = s0 + (uint32_t)(2 * n_full);
     if (b->record) {
@@ -1081,6 +1148,68 @@ shaken_status shaken_batch_get_log(shaken_batch *b, int32_t i, int64_t *H_out, i
     HIPCHK(hipMemcpyAsync(raw.data(), c->log_dev, raw.size() * 8, hipMemcpyDeviceToHost, b->stream));
     HIPCHK(hipStreamSynchronize(b->stream));
     convert_log(c, raw, slots, H_out, M_out);
+    return SHAKEN_OK;
+}
+
+shaken_status shaken_batch_set_params(shaken_batch *b, const double *beta, const double *q) {
+    if (!b || !beta || !q) return fail(SHAKEN_EINVAL, "batch, beta and q must be non-NULL");
+    const size_t n = b->ctx.size();
+    for (size_t i = 0; i < n; ++i)
+        if (!finite_nonneg(beta[i]) || !finite_nonneg(q[i]))
+            return fail(SHAKEN_EINVAL, "beta and q must be finite and >= 0 (chain " + std::to_string(i) + ")");
+    DeviceGuard guard(b->device);
+    HIPCHK(hipStreamSynchronize(b->stream));
+    bool fold_changed = false;
+    for (size_t i = 0; i < n; ++i) {
+        shaken_ctx *c = b->ctx[i];
+        const int fold_before = c->hd.fold3;
+        c->beta = beta[i];
+        c->q = q[i];
+        build_tables(c);
+        c->lut_stale = true;
+        fold_changed |= fold_before != c->hd.fold3;
+        std::copy(c->lut.begin(), c->lut.end(), b->lut_host.begin() + b->lut_off[i]);
+    }
+    HIPCHK(hipMemcpyAsync(b->lut_pool, b->lut_host.data(), b->lut_host.size() * 8,
+                          hipMemcpyHostToDevice, b->stream));
+    CHK(batch_upload(b));
+    if (fold_changed && b->gexec) {
+        (void)hipGraphExecDestroy(b->gexec);
+        b->gexec = nullptr;
+    }
+    return SHAKEN_OK;
+}
+
+shaken_status shaken_batch_get_track(shaken_batch *b, int64_t *H_last, int64_t *H_best,
+                                     int8_t *best_spins) {
+    if (!b) return fail(SHAKEN_EINVAL, "batch is NULL");
+    if (!b->track || b->last_n_full < 0) return fail(SHAKEN_ESTATE, "no tracked sweep");
+    DeviceGuard guard(b->device);
+    const size_t n = b->ctx.size();
+    std::vector<int64_t> tr(2 * n);
+    HIPCHK(hipMemcpyAsync(tr.data(), b->track_pool, tr.size() * 8, hipMemcpyDeviceToHost, b->stream));
+    std::vector<uint32_t> w;
+    if (best_spins) {
+        w.resize(b->best_off.back() + bit_words(b->ctx.back()));
+        HIPCHK(hipMemcpyAsync(w.data(), b->best_pool, w.size() * 4, hipMemcpyDeviceToHost, b->stream));
+    }
+    HIPCHK(hipStreamSynchronize(b->stream));
+    size_t off = 0;
+    for (size_t i = 0; i < n; ++i) {
+        if (H_last) H_last[i] = tr[2 * i];
+        if (H_best) H_best[i] = tr[2 * i + 1];
+        if (best_spins) {
+            shaken_ctx *c = b->ctx[i];
+            const uint32_t *wi = w.data() + b->best_off[i];
+            if (c->kind == KIND_TORUS) {
+                std::vector<uint32_t> tmp(wi, wi + bit_words(c));
+                unpack_torus(tmp, c->L, c->W, best_spins + off);
+            } else {
+                for (int v = 0; v < c->n; ++v) best_spins[off + v] = ((wi[v >> 5] >> (v & 31)) & 1u) ? 1 : -1;
+            }
+            off += (size_t)c->n;
+        }
+    }
     return SHAKEN_OK;
 }
 

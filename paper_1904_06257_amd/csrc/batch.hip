@@ -45,9 +45,16 @@ __device__ __forceinline__ void block_sum2(int &e, int &p, int *sh) {
 
 // One half-step (or, with dst == nullptr, only the observables of src) of an
 // L x L bit-packed torus held in LDS.
+// Observables of one configuration, valid in thread 0: E_J and the +1 count of
+// every field class.
+struct Obs {
+    int e;
+    int plus[kPClasses];
+};
+
 template <bool FOLD3>
 __device__ void torus_lds_half(const ChainDesc &d, const uint32_t *src, uint32_t *dst, uint32_t s,
-                               bool obs, int *sh_red, int64_t *log_slot) {
+                               bool obs, int *sh_red, Obs *o) {
     const int L = d.L, W = d.W, nw = L * W;
     const int phase = (int)(s & 1u);
     const uint32_t k0 = (uint32_t)d.seed, k1 = (uint32_t)(d.seed >> 32);
@@ -81,30 +88,70 @@ __device__ void torus_lds_half(const ChainDesc &d, const uint32_t *src, uint32_t
     if (obs) {
         block_sum2(e_acc, p_acc, sh_red);
         if (threadIdx.x == 0) {
-            log_slot[0] = e_acc;
-            log_slot[1] = p_acc;
+            o->e = e_acc;
+            o->plus[0] = p_acc;
         }
     }
 }
 
+// Record and / or track one observation (thread 0 holds `o`).  Tracking keeps
+// the lowest H in *best_h (thread 0) and copies the configuration `cfg`
+// (nwords words of bits) to d.best when it improves.
+__device__ void observe_step(const ChainDesc &d, const Obs &o, int64_t *log_slot, bool track,
+                             int64_t *best_h, int64_t *last_h, const uint32_t *cfg, int nwords,
+                             int *sh_flag) {
+    if (threadIdx.x == 0) {
+        if (log_slot) {
+            log_slot[0] = o.e;
+            for (int c = 0; c < d.ncls; ++c) log_slot[1 + c] = o.plus[c];
+        }
+        int improved = 0;
+        if (track) {
+            int64_t h = -(int64_t)o.e;
+            for (int c = 0; c < d.ncls; ++c)
+                h -= (int64_t)d.lam2[c] * (2 * (int64_t)o.plus[c] - d.csize[c]);
+            *last_h = h;
+            if (h < *best_h) {
+                *best_h = h;
+                improved = 1;
+            }
+        }
+        *sh_flag = improved;
+    }
+    __syncthreads();
+    if (*sh_flag)
+        for (int w = threadIdx.x; w < nwords; w += kPBlock) d.best[w] = cfg[w];
+    __syncthreads();
+}
+
 template <bool FOLD3>
 __device__ void run_torus(const ChainDesc &d, uint32_t (*buf)[kPWords], uint32_t s0, int64_t n_full,
-                          int record, int *sh_red) {
+                          int record, int track, int *sh_red, int *sh_flag) {
     const int nw = d.L * d.W;
+    const bool obs = record || track;
     const uint32_t *g = (const uint32_t *)d.spin[0];
     for (int w = threadIdx.x; w < nw; w += kPBlock) buf[0][w] = g[w];
     __syncthreads();
+    Obs o;
+    int64_t best_h = INT64_MAX, last_h = 0;
     for (int64_t t = 0; t < n_full; ++t) {
         const uint32_t s = s0 + 2u * (uint32_t)t;
-        int64_t *lg = record ? d.log + t * d.log_stride : nullptr;
-        torus_lds_half<FOLD3>(d, buf[0], buf[1], s, record != 0, sh_red, lg);
+        torus_lds_half<FOLD3>(d, buf[0], buf[1], s, obs, sh_red, &o);
+        if (obs)
+            observe_step(d, o, record ? d.log + t * d.log_stride : nullptr, track, &best_h, &last_h,
+                         buf[0], nw, sh_flag);
         __syncthreads();
         torus_lds_half<FOLD3>(d, buf[1], buf[0], s + 1u, false, sh_red, nullptr);
         __syncthreads();
     }
-    if (record) {
-        torus_lds_half<FOLD3>(d, buf[0], nullptr, s0, true, sh_red, d.log + n_full * d.log_stride);
-        __syncthreads();
+    if (obs) {
+        torus_lds_half<FOLD3>(d, buf[0], nullptr, s0, true, sh_red, &o);
+        observe_step(d, o, record ? d.log + n_full * d.log_stride : nullptr, track, &best_h, &last_h,
+                     buf[0], nw, sh_flag);
+        if (track && threadIdx.x == 0) {
+            d.track[0] = last_h;
+            d.track[1] = best_h;
+        }
     }
     uint32_t *go = (uint32_t *)d.spin[0];
     for (int w = threadIdx.x; w < nw; w += kPBlock) go[w] = buf[0][w];
@@ -121,7 +168,7 @@ __device__ __forceinline__ int lds_spin(const uint32_t *bits, int v) {
 // Philox call); 8 consecutive lanes own one 32-vertex output word and merge
 // their 4-bit pieces with lane shuffles.
 __device__ void graph_lds_half(const ChainDesc &d, const uint32_t *src, uint32_t *dst, uint32_t s,
-                               bool obs, int *sh_red, int *sh_plus, int64_t *log_slot) {
+                               bool obs, int *sh_red, int *sh_plus, Obs *o) {
     const int n = d.n;
     const int half = dst ? (int)(s & 1u) : 0;  // observables use the in-half
     const int32_t *__restrict__ rp = d.rowptr[half];
@@ -196,15 +243,18 @@ __device__ void graph_lds_half(const ChainDesc &d, const uint32_t *src, uint32_t
     }
     if (obs) {
         int dummy = 0;
-        block_sum2(e_acc, dummy, sh_red);
-        if (threadIdx.x == 0) log_slot[0] = e_acc;
-        if (threadIdx.x < ncls) log_slot[1 + threadIdx.x] = sh_plus[threadIdx.x];
+        block_sum2(e_acc, dummy, sh_red);  // ends with a barrier: sh_plus is complete
+        if (threadIdx.x == 0) {
+            o->e = e_acc;
+            for (int c = 0; c < ncls; ++c) o->plus[c] = sh_plus[c];
+        }
     }
 }
 
 __device__ void run_graph(const ChainDesc &d, uint32_t (*buf)[kPWords], uint32_t s0, int64_t n_full,
-                          int record, int *sh_red, int *sh_plus) {
+                          int record, int track, int *sh_red, int *sh_plus, int *sh_flag) {
     const int n = d.n, nw = (n + 31) / 32;
+    const bool obs = record || track;
     const int8_t *g = (const int8_t *)d.spin[0];
     for (int w = threadIdx.x; w < nw; w += kPBlock) {
         uint32_t word = 0;
@@ -215,17 +265,26 @@ __device__ void run_graph(const ChainDesc &d, uint32_t (*buf)[kPWords], uint32_t
         buf[0][w] = word;
     }
     __syncthreads();
+    Obs o;
+    int64_t best_h = INT64_MAX, last_h = 0;
     for (int64_t t = 0; t < n_full; ++t) {
         const uint32_t s = s0 + 2u * (uint32_t)t;
-        int64_t *lg = record ? d.log + t * d.log_stride : nullptr;
-        graph_lds_half(d, buf[0], buf[1], s, record != 0, sh_red, sh_plus, lg);
+        graph_lds_half(d, buf[0], buf[1], s, obs, sh_red, sh_plus, &o);
+        if (obs)
+            observe_step(d, o, record ? d.log + t * d.log_stride : nullptr, track, &best_h, &last_h,
+                         buf[0], nw, sh_flag);
         __syncthreads();
         graph_lds_half(d, buf[1], buf[0], s + 1u, false, sh_red, sh_plus, nullptr);
         __syncthreads();
     }
-    if (record) {
-        graph_lds_half(d, buf[0], nullptr, s0, true, sh_red, sh_plus, d.log + n_full * d.log_stride);
-        __syncthreads();
+    if (obs) {
+        graph_lds_half(d, buf[0], nullptr, s0, true, sh_red, sh_plus, &o);
+        observe_step(d, o, record ? d.log + n_full * d.log_stride : nullptr, track, &best_h, &last_h,
+                     buf[0], nw, sh_flag);
+        if (track && threadIdx.x == 0) {
+            d.track[0] = last_h;
+            d.track[1] = best_h;
+        }
     }
     int8_t *go = (int8_t *)d.spin[0];
     for (int v = threadIdx.x; v < n; v += kPBlock) go[v] = (int8_t)lds_spin(buf[0], v);
@@ -237,9 +296,10 @@ __global__ __launch_bounds__(kPBlock) void k_persistent(const ChainDesc *__restr
                                                         int nchains,
                                                         const int32_t *__restrict__ order,
                                                         int32_t *counter, uint32_t s0,
-                                                        int64_t n_full, int record) {
+                                                        int64_t n_full, int record, int track) {
     __shared__ uint32_t buf[2][kPWords];
     __shared__ int sh_item;
+    __shared__ int sh_flag;
     __shared__ int sh_red[2 * (kPBlock / 64)];
     __shared__ int sh_plus[kPClasses];
     for (;;) {
@@ -254,24 +314,24 @@ __global__ __launch_bounds__(kPBlock) void k_persistent(const ChainDesc *__restr
         const ChainDesc &d = descs[item];
         if (d.kind == KIND_TORUS) {
             if (d.fold3)
-                run_torus<true>(d, buf, s0, n_full, record, sh_red);
+                run_torus<true>(d, buf, s0, n_full, record, track, sh_red, &sh_flag);
             else
-                run_torus<false>(d, buf, s0, n_full, record, sh_red);
+                run_torus<false>(d, buf, s0, n_full, record, track, sh_red, &sh_flag);
         } else {
-            run_graph(d, buf, s0, n_full, record, sh_red, sh_plus);
+            run_graph(d, buf, s0, n_full, record, track, sh_red, sh_plus, &sh_flag);
         }
         __syncthreads();
     }
 }
 
 hipError_t launch_persistent(const ChainDesc *dev_descs, int nchains, const int32_t *order,
-                             int32_t *counter, uint32_t s0, int64_t n_full, int record, int block,
-                             int grid, hipStream_t stream) {
+                             int32_t *counter, uint32_t s0, int64_t n_full, int record, int track,
+                             int block, int grid, hipStream_t stream) {
     (void)block;
     if (nchains <= 0) return hipSuccess;
     const int g = grid > 0 ? grid : nchains;
     hipLaunchKernelGGL(k_persistent, dim3(g), dim3(kPBlock), 0, stream, dev_descs, nchains, order,
-                       counter, s0, n_full, record);
+                       counter, s0, n_full, record, track);
     return hipGetLastError();
 }
 

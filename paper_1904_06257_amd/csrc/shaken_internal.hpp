@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "shaken.h"
+
 namespace shaken {
 
 constexpr uint32_t kGraphStream = 0x80000000u;  // fourth counter word, graph uniforms
@@ -49,6 +51,13 @@ struct ChainDesc {
     int64_t *log;
     int64_t log_line;        // 1 + ncls rounded up to 16 (one 128-byte line)
     int64_t log_stride;      // kLogParts * log_line
+    // best-energy tracking (persistent batches): H = -E_J - sum_c lam2[c] *
+    // (2 plus_c - csize[c]); track[0] = H of the last configuration, track[1] =
+    // lowest H of the call; best = that configuration as bits
+    int64_t *track;
+    uint32_t *best;
+    int32_t lam2[16];
+    int32_t csize[16];
 };
 
 // ---------------------------------------------------------------- launchers
@@ -88,9 +97,12 @@ hipError_t launch_fill_i64(int64_t *p, int64_t count, int64_t value, hipStream_t
 // Writes the final configuration back into spin[0].
 hipError_t launch_persistent(const ChainDesc *dev_descs, int nchains, const int32_t *order,
                              int32_t *counter, uint32_t s0, int64_t n_full, int record,
-                             int block, int grid, hipStream_t stream);
+                             int track, int block, int grid, hipStream_t stream);
 
 // can chain d run in the persistent kernel?
 bool persistent_fits(const ChainDesc &d);
+
+// record the thread-local message returned by shaken_last_error()
+shaken_status set_error(shaken_status s, const char *msg);
 
 }  // namespace shaken
