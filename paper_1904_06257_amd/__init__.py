@@ -18,6 +18,11 @@ import os
 
 import numpy as np
 
+# torch first: its HIP runtime (same soname as ROCm's) is then the one the
+# library binds to, so the process holds a single HIP runtime whichever of the
+# two the caller imports first
+import torch  # noqa: E402,F401
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libshaken.so")
 

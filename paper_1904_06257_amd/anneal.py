@@ -66,19 +66,19 @@ class GeometricPolicy:
 
 
 class PerturbedPolicy:
-    """Geometric base with a per-chain random walk in (log beta, log q)."""
+    """A base policy plus a per-chain random walk in (log beta, log q) and a
+    per-chain offset of log q."""
 
-    def __init__(self, base: GeometricPolicy, rows, n_chunks, seed, sigma_b=0.12, sigma_q=0.15,
-                 q_spread=0.6):
+    def __init__(self, base, rows, n_chunks, seed, sigma_b=0.12, sigma_q=0.15, q_spread=0.6):
         rng = np.random.Generator(np.random.PCG64(seed))
         self.base = base
         self.db = np.cumsum(rng.normal(0, sigma_b, (n_chunks, rows)), axis=0)
-        self.dq = np.log(base.q) + rng.uniform(-q_spread, q_spread, rows)[None, :] + \
+        self.dq = rng.uniform(-q_spread, q_spread, rows)[None, :] + \
             np.cumsum(rng.normal(0, sigma_q, (n_chunks, rows)), axis=0)
 
     def __call__(self, F, c, n_chunks):
-        lb, _ = self.base(F, c, n_chunks)
-        return lb + self.db[c], self.dq[c]
+        lb, lq = self.base(F, c, n_chunks)
+        return lb + self.db[c], lq + self.dq[c]
 
 
 class MLPPolicy:
@@ -99,6 +99,21 @@ class MLPPolicy:
         lb = np.clip(np.where(bad, 0.0, lb), *LOG_BETA_RANGE)
         lq = np.clip(np.where(bad, 0.0, lq), *LOG_Q_RANGE)
         return lb, lq
+
+
+def init_params(seed: int) -> np.ndarray:
+    """Random initial parameters of the schedule network (He initialisation of
+    the hidden layers, small output layer whose unused rows are zero); the
+    output bias starts at (log 1, log 1)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ni, nh, no = 16, 128, 16
+    parts = [rng.normal(0, np.sqrt(2.0 / ni), nh * ni), np.zeros(nh),
+             rng.normal(0, np.sqrt(2.0 / nh), nh * nh), np.zeros(nh),
+             rng.normal(0, np.sqrt(2.0 / nh), nh * nh), np.zeros(nh)]
+    w4 = np.zeros((no, nh))
+    w4[:2] = rng.normal(0, 0.1 / np.sqrt(nh), (2, nh))
+    parts += [w4.reshape(-1), np.zeros(no)]
+    return np.concatenate(parts).astype(np.float32)
 
 
 @dataclasses.dataclass
