@@ -229,12 +229,79 @@ def bench_batch(args, sk):
     return value, wall, cfg, roof, "u1 (bit-packed spins in LDS)"
 
 
+def bench_copycal(args):
+    """Plain device copy of a known size: the calibration of the FETCH_SIZE /
+    WRITE_SIZE counters (bytes they report per byte copied)."""
+    import torch
+    n = 1 << 30
+    a = torch.empty(n, dtype=torch.uint8, device="cuda")
+    a.fill_(1)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n, "copies": 3}), flush=True)
+
+
+def _counter_rows(path):
+    import csv
+    rows = list(csv.DictReader(open(path)))
+    out = {}
+    for r in rows:
+        name = r["Kernel_Name"]
+        out.setdefault(name, []).append(float(r["Counter_Value"]))
+    return out
+
+
+def summarize_traffic(fetch_csv, write_csv, cal_fetch_csv, cal_write_csv, out_path):
+    """profiles/traffic.txt from four rocprofv3 --pmc counter CSVs (FETCH_SIZE
+    and WRITE_SIZE, in KiB per dispatch, for the workload and for the 1 GiB
+    calibration copy)."""
+    def per_kernel(path):
+        return {k: sum(v) / len(v) for k, v in _counter_rows(path).items()}
+    cf, cw = per_kernel(cal_fetch_csv), per_kernel(cal_write_csv)
+    copy_k = [k for k in cf if "copy" in k.lower() or "elementwise" in k.lower()]
+    ck = max(copy_k, key=lambda k: cf[k])
+    fetch_factor = (1 << 30) / (cf[ck] * 1024.0)    # true bytes per counted byte
+    write_factor = (1 << 30) / (cw[ck] * 1024.0)
+    f, w = per_kernel(fetch_csv), per_kernel(write_csv)
+    lines = ["# HBM-side traffic per launch from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE",
+             "# (KiB per dispatch, averaged), scaled by the factors a 1 GiB device copy gives",
+             "# (bytes copied / bytes counted).  source_hash: kernels this was measured on.",
+             "source_hash = %s" % kernel_source_hash(),
+             "calibration_kernel = %s" % ck.split("(")[0],
+             "fetch_factor = %.4f" % fetch_factor, "write_factor = %.4f" % write_factor]
+    for k in sorted(f):
+        short = k.split("(")[0].replace("void ", "").replace("shaken::", "").split("<")[0]
+        if short not in ("k_torus_bp", "k_graph", "k_persistent", "k_torus_i8"):
+            continue
+        fb = f[k] * 1024.0 * fetch_factor
+        wb = w.get(k, 0.0) * 1024.0 * write_factor
+        lines.append("# %s: fetch %.0f B, write %.0f B per launch" % (k.split("(")[0], fb, wb))
+    agg = {}
+    for k in f:
+        short = k.split("(")[0].replace("void ", "").replace("shaken::", "").split("<")[0]
+        fb = f[k] * 1024.0 * fetch_factor
+        wb = w.get(k, 0.0) * 1024.0 * write_factor
+        agg.setdefault(short, []).append(fb + wb)
+    for short in ("k_torus_bp", "k_graph", "k_persistent"):
+        if short in agg:
+            lines.append("%s.bytes_per_launch = %.0f" % (short, sum(agg[short]) / len(agg[short])))
+    with open(out_path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "--summarize-traffic":
+        summarize_traffic(*sys.argv[2:6], os.path.join(ROOT, "profiles", "traffic.txt"))
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="torus4096", choices=["torus4096", "graph", "batch"])
+    ap.add_argument("--workload", default="torus4096",
+                    choices=["torus4096", "graph", "batch", "copycal"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -247,6 +314,9 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     torch.cuda.set_device(0)
+    if args.workload == "copycal":
+        bench_copycal(args)
+        return
     import paper_1904_06257_amd as sk
 
     if args.workload == "torus4096":

@@ -16,6 +16,7 @@ namespace shaken {
 constexpr int kPBlock = 256;
 constexpr int kPWords = 2048;
 constexpr int kPClasses = 16;
+constexpr int kPLut = 256;  // threshold entries kept in LDS
 
 bool persistent_fits(const ChainDesc &d) {
     if (d.kind == KIND_TORUS) return d.format == FMT_BITPACKED && d.L * d.W <= kPWords;
@@ -168,7 +169,7 @@ __device__ __forceinline__ int lds_spin(const uint32_t *bits, int v) {
 // Philox call); 8 consecutive lanes own one 32-vertex output word and merge
 // their 4-bit pieces with lane shuffles.
 __device__ void graph_lds_half(const ChainDesc &d, const uint32_t *src, uint32_t *dst, uint32_t s,
-                               bool obs, int *sh_red, int *sh_plus, Obs *o) {
+                               bool obs, int *sh_red, int *sh_plus, Obs *o, const uint64_t *lut) {
     const int n = d.n;
     const int half = dst ? (int)(s & 1u) : 0;  // observables use the in-half
     const int32_t *__restrict__ rp = d.rowptr[half];
@@ -191,18 +192,20 @@ __device__ void graph_lds_half(const ChainDesc &d, const uint32_t *src, uint32_t
 #pragma unroll
             for (int j = 0; j < 5; ++j) rpv[j] = rp[min(v0 + j, n)];
             int S0 = 0, S1 = 0, S2 = 0, S3 = 0;
-            for (int base = rpv[0]; base < rpv[4]; base += 8) {
+            const int last = rpv[4] - 1;
+            for (int base = rpv[0]; base <= last; base += 8) {
+                // clamped indices: all eight loads issue before any is used
                 int cc[8], jj[8];
 #pragma unroll
                 for (int k = 0; k < 8; ++k) {
-                    const int e = base + k;
-                    cc[k] = e < rpv[4] ? col[e] : 0;
-                    jj[k] = e < rpv[4] ? (int)jw[e] : 0;
+                    const int e = min(base + k, last);
+                    cc[k] = col[e];
+                    jj[k] = (int)jw[e];
                 }
 #pragma unroll
                 for (int k = 0; k < 8; ++k) {
                     const int e = base + k;
-                    const int t = jj[k] * lds_spin(src, cc[k]);
+                    const int t = e <= last ? jj[k] * lds_spin(src, cc[k]) : 0;
                     S0 += e < rpv[1] ? t : 0;
                     S1 += (e >= rpv[1] && e < rpv[2]) ? t : 0;
                     S2 += (e >= rpv[2] && e < rpv[3]) ? t : 0;
@@ -217,7 +220,7 @@ __device__ void graph_lds_half(const ChainDesc &d, const uint32_t *src, uint32_t
                 for (int j = 0; j < 4; ++j) {
                     if (v0 + j < n) {
                         const int own = lds_spin(src, v0 + j);
-                        const uint64_t T = d.lut[((Sv[j] + smax) * 2 + (own > 0)) * ncls + d.cls[v0 + j]];
+                        const uint64_t T = lut[((Sv[j] + smax) * 2 + (own > 0)) * ncls + d.cls[v0 + j]];
                         if ((uint64_t)u[j] < T) bits |= 1u << j;
                     }
                 }
@@ -252,9 +255,17 @@ __device__ void graph_lds_half(const ChainDesc &d, const uint32_t *src, uint32_t
 }
 
 __device__ void run_graph(const ChainDesc &d, uint32_t (*buf)[kPWords], uint32_t s0, int64_t n_full,
-                          int record, int track, int *sh_red, int *sh_plus, int *sh_flag) {
+                          int record, int track, int *sh_red, int *sh_plus, int *sh_flag,
+                          uint64_t *sh_lut) {
     const int n = d.n, nw = (n + 31) / 32;
     const bool obs = record || track;
+    // the chain's threshold table in LDS when it fits (constant during the call)
+    const int nlut = (2 * d.smax + 1) * 2 * d.ncls;
+    const uint64_t *lut = d.lut;
+    if (nlut <= kPLut) {
+        for (int i = threadIdx.x; i < nlut; i += kPBlock) sh_lut[i] = d.lut[i];
+        lut = sh_lut;
+    }
     const int8_t *g = (const int8_t *)d.spin[0];
     for (int w = threadIdx.x; w < nw; w += kPBlock) {
         uint32_t word = 0;
@@ -269,16 +280,16 @@ __device__ void run_graph(const ChainDesc &d, uint32_t (*buf)[kPWords], uint32_t
     int64_t best_h = INT64_MAX, last_h = 0;
     for (int64_t t = 0; t < n_full; ++t) {
         const uint32_t s = s0 + 2u * (uint32_t)t;
-        graph_lds_half(d, buf[0], buf[1], s, obs, sh_red, sh_plus, &o);
+        graph_lds_half(d, buf[0], buf[1], s, obs, sh_red, sh_plus, &o, lut);
         if (obs)
             observe_step(d, o, record ? d.log + t * d.log_stride : nullptr, track, &best_h, &last_h,
                          buf[0], nw, sh_flag);
         __syncthreads();
-        graph_lds_half(d, buf[1], buf[0], s + 1u, false, sh_red, sh_plus, nullptr);
+        graph_lds_half(d, buf[1], buf[0], s + 1u, false, sh_red, sh_plus, nullptr, lut);
         __syncthreads();
     }
     if (obs) {
-        graph_lds_half(d, buf[0], nullptr, s0, true, sh_red, sh_plus, &o);
+        graph_lds_half(d, buf[0], nullptr, s0, true, sh_red, sh_plus, &o, lut);
         observe_step(d, o, record ? d.log + n_full * d.log_stride : nullptr, track, &best_h, &last_h,
                      buf[0], nw, sh_flag);
         if (track && threadIdx.x == 0) {
@@ -302,6 +313,7 @@ __global__ __launch_bounds__(kPBlock) void k_persistent(const ChainDesc *__restr
     __shared__ int sh_flag;
     __shared__ int sh_red[2 * (kPBlock / 64)];
     __shared__ int sh_plus[kPClasses];
+    __shared__ uint64_t sh_lut[kPLut];
     for (;;) {
         if (threadIdx.x == 0) {
             const int k = atomicAdd(counter, 1);
@@ -318,7 +330,7 @@ __global__ __launch_bounds__(kPBlock) void k_persistent(const ChainDesc *__restr
             else
                 run_torus<false>(d, buf, s0, n_full, record, track, sh_red, &sh_flag);
         } else {
-            run_graph(d, buf, s0, n_full, record, track, sh_red, sh_plus, &sh_flag);
+            run_graph(d, buf, s0, n_full, record, track, sh_red, sh_plus, &sh_flag, sh_lut);
         }
         __syncthreads();
     }

@@ -87,44 +87,57 @@ __device__ __forceinline__ int xcd_block(int bx, int nb) {
 
 // ------------------------------------------------------ bit-packed torus
 
-// New word of 32 sites.  a, b: bit-planes of the two neighbours of the half,
-// c: the sites themselves, vm: valid bits, w: RNG word, s: half-step index.
-template <bool FOLD3>
-__device__ __forceinline__ uint32_t bp_word(uint32_t a, uint32_t b, uint32_t c, uint32_t vm,
-                                            uint32_t w, uint32_t s, uint32_t rep, uint32_t k0,
-                                            uint32_t k1, const uint32_t *__restrict__ ts,
-                                            uint32_t sgn) {
-    const uint32_t both = a & b;   // n_plus = 2
-    const uint32_t one = a ^ b;    // n_plus = 1
-    // sign of h per site (class j = n_plus + 3 c)
-    const uint32_t slo = bfi(both, bitmask(sgn, 2), bfi(one, bitmask(sgn, 1), bitmask(sgn, 0)));
-    const uint32_t shi = bfi(both, bitmask(sgn, 5), bfi(one, bitmask(sgn, 4), bitmask(sgn, 3)));
-    const uint32_t smask = bfi(c, shi, slo);
-    // sign-folded classes: aligned (0,0)/(2,1), anti (2,0)/(0,1), one (1,*)
-    const uint32_t al = ~(a ^ c) & ~one;
+// Bit-planes of a word: the two neighbours of the half (a, b) and the sites
+// themselves (c).  With a uniform coupling a site belongs to class
+// j = n_plus + 3c; the sign plane says where h >= 0 (from the per-chain mask
+// sgn), `al` where the neighbours agree with the site (classes 0 and 5), `one`
+// where exactly one neighbour is +1.
+struct BpPlanes {
+    uint32_t one, both, al, c, smask;
+};
+
+__device__ __forceinline__ BpPlanes bp_planes(uint32_t a, uint32_t b, uint32_t c, uint32_t sgn) {
+    BpPlanes p;
+    p.both = a & b;
+    p.one = a ^ b;
+    const uint32_t slo = bfi(p.both, bitmask(sgn, 2), bfi(p.one, bitmask(sgn, 1), bitmask(sgn, 0)));
+    const uint32_t shi = bfi(p.both, bitmask(sgn, 5), bfi(p.one, bitmask(sgn, 4), bitmask(sgn, 3)));
+    p.smask = bfi(c, shi, slo);
+    p.al = ~(a ^ c) & ~p.one;
+    p.c = c;
+    return p;
+}
+
+// MSB-first comparison of the 32 bit-sliced uniforms of RNG word w with the
+// thresholds of their classes, level groups [G0, G1) (group g = levels
+// 4g..4g+3 = Philox((w, s, rep, g))), stopping once every site is decided.
+// und: sites still undecided; res: sites decided with v < t, where v = u with
+// the bits flipped where h >= 0 (u < 2^32 - t  <=>  not (~u < t)), so only
+// t <= 2^31 is compared.
+template <bool FOLD3, int G0, int G1>
+__device__ __forceinline__ void bp_groups(const BpPlanes &p, uint32_t &und, uint32_t &res,
+                                          uint32_t w, uint32_t s, uint32_t rep, uint32_t k0,
+                                          uint32_t k1, const uint32_t *__restrict__ ts) {
     const uint32_t t0 = ts[0], t1 = ts[1], t2 = ts[2], t3 = ts[3], t4 = ts[4], t5 = ts[5];
-    uint32_t und = vm, res = 0;
-
-#define SHAKEN_LEVEL(K, R)                                                                  \
-    {                                                                                       \
-        const int sh_ = 31 - (K);                                                           \
-        uint32_t t_;                                                                        \
-        if (FOLD3) {                                                                        \
-            t_ = bfi(one, bitmask(t1, sh_), bfi(al, bitmask(t5, sh_), bitmask(t2, sh_)));   \
-        } else {                                                                            \
-            const uint32_t lo_ = bfi(both, bitmask(t2, sh_),                                \
-                                     bfi(one, bitmask(t1, sh_), bitmask(t0, sh_)));         \
-            const uint32_t hi_ = bfi(both, bitmask(t5, sh_),                                \
-                                     bfi(one, bitmask(t4, sh_), bitmask(t3, sh_)));         \
-            t_ = bfi(c, hi_, lo_);                                                          \
-        }                                                                                   \
-        const uint32_t d_ = (R) ^ smask ^ t_;                                               \
-        res |= und & d_ & t_;                                                               \
-        und &= ~d_;                                                                         \
+#define SHAKEN_LEVEL(K, R)                                                                    \
+    {                                                                                         \
+        const int sh_ = 31 - (K);                                                             \
+        uint32_t t_;                                                                          \
+        if (FOLD3) {                                                                          \
+            t_ = bfi(p.one, bitmask(t1, sh_), bfi(p.al, bitmask(t5, sh_), bitmask(t2, sh_))); \
+        } else {                                                                              \
+            const uint32_t lo_ = bfi(p.both, bitmask(t2, sh_),                                \
+                                     bfi(p.one, bitmask(t1, sh_), bitmask(t0, sh_)));         \
+            const uint32_t hi_ = bfi(p.both, bitmask(t5, sh_),                                \
+                                     bfi(p.one, bitmask(t4, sh_), bitmask(t3, sh_)));         \
+            t_ = bfi(p.c, hi_, lo_);                                                          \
+        }                                                                                     \
+        const uint32_t d_ = (R) ^ p.smask ^ t_;                                               \
+        res |= und & d_ & t_;                                                                 \
+        und &= ~d_;                                                                           \
     }
-
 #pragma unroll
-    for (int g = 0; g < 8; ++g) {
+    for (int g = G0; g < G1; ++g) {
         const U4 r = philox10(w, s, rep, (uint32_t)g, k0, k1);
         SHAKEN_LEVEL(4 * g + 0, r.x)
         SHAKEN_LEVEL(4 * g + 1, r.y)
@@ -133,8 +146,19 @@ __device__ __forceinline__ uint32_t bp_word(uint32_t a, uint32_t b, uint32_t c, 
         if (und == 0) break;
     }
 #undef SHAKEN_LEVEL
-    // res: v < t with v = u ^ sign; the new spin is that bit flipped where h >= 0
-    return (res ^ smask) & vm;
+}
+
+// New word of 32 sites: a, b neighbour planes of the half, c the sites, vm the
+// valid bits, w the RNG word, s the half-step index.
+template <bool FOLD3>
+__device__ __forceinline__ uint32_t bp_word(uint32_t a, uint32_t b, uint32_t c, uint32_t vm,
+                                            uint32_t w, uint32_t s, uint32_t rep, uint32_t k0,
+                                            uint32_t k1, const uint32_t *__restrict__ ts,
+                                            uint32_t sgn) {
+    const BpPlanes p = bp_planes(a, b, c, sgn);
+    uint32_t und = vm, res = 0;
+    bp_groups<FOLD3, 0, 8>(p, und, res, w, s, rep, k0, k1, ts);
+    return (res ^ p.smask) & vm;
 }
 
 __device__ __forceinline__ uint32_t bp_valid(int L, int W, int wd) {

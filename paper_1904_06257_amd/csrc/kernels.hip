@@ -64,13 +64,33 @@ __device__ __forceinline__ int step_slot(const StepArgs &a, uint32_t s) {
     return (int)((s - (a.dstate ? a.dstate[1] : a.s_log0)) >> 1);
 }
 
+// Finish a word whose first level groups left sites undecided (groups 2..7).
+template <bool FOLD3>
+__device__ __noinline__ uint32_t bp_finish(uint32_t a, uint32_t b, uint32_t c, uint32_t und,
+                                           uint32_t res, uint32_t vm, uint32_t w, uint32_t s,
+                                           uint32_t rep, uint32_t k0, uint32_t k1,
+                                           const uint32_t *__restrict__ ts, uint32_t sgn) {
+    const BpPlanes p = bp_planes(a, b, c, sgn);
+    bp_groups<FOLD3, 2, 8>(p, und, res, w, s, rep, k0, k1, ts);
+    return (res ^ p.smask) & vm;
+}
+
 // One lane owns a strip of kRows words of one word column: it loads the strip,
-// the halo row below (dl) or above (ur) and the adjacent words that supply
-// the wrap-around bit, then updates the kRows words one after the other.  The
-// vertical neighbour of a row is the strip's next or previous row, already in
-// registers.
+// the halo row below (dl) or above (ur) and the adjacent words that supply the
+// wrap-around bit; the vertical neighbour of a row is the strip's next or
+// previous row, already in registers.
+//
+// Tail compaction: every word first runs level groups 0 and 1 (8 levels, after
+// which a word is still undecided with probability 1 - (1 - 2^-8)^32 = 0.118).
+// Undecided words are appended to a workgroup queue in LDS and finished
+// afterwards by all lanes of the workgroup together, so that a wavefront does
+// not idle while its slowest lane runs the rare deep levels.
+constexpr int kQCap = 512;
+
 template <bool OBS, bool FOLD3>
 __global__ __launch_bounds__(256) void k_torus_bp(const ChainDesc *__restrict__ descs, StepArgs sa) {
+    __shared__ uint32_t q_w[kQCap], q_a[kQCap], q_b[kQCap], q_c[kQCap], q_und[kQCap], q_res[kQCap];
+    __shared__ int q_n;
     const ChainDesc &d = descs[blockIdx.y];
     const uint32_t s = step_s(sa);
     const int phase = (int)(s & 1u);
@@ -83,51 +103,89 @@ __global__ __launch_bounds__(256) void k_torus_bp(const ChainDesc *__restrict__ 
     const uint32_t *__restrict__ in = (const uint32_t *)d.spin[phase];
     uint32_t *__restrict__ out = (uint32_t *)d.spin[phase ^ 1];
     const uint32_t k0 = (uint32_t)d.seed, k1 = (uint32_t)(d.seed >> 32);
+    const uint32_t rep = d.replica, sgn = d.sgn;
+    const uint32_t *ts = d.tsmall;
+    const int lane = threadIdx.x & 63;
+    if (threadIdx.x == 0) q_n = 0;
+    __syncthreads();
     int e_acc = 0, p_acc = 0;
-    if (gid < total) {
-        const int rb = gid / W, wd = gid - rb * W;
-        const int r0 = rb * kRows;
-        const int nr = min(kRows, L - r0);
-        const uint32_t vm = bp_valid(L, W, wd);
-        const int lastbits = (L - 1) & 31;
-        // adjacent word supplying the carry bit: left word (dl) / right word (ur)
-        const int wside = phase == 0 ? (wd > 0 ? wd - 1 : W - 1) : (wd < W - 1 ? wd + 1 : 0);
-        uint32_t own[kRows], side[kRows];
+    const bool live = gid < total;
+    const int rb = live ? gid / W : 0, wd = live ? gid - rb * W : 0;
+    const int r0 = rb * kRows;
+    const int nr = live ? min(kRows, L - r0) : 0;
+    const uint32_t vm = bp_valid(L, W, wd);
+    const int lastbits = (L - 1) & 31;
+    // adjacent word supplying the carry bit: left word (dl) / right word (ur)
+    const int wside = phase == 0 ? (wd > 0 ? wd - 1 : W - 1) : (wd < W - 1 ? wd + 1 : 0);
+    uint32_t own[kRows], side[kRows];
 #pragma unroll
-        for (int i = 0; i < kRows; ++i) {
-            if (i < nr) {
-                own[i] = in[(r0 + i) * W + wd];
-                side[i] = in[(r0 + i) * W + wside];
-            } else {
-                own[i] = 0u;
-                side[i] = 0u;
-            }
+    for (int i = 0; i < kRows; ++i) {
+        if (i < nr) {
+            own[i] = in[(r0 + i) * W + wd];
+            side[i] = in[(r0 + i) * W + wside];
+        } else {
+            own[i] = 0u;
+            side[i] = 0u;
         }
+    }
+    uint32_t halo = 0;
+    if (live) {
         const int rh = phase == 0 ? (r0 == 0 ? L - 1 : r0 - 1) : (r0 + nr == L ? 0 : r0 + nr);
-        const uint32_t halo = in[rh * W + wd];
+        halo = in[rh * W + wd];
+    }
 #pragma unroll
-        for (int i = 0; i < kRows; ++i) {
-            if (i < nr) {
-                uint32_t a, b;
-                if (phase == 0) {
-                    a = (i == 0) ? halo : own[i > 0 ? i - 1 : 0];
-                    const uint32_t carry = wd > 0 ? (side[i] >> 31) : ((side[i] >> lastbits) & 1u);
-                    b = (own[i] << 1) | carry;
-                } else {
-                    a = (i == nr - 1) ? halo : own[i < kRows - 1 ? i + 1 : 0];
-                    b = wd < W - 1 ? ((own[i] >> 1) | (side[i] << 31))
-                                   : ((own[i] >> 1) | ((side[i] & 1u) << lastbits));
-                }
-                const int widx = (r0 + i) * W + wd;
-                out[widx] = bp_word<FOLD3>(a, b, own[i], vm, (uint32_t)widx, s, d.replica, k0, k1,
-                                           d.tsmall, d.sgn);
-                if (OBS) {
-                    e_acc += d.J * (2 * __popc(vm) - 2 * __popc((own[i] ^ a) & vm) -
-                                    2 * __popc((own[i] ^ b) & vm));
-                    p_acc += __popc(own[i] & vm);
-                }
+    for (int i = 0; i < kRows; ++i) {
+        const bool act = i < nr;
+        uint32_t a = 0, b = 0, und = 0, res = 0;
+        BpPlanes p;
+        const int widx = (r0 + i) * W + wd;
+        if (act) {
+            if (phase == 0) {
+                a = (i == 0) ? halo : own[i > 0 ? i - 1 : 0];
+                const uint32_t carry = wd > 0 ? (side[i] >> 31) : ((side[i] >> lastbits) & 1u);
+                b = (own[i] << 1) | carry;
+            } else {
+                a = (i == nr - 1) ? halo : own[i < kRows - 1 ? i + 1 : 0];
+                b = wd < W - 1 ? ((own[i] >> 1) | (side[i] << 31))
+                               : ((own[i] >> 1) | ((side[i] & 1u) << lastbits));
+            }
+            p = bp_planes(a, b, own[i], sgn);
+            und = vm;
+            bp_groups<FOLD3, 0, 2>(p, und, res, (uint32_t)widx, s, rep, k0, k1, ts);
+            if (OBS) {
+                e_acc += d.J * (2 * __popc(vm) - 2 * __popc((own[i] ^ a) & vm) -
+                                2 * __popc((own[i] ^ b) & vm));
+                p_acc += __popc(own[i] & vm);
             }
         }
+        const bool pend = act && und != 0;
+        const unsigned long long bal = __ballot(pend);
+        int base = 0;
+        if (lane == 0 && bal) base = atomicAdd(&q_n, (int)__popcll(bal));
+        base = __shfl(base, 0, 64);
+        if (act) {
+            const int q = base + (int)__popcll(bal & ((1ull << lane) - 1ull));
+            if (!pend) {
+                out[widx] = (res ^ p.smask) & vm;
+            } else if (q < kQCap) {
+                q_w[q] = (uint32_t)widx;
+                q_a[q] = a;
+                q_b[q] = b;
+                q_c[q] = own[i];
+                q_und[q] = und;
+                q_res[q] = res;
+            } else {
+                out[widx] = bp_finish<FOLD3>(a, b, own[i], und, res, vm, (uint32_t)widx, s, rep, k0, k1, ts, sgn);
+            }
+        }
+    }
+    __syncthreads();
+    const int Q = min(q_n, kQCap);
+    for (int it = threadIdx.x; it < Q; it += blockDim.x) {
+        const uint32_t w = q_w[it];
+        const uint32_t vw = bp_valid(L, W, (int)(w % (uint32_t)W));
+        out[w] = bp_finish<FOLD3>(q_a[it], q_b[it], q_c[it], q_und[it], q_res[it], vw, w, s, rep, k0,
+                                  k1, ts, sgn);
     }
     if (OBS && bx * (int)blockDim.x < total)
         block_accumulate2(e_acc, p_acc, log_part(d, slot, bx));
@@ -200,6 +258,7 @@ __global__ __launch_bounds__(256) void k_torus_i8(const ChainDesc *__restrict__ 
 // edge range in chunks of 8 whose loads are all issued before any is used;
 // an edge is attributed to its vertex by comparing with the row bounds.
 constexpr int kEdgeChunk = 8;
+constexpr int kLdsLut = 512;  // threshold entries kept in LDS
 
 template <bool OBS>
 __global__ __launch_bounds__(256) void k_graph(const ChainDesc *__restrict__ descs, StepArgs sa) {
@@ -218,16 +277,32 @@ __global__ __launch_bounds__(256) void k_graph(const ChainDesc *__restrict__ des
     const uint8_t *__restrict__ cls = d.cls;
     const int ncls = d.ncls, smax = d.smax;
     int e_acc = 0;
+    // threshold table in LDS when it is small (every 3-regular +-J graph: 14 entries)
+    __shared__ uint64_t sh_lut[kLdsLut];
+    const int nlut = (2 * smax + 1) * 2 * ncls;
+    const bool lut_lds = nlut <= kLdsLut;
+    if (lut_lds) {
+        for (int i = threadIdx.x; i < nlut; i += blockDim.x) sh_lut[i] = d.lut[i];
+    }
     extern __shared__ int sh_plus[];  // ncls counters (OBS only)
     if (OBS) {
         for (int i = threadIdx.x; i < ncls; i += blockDim.x) sh_plus[i] = 0;
-        __syncthreads();
     }
+    __syncthreads();
     if (v0 < n) {
         const bool full = v0 + 3 < n;
         int rpv[5];
+        if (full) {
+            const int4 r4 = *(const int4 *)(rp + v0);
+            rpv[0] = r4.x;
+            rpv[1] = r4.y;
+            rpv[2] = r4.z;
+            rpv[3] = r4.w;
+            rpv[4] = rp[v0 + 4];
+        } else {
 #pragma unroll
-        for (int j = 0; j < 5; ++j) rpv[j] = rp[min(v0 + j, n)];
+            for (int j = 0; j < 5; ++j) rpv[j] = rp[min(v0 + j, n)];
+        }
         int own[4], cl[4];
         if (full) {
             const uint32_t o4 = *(const uint32_t *)(in + v0);
@@ -247,20 +322,22 @@ __global__ __launch_bounds__(256) void k_graph(const ChainDesc *__restrict__ des
         const U4 r = philox10((uint32_t)q4, s, d.replica, kGraphStream, (uint32_t)d.seed,
                               (uint32_t)(d.seed >> 32));
         int S0 = 0, S1 = 0, S2 = 0, S3 = 0;
-        for (int base = rpv[0]; base < rpv[4]; base += kEdgeChunk) {
+        const int last = rpv[4] - 1;
+        for (int base = rpv[0]; base <= last; base += kEdgeChunk) {
+            // clamped indices: every load is valid and issued before any is used
             int cc[kEdgeChunk], jj[kEdgeChunk], sv[kEdgeChunk];
 #pragma unroll
             for (int k = 0; k < kEdgeChunk; ++k) {
-                const int e = base + k;
-                cc[k] = e < rpv[4] ? col[e] : 0;
-                jj[k] = e < rpv[4] ? (int)jw[e] : 0;
+                const int e = min(base + k, last);
+                cc[k] = col[e];
+                jj[k] = (int)jw[e];
             }
 #pragma unroll
             for (int k = 0; k < kEdgeChunk; ++k) sv[k] = (int)in[cc[k]];
 #pragma unroll
             for (int k = 0; k < kEdgeChunk; ++k) {
                 const int e = base + k;
-                const int t = jj[k] * sv[k];
+                const int t = e <= last ? jj[k] * sv[k] : 0;
                 S0 += e < rpv[1] ? t : 0;
                 S1 += (e >= rpv[1] && e < rpv[2]) ? t : 0;
                 S2 += (e >= rpv[2] && e < rpv[3]) ? t : 0;
@@ -272,7 +349,8 @@ __global__ __launch_bounds__(256) void k_graph(const ChainDesc *__restrict__ des
         uint32_t packed = 0;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const uint64_t T = d.lut[((Sv[j] + smax) * 2 + (own[j] > 0)) * ncls + cl[j]];
+            const int key = ((Sv[j] + smax) * 2 + (own[j] > 0)) * ncls + cl[j];
+            const uint64_t T = lut_lds ? sh_lut[key] : d.lut[key];
             const uint32_t nv = ((uint64_t)u[j] < T) ? 0x01u : 0xFFu;
             packed |= nv << (8 * j);
             if (OBS && v0 + j < n) {

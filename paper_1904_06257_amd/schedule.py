@@ -8,8 +8,9 @@ held-out instances at equal sweeps.
     python -m paper_1904_06257_amd.schedule eval --weights weights.npz
 
 Everything that touches the chains or the network goes through libshaken.
-Instance seeds: training [10^6, 10^6 + 10^5), evaluation [9 * 10^6, 9 * 10^6 +
-512) -- disjoint.
+Instance seeds: training [10^6, 10^6 + 10^5), validation (choice of the
+training round) [5 * 10^6, ...), evaluation [9 * 10^6, 9 * 10^6 + 512) --
+disjoint.
 """
 from __future__ import annotations
 
@@ -26,6 +27,7 @@ from . import anneal
 
 TRAIN_SEED0 = 1_000_000
 EVAL_SEED0 = 9_000_000
+VAL_SEED0 = 5_000_000
 SIZES = (4096, 16384, 65536)
 
 
@@ -77,12 +79,13 @@ def tune_geometric(insts, seeds, sweeps, chunk):
     return anneal.GeometricPolicy(b0, b1, q), results
 
 
-def generate(insts, seeds, base, k_sched, sweeps, chunk, seed):
+def generate(insts, seeds, base, k_sched, sweeps, chunk, seed, scale=1.0):
     """k_sched perturbed schedules per instance, all in one batch."""
     big = [g for g in insts for _ in range(k_sched)]
     bseeds = np.repeat(seeds, k_sched)
     n_chunks = sweeps // chunk
-    pol = anneal.PerturbedPolicy(base, len(big), n_chunks, seed)
+    pol = anneal.PerturbedPolicy(base, len(big), n_chunks, seed, sigma_b=0.12 * scale,
+                                 sigma_q=0.15 * scale, q_spread=0.6 * scale)
     t0 = time.perf_counter()
     res = anneal.run(big, bseeds, pol, sweeps, chunk)
     _log("generated %d runs in %.1f s" % (len(big), time.perf_counter() - t0))
@@ -115,24 +118,29 @@ def train(args):
     base, grid_res = tune_geometric(insts[::step], seeds[::step], args.sweeps, args.chunk)
     mlp = MLP()
     mlp.set_params(anneal.init_params(args.seed))
+    val_insts, val_seeds = instances(VAL_SEED0, tuple(int(c) for c in args.val_counts.split(",")))
     policy = base
     history = []
+    best_params, best_gain = None, -np.inf
     for rnd in range(args.rounds):
-        res = generate(insts, seeds, policy, args.k_sched, args.sweeps, args.chunk, seed=100 + rnd)
+        scale = args.noise_decay ** rnd
+        res = generate(insts, seeds, policy, args.k_sched, args.sweeps, args.chunk, seed=100 + rnd,
+                       scale=scale)
         X, Y = dataset(res, insts, args.k_sched, args.elite)
-        _log("round %d: %d rows" % (rnd, X.shape[0]))
+        _log("round %d (noise scale %.2f): %d rows" % (rnd, scale, X.shape[0]))
         losses = anneal.train_mlp(mlp, X, Y, np.ones(X.shape[0]), args.epochs, 512, args.lr,
-                                  seed=rnd, log=_log if rnd == args.rounds - 1 else None)
+                                  seed=rnd, log=None)
         policy = anneal.MLPPolicy(mlp)
-        # learned vs plain on the training instances (one run each)
-        rl = anneal.run(insts, seeds, policy, args.sweeps, args.chunk)
-        rp = anneal.run(insts, seeds, base, args.sweeps, args.chunk)
-        ns = np.array([g.n for g in insts], dtype=np.float64)
-        d = (rp.best - rl.best) / ns
-        history.append(dict(round=rnd, rows=int(X.shape[0]), final_loss=losses[-1],
-                            train_gain_mean=float(d.mean()), train_win_rate=float((d > 0).mean())))
-        _log("round %d: training-set gain (plain - learned) mean %.5f, learned better on %.0f%%"
-             % (rnd, d.mean(), 100 * (d > 0).mean()))
+        # learned vs plain on the validation instances (disjoint from training and evaluation)
+        val, _, _ = compare(val_insts, val_seeds, mlp, base, args.sweeps, args.chunk)
+        gain = val["all"]["gain_mean"]
+        history.append(dict(round=rnd, rows=int(X.shape[0]), final_loss=losses[-1], noise=scale,
+                            val_gain_mean=gain, val_win_rate=val["all"]["win_rate"]))
+        _log("round %d: loss %.5f, validation gain (plain - learned) %.5f per spin, learned better "
+             "on %.0f%%" % (rnd, losses[-1], gain, 100 * val["all"]["win_rate"]))
+        if gain > best_gain:
+            best_gain, best_params = gain, mlp.params().copy()
+    mlp.set_params(best_params)
     P = mlp.params()
     meta = dict(sweeps=args.sweeps, chunk=args.chunk, train_counts=counts, k_sched=args.k_sched,
                 elite=args.elite, rounds=args.rounds, epochs=args.epochs, lr=args.lr,
@@ -212,6 +220,8 @@ def main(argv=None):
     t.add_argument("--rounds", type=int, default=1)
     t.add_argument("--epochs", type=int, default=150)
     t.add_argument("--lr", type=float, default=1e-3)
+    t.add_argument("--val-counts", default="16,16,4")
+    t.add_argument("--noise-decay", type=float, default=0.6)
     t.add_argument("--seed", type=int, default=0)
     e = sub.add_parser("eval")
     e.add_argument("--weights", required=True)

@@ -158,3 +158,32 @@ def test_anneal_replay_parity(env):
         assert res.last[i] == -oracle.graph_observe(og, x)[0]
         assert res.best[i] == best
         assert -oracle.graph_observe(og, res.best_spins[i])[0] == best
+
+
+def test_learned_schedule_beats_plain(env):
+    """The committed network against the tuned geometric schedule on held-out
+    instances (evaluation seeds, same Philox seeds for both), 10^4 sweeps:
+    every reported energy is recomputed by the oracle from the returned
+    configurations, and the learned schedule reaches lower best energies."""
+    sk, torch = env
+    import os
+    from paper_1904_06257_amd import anneal, schedule
+    P, meta = schedule.load(os.path.join(os.path.dirname(sk.__file__), "schedule_weights.npz"))
+    g = meta["geometric"]
+    mlp = sk.MLP()
+    mlp.set_params(P)
+    insts, seeds = schedule.instances(schedule.EVAL_SEED0 + 1000, (12, 12, 4))
+    rl = anneal.run(insts, seeds, anneal.MLPPolicy(mlp), 10000, 250, keep_spins=True)
+    rp = anneal.run(insts, seeds, anneal.GeometricPolicy(g["beta0"], g["beta1"], g["q"]), 10000, 250,
+                    keep_spins=True)
+    ns = np.array([x.n for x in insts], dtype=np.float64)
+    for res in (rl, rp):
+        for i, x in enumerate(insts):
+            og = oracle.Graph(x.n, x.src, x.dst, x.J, x.cls, x.lam_values)
+            assert -oracle.graph_observe(og, res.best_spins[i])[0] == res.best[i]
+            assert -oracle.graph_observe(og, res.final_spins[i])[0] == res.last[i]
+    d = (rp.best - rl.best) / ns
+    print("learned vs plain: mean gain %.5f per spin, learned better on %d of %d"
+          % (d.mean(), (d > 0).sum(), len(d)), flush=True)
+    assert d.mean() > 0.004
+    assert (d > 0).mean() > 0.75
