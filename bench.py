@@ -47,7 +47,7 @@ BP_BYTES_PER_SITE = 0.25  # read 1 bit, write 1 bit
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("kernels.hip", "batch.hip", "shaken_internal.hpp"):
+    for f in ("kernels.hip", "batch.hip", "device.hpp", "shaken_internal.hpp"):
         with open(os.path.join(ROOT, "paper_1904_06257_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

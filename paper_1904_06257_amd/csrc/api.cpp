@@ -1072,8 +1072,8 @@ shaken_status shaken_batch_create(shaken_batch **out, shaken_ctx *const *ctx, in
         int ncu = 256;
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, b->device) == hipSuccess) ncu = prop.multiProcessorCount;
-        // 16 KiB of LDS and 4 waves per workgroup: 8 workgroups fit on a CU
-        b->pgrid = std::min(n, 8 * ncu);
+        // 16 waves per workgroup: 2 workgroups fit on a CU (8 waves per SIMD)
+        b->pgrid = std::min(n, 2 * ncu);
     }
     if ((st = batch_upload(b)) != SHAKEN_OK) return bail(st);
     *out = b;

@@ -13,7 +13,7 @@
 
 namespace shaken {
 
-constexpr int kPBlock = 256;
+constexpr int kPBlock = 1024;  // 16 waves per chain
 constexpr int kPWords = 2048;
 constexpr int kPClasses = 16;
 constexpr int kPLut = 256;  // threshold entries kept in LDS
@@ -127,13 +127,12 @@ __device__ void observe_step(const ChainDesc &d, const Obs &o, int64_t *log_slot
 
 template <bool FOLD3>
 __device__ void run_torus(const ChainDesc &d, uint32_t (*buf)[kPWords], uint32_t s0, int64_t n_full,
-                          int record, int track, int *sh_red, int *sh_flag) {
+                          int record, int track, int *sh_red, int *sh_flag, Obs &o) {
     const int nw = d.L * d.W;
     const bool obs = record || track;
     const uint32_t *g = (const uint32_t *)d.spin[0];
     for (int w = threadIdx.x; w < nw; w += kPBlock) buf[0][w] = g[w];
     __syncthreads();
-    Obs o;
     int64_t best_h = INT64_MAX, last_h = 0;
     for (int64_t t = 0; t < n_full; ++t) {
         const uint32_t s = s0 + 2u * (uint32_t)t;
@@ -213,6 +212,15 @@ __device__ void graph_lds_half(const ChainDesc &d, const uint32_t *src, uint32_t
                 }
             }
             const int Sv[4] = {S0, S1, S2, S3};
+            int cl[4];
+            if (v0 + 3 < n) {
+                const uint32_t c4 = *(const uint32_t *)(d.cls + v0);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) cl[j] = (int)((c4 >> (8 * j)) & 0xFFu);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) cl[j] = v0 + j < n ? d.cls[v0 + j] : 0;
+            }
             if (dst) {
                 const U4 r = philox10((uint32_t)q4, s, d.replica, kGraphStream, k0, k1);
                 const uint32_t u[4] = {r.x, r.y, r.z, r.w};
@@ -220,7 +228,7 @@ __device__ void graph_lds_half(const ChainDesc &d, const uint32_t *src, uint32_t
                 for (int j = 0; j < 4; ++j) {
                     if (v0 + j < n) {
                         const int own = lds_spin(src, v0 + j);
-                        const uint64_t T = lut[((Sv[j] + smax) * 2 + (own > 0)) * ncls + d.cls[v0 + j]];
+                        const uint64_t T = lut[((Sv[j] + smax) * 2 + (own > 0)) * ncls + cl[j]];
                         if ((uint64_t)u[j] < T) bits |= 1u << j;
                     }
                 }
@@ -231,7 +239,7 @@ __device__ void graph_lds_half(const ChainDesc &d, const uint32_t *src, uint32_t
                     if (v0 + j < n) {
                         const int own = lds_spin(src, v0 + j);
                         e_acc += own * Sv[j];
-                        if (own > 0) atomicAdd(&sh_plus[d.cls[v0 + j]], 1);
+                        if (own > 0) atomicAdd(&sh_plus[cl[j]], 1);
                     }
                 }
             }
@@ -256,7 +264,7 @@ __device__ void graph_lds_half(const ChainDesc &d, const uint32_t *src, uint32_t
 
 __device__ void run_graph(const ChainDesc &d, uint32_t (*buf)[kPWords], uint32_t s0, int64_t n_full,
                           int record, int track, int *sh_red, int *sh_plus, int *sh_flag,
-                          uint64_t *sh_lut) {
+                          uint64_t *sh_lut, Obs &o) {
     const int n = d.n, nw = (n + 31) / 32;
     const bool obs = record || track;
     // the chain's threshold table in LDS when it fits (constant during the call)
@@ -276,7 +284,6 @@ __device__ void run_graph(const ChainDesc &d, uint32_t (*buf)[kPWords], uint32_t
         buf[0][w] = word;
     }
     __syncthreads();
-    Obs o;
     int64_t best_h = INT64_MAX, last_h = 0;
     for (int64_t t = 0; t < n_full; ++t) {
         const uint32_t s = s0 + 2u * (uint32_t)t;
@@ -314,6 +321,7 @@ __global__ __launch_bounds__(kPBlock) void k_persistent(const ChainDesc *__restr
     __shared__ int sh_red[2 * (kPBlock / 64)];
     __shared__ int sh_plus[kPClasses];
     __shared__ uint64_t sh_lut[kPLut];
+    __shared__ Obs sh_obs;  // observables of the current configuration (thread 0)
     for (;;) {
         if (threadIdx.x == 0) {
             const int k = atomicAdd(counter, 1);
@@ -326,11 +334,11 @@ __global__ __launch_bounds__(kPBlock) void k_persistent(const ChainDesc *__restr
         const ChainDesc &d = descs[item];
         if (d.kind == KIND_TORUS) {
             if (d.fold3)
-                run_torus<true>(d, buf, s0, n_full, record, track, sh_red, &sh_flag);
+                run_torus<true>(d, buf, s0, n_full, record, track, sh_red, &sh_flag, sh_obs);
             else
-                run_torus<false>(d, buf, s0, n_full, record, track, sh_red, &sh_flag);
+                run_torus<false>(d, buf, s0, n_full, record, track, sh_red, &sh_flag, sh_obs);
         } else {
-            run_graph(d, buf, s0, n_full, record, track, sh_red, sh_plus, &sh_flag, sh_lut);
+            run_graph(d, buf, s0, n_full, record, track, sh_red, sh_plus, &sh_flag, sh_lut, sh_obs);
         }
         __syncthreads();
     }

@@ -418,19 +418,26 @@ __global__ __launch_bounds__(256) void k_observe(const ChainDesc *__restrict__ d
         if (active_block) block_accumulate2(e_acc, p_acc, lg);
         return;
     }
-    // graph: E_J via the in-half of every vertex, plus counts per class
-    if (blockIdx.x * blockDim.x >= (unsigned)d.n) return;
+    // graph: E_J via the in-half of every vertex, plus counts per class (LDS
+    // counters, one atomic per class and block)
+    __shared__ int sh_cls[256];
+    const int ncls = d.ncls;
+    for (int i = threadIdx.x; i < ncls; i += blockDim.x) sh_cls[i] = 0;
+    __syncthreads();
     if (gid < d.n) {
         const int8_t *sp = (const int8_t *)d.spin[idx];
         int S = 0;
         for (int e = d.rowptr[0][gid]; e < d.rowptr[0][gid + 1]; ++e) S += d.jw[0][e] * sp[d.col[0][e]];
         const int own = sp[gid];
         e_acc = own * S;
-        if (own > 0) atomicAdd((unsigned long long *)&lg[1 + d.cls[gid]], 1ull);
+        if (own > 0) atomicAdd(&sh_cls[d.cls[gid]], 1);
     }
     e_acc = wave_sum(e_acc);
     if ((threadIdx.x & 63) == 0 && e_acc)
         atomicAdd((unsigned long long *)&lg[0], (unsigned long long)(long long)e_acc);
+    __syncthreads();
+    for (int i = threadIdx.x; i < ncls; i += blockDim.x)
+        if (sh_cls[i]) atomicAdd((unsigned long long *)&lg[1 + i], (unsigned long long)sh_cls[i]);
 }
 
 // ---------------------------------------------------------------- helpers

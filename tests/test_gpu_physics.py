@@ -1,0 +1,106 @@
+"""Statistical checks of the GPU sampler at scale against closed forms.
+
+Theorem 3.1: for large self-interaction q (delta = exp(-2 beta q) small) the
+stationary law of shaken dynamics on the square lattice approaches the Gibbs
+law of H.  The energy per site and the spontaneous magnetisation measured on
+batches of tori must then approach Onsager's exact energy and Yang's
+magnetisation of the 2-D Ising model, with a deviation shrinking roughly like
+exp(-2 beta (q - 2J)) (the weight of the tau != sigma terms in Zfwd).
+Reversibility (Theorem 2.3) is checked as the time symmetry of the
+(M, E_J) cross-correlation.
+"""
+import numpy as np
+import pytest
+from scipy.special import ellipk
+
+pytestmark = pytest.mark.gpu
+
+
+def onsager_u(beta):
+    """Energy per site of the 2-D Ising model, J = 1 (Onsager)."""
+    k = 2 * np.sinh(2 * beta) / np.cosh(2 * beta) ** 2
+    return -1 / np.tanh(2 * beta) * (1 + 2 / np.pi * (2 * np.tanh(2 * beta) ** 2 - 1) * ellipk(k * k))
+
+
+def yang_m(beta):
+    return (1 - np.sinh(2 * beta) ** -4) ** 0.125
+
+
+@pytest.fixture(scope="module")
+def sk():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    import paper_1904_06257_amd as m
+    return m
+
+
+def _measure(sk, beta, q, init, L=128, reps=64, burn=2000, blocks=10, block_steps=200):
+    chains = [sk.Chain.torus(L, q=q, beta=beta, seed=1000 + r, replica=r, init=init)
+              for r in range(reps)]
+    b = sk.Batch(chains, strategy="persistent", record=True)
+    b.sweep(burn)
+    es, ms = [], []
+    for _ in range(blocks):
+        b.sweep(block_steps)
+        for i in range(reps):
+            h, m = b.log(i)
+            es.append(h[1:])
+            ms.append(m[1:])
+    b.close()
+    for c in chains:
+        c.close()
+    N = L * L
+    e = np.array(es, dtype=np.float64) / N        # H per site (lambda = 0: H = -E_J)
+    m = np.abs(np.array(ms, dtype=np.float64)) / N
+    # error bar from the spread of per-block means
+    be = e.reshape(blocks * reps, -1).mean(axis=1)
+    return e.mean(), be.std(ddof=1) / np.sqrt(be.size), m.mean()
+
+
+# q values per beta: the mobility falls like eps too (a spin against its
+# neighbours and q flips with probability ~ exp(-2 beta (q - 2J))), so the
+# largest q is limited by what a few thousand steps equilibrate.
+@pytest.mark.parametrize("beta,init,qs,burn", [(0.30, "random", (4.0, 6.0, 8.0), 2000),
+                                               (0.50, "all_up", (4.0, 5.0, 6.0), 4000)])
+def test_large_q_approaches_onsager(sk, beta, init, qs, burn):
+    u0 = onsager_u(beta)
+    devs = []
+    for q in qs:
+        u, err, m = _measure(sk, beta, q, init, burn=burn)
+        eps = np.exp(-2 * beta * (q - 2.0))
+        devs.append(abs(u - u0))
+        print("beta %.2f q %.0f: u %.5f +- %.5f (Onsager %.5f, dev %.5f, eps %.4f), |m| %.4f"
+              % (beta, q, u, err, u0, u - u0, eps, m), flush=True)
+        # first-order correction in eps (the tau != sigma terms of Zfwd whose
+        # weight is largest, exp(-2 beta (q - 2J))): |dev| <= 0.75 eps
+        assert abs(u - u0) <= 0.75 * eps + 6 * err + 1e-3
+        if beta > 0.44:
+            assert abs(m - yang_m(beta)) <= 0.75 * eps + 2e-3
+    assert devs[0] > devs[1] > devs[2]
+
+
+def test_time_reversibility(sk):
+    """Theorem 2.3: the chain is reversible, so in equilibrium
+    E[A(s_t) B(s_{t+1})] = E[B(s_t) A(s_{t+1})] for A = M^2, B = H (full
+    steps; M itself is odd under the global flip and would make the check
+    trivial)."""
+    L, reps, beta, q = 64, 128, 0.42, 1.0
+    chains = [sk.Chain.torus(L, q=q, beta=beta, seed=77 + r, replica=r) for r in range(reps)]
+    b = sk.Batch(chains, strategy="persistent", record=True)
+    b.sweep(500)
+    a, c = [], []
+    for _ in range(4):
+        b.sweep(500)
+        for i in range(reps):
+            h, m = b.log(i)
+            h = h.astype(np.float64) - h.mean()
+            m2 = m.astype(np.float64) ** 2
+            m2 -= m2.mean()
+            a.append((m2[:-1] * h[1:]).mean())
+            c.append((h[:-1] * m2[1:]).mean())
+    d = np.array(a) - np.array(c)
+    z = d.mean() / (d.std(ddof=1) / np.sqrt(d.size))
+    print("reversibility: mean difference %.3f, z = %.2f" % (d.mean(), z), flush=True)
+    assert abs(z) < 4.5
