@@ -136,7 +136,7 @@ def bench_graph(args, sk):
     n = 1 << 20
     inst = synth.oriented_instance(n, 3, 3, lam_values=(-0.5, 0.0, 0.5), pm_j=True)
     ch = sk.Chain.graph(n, inst.src, inst.dst, J=inst.J, lam_values=inst.lam_values,
-                        lam_class=inst.cls, q=1.5, beta=0.8, seed=1)
+                        lam_class=inst.cls, q=1.5, beta=0.8, seed=1, layout="csr")
     batch = sk.Batch([ch], strategy="grid", use_hipgraph=True, record=True, autotune=True)
     batch.sweep(args.warmup)
     torch.cuda.synchronize()

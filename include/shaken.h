@@ -118,6 +118,15 @@ enum {
     SHAKEN_INIT_USER = 3       /* init_spins: host int8, +1/-1, n or L*L      */
 };
 
+enum {
+    SHAKEN_LAYOUT_AUTO = 0,    /* ELL when it applies, else CSR               */
+    SHAKEN_LAYOUT_CSR = 1,     /* in-half and out-half CSR (any graph)        */
+    SHAKEN_LAYOUT_ELL = 2      /* couplings +-1 and degree <= 4 only: one
+                                  slot-major record per neighbour slot holding
+                                  the index, the half it belongs to and the
+                                  sign of J                                   */
+};
+
 typedef struct shaken_opts {
     int32_t format;            /* SHAKEN_FMT_*                                */
     int32_t init;              /* SHAKEN_INIT_*                               */
@@ -125,6 +134,8 @@ typedef struct shaken_opts {
     uint32_t replica;          /* third Philox counter word                   */
     int32_t device;            /* HIP device ordinal; -1 = current device     */
     void *stream;              /* hipStream_t; NULL = the null stream         */
+    int32_t graph_layout;      /* SHAKEN_LAYOUT_* (graphs only)               */
+    int32_t reserved;
 } shaken_opts;
 
 typedef struct shaken_ctx shaken_ctx;

@@ -43,6 +43,8 @@ _INIT = {"random": SHAKEN_INIT_RANDOM, "all_up": SHAKEN_INIT_ALL_UP,
 _FMT = {"auto": SHAKEN_FMT_AUTO, "int8": SHAKEN_FMT_INT8, "bitpacked": SHAKEN_FMT_BITPACKED}
 _STRAT = {"auto": SHAKEN_BATCH_AUTO, "grid": SHAKEN_BATCH_GRID,
           "persistent": SHAKEN_BATCH_PERSISTENT}
+SHAKEN_LAYOUT_AUTO, SHAKEN_LAYOUT_CSR, SHAKEN_LAYOUT_ELL = 0, 1, 2
+_LAYOUT = {"auto": SHAKEN_LAYOUT_AUTO, "csr": SHAKEN_LAYOUT_CSR, "ell": SHAKEN_LAYOUT_ELL}
 
 
 class shaken_graph(ctypes.Structure):
@@ -59,7 +61,8 @@ class shaken_field(ctypes.Structure):
 class shaken_opts(ctypes.Structure):
     _fields_ = [("format", ctypes.c_int32), ("init", ctypes.c_int32),
                 ("init_spins", ctypes.POINTER(ctypes.c_int8)), ("replica", ctypes.c_uint32),
-                ("device", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("device", ctypes.c_int32), ("stream", ctypes.c_void_p),
+                ("graph_layout", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class shaken_obs(ctypes.Structure):
@@ -201,7 +204,7 @@ class Chain:
 
     def __init__(self, kind, *, L=0, n=0, src=None, dst=None, J=None, lam_values=None,
                  lam_class=None, q=1.0, beta=1.0, seed=0, replica=0, init="random",
-                 init_spins=None, fmt="auto", device=-1, stream=None):
+                 init_spins=None, fmt="auto", device=-1, stream=None, layout="auto"):
         g = shaken_graph()
         self._keep = []
         if kind == "torus":
@@ -241,6 +244,7 @@ class Chain:
         o.replica = int(replica)
         o.device = int(device)
         o.stream = _stream_handle(stream)
+        o.graph_layout = _LAYOUT[layout]
         self.kind = kind
         self.handle = shaken_init(g, Jarr, field, q, beta, seed, o)
         self._keep = None

@@ -131,6 +131,9 @@ struct shaken_ctx {
     int32_t *col[2] = {nullptr, nullptr};
     int8_t *jw[2] = {nullptr, nullptr};
     uint8_t *cls_dev = nullptr;
+    uint32_t *ell_dev = nullptr;
+    int ell_k = 0;
+    int64_t ell_stride = 0;
     int64_t *log_dev = nullptr;
     int64_t log_cap = 0;  // slots
     int64_t *obs_dev = nullptr;
@@ -160,6 +163,7 @@ void release(shaken_ctx *c) {
         dfree(c->jw[h]);
     }
     dfree(c->cls_dev);
+    dfree(c->ell_dev);
     dfree(c->log_dev);
     dfree(c->obs_dev);
     dfree(c->dd);
@@ -324,7 +328,40 @@ struct HostLayout {
     std::vector<uint8_t> cls_host;
     std::vector<int32_t> rp[2], col[2];
     std::vector<int8_t> jw[2];
+    std::vector<uint32_t> ell;  // slot-major, ell_k * ell_stride entries
+    int ell_k = 0;
+    int64_t ell_stride = 0;
 };
+
+// ELL layout when every coupling is +-1 and every vertex has at most 4
+// neighbours: slot k of vertex v holds the neighbour index, the half it belongs
+// to (1 = in-half, 2 = out-half) and the sign of J; empty slots point to v
+// itself with half 0.  Returns false when the layout does not apply.
+bool build_ell(int n, HostLayout &hl) {
+    if (n >= (1 << 29)) return false;
+    int kmax = 0;
+    for (int v = 0; v < n; ++v) {
+        const int deg = (hl.rp[0][v + 1] - hl.rp[0][v]) + (hl.rp[1][v + 1] - hl.rp[1][v]);
+        kmax = std::max(kmax, deg);
+    }
+    if (kmax == 0 || kmax > 4) return false;
+    for (int h = 0; h < 2; ++h)
+        for (int8_t j : hl.jw[h])
+            if (j != 1 && j != -1) return false;
+    hl.ell_k = kmax;
+    hl.ell_stride = ((int64_t)n + 3) / 4 * 4;
+    hl.ell.assign((size_t)kmax * hl.ell_stride, 0u);
+    for (int64_t v = 0; v < hl.ell_stride; ++v)
+        for (int k = 0; k < kmax; ++k) hl.ell[k * hl.ell_stride + v] = (uint32_t)std::min<int64_t>(v, n - 1);
+    for (int v = 0; v < n; ++v) {
+        int k = 0;
+        for (int h = 0; h < 2; ++h)
+            for (int32_t e = hl.rp[h][v]; e < hl.rp[h][v + 1]; ++e, ++k)
+                hl.ell[k * hl.ell_stride + v] = (uint32_t)hl.col[h][e] | ((uint32_t)(h + 1) << 29) |
+                                                (hl.jw[h][e] < 0 ? 0x80000000u : 0u);
+    }
+    return true;
+}
 
 // Host phase of shaken_init: validation, layout and tables; touches no device.
 shaken_status init_host(shaken_ctx *c, const shaken_graph *g, const int8_t *J,
@@ -386,6 +423,13 @@ shaken_status init_host(shaken_ctx *c, const shaken_graph *g, const int8_t *J,
             return fail(SHAKEN_EINVAL, "unknown format");
         c->format = FMT_INT8;
         CHK(build_graph(c, g, J, rp, col, jw));
+        if (o->graph_layout < SHAKEN_LAYOUT_AUTO || o->graph_layout > SHAKEN_LAYOUT_ELL)
+            return fail(SHAKEN_EINVAL, "unknown graph layout");
+        if (o->graph_layout != SHAKEN_LAYOUT_CSR) {
+            const bool ok = build_ell(c->n, hl);
+            if (!ok && o->graph_layout == SHAKEN_LAYOUT_ELL)
+                return fail(SHAKEN_EINVAL, "ELL layout needs couplings +-1 and at most 4 neighbours per vertex");
+        }
         cls_host.assign((size_t)c->n, 0);
         if (lambda && lambda->class_of_vertex) {
             for (int v = 0; v < c->n; ++v) {
@@ -440,6 +484,12 @@ shaken_status init_device(shaken_ctx *c, const shaken_opts *o, HostLayout &hl) {
         }
         CHK(dalloc(&c->cls_dev, (size_t)c->n));
         HIPCHK(hipMemcpyAsync(c->cls_dev, cls_host.data(), (size_t)c->n, hipMemcpyHostToDevice, c->stream));
+        if (hl.ell_k > 0) {
+            CHK(dalloc(&c->ell_dev, hl.ell.size()));
+            HIPCHK(hipMemcpyAsync(c->ell_dev, hl.ell.data(), hl.ell.size() * 4, hipMemcpyHostToDevice, c->stream));
+            c->ell_k = hl.ell_k;
+            c->ell_stride = hl.ell_stride;
+        }
     }
 
     // descriptor
@@ -463,6 +513,9 @@ shaken_status init_device(shaken_ctx *c, const shaken_opts *o, HostLayout &hl) {
     }
     d.cls = c->cls_dev;
     d.maxdeg = c->maxdeg;
+    d.ell = c->ell_dev;
+    d.ell_k = c->ell_k;
+    d.ell_stride = c->ell_stride;
     d.log_line = c->line();
     d.log_stride = c->stride();
     for (size_t k = 0; k < c->lam.size() && k < 16; ++k) {
@@ -518,6 +571,7 @@ shaken_status shaken_init(shaken_ctx **out, const shaken_graph *g, const int8_t 
     o.format = SHAKEN_FMT_AUTO;
     o.init = SHAKEN_INIT_RANDOM;
     o.device = -1;
+    o.graph_layout = SHAKEN_LAYOUT_AUTO;
     if (opts) o = *opts;
     shaken_ctx *c = new (std::nothrow) shaken_ctx();
     if (!c) return fail(SHAKEN_ENOMEM, "host allocation failed");

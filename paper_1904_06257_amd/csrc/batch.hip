@@ -187,10 +187,31 @@ __device__ void graph_lds_half(const ChainDesc &d, const uint32_t *src, uint32_t
         uint32_t bits = 0;
         if (q4 < nq) {
             const int v0 = 4 * q4;
+            int S0 = 0, S1 = 0, S2 = 0, S3 = 0;
+            if (d.ell) {
+                // ELL: one 16-byte record per slot for the 4 vertices, no row pointers
+                const int K = d.ell_k;
+                const uint32_t want = dst ? (uint32_t)((s & 1u) + 1u) : 1u;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const uint4 rec = *(const uint4 *)(d.ell + min(k, K - 1) * d.ell_stride + v0);
+                    const uint32_t e[4] = {rec.x, rec.y, rec.z, rec.w};
+                    int t[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int sv = lds_spin(src, (int)(e[j] & 0x1FFFFFFFu));
+                        const int v = (e[j] >> 31) ? -sv : sv;
+                        t[j] = (k < K && ((e[j] >> 29) & 3u) == want) ? v : 0;
+                    }
+                    S0 += t[0];
+                    S1 += t[1];
+                    S2 += t[2];
+                    S3 += t[3];
+                }
+            } else {
             int rpv[5];
 #pragma unroll
             for (int j = 0; j < 5; ++j) rpv[j] = rp[min(v0 + j, n)];
-            int S0 = 0, S1 = 0, S2 = 0, S3 = 0;
             const int last = rpv[4] - 1;
             for (int base = rpv[0]; base <= last; base += 8) {
                 // clamped indices: all eight loads issue before any is used
@@ -210,6 +231,7 @@ __device__ void graph_lds_half(const ChainDesc &d, const uint32_t *src, uint32_t
                     S2 += (e >= rpv[2] && e < rpv[3]) ? t : 0;
                     S3 += (e >= rpv[3]) ? t : 0;
                 }
+            }
             }
             const int Sv[4] = {S0, S1, S2, S3};
             int cl[4];

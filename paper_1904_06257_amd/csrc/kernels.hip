@@ -288,8 +288,12 @@ __global__ __launch_bounds__(256) void k_graph(const ChainDesc *__restrict__ des
     if (OBS) {
         for (int i = threadIdx.x; i < ncls; i += blockDim.x) sh_plus[i] = 0;
     }
-    __syncthreads();
-    if (v0 < n) {
+    // (the barrier that publishes sh_lut / sh_plus comes after this lane's
+    // loads are issued, so the table load overlaps them)
+    const int active = v0 < n;
+    int Sv[4] = {0, 0, 0, 0}, own[4] = {1, 1, 1, 1}, cl[4] = {0, 0, 0, 0};
+    U4 r = {0u, 0u, 0u, 0u};
+    if (active) {
         const bool full = v0 + 3 < n;
         int rpv[5];
         if (full) {
@@ -303,7 +307,6 @@ __global__ __launch_bounds__(256) void k_graph(const ChainDesc *__restrict__ des
 #pragma unroll
             for (int j = 0; j < 5; ++j) rpv[j] = rp[min(v0 + j, n)];
         }
-        int own[4], cl[4];
         if (full) {
             const uint32_t o4 = *(const uint32_t *)(in + v0);
             const uint32_t c4 = *(const uint32_t *)(cls + v0);
@@ -319,8 +322,8 @@ __global__ __launch_bounds__(256) void k_graph(const ChainDesc *__restrict__ des
                 cl[j] = v0 + j < n ? cls[v0 + j] : 0;
             }
         }
-        const U4 r = philox10((uint32_t)q4, s, d.replica, kGraphStream, (uint32_t)d.seed,
-                              (uint32_t)(d.seed >> 32));
+        r = philox10((uint32_t)q4, s, d.replica, kGraphStream, (uint32_t)d.seed,
+                     (uint32_t)(d.seed >> 32));
         int S0 = 0, S1 = 0, S2 = 0, S3 = 0;
         const int last = rpv[4] - 1;
         for (int base = rpv[0]; base <= last; base += kEdgeChunk) {
@@ -344,7 +347,124 @@ __global__ __launch_bounds__(256) void k_graph(const ChainDesc *__restrict__ des
                 S3 += (e >= rpv[3]) ? t : 0;
             }
         }
-        const int Sv[4] = {S0, S1, S2, S3};
+        Sv[0] = S0;
+        Sv[1] = S1;
+        Sv[2] = S2;
+        Sv[3] = S3;
+    }
+    __syncthreads();
+    if (active) {
+        const bool full = v0 + 3 < n;
+        const uint32_t u[4] = {r.x, r.y, r.z, r.w};
+        uint32_t packed = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int key = ((Sv[j] + smax) * 2 + (own[j] > 0)) * ncls + cl[j];
+            const uint64_t T = lut_lds ? sh_lut[key] : d.lut[key];
+            const uint32_t nv = ((uint64_t)u[j] < T) ? 0x01u : 0xFFu;
+            packed |= nv << (8 * j);
+            if (OBS && v0 + j < n) {
+                e_acc += own[j] * Sv[j];
+                if (own[j] > 0) atomicAdd(&sh_plus[cl[j]], 1);
+            }
+        }
+        if (full) {
+            *(uint32_t *)(out + v0) = packed;
+        } else {
+            for (int j = 0; j < 4 && v0 + j < n; ++j) out[v0 + j] = (int8_t)(packed >> (8 * j));
+        }
+    }
+    if (OBS && blockIdx.x < (unsigned)((n + 4 * blockDim.x - 1) / (4 * blockDim.x))) {
+        int64_t *lg = log_part(d, slot, blockIdx.x);
+        __shared__ int sh_e[16];
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        e_acc = wave_sum(e_acc);
+        if (lane == 0) sh_e[wv] = e_acc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            long long se = 0;
+            for (int i = 0; i < (int)((blockDim.x + 63) >> 6); ++i) se += sh_e[i];
+            if (se) atomicAdd((unsigned long long *)&lg[0], (unsigned long long)se);
+        }
+        for (int i = threadIdx.x; i < ncls; i += blockDim.x)
+            if (sh_plus[i]) atomicAdd((unsigned long long *)&lg[1 + i], (unsigned long long)sh_plus[i]);
+    }
+}
+
+// ELL variant (couplings +-1, at most 4 neighbours): a lane loads the slot
+// records of its 4 vertices as one 16-byte load per slot, gathers every
+// neighbour spin at once (empty slots point to the vertex itself) and keeps
+// those of the half being updated.  Two dependent memory levels instead of
+// three (no row pointers).
+template <bool OBS, int K>
+__global__ __launch_bounds__(256) void k_graph_ell(const ChainDesc *__restrict__ descs, StepArgs sa) {
+    const ChainDesc &d = descs[blockIdx.y];
+    const uint32_t s = step_s(sa);
+    const int half = (int)(s & 1u);
+    const uint32_t want = (uint32_t)(half + 1);
+    const int slot = OBS ? step_slot(sa, s) : 0;
+    const int n = d.n;
+    const int q4 = blockIdx.x * blockDim.x + threadIdx.x;
+    const int v0 = q4 * 4;
+    const int8_t *__restrict__ in = (const int8_t *)d.spin[half];
+    int8_t *__restrict__ out = (int8_t *)d.spin[half ^ 1];
+    const uint32_t *__restrict__ ell = d.ell;
+    const int64_t stride = d.ell_stride;
+    const uint8_t *__restrict__ cls = d.cls;
+    const int ncls = d.ncls, smax = d.smax;
+    int e_acc = 0;
+    __shared__ uint64_t sh_lut[kLdsLut];
+    const int nlut = (2 * smax + 1) * 2 * ncls;
+    const bool lut_lds = nlut <= kLdsLut;
+    if (lut_lds) {
+        for (int i = threadIdx.x; i < nlut; i += blockDim.x) sh_lut[i] = d.lut[i];
+    }
+    extern __shared__ int sh_plus[];
+    if (OBS) {
+        for (int i = threadIdx.x; i < ncls; i += blockDim.x) sh_plus[i] = 0;
+    }
+    __syncthreads();
+    if (v0 < n) {
+        const bool full = v0 + 3 < n;
+        uint4 rec[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) rec[k] = *(const uint4 *)(ell + k * stride + v0);
+        int own[4], cl[4];
+        if (full) {
+            const uint32_t o4 = *(const uint32_t *)(in + v0);
+            const uint32_t c4 = *(const uint32_t *)(cls + v0);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                own[j] = (int)(int8_t)(o4 >> (8 * j));
+                cl[j] = (int)((c4 >> (8 * j)) & 0xFFu);
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                own[j] = v0 + j < n ? in[v0 + j] : 1;
+                cl[j] = v0 + j < n ? cls[v0 + j] : 0;
+            }
+        }
+        const U4 r = philox10((uint32_t)q4, s, d.replica, kGraphStream, (uint32_t)d.seed,
+                              (uint32_t)(d.seed >> 32));
+        int sv[K][4];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            sv[k][0] = in[rec[k].x & 0x1FFFFFFFu];
+            sv[k][1] = in[rec[k].y & 0x1FFFFFFFu];
+            sv[k][2] = in[rec[k].z & 0x1FFFFFFFu];
+            sv[k][3] = in[rec[k].w & 0x1FFFFFFFu];
+        }
+        int Sv[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const uint32_t e[4] = {rec[k].x, rec[k].y, rec[k].z, rec[k].w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int t = (int)(e[j] >> 31) ? -sv[k][j] : sv[k][j];
+                Sv[j] += ((e[j] >> 29) & 3u) == want ? t : 0;
+            }
+        }
         const uint32_t u[4] = {r.x, r.y, r.z, r.w};
         uint32_t packed = 0;
 #pragma unroll
@@ -534,8 +654,19 @@ hipError_t launch_half_step_grid(const ChainDesc *dev_descs, const ChainDesc *ho
         else hipLaunchKernelGGL((k_torus_i8<false>), grid, dim3(b), 0, stream, dev_descs, sa);
     } else {
         const size_t shm = obs ? sizeof(int) * (size_t)maxcls : 0;
-        if (obs) hipLaunchKernelGGL((k_graph<true>), grid, dim3(b), shm, stream, dev_descs, sa);
+        int ellk = host_descs[0].ell_k;
+        for (int i = 0; i < nchains; ++i)
+            if (host_descs[i].ell_k != ellk || !host_descs[i].ell) ellk = 0;
+#define SHAKEN_ELL(KK)                                                                          \
+    if (obs) hipLaunchKernelGGL((k_graph_ell<true, KK>), grid, dim3(b), shm, stream, dev_descs, sa); \
+    else hipLaunchKernelGGL((k_graph_ell<false, KK>), grid, dim3(b), 0, stream, dev_descs, sa);
+        if (ellk == 1) { SHAKEN_ELL(1) }
+        else if (ellk == 2) { SHAKEN_ELL(2) }
+        else if (ellk == 3) { SHAKEN_ELL(3) }
+        else if (ellk == 4) { SHAKEN_ELL(4) }
+        else if (obs) hipLaunchKernelGGL((k_graph<true>), grid, dim3(b), shm, stream, dev_descs, sa);
         else hipLaunchKernelGGL((k_graph<false>), grid, dim3(b), 0, stream, dev_descs, sa);
+#undef SHAKEN_ELL
     }
     return hipGetLastError();
 }

@@ -43,7 +43,12 @@ struct ChainDesc {
     const int8_t *jw[2];     // coupling per CSR entry
     const uint8_t *cls;      // field class per vertex (never NULL on device)
     int32_t maxdeg;          // largest half-degree
-    int32_t pad0;
+    int32_t ell_k;           // ELL: slots per vertex (0 = no ELL layout)
+    // ELL (couplings +-1, degree <= 4): ell[k * ell_stride + v] = index (bits
+    // 0-28) | half (bits 29-30: 1 = in-half, 2 = out-half, 0 = empty slot,
+    // whose index is v itself) | J < 0 (bit 31)
+    const uint32_t *ell;
+    int64_t ell_stride;      // n rounded up to a multiple of 4
     // observables log: slot t is kLogParts lines of log_line int64; line p holds
     // partial sums [E_J, plus_0 .. plus_{ncls-1}] (a block adds into line
     // blockIdx % kLogParts, so that thousands of blocks do not queue on one

@@ -70,3 +70,13 @@ def test_valid_arguments_reach_the_device_check():
     import paper_1904_06257_amd as sk
     st, msg = _init_status(kind="torus", L=8)
     assert st == sk.SHAKEN_EDEVICE
+
+
+def test_ell_layout_rejected_when_it_does_not_apply():
+    import paper_1904_06257_amd as sk
+    st, msg = _init_status(kind="graph", n=4, src=[0, 1], dst=[1, 2], J=[2, 1], layout="ell")
+    assert st == sk.SHAKEN_EINVAL and "ELL" in msg
+    src = [0, 0, 0, 0, 0]
+    dst = [1, 2, 3, 4, 5]
+    st, msg = _init_status(kind="graph", n=6, src=src, dst=dst, layout="ell")
+    assert st == sk.SHAKEN_EINVAL and "ELL" in msg

@@ -104,3 +104,57 @@ def test_time_reversibility(sk):
     z = d.mean() / (d.std(ddof=1) / np.sqrt(d.size))
     print("reversibility: mean difference %.3f, z = %.2f" % (d.mean(), z), flush=True)
     assert abs(z) < 4.5
+
+
+def _chi2_p(counts, probs):
+    from scipy import stats
+    probs = np.asarray(probs)
+    keep = probs * counts.sum() >= 5
+    obs = np.append(counts[keep], counts[~keep].sum())
+    exp = np.append(probs[keep], probs[~keep].sum()) * counts.sum()
+    if exp[-1] == 0:
+        obs, exp = obs[:-1], exp[:-1]
+    return stats.chisquare(obs, exp).pvalue
+
+
+@pytest.mark.parametrize("case,T", [("graph6", 40), ("torus3", 150)])
+def test_long_run_state_histogram_chi2(sk, case, T):
+    """Sixteen thousand independent GPU chains on a tiny system: the histogram
+    of their states after T full steps against the exact stationary law pi of
+    Theorem 2.3 (float64 enumeration).  T is long enough that the exact law
+    after T steps from the uniform start is within 1e-4 of pi in total
+    variation (checked here), and the Gibbs law of H, which pi is not at this
+    small q, is rejected by the same data (the test has power)."""
+    import synth
+    from oracle import enumeration as en
+    reps = 16384
+    if case == "graph6":
+        inst = synth.random_oriented_graph(6, 0.6, 3, jmax=1, n_classes=3, lam_scale=0.25)
+        q, beta = 0.7, 0.3
+        m = en.Model(inst.n, inst.src, inst.dst, J=inst.J.astype(float),
+                     lam=inst.lam_values[inst.cls], q=q, beta=beta)
+        chains = [sk.Chain.graph(inst.n, inst.src, inst.dst, J=inst.J, lam_values=inst.lam_values,
+                                 lam_class=inst.cls, q=q, beta=beta, seed=5, replica=r)
+                  for r in range(reps)]
+    else:
+        L, q, beta, lam = 3, 0.8, 0.5, 0.15
+        s, d = en.torus_edges(L)
+        m = en.Model(L * L, s, d, lam=np.full(L * L, lam), q=q, beta=beta)
+        chains = [sk.Chain.torus(L, q=q, beta=beta, lam_values=[lam], seed=6, replica=r)
+                  for r in range(reps)]
+    pi = m.pi()
+    u = np.full(pi.size, 1.0 / pi.size)
+    pT = u @ np.linalg.matrix_power(m.Psh(), T)
+    assert 0.5 * np.abs(pT - pi).sum() < 1e-4
+    b = sk.Batch(chains, strategy="grid", use_hipgraph=True)
+    b.sweep(T)
+    cnt = np.zeros(pi.size)
+    for c in chains:
+        cnt[en.index_of(c.spins().reshape(-1))] += 1
+        c.close()
+    b.close()
+    p = _chi2_p(cnt, pi)
+    p_gibbs = _chi2_p(cnt, m.gibbs())
+    print("%s: chi2 p-value vs pi %.3g, vs Gibbs %.3g" % (case, p, p_gibbs), flush=True)
+    assert p > 1e-4
+    assert p_gibbs < 1e-10
