@@ -53,9 +53,9 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def read_traffic(kernel_key):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None if the kernels changed since it was taken."""
+def read_traffic(kernel_key, per="launch"):
+    """HBM bytes per launch (or per full step) from the committed rocprofv3
+    counter summary, or None if the kernels changed since it was taken."""
     path = os.path.join(ROOT, "profiles", "traffic.txt")
     if not os.path.exists(path):
         return None
@@ -68,7 +68,7 @@ def read_traffic(kernel_key):
             vals[k.strip()] = v.strip()
     if vals.get("source_hash") != kernel_source_hash():
         return None
-    v = vals.get(kernel_key + ".bytes_per_launch")
+    v = vals.get(kernel_key + ".bytes_per_" + per)
     return float(v) if v else None
 
 
@@ -152,6 +152,9 @@ def bench_graph(args, sk):
     # gathered spins (m), field class, written spin
     bytes_launch = 4 * (n + 1) + 5 * m + n + m + n + n
     achieved = bytes_launch / per_launch_s / 1e9
+    traffic = read_traffic("k_persistent", per="full_step")
+    if traffic is not None:
+        traffic *= args.steps
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": read_traffic("k_graph"),
             "kernel": "k_graph", "launch_us": per_launch_s * 1e6}
@@ -216,8 +219,11 @@ def bench_batch(args, sk):
     per_launch_s = ev_ms * 1e-3  # one persistent launch per sweep
     bytes_launch = adj_bytes_half * 2 * args.steps
     achieved = bytes_launch / per_launch_s / 1e9
+    traffic = read_traffic("k_persistent", per="full_step")
+    if traffic is not None:
+        traffic *= args.steps
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": read_traffic("k_persistent"),
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "kernel": "k_persistent", "launch_us": per_launch_s * 1e6,
             "note": "graph adjacency streamed from HBM; tori are LDS-resident (0 B)"}
     cfg = {"workload": "2048 mixed chains in one persistent launch: 1024 tori L in {16..256}, "
@@ -253,40 +259,49 @@ def _counter_rows(path):
     return out
 
 
-def summarize_traffic(fetch_csv, write_csv, cal_fetch_csv, cal_write_csv, out_path):
-    """profiles/traffic.txt from four rocprofv3 --pmc counter CSVs (FETCH_SIZE
-    and WRITE_SIZE, in KiB per dispatch, for the workload and for the 1 GiB
-    calibration copy)."""
-    def per_kernel(path):
-        return {k: sum(v) / len(v) for k, v in _counter_rows(path).items()}
-    cf, cw = per_kernel(cal_fetch_csv), per_kernel(cal_write_csv)
+def summarize_traffic(cal_fetch_csv, cal_write_csv, workloads, out_path):
+    """profiles/traffic.txt from rocprofv3 --pmc counter CSVs: FETCH_SIZE and
+    WRITE_SIZE (KiB per dispatch) of the 1 GiB calibration copy, then per
+    workload (kernel, fetch csv, write csv, full steps per timed launch or 0).
+    Only the named kernel of each workload is summarised; a kernel whose launch
+    covers many full steps (the persistent batch) is reported per full step,
+    from its largest dispatch."""
+    def rows(path):
+        return _counter_rows(path)
+
+    def short_name(k):
+        return k.split("(")[0].replace("void ", "").replace("shaken::", "").split("<")[0]
+
+    cf, cw = rows(cal_fetch_csv), rows(cal_write_csv)
     copy_k = [k for k in cf if "copy" in k.lower() or "elementwise" in k.lower()]
-    ck = max(copy_k, key=lambda k: cf[k])
-    fetch_factor = (1 << 30) / (cf[ck] * 1024.0)    # true bytes per counted byte
-    write_factor = (1 << 30) / (cw[ck] * 1024.0)
-    f, w = per_kernel(fetch_csv), per_kernel(write_csv)
-    lines = ["# HBM-side traffic per launch from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE",
-             "# (KiB per dispatch, averaged), scaled by the factors a 1 GiB device copy gives",
-             "# (bytes copied / bytes counted).  source_hash: kernels this was measured on.",
+    ck = max(copy_k, key=lambda k: max(cf[k]))
+    fetch_factor = (1 << 30) / (max(cf[ck]) * 1024.0)    # true bytes per counted byte
+    write_factor = (1 << 30) / (max(cw[ck]) * 1024.0)
+    lines = ["# HBM-side traffic from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per",
+             "# dispatch), scaled by the factors a 1 GiB device copy gives (bytes copied /",
+             "# bytes counted).  source_hash: kernels this was measured on.",
              "source_hash = %s" % kernel_source_hash(),
              "calibration_kernel = %s" % ck.split("(")[0],
              "fetch_factor = %.4f" % fetch_factor, "write_factor = %.4f" % write_factor]
-    for k in sorted(f):
-        short = k.split("(")[0].replace("void ", "").replace("shaken::", "").split("<")[0]
-        if short not in ("k_torus_bp", "k_graph", "k_persistent", "k_torus_i8"):
-            continue
-        fb = f[k] * 1024.0 * fetch_factor
-        wb = w.get(k, 0.0) * 1024.0 * write_factor
-        lines.append("# %s: fetch %.0f B, write %.0f B per launch" % (k.split("(")[0], fb, wb))
-    agg = {}
-    for k in f:
-        short = k.split("(")[0].replace("void ", "").replace("shaken::", "").split("<")[0]
-        fb = f[k] * 1024.0 * fetch_factor
-        wb = w.get(k, 0.0) * 1024.0 * write_factor
-        agg.setdefault(short, []).append(fb + wb)
-    for short in ("k_torus_bp", "k_graph", "k_persistent"):
-        if short in agg:
-            lines.append("%s.bytes_per_launch = %.0f" % (short, sum(agg[short]) / len(agg[short])))
+    for kernel, fetch_csv, write_csv, steps in workloads:
+        f, w = rows(fetch_csv), rows(write_csv)
+        fb_all, wb_all = [], []
+        for k in sorted(f):
+            if short_name(k) != kernel:
+                continue
+            fv = [x * 1024.0 * fetch_factor for x in f[k]]
+            wv = [x * 1024.0 * write_factor for x in w.get(k, [0.0])]
+            if steps:
+                fv, wv = [max(fv) / steps], [max(wv) / steps]
+            lines.append("# %s: fetch %.0f B, write %.0f B per %s (%d dispatches)"
+                         % (k.split("(")[0], sum(fv) / len(fv), sum(wv) / len(wv),
+                            "full step" if steps else "launch", len(f[k])))
+            fb_all += fv
+            wb_all += wv
+        if not fb_all:
+            raise SystemExit("kernel %s not found in %s" % (kernel, fetch_csv))
+        key = "bytes_per_full_step" if steps else "bytes_per_launch"
+        lines.append("%s.%s = %.0f" % (kernel, key, sum(fb_all) / len(fb_all) + sum(wb_all) / len(wb_all)))
     with open(out_path, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("\n".join(lines))
@@ -294,7 +309,14 @@ def summarize_traffic(fetch_csv, write_csv, cal_fetch_csv, cal_write_csv, out_pa
 
 def main():
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-traffic":
-        summarize_traffic(*sys.argv[2:6], os.path.join(ROOT, "profiles", "traffic.txt"))
+        # bench.py --summarize-traffic CAL_FETCH CAL_WRITE KERNEL[@STEPS]=FETCH,WRITE ...
+        wl = []
+        for arg in sys.argv[4:]:
+            name, files = arg.split("=", 1)
+            kernel, _, steps = name.partition("@")
+            fetch, write = files.split(",")
+            wl.append((kernel, fetch, write, int(steps or 0)))
+        summarize_traffic(sys.argv[2], sys.argv[3], wl, os.path.join(ROOT, "profiles", "traffic.txt"))
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)

@@ -119,12 +119,19 @@ enum {
 };
 
 enum {
-    SHAKEN_LAYOUT_AUTO = 0,    /* ELL when it applies, else CSR               */
+    SHAKEN_LAYOUT_AUTO = 0,    /* PACKED when it applies, else ELL when it
+                                  applies, else CSR                           */
     SHAKEN_LAYOUT_CSR = 1,     /* in-half and out-half CSR (any graph)        */
-    SHAKEN_LAYOUT_ELL = 2      /* couplings +-1 and degree <= 4 only: one
+    SHAKEN_LAYOUT_ELL = 2,     /* couplings +-1 and degree <= 4 only: one
                                   slot-major record per neighbour slot holding
                                   the index, the half it belongs to and the
                                   sign of J                                   */
+    SHAKEN_LAYOUT_PACKED = 3   /* ELL plus one 8-byte record per vertex (three
+                                  16-bit neighbour indices, their halves,
+                                  signs and the field class) read by the
+                                  persistent batch kernel; needs couplings
+                                  +-1, degree <= 3, n <= 65536 and at most 16
+                                  field classes                               */
 };
 
 typedef struct shaken_opts {

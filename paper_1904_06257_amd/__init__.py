@@ -43,8 +43,9 @@ _INIT = {"random": SHAKEN_INIT_RANDOM, "all_up": SHAKEN_INIT_ALL_UP,
 _FMT = {"auto": SHAKEN_FMT_AUTO, "int8": SHAKEN_FMT_INT8, "bitpacked": SHAKEN_FMT_BITPACKED}
 _STRAT = {"auto": SHAKEN_BATCH_AUTO, "grid": SHAKEN_BATCH_GRID,
           "persistent": SHAKEN_BATCH_PERSISTENT}
-SHAKEN_LAYOUT_AUTO, SHAKEN_LAYOUT_CSR, SHAKEN_LAYOUT_ELL = 0, 1, 2
-_LAYOUT = {"auto": SHAKEN_LAYOUT_AUTO, "csr": SHAKEN_LAYOUT_CSR, "ell": SHAKEN_LAYOUT_ELL}
+SHAKEN_LAYOUT_AUTO, SHAKEN_LAYOUT_CSR, SHAKEN_LAYOUT_ELL, SHAKEN_LAYOUT_PACKED = 0, 1, 2, 3
+_LAYOUT = {"auto": SHAKEN_LAYOUT_AUTO, "csr": SHAKEN_LAYOUT_CSR, "ell": SHAKEN_LAYOUT_ELL,
+           "packed": SHAKEN_LAYOUT_PACKED}
 
 
 class shaken_graph(ctypes.Structure):

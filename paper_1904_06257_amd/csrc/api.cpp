@@ -132,6 +132,7 @@ struct shaken_ctx {
     int8_t *jw[2] = {nullptr, nullptr};
     uint8_t *cls_dev = nullptr;
     uint32_t *ell_dev = nullptr;
+    uint64_t *pell_dev = nullptr;
     int ell_k = 0;
     int64_t ell_stride = 0;
     int64_t *log_dev = nullptr;
@@ -164,6 +165,7 @@ void release(shaken_ctx *c) {
     }
     dfree(c->cls_dev);
     dfree(c->ell_dev);
+    dfree(c->pell_dev);
     dfree(c->log_dev);
     dfree(c->obs_dev);
     dfree(c->dd);
@@ -329,6 +331,7 @@ struct HostLayout {
     std::vector<int32_t> rp[2], col[2];
     std::vector<int8_t> jw[2];
     std::vector<uint32_t> ell;  // slot-major, ell_k * ell_stride entries
+    std::vector<uint64_t> pell; // packed record per vertex, ell_stride entries
     int ell_k = 0;
     int64_t ell_stride = 0;
 };
@@ -359,6 +362,28 @@ bool build_ell(int n, HostLayout &hl) {
             for (int32_t e = hl.rp[h][v]; e < hl.rp[h][v + 1]; ++e, ++k)
                 hl.ell[k * hl.ell_stride + v] = (uint32_t)hl.col[h][e] | ((uint32_t)(h + 1) << 29) |
                                                 (hl.jw[h][e] < 0 ? 0x80000000u : 0u);
+    }
+    return true;
+}
+
+// Packed record per vertex for the persistent kernel (layout in ChainDesc::pell):
+// needs the ELL layout with at most 3 slots, n <= 65536 and classes < 16.
+bool build_pell(int n, HostLayout &hl) {
+    if (hl.ell_k == 0 || hl.ell_k > 3 || n > 65536) return false;
+    for (int v = 0; v < n; ++v)
+        if (hl.cls_host[v] >= 16) return false;
+    hl.pell.assign((size_t)hl.ell_stride, 0ull);
+    for (int v = 0; v < n; ++v) {
+        uint64_t r = (uint64_t)hl.cls_host[v] << 57;
+        int k = 0;
+        for (int h = 0; h < 2; ++h)
+            for (int32_t e = hl.rp[h][v]; e < hl.rp[h][v + 1]; ++e, ++k) {
+                r |= (uint64_t)(uint32_t)hl.col[h][e] << (16 * k);
+                r |= (uint64_t)h << (48 + k);
+                r |= (uint64_t)(hl.jw[h][e] < 0) << (51 + k);
+                r |= 1ull << (54 + k);
+            }
+        hl.pell[v] = r;
     }
     return true;
 }
@@ -423,11 +448,11 @@ shaken_status init_host(shaken_ctx *c, const shaken_graph *g, const int8_t *J,
             return fail(SHAKEN_EINVAL, "unknown format");
         c->format = FMT_INT8;
         CHK(build_graph(c, g, J, rp, col, jw));
-        if (o->graph_layout < SHAKEN_LAYOUT_AUTO || o->graph_layout > SHAKEN_LAYOUT_ELL)
+        if (o->graph_layout < SHAKEN_LAYOUT_AUTO || o->graph_layout > SHAKEN_LAYOUT_PACKED)
             return fail(SHAKEN_EINVAL, "unknown graph layout");
         if (o->graph_layout != SHAKEN_LAYOUT_CSR) {
             const bool ok = build_ell(c->n, hl);
-            if (!ok && o->graph_layout == SHAKEN_LAYOUT_ELL)
+            if (!ok && o->graph_layout != SHAKEN_LAYOUT_AUTO)
                 return fail(SHAKEN_EINVAL, "ELL layout needs couplings +-1 and at most 4 neighbours per vertex");
         }
         cls_host.assign((size_t)c->n, 0);
@@ -440,6 +465,12 @@ shaken_status init_host(shaken_ctx *c, const shaken_graph *g, const int8_t *J,
         }
         c->class_size.assign(c->lam.size(), 0);
         for (int v = 0; v < c->n; ++v) c->class_size[cls_host[v]]++;
+        if (o->graph_layout == SHAKEN_LAYOUT_AUTO || o->graph_layout == SHAKEN_LAYOUT_PACKED) {
+            const bool ok = build_pell(c->n, hl);
+            if (!ok && o->graph_layout == SHAKEN_LAYOUT_PACKED)
+                return fail(SHAKEN_EINVAL, "packed layout needs couplings +-1, at most 3 neighbours per "
+                                           "vertex, n <= 65536 and at most 16 field classes");
+        }
     } else {
         return fail(SHAKEN_EINVAL, "unknown graph kind");
     }
@@ -490,6 +521,10 @@ shaken_status init_device(shaken_ctx *c, const shaken_opts *o, HostLayout &hl) {
             c->ell_k = hl.ell_k;
             c->ell_stride = hl.ell_stride;
         }
+        if (!hl.pell.empty()) {
+            CHK(dalloc(&c->pell_dev, hl.pell.size()));
+            HIPCHK(hipMemcpyAsync(c->pell_dev, hl.pell.data(), hl.pell.size() * 8, hipMemcpyHostToDevice, c->stream));
+        }
     }
 
     // descriptor
@@ -516,6 +551,7 @@ shaken_status init_device(shaken_ctx *c, const shaken_opts *o, HostLayout &hl) {
     d.ell = c->ell_dev;
     d.ell_k = c->ell_k;
     d.ell_stride = c->ell_stride;
+    d.pell = c->pell_dev;
     d.log_line = c->line();
     d.log_stride = c->stride();
     for (size_t k = 0; k < c->lam.size() && k < 16; ++k) {

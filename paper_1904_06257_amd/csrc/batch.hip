@@ -188,7 +188,36 @@ __device__ void graph_lds_half(const ChainDesc &d, const uint32_t *src, uint32_t
         if (q4 < nq) {
             const int v0 = 4 * q4;
             int S0 = 0, S1 = 0, S2 = 0, S3 = 0;
-            if (d.ell) {
+            int cl[4];
+            if (d.pell) {
+                // packed: one 8-byte record per vertex holds neighbours, halves,
+                // signs and class (two 16-byte loads per thread)
+                const uint4 a = *(const uint4 *)(d.pell + v0);
+                const uint4 b = *(const uint4 *)(d.pell + v0 + 2);
+                const uint32_t lo[4] = {a.x, a.z, b.x, b.z};
+                const uint32_t hi[4] = {a.y, a.w, b.y, b.w};
+                const bool out_half = dst && (s & 1u);
+                int t[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const uint32_t meta = hi[j] >> 16;
+                    const uint32_t sel = (out_half ? meta : ~meta) & (meta >> 6) & 7u;
+                    const uint32_t idx[3] = {lo[j] & 0xFFFFu, lo[j] >> 16, hi[j] & 0xFFFFu};
+                    int acc = 0;
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        const int sv = lds_spin(src, (int)idx[k]);
+                        const int v = ((meta >> (3 + k)) & 1u) ? -sv : sv;
+                        acc += ((sel >> k) & 1u) ? v : 0;
+                    }
+                    t[j] = acc;
+                    cl[j] = (int)((meta >> 9) & 15u);
+                }
+                S0 = t[0];
+                S1 = t[1];
+                S2 = t[2];
+                S3 = t[3];
+            } else if (d.ell) {
                 // ELL: one 16-byte record per slot for the 4 vertices, no row pointers
                 const int K = d.ell_k;
                 const uint32_t want = dst ? (uint32_t)((s & 1u) + 1u) : 1u;
@@ -234,14 +263,15 @@ __device__ void graph_lds_half(const ChainDesc &d, const uint32_t *src, uint32_t
             }
             }
             const int Sv[4] = {S0, S1, S2, S3};
-            int cl[4];
-            if (v0 + 3 < n) {
-                const uint32_t c4 = *(const uint32_t *)(d.cls + v0);
+            if (!d.pell) {
+                if (v0 + 3 < n) {
+                    const uint32_t c4 = *(const uint32_t *)(d.cls + v0);
 #pragma unroll
-                for (int j = 0; j < 4; ++j) cl[j] = (int)((c4 >> (8 * j)) & 0xFFu);
-            } else {
+                    for (int j = 0; j < 4; ++j) cl[j] = (int)((c4 >> (8 * j)) & 0xFFu);
+                } else {
 #pragma unroll
-                for (int j = 0; j < 4; ++j) cl[j] = v0 + j < n ? d.cls[v0 + j] : 0;
+                    for (int j = 0; j < 4; ++j) cl[j] = v0 + j < n ? d.cls[v0 + j] : 0;
+                }
             }
             if (dst) {
                 const U4 r = philox10((uint32_t)q4, s, d.replica, kGraphStream, k0, k1);

@@ -49,6 +49,11 @@ struct ChainDesc {
     // whose index is v itself) | J < 0 (bit 31)
     const uint32_t *ell;
     int64_t ell_stride;      // n rounded up to a multiple of 4
+    // packed record per vertex (couplings +-1, degree <= 3, n <= 65536, at most
+    // 16 classes), ell_stride entries: bits 0-47 three 16-bit neighbour
+    // indices; bits 48-50 slot k in the out-half; 51-53 J < 0; 54-56 slot
+    // used; 57-60 field class.  Unused slots and padding vertices read index 0.
+    const uint64_t *pell;
     // observables log: slot t is kLogParts lines of log_line int64; line p holds
     // partial sums [E_J, plus_0 .. plus_{ncls-1}] (a block adds into line
     // blockIdx % kLogParts, so that thousands of blocks do not queue on one

@@ -80,3 +80,27 @@ def test_ell_layout_rejected_when_it_does_not_apply():
     dst = [1, 2, 3, 4, 5]
     st, msg = _init_status(kind="graph", n=6, src=src, dst=dst, layout="ell")
     assert st == sk.SHAKEN_EINVAL and "ELL" in msg
+
+
+def test_packed_layout_rejected_when_it_does_not_apply():
+    """The packed per-vertex record needs degree <= 3, n <= 65536 and at most
+    16 field classes; AUTO falls back silently, PACKED reports why."""
+    import torch
+    import paper_1904_06257_amd as sk
+    star4 = dict(kind="graph", n=5, src=[0, 0, 0, 0], dst=[1, 2, 3, 4])      # degree 4
+    st, msg = _init_status(layout="packed", **star4)
+    assert st == sk.SHAKEN_EINVAL and "packed" in msg
+    big = dict(kind="graph", n=70000, src=[0, 1], dst=[1, 2])                # n > 65536
+    st, msg = _init_status(layout="packed", **big)
+    assert st == sk.SHAKEN_EINVAL and "packed" in msg
+    cls = dict(kind="graph", n=20, src=[0, 1], dst=[1, 2], lam_values=np.zeros(17),
+               lam_class=np.arange(20) % 17)                                  # 17 classes
+    st, msg = _init_status(layout="packed", **cls)
+    assert st == sk.SHAKEN_EINVAL and "packed" in msg
+    st, msg = _init_status(layout="packed", kind="graph", n=4, src=[0, 1], dst=[1, 2], J=[2, 1])
+    assert st == sk.SHAKEN_EINVAL
+    if not torch.cuda.is_available():
+        for kw in (star4, big, cls):
+            assert _init_status(layout="auto", **kw)[0] == sk.SHAKEN_EDEVICE
+        st, _ = _init_status(layout="packed", kind="graph", n=4, src=[0, 1], dst=[1, 2])
+        assert st == sk.SHAKEN_EDEVICE

@@ -375,18 +375,19 @@ def test_batch_persistent_equals_grid(sk):
         assert np.array_equal(x.spins().reshape(sp["want"].shape), sp["want"])
 
 
-@pytest.mark.parametrize("n,deg", [(1002, 3), (4096, 4), (37, 2)])
+@pytest.mark.parametrize("n,deg", [(1002, 3), (4096, 4), (37, 2), (65536, 3)])
 def test_graph_ell_equals_csr_equals_oracle(sk, n, deg):
-    """The ELL and CSR layouts give the same trajectory as the oracle (grid and
-    persistent strategies)."""
+    """The CSR, ELL and packed layouts give the same trajectory as the oracle
+    (grid and persistent strategies; the grid kernels read ELL where the packed
+    record is given)."""
     T = 40
     _print_case("ell vs csr", n, deg)
     inst = synth.oriented_instance(n, deg, 300 + n, lam_values=(-0.5, 0.5), pm_j=True)
     g = oracle.Graph(inst.n, inst.src, inst.dst, inst.J, inst.cls, inst.lam_values)
     sp0 = oracle.graph_init_random(n, 4, 1)
     want, ej, plus = oracle.graph_run(g, sp0, 0.9, 0.6, 4, 1, T)
-    got = {}
-    for layout in ("csr", "ell"):
+    layouts = ("csr", "ell", "packed", "auto") if deg <= 3 else ("csr", "ell", "auto")
+    for layout in layouts:
         for strat in ("grid", "persistent"):
             ch = sk.Chain.graph(n, inst.src, inst.dst, J=inst.J, lam_values=inst.lam_values,
                                 lam_class=inst.cls, q=0.9, beta=0.6, seed=4, replica=1, layout=layout)
