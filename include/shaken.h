@@ -252,7 +252,10 @@ typedef struct shaken_batch_opts {
                               configuration) over the full-step
                               configurations of each sweep call; needs every
                               2*lambda to be an integer                      */
-    int32_t reserved;
+    int32_t log_reserve;   /* with record: log space for sweeps of up to this
+                              many full steps is allocated at creation, so
+                              such sweeps allocate nothing; 0 = allocate on
+                              the first sweep that needs more (>= 0)         */
 } shaken_batch_opts;
 
 typedef struct shaken_batch shaken_batch;

@@ -76,7 +76,7 @@ class shaken_batch_opts(ctypes.Structure):
     _fields_ = [("strategy", ctypes.c_int32), ("use_hipgraph", ctypes.c_int32),
                 ("autotune", ctypes.c_int32), ("record", ctypes.c_int32),
                 ("stream", ctypes.c_void_p), ("track", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("log_reserve", ctypes.c_int32)]
 
 
 _vp = ctypes.c_void_p
@@ -334,10 +334,10 @@ class Batch:
     """A batch of chains advanced by fused launches (libshaken batch)."""
 
     def __init__(self, chains, strategy="auto", use_hipgraph=False, autotune=False,
-                 record=False, stream=None, track=False):
+                 record=False, stream=None, track=False, log_reserve=0):
         self.chains = list(chains)
         o = shaken_batch_opts(_STRAT[strategy], int(use_hipgraph), int(autotune), int(record),
-                              _stream_handle(stream), int(track), 0)
+                              _stream_handle(stream), int(track), int(log_reserve))
         arr = (_vp * len(self.chains))(*[c.handle.value for c in self.chains])
         h = _vp()
         _check(_lib.shaken_batch_create(ctypes.byref(h), arr, len(self.chains), ctypes.byref(o)))

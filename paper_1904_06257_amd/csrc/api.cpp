@@ -252,12 +252,14 @@ void unpack_torus(const std::vector<uint32_t> &in, int L, int W, int8_t *out) {
 }
 
 // Convert a device log (slots x stride) to H and M per slot.
-void convert_log(const shaken_ctx *c, const std::vector<int64_t> &raw, int64_t slots,
+// raw holds `parts` partial lines per slot (kLogParts for the grid kernels, 1
+// for the persistent kernel, which owns a chain's whole slot).
+void convert_log(const shaken_ctx *c, const std::vector<int64_t> &raw, int64_t slots, int parts,
                  int64_t *H, int64_t *M) {
-    const int64_t st = c->stride(), ln = c->line();
+    const int64_t ln = c->line(), st = parts * ln;
     auto val = [&](int64_t t, int64_t v) {
         int64_t a = 0;
-        for (int p = 0; p < kLogParts; ++p) a += raw[t * st + p * ln + v];
+        for (int p = 0; p < parts; ++p) a += raw[t * st + p * ln + v];
         return a;
     };
     for (int64_t t = 0; t < slots; ++t) {
@@ -698,7 +700,7 @@ shaken_status shaken_sweep(shaken_ctx *ctx, int64_t n_full, int64_t *H_out, int6
         std::vector<int64_t> raw((size_t)((n_full + 1) * ctx->stride()));
         HIPCHK(hipMemcpyAsync(raw.data(), ctx->log_dev, raw.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
         HIPCHK(hipStreamSynchronize(ctx->stream));
-        convert_log(ctx, raw, n_full + 1, H_out, M_out);
+        convert_log(ctx, raw, n_full + 1, kLogParts, H_out, M_out);
     }
     return SHAKEN_OK;
 }
@@ -888,6 +890,13 @@ struct shaken_batch {
     int64_t *track_pool = nullptr;
     uint32_t *best_pool = nullptr;
     std::vector<size_t> best_off;
+    // observables log, slot-major: slot t of chain i starts at
+    // log_pool + t * log_row + log_off[i] and holds log_parts lines
+    int64_t *log_pool = nullptr;
+    int64_t log_cap = 0;  // slots
+    int64_t log_row = 0;  // entries per slot over all chains
+    std::vector<int64_t> log_off;
+    int log_parts = kLogParts;
     uint32_t *dstate = nullptr;  // [0] half-step base, [1] log base
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
@@ -911,6 +920,7 @@ void batch_release(shaken_batch *b) {
     dfree(b->lut_pool);
     dfree(b->track_pool);
     dfree(b->best_pool);
+    dfree(b->log_pool);
     dfree(b->pdescs);
     dfree(b->order);
     dfree(b->counter);
@@ -931,7 +941,28 @@ ChainDesc batch_desc(shaken_batch *b, size_t i) {
     d.lut = b->lut_pool + b->lut_off[i];
     d.track = b->track_pool ? b->track_pool + 2 * i : nullptr;
     d.best = b->best_pool ? b->best_pool + b->best_off[i] : nullptr;
+    d.log = b->log_pool ? b->log_pool + b->log_off[i] : nullptr;
+    d.log_stride = b->log_row;
     return d;
+}
+
+// log space for `slots` slots of every chain (one allocation for the batch)
+shaken_status batch_ensure_log(shaken_batch *b, int64_t slots, bool *changed) {
+    if (slots <= b->log_cap) return SHAKEN_OK;
+    dfree(b->log_pool);
+    b->log_pool = nullptr;
+    b->log_cap = 0;
+    b->log_off.assign(b->ctx.size(), 0);
+    int64_t row = 0;
+    for (size_t i = 0; i < b->ctx.size(); ++i) {
+        b->log_off[i] = row;
+        row += b->log_parts * b->ctx[i]->line();
+    }
+    b->log_row = row;
+    CHK(dalloc(&b->log_pool, (size_t)(slots * row)));
+    b->log_cap = slots;
+    *changed = true;
+    return SHAKEN_OK;
 }
 
 shaken_status batch_upload(shaken_batch *b) {
@@ -1066,6 +1097,7 @@ shaken_status shaken_batch_create(shaken_batch **out, shaken_ctx *const *ctx, in
     if (ctx[0]->s & 1u) return fail(SHAKEN_ESTATE, "batches need an even half-step counter");
     if (o.strategy < SHAKEN_BATCH_AUTO || o.strategy > SHAKEN_BATCH_PERSISTENT)
         return fail(SHAKEN_EINVAL, "unknown batch strategy");
+    if (o.log_reserve < 0) return fail(SHAKEN_EINVAL, "log_reserve must be >= 0");
     shaken_batch *b = new (std::nothrow) shaken_batch();
     if (!b) return fail(SHAKEN_ENOMEM, "host allocation failed");
     b->ctx.assign(ctx, ctx + n);
@@ -1100,6 +1132,11 @@ shaken_status shaken_batch_create(shaken_batch **out, shaken_ctx *const *ctx, in
     if (b->track && strat != SHAKEN_BATCH_PERSISTENT)
         return bail(fail(SHAKEN_EINVAL, "tracking needs the persistent strategy"));
     b->strategy = strat;
+    b->log_parts = strat == SHAKEN_BATCH_PERSISTENT ? 1 : kLogParts;
+    if (b->record && o.log_reserve > 0) {
+        bool changed = false;
+        if ((st = batch_ensure_log(b, (int64_t)o.log_reserve + 1, &changed)) != SHAKEN_OK) return bail(st);
+    }
     // threshold pool (current tables of every chain)
     {
         size_t tot = 0;
@@ -1180,12 +1217,11 @@ shaken_status shaken_batch_sweep(shaken_batch *b, int64_t n_full) {
         if (c->s != s0) return fail(SHAKEN_ESTATE, "a context of the batch was stepped on its own");
     if (b->record) {
         bool changed = false;
-        for (auto *c : b->ctx) {
-            int64_t *before = c->log_dev;
-            CHK(ensure_log(c, n_full + 1));
-            changed |= before != c->log_dev;
-            HIPCHK(launch_fill_i64(c->log_dev, (n_full + 1) * c->stride(), 0, b->stream));
-        }
+        CHK(batch_ensure_log(b, n_full + 1, &changed));
+        // the grid kernels add partial sums into the slots; the persistent
+        // kernel writes every slot it logs
+        if (b->strategy == SHAKEN_BATCH_GRID)
+            HIPCHK(launch_fill_i64(b->log_pool, (n_full + 1) * b->log_row, 0, b->stream));
         if (changed) {
             CHK(batch_upload(b));
             if (b->gexec) {
@@ -1234,10 +1270,12 @@ shaken_status shaken_batch_get_log(shaken_batch *b, int32_t i, int64_t *H_out, i
     const int64_t slots = b->last_n_full + 1;
     if (cap < slots) return fail(SHAKEN_EINVAL, "capacity too small");
     DeviceGuard guard(b->device);
-    std::vector<int64_t> raw((size_t)(slots * c->stride()));
-    HIPCHK(hipMemcpyAsync(raw.data(), c->log_dev, raw.size() * 8, hipMemcpyDeviceToHost, b->stream));
+    const int64_t width = b->log_parts * c->line();
+    std::vector<int64_t> raw((size_t)(slots * width));
+    HIPCHK(hipMemcpy2DAsync(raw.data(), (size_t)width * 8, b->log_pool + b->log_off[i], (size_t)b->log_row * 8,
+                            (size_t)width * 8, (size_t)slots, hipMemcpyDeviceToHost, b->stream));
     HIPCHK(hipStreamSynchronize(b->stream));
-    convert_log(c, raw, slots, H_out, M_out);
+    convert_log(c, raw, slots, b->log_parts, H_out, M_out);
     return SHAKEN_OK;
 }
 

@@ -361,6 +361,36 @@ def test_batch_persistent_mixed(sk):
     assert np.array_equal(chains[0].spins(), x)
 
 
+@pytest.mark.parametrize("strategy", ["grid", "persistent"])
+def test_batch_log_reserve_and_growth(sk, strategy):
+    """Logs of consecutive sweeps of different lengths, within the reserved log
+    space and beyond it (the batch then grows it), against the oracle's
+    trajectory cut at the same points."""
+    lengths = [7, 20, 3, 33]
+    T = sum(lengths)
+    _print_case("log reserve", strategy)
+    specs = _mixed_specs(T, [16, 100], [1024, 2050], seed0=11)
+    chains = [_make(sk, sp) for sp in specs]
+    with pytest.raises(sk.ShakenError):
+        sk.Batch(chains, strategy=strategy, record=True, log_reserve=-1)
+    b = sk.Batch(chains, strategy=strategy, record=True, use_hipgraph=(strategy == "grid"),
+                 log_reserve=20)
+    t0 = 0
+    for n_full in lengths:
+        b.sweep(n_full)
+        for i, sp in enumerate(specs):
+            h, m = b.log(i, with_H=sp["H"] is not None)
+            assert np.array_equal(m, sp["M"][t0:t0 + n_full + 1]), (i, n_full)
+            if sp["H"] is not None:
+                assert np.array_equal(h, sp["H"][t0:t0 + n_full + 1]), (i, n_full)
+        t0 += n_full
+    for i, sp in enumerate(specs):
+        assert np.array_equal(chains[i].spins().reshape(sp["want"].shape), sp["want"]), i
+    b.close()
+    for c in chains:
+        c.close()
+
+
 def test_batch_persistent_equals_grid(sk):
     T = 12
     specs = _mixed_specs(T, [32, 80], [4096], seed0=3)
