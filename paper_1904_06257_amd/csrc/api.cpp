@@ -1199,8 +1199,8 @@ shaken_status shaken_batch_create(shaken_batch **out, shaken_ctx *const *ctx, in
         int ncu = 256;
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, b->device) == hipSuccess) ncu = prop.multiProcessorCount;
-        // 16 waves per workgroup: 2 workgroups fit on a CU (8 waves per SIMD)
-        b->pgrid = std::min(n, 2 * ncu);
+        // as many workgroups as are resident at once: each loops over the queue
+        b->pgrid = std::min(n, persistent_resident_blocks() * ncu);
     }
     if ((st = batch_upload(b)) != SHAKEN_OK) return bail(st);
     *out = b;

@@ -13,7 +13,10 @@
 
 namespace shaken {
 
-constexpr int kPBlock = 1024;  // 16 waves per chain
+#ifndef SHAKEN_PBLOCK
+#define SHAKEN_PBLOCK 1024
+#endif
+constexpr int kPBlock = SHAKEN_PBLOCK;  // threads per chain
 constexpr int kPWords = 2048;
 constexpr int kPClasses = 16;
 constexpr int kPLut = 256;  // threshold entries kept in LDS
@@ -167,6 +170,11 @@ __device__ __forceinline__ int lds_spin(const uint32_t *bits, int v) {
 // graph whose spins are bits in LDS.  A lane takes 4 consecutive vertices (one
 // Philox call); 8 consecutive lanes own one 32-vertex output word and merge
 // their 4-bit pieces with lane shuffles.
+// Adjacency layouts of a graph chain (one instantiation each, so that every
+// path gets its own register allocation).
+enum GraphLayout : int { GL_CSR = 0, GL_ELL = 1, GL_PACKED = 2 };
+
+template <int LAY>
 __device__ void graph_lds_half(const ChainDesc &d, const uint32_t *src, uint32_t *dst, uint32_t s,
                                bool obs, int *sh_red, int *sh_plus, Obs *o, const uint64_t *lut) {
     const int n = d.n;
@@ -189,7 +197,7 @@ __device__ void graph_lds_half(const ChainDesc &d, const uint32_t *src, uint32_t
             const int v0 = 4 * q4;
             int S0 = 0, S1 = 0, S2 = 0, S3 = 0;
             int cl[4];
-            if (d.pell) {
+            if constexpr (LAY == GL_PACKED) {
                 // packed: one 8-byte record per vertex holds neighbours, halves,
                 // signs and class (two 16-byte loads per thread)
                 const uint4 a = *(const uint4 *)(d.pell + v0);
@@ -217,7 +225,7 @@ __device__ void graph_lds_half(const ChainDesc &d, const uint32_t *src, uint32_t
                 S1 = t[1];
                 S2 = t[2];
                 S3 = t[3];
-            } else if (d.ell) {
+            } else if constexpr (LAY == GL_ELL) {
                 // ELL: one 16-byte record per slot for the 4 vertices, no row pointers
                 const int K = d.ell_k;
                 const uint32_t want = dst ? (uint32_t)((s & 1u) + 1u) : 1u;
@@ -263,7 +271,7 @@ __device__ void graph_lds_half(const ChainDesc &d, const uint32_t *src, uint32_t
             }
             }
             const int Sv[4] = {S0, S1, S2, S3};
-            if (!d.pell) {
+            if constexpr (LAY != GL_PACKED) {
                 if (v0 + 3 < n) {
                     const uint32_t c4 = *(const uint32_t *)(d.cls + v0);
 #pragma unroll
@@ -314,6 +322,7 @@ __device__ void graph_lds_half(const ChainDesc &d, const uint32_t *src, uint32_t
     }
 }
 
+template <int LAY>
 __device__ void run_graph(const ChainDesc &d, uint32_t (*buf)[kPWords], uint32_t s0, int64_t n_full,
                           int record, int track, int *sh_red, int *sh_plus, int *sh_flag,
                           uint64_t *sh_lut, Obs &o) {
@@ -339,16 +348,16 @@ __device__ void run_graph(const ChainDesc &d, uint32_t (*buf)[kPWords], uint32_t
     int64_t best_h = INT64_MAX, last_h = 0;
     for (int64_t t = 0; t < n_full; ++t) {
         const uint32_t s = s0 + 2u * (uint32_t)t;
-        graph_lds_half(d, buf[0], buf[1], s, obs, sh_red, sh_plus, &o, lut);
+        graph_lds_half<LAY>(d, buf[0], buf[1], s, obs, sh_red, sh_plus, &o, lut);
         if (obs)
             observe_step(d, o, record ? d.log + t * d.log_stride : nullptr, track, &best_h, &last_h,
                          buf[0], nw, sh_flag);
         __syncthreads();
-        graph_lds_half(d, buf[1], buf[0], s + 1u, false, sh_red, sh_plus, nullptr, lut);
+        graph_lds_half<LAY>(d, buf[1], buf[0], s + 1u, false, sh_red, sh_plus, nullptr, lut);
         __syncthreads();
     }
     if (obs) {
-        graph_lds_half(d, buf[0], nullptr, s0, true, sh_red, sh_plus, &o, lut);
+        graph_lds_half<LAY>(d, buf[0], nullptr, s0, true, sh_red, sh_plus, &o, lut);
         observe_step(d, o, record ? d.log + n_full * d.log_stride : nullptr, track, &best_h, &last_h,
                      buf[0], nw, sh_flag);
         if (track && threadIdx.x == 0) {
@@ -362,7 +371,13 @@ __device__ void run_graph(const ChainDesc &d, uint32_t (*buf)[kPWords], uint32_t
 
 // ------------------------------------------------------------------ kernel
 
-__global__ __launch_bounds__(kPBlock) void k_persistent(const ChainDesc *__restrict__ descs,
+// At least 8 waves per SIMD: two 1024-thread workgroups per CU, 64 VGPRs.
+// Twice the occupancy of the unconstrained allocation (120 VGPRs) outweighs
+// the few spills it costs.
+#ifndef SHAKEN_PWAVES
+#define SHAKEN_PWAVES 8
+#endif
+__global__ __launch_bounds__(kPBlock, SHAKEN_PWAVES) void k_persistent(const ChainDesc *__restrict__ descs,
                                                         int nchains,
                                                         const int32_t *__restrict__ order,
                                                         int32_t *counter, uint32_t s0,
@@ -390,10 +405,22 @@ __global__ __launch_bounds__(kPBlock) void k_persistent(const ChainDesc *__restr
             else
                 run_torus<false>(d, buf, s0, n_full, record, track, sh_red, &sh_flag, sh_obs);
         } else {
-            run_graph(d, buf, s0, n_full, record, track, sh_red, sh_plus, &sh_flag, sh_lut, sh_obs);
+            if (d.pell)
+                run_graph<GL_PACKED>(d, buf, s0, n_full, record, track, sh_red, sh_plus, &sh_flag, sh_lut, sh_obs);
+            else if (d.ell)
+                run_graph<GL_ELL>(d, buf, s0, n_full, record, track, sh_red, sh_plus, &sh_flag, sh_lut, sh_obs);
+            else
+                run_graph<GL_CSR>(d, buf, s0, n_full, record, track, sh_red, sh_plus, &sh_flag, sh_lut, sh_obs);
         }
         __syncthreads();
     }
+}
+
+int persistent_resident_blocks() {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_persistent, kPBlock, 0) != hipSuccess || nb < 1)
+        nb = 1;
+    return nb;
 }
 
 hipError_t launch_persistent(const ChainDesc *dev_descs, int nchains, const int32_t *order,

@@ -112,6 +112,9 @@ hipError_t launch_persistent(const ChainDesc *dev_descs, int nchains, const int3
 // can chain d run in the persistent kernel?
 bool persistent_fits(const ChainDesc &d);
 
+// workgroups of the persistent kernel resident on one compute unit at once
+int persistent_resident_blocks();
+
 // record the thread-local message returned by shaken_last_error()
 shaken_status set_error(shaken_status s, const char *msg);
 
