@@ -381,9 +381,8 @@ bool build_pell(int n, HostLayout &hl) {
         for (int h = 0; h < 2; ++h)
             for (int32_t e = hl.rp[h][v]; e < hl.rp[h][v + 1]; ++e, ++k) {
                 r |= (uint64_t)(uint32_t)hl.col[h][e] << (16 * k);
-                r |= (uint64_t)h << (48 + k);
-                r |= (uint64_t)(hl.jw[h][e] < 0) << (51 + k);
-                r |= 1ull << (54 + k);
+                r |= 1ull << (48 + 3 * h + k);
+                r |= (uint64_t)(hl.jw[h][e] < 0) << (54 + k);
             }
         hl.pell[v] = r;
     }

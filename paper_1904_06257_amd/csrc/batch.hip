@@ -198,28 +198,29 @@ __device__ void graph_lds_half(const ChainDesc &d, const uint32_t *src, uint32_t
             int S0 = 0, S1 = 0, S2 = 0, S3 = 0;
             int cl[4];
             if constexpr (LAY == GL_PACKED) {
-                // packed: one 8-byte record per vertex holds neighbours, halves,
-                // signs and class (two 16-byte loads per thread)
+                // packed: one 8-byte record per vertex holds neighbours, the
+                // slots of each half, signs and class (two 16-byte loads per
+                // thread).  With b_k the spin bits of the neighbours as 0/1,
+                // S = sum over the half's slots of J_k (2 b_k - 1)
+                //   = 2 popc((b ^ neg) & sel) - popc(sel).
                 const uint4 a = *(const uint4 *)(d.pell + v0);
                 const uint4 b = *(const uint4 *)(d.pell + v0 + 2);
                 const uint32_t lo[4] = {a.x, a.z, b.x, b.z};
                 const uint32_t hi[4] = {a.y, a.w, b.y, b.w};
-                const bool out_half = dst && (s & 1u);
+                const uint32_t selsh = (dst && (s & 1u)) ? 19u : 16u;
                 int t[4];
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    const uint32_t meta = hi[j] >> 16;
-                    const uint32_t sel = (out_half ? meta : ~meta) & (meta >> 6) & 7u;
-                    const uint32_t idx[3] = {lo[j] & 0xFFFFu, lo[j] >> 16, hi[j] & 0xFFFFu};
-                    int acc = 0;
-#pragma unroll
-                    for (int k = 0; k < 3; ++k) {
-                        const int sv = lds_spin(src, (int)idx[k]);
-                        const int v = ((meta >> (3 + k)) & 1u) ? -sv : sv;
-                        acc += ((sel >> k) & 1u) ? v : 0;
-                    }
-                    t[j] = acc;
-                    cl[j] = (int)((meta >> 9) & 15u);
+                    const uint32_t w0 = src[(lo[j] & 0xFFFFu) >> 5];
+                    const uint32_t w1 = src[lo[j] >> 21];
+                    const uint32_t w2 = src[(hi[j] & 0xFFFFu) >> 5];
+                    const uint32_t x = ((w0 >> (lo[j] & 31u)) & 1u) |
+                                       (((w1 >> ((lo[j] >> 16) & 31u)) & 1u) << 1) |
+                                       (((w2 >> (hi[j] & 31u)) & 1u) << 2);
+                    const uint32_t sel = (hi[j] >> selsh) & 7u;
+                    const uint32_t y = (x ^ (hi[j] >> 22)) & sel;
+                    t[j] = 2 * (int)__popc(y) - (int)__popc(sel);
+                    cl[j] = (int)((hi[j] >> 25) & 15u);
                 }
                 S0 = t[0];
                 S1 = t[1];
@@ -281,14 +282,16 @@ __device__ void graph_lds_half(const ChainDesc &d, const uint32_t *src, uint32_t
                     for (int j = 0; j < 4; ++j) cl[j] = v0 + j < n ? d.cls[v0 + j] : 0;
                 }
             }
+            // own spins of the four vertices: bits (v0 & 31) .. +3 of one word
+            const uint32_t ownw = src[v0 >> 5] >> (v0 & 31);
             if (dst) {
                 const U4 r = philox10((uint32_t)q4, s, d.replica, kGraphStream, k0, k1);
                 const uint32_t u[4] = {r.x, r.y, r.z, r.w};
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     if (v0 + j < n) {
-                        const int own = lds_spin(src, v0 + j);
-                        const uint64_t T = lut[((Sv[j] + smax) * 2 + (own > 0)) * ncls + cl[j]];
+                        const int own = (int)((ownw >> j) & 1u);
+                        const uint64_t T = lut[((Sv[j] + smax) * 2 + own) * ncls + cl[j]];
                         if ((uint64_t)u[j] < T) bits |= 1u << j;
                     }
                 }
@@ -297,9 +300,9 @@ __device__ void graph_lds_half(const ChainDesc &d, const uint32_t *src, uint32_t
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     if (v0 + j < n) {
-                        const int own = lds_spin(src, v0 + j);
-                        e_acc += own * Sv[j];
-                        if (own > 0) atomicAdd(&sh_plus[cl[j]], 1);
+                        const bool up = (ownw >> j) & 1u;
+                        e_acc += up ? Sv[j] : -Sv[j];
+                        if (up) atomicAdd(&sh_plus[cl[j]], 1);
                     }
                 }
             }

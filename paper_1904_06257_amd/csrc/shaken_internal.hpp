@@ -51,8 +51,9 @@ struct ChainDesc {
     int64_t ell_stride;      // n rounded up to a multiple of 4
     // packed record per vertex (couplings +-1, degree <= 3, n <= 65536, at most
     // 16 classes), ell_stride entries: bits 0-47 three 16-bit neighbour
-    // indices; bits 48-50 slot k in the out-half; 51-53 J < 0; 54-56 slot
-    // used; 57-60 field class.  Unused slots and padding vertices read index 0.
+    // indices; bit 48+k: slot k is in the in-half; 51+k: in the out-half;
+    // 54+k: J < 0; bits 57-60 field class.  Unused slots and padding vertices
+    // have index 0 and no half bit.
     const uint64_t *pell;
     // observables log: slot t is kLogParts lines of log_line int64; line p holds
     // partial sums [E_J, plus_0 .. plus_{ncls-1}] (a block adds into line
