@@ -19,11 +19,13 @@ namespace shaken {
 constexpr int kPBlock = SHAKEN_PBLOCK;  // threads per chain
 constexpr int kPWords = 2048;
 constexpr int kPClasses = 16;
-constexpr int kPLut = 256;  // threshold entries kept in LDS
+constexpr int kPLut = 512;  // threshold entries kept in LDS
 
 bool persistent_fits(const ChainDesc &d) {
     if (d.kind == KIND_TORUS) return d.format == FMT_BITPACKED && d.L * d.W <= kPWords;
-    return d.n <= 32 * kPWords && d.ncls <= kPClasses;
+    // the ELL and packed paths read the threshold table from LDS only
+    const bool lut_lds = (2 * d.smax + 1) * 2 * d.ncls <= kPLut;
+    return d.n <= 32 * kPWords && d.ncls <= kPClasses && (lut_lds || (!d.ell && !d.pell));
 }
 
 // Sum e and p over the workgroup; the totals are valid in thread 0.
@@ -334,10 +336,11 @@ __device__ void run_graph(const ChainDesc &d, uint32_t (*buf)[kPWords], uint32_t
     // the chain's threshold table in LDS when it fits (constant during the call)
     const int nlut = (2 * d.smax + 1) * 2 * d.ncls;
     const uint64_t *lut = d.lut;
-    if (nlut <= kPLut) {
+    if (LAY != GL_CSR || nlut <= kPLut) {
         for (int i = threadIdx.x; i < nlut; i += kPBlock) sh_lut[i] = d.lut[i];
         lut = sh_lut;
     }
+    if constexpr (LAY != GL_CSR) lut = sh_lut;  // always LDS (checked on the host)
     const int8_t *g = (const int8_t *)d.spin[0];
     for (int w = threadIdx.x; w < nw; w += kPBlock) {
         uint32_t word = 0;
