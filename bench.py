@@ -73,10 +73,10 @@ def read_traffic(kernel_key, per="launch"):
 
 
 def cpu_baseline_torus():
-    """The oracle as it stands: four full steps (eight half-steps) of one
-    4096^2 chain, single-threaded C."""
+    """The oracle as it stands: ten full steps (twenty half-steps) of one
+    4096^2 chain, single-threaded C (about 10 s of host time)."""
     import oracle
-    L, steps = 4096, 4
+    L, steps = 4096, 10
     sp = oracle.torus_init_random(L, 2)
     t0 = time.perf_counter()
     oracle.torus_run(sp, 1, 0.0, 1.0, 0.44, 2, 0, steps, log=False)
