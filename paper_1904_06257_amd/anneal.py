@@ -80,6 +80,14 @@ class PerturbedPolicy:
         lb, lq = self.base(F, c, n_chunks)
         return lb + self.db[c], lq + self.dq[c]
 
+    def piece(self, a, b):
+        """The same perturbations restricted to rows [a, b)."""
+        p = PerturbedPolicy.__new__(PerturbedPolicy)
+        p.base = self.base
+        p.db = self.db[:, a:b]
+        p.dq = self.dq[:, a:b]
+        return p
+
 
 class MLPPolicy:
     def __init__(self, mlp: MLP, device="cuda"):

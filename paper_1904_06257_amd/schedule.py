@@ -79,15 +79,25 @@ def tune_geometric(insts, seeds, sweeps, chunk):
     return anneal.GeometricPolicy(b0, b1, q), results
 
 
-def generate(insts, seeds, base, k_sched, sweeps, chunk, seed, scale=1.0):
-    """k_sched perturbed schedules per instance, all in one batch."""
+def generate(insts, seeds, base, k_sched, sweeps, chunk, seed, scale=1.0, piece=8192):
+    """k_sched perturbed schedules per instance, in batches of at most `piece`
+    runs (one persistent batch each)."""
     big = [g for g in insts for _ in range(k_sched)]
     bseeds = np.repeat(seeds, k_sched)
     n_chunks = sweeps // chunk
     pol = anneal.PerturbedPolicy(base, len(big), n_chunks, seed, sigma_b=0.12 * scale,
                                  sigma_q=0.15 * scale, q_spread=0.6 * scale)
     t0 = time.perf_counter()
-    res = anneal.run(big, bseeds, pol, sweeps, chunk)
+    parts = []
+    for a in range(0, len(big), piece):
+        b = min(a + piece, len(big))
+        parts.append(anneal.run(big[a:b], bseeds[a:b], pol.piece(a, b), sweeps, chunk, replica0=a))
+        _log("  runs %d..%d done (%.1f s)" % (a, b, time.perf_counter() - t0))
+    res = anneal.RunResult(np.concatenate([r.best for r in parts]), np.concatenate([r.last for r in parts]),
+                           [], [], np.concatenate([r.feats for r in parts], axis=1),
+                           np.concatenate([r.log_beta for r in parts], axis=1),
+                           np.concatenate([r.log_q for r in parts], axis=1),
+                           sum(r.seconds for r in parts))
     _log("generated %d runs in %.1f s" % (len(big), time.perf_counter() - t0))
     return res
 

@@ -161,9 +161,10 @@ def test_anneal_replay_parity(env):
 
 
 def test_learned_schedule_beats_plain(env):
-    """The committed network against the tuned geometric schedule on held-out
-    instances (evaluation seeds, same Philox seeds for both), 10^4 sweeps:
-    every reported energy is recomputed by the oracle from the returned
+    """The committed network against the tuned geometric schedule on the 512
+    held-out evaluation instances (171 / 171 / 170 graphs of n = 4096 / 16384 /
+    65536; same Philox seeds for both schedules), 10^4 sweeps: every reported
+    best and final energy is recomputed by the oracle from the returned
     configurations, and the learned schedule reaches lower best energies."""
     sk, torch = env
     import os
@@ -172,7 +173,8 @@ def test_learned_schedule_beats_plain(env):
     g = meta["geometric"]
     mlp = sk.MLP()
     mlp.set_params(P)
-    insts, seeds = schedule.instances(schedule.EVAL_SEED0 + 1000, (12, 12, 4))
+    insts, seeds = schedule.instances(schedule.EVAL_SEED0, (171, 171, 170))
+    print("case: 512 held-out instances", flush=True)
     rl = anneal.run(insts, seeds, anneal.MLPPolicy(mlp), 10000, 250, keep_spins=True)
     rp = anneal.run(insts, seeds, anneal.GeometricPolicy(g["beta0"], g["beta1"], g["q"]), 10000, 250,
                     keep_spins=True)
@@ -182,8 +184,9 @@ def test_learned_schedule_beats_plain(env):
             og = oracle.Graph(x.n, x.src, x.dst, x.J, x.cls, x.lam_values)
             assert -oracle.graph_observe(og, res.best_spins[i])[0] == res.best[i]
             assert -oracle.graph_observe(og, res.final_spins[i])[0] == res.last[i]
+            assert res.best[i] <= res.last[i]
     d = (rp.best - rl.best) / ns
-    print("learned vs plain: mean gain %.5f per spin, learned better on %d of %d"
-          % (d.mean(), (d > 0).sum(), len(d)), flush=True)
-    assert d.mean() > 0.004
-    assert (d > 0).mean() > 0.75
+    print("learned vs plain: mean best %.5f vs %.5f per spin, gain %.5f, learned better on %d of %d"
+          % ((rl.best / ns).mean(), (rp.best / ns).mean(), d.mean(), (d > 0).sum(), len(d)), flush=True)
+    assert d.mean() > 0.008
+    assert (d > 0).mean() > 0.95
