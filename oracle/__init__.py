@@ -73,6 +73,22 @@ def lib():
                                        ctypes.c_double, ctypes.c_uint64, ctypes.c_uint32,
                                        ctypes.c_uint32, _i8p, ctypes.c_int64, _i64p, _i64p]
         L.oracle_torus_run.restype = ctypes.c_int
+        L.oracle_torus_site_j.argtypes = [ctypes.c_int, ctypes.c_int, _i8p, _i8p, ctypes.c_double,
+                                          ctypes.c_double, ctypes.c_double, ctypes.c_uint64,
+                                          ctypes.c_uint32, ctypes.c_uint32, _i8p, ctypes.c_int,
+                                          ctypes.c_int]
+        L.oracle_torus_site_j.restype = ctypes.c_int
+        L.oracle_torus_half_step_j.argtypes = [ctypes.c_int, ctypes.c_int, _i8p, _i8p,
+                                               ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                               ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                                               _i8p, _i8p]
+        L.oracle_torus_observe_j.argtypes = [ctypes.c_int, ctypes.c_int, _i8p, _i8p, _i8p, _i64p,
+                                             _i64p]
+        L.oracle_torus_run_j.argtypes = [ctypes.c_int, ctypes.c_int, _i8p, _i8p, ctypes.c_double,
+                                         ctypes.c_double, ctypes.c_double, ctypes.c_uint64,
+                                         ctypes.c_uint32, ctypes.c_uint32, _i8p, ctypes.c_int64,
+                                         _i64p, _i64p]
+        L.oracle_torus_run_j.restype = ctypes.c_int
         L.oracle_graph_uniform.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
                                            ctypes.c_uint32]
         L.oracle_graph_uniform.restype = ctypes.c_uint32
@@ -130,40 +146,56 @@ def torus_uniform(L, seed, replica, s, r, c) -> int:
     return int(lib().oracle_torus_uniform(L, ctypes.c_uint64(seed), replica, s, r, c))
 
 
+def _couplings(J, L):
+    """J as an int (uniform coupling) or a pair (Jup, Jright) of int8 [L, L]
+    arrays: Jup[r, c] couples (r, c) to (r+1, c), Jright[r, c] to (r, c+1)."""
+    if np.isscalar(J):
+        return int(J), None, None
+    ju = np.ascontiguousarray(J[0], dtype=np.int8).reshape(L * L)
+    jr = np.ascontiguousarray(J[1], dtype=np.int8).reshape(L * L)
+    return 0, ju, jr
+
+
 def torus_half_step(spins, J, lam, q, beta, seed, replica, s) -> np.ndarray:
     L = spins.shape[0]
     a = np.ascontiguousarray(spins, dtype=np.int8)
     out = np.zeros_like(a)
-    lib().oracle_torus_half_step(L, int(J), float(lam), float(q), float(beta),
-                                 ctypes.c_uint64(seed), replica, s & 0xFFFFFFFF,
-                                 _p(a, _i8p), _p(out, _i8p))
+    j, ju, jr = _couplings(J, L)
+    lib().oracle_torus_half_step_j(L, j, _p(ju, _i8p), _p(jr, _i8p), float(lam), float(q),
+                                   float(beta), ctypes.c_uint64(seed), replica, s & 0xFFFFFFFF,
+                                   _p(a, _i8p), _p(out, _i8p))
     return out
 
 
 def torus_site(spins, J, lam, q, beta, seed, replica, s, r, c) -> int:
     a = np.ascontiguousarray(spins, dtype=np.int8)
-    return int(lib().oracle_torus_site(a.shape[0], int(J), float(lam), float(q), float(beta),
-                                       ctypes.c_uint64(seed), replica, s & 0xFFFFFFFF,
-                                       _p(a, _i8p), int(r), int(c)))
+    j, ju, jr = _couplings(J, a.shape[0])
+    return int(lib().oracle_torus_site_j(a.shape[0], j, _p(ju, _i8p), _p(jr, _i8p), float(lam),
+                                         float(q), float(beta), ctypes.c_uint64(seed), replica,
+                                         s & 0xFFFFFFFF, _p(a, _i8p), int(r), int(c)))
 
 
 def torus_observe(spins, J=1):
     a = np.ascontiguousarray(spins, dtype=np.int8)
     e = ctypes.c_int64()
     m = ctypes.c_int64()
-    lib().oracle_torus_observe(a.shape[0], int(J), _p(a, _i8p), ctypes.byref(e), ctypes.byref(m))
+    j, ju, jr = _couplings(J, a.shape[0])
+    lib().oracle_torus_observe_j(a.shape[0], j, _p(ju, _i8p), _p(jr, _i8p), _p(a, _i8p),
+                                 ctypes.byref(e), ctypes.byref(m))
     return e.value, m.value
 
 
 def torus_run(spins, J, lam, q, beta, seed, replica, n_full, s0=0, log=True):
-    """Returns (final spins, E_J log, M log); logs have n_full+1 entries."""
+    """Returns (final spins, E_J log, M log); logs have n_full+1 entries.  J is
+    an int or a pair (Jup, Jright) of [L, L] int8 arrays."""
     a = np.ascontiguousarray(spins, dtype=np.int8).copy()
     L = a.shape[0]
     ej = np.zeros(n_full + 1, dtype=np.int64) if log else None
     m = np.zeros(n_full + 1, dtype=np.int64) if log else None
-    rc = lib().oracle_torus_run(L, int(J), float(lam), float(q), float(beta),
-                                ctypes.c_uint64(seed), replica, s0, _p(a, _i8p), n_full,
-                                _p(ej, _i64p), _p(m, _i64p))
+    j, ju, jr = _couplings(J, L)
+    rc = lib().oracle_torus_run_j(L, j, _p(ju, _i8p), _p(jr, _i8p), float(lam), float(q),
+                                  float(beta), ctypes.c_uint64(seed), replica, s0, _p(a, _i8p),
+                                  n_full, _p(ej, _i64p), _p(m, _i64p))
     if rc != 0:
         raise RuntimeError("oracle_torus_run failed")
     return a, ej, m

@@ -147,29 +147,48 @@ void oracle_torus_init_random(int L, uint64_t seed, uint32_t replica, int8_t *sp
         }
 }
 
-/* neighbour sum of site (r,c): phase 0 = down + left, phase 1 = up + right */
-static int torus_nsum(int L, const int8_t *sp, int r, int c, int phase)
+/* Coupling-weighted neighbour sum of site (r,c).  The oriented edges of the
+ * torus are (x, x_up) with coupling Jup[x] and (x, x_right) with Jr[x]
+ * (row-major site index); Jup == NULL means every coupling equals J.
+ *   phase 0 (in-half, dl):  Jup[x_down] sigma(x_down) + Jr[x_left] sigma(x_left)
+ *   phase 1 (out-half, ur): Jup[x] sigma(x_up) + Jr[x] sigma(x_right)        */
+static int64_t torus_fsum(int L, int J, const int8_t *Jup, const int8_t *Jr,
+                          const int8_t *sp, int r, int c, int phase)
 {
-    if (phase == 0)
-        return sp[((r - 1 + L) % L) * L + c] + sp[r * L + (c - 1 + L) % L];
-    return sp[((r + 1) % L) * L + c] + sp[r * L + (c + 1) % L];
+    int x = r * L + c;
+    if (phase == 0) {
+        int xd = ((r - 1 + L) % L) * L + c, xl = r * L + (c - 1 + L) % L;
+        if (!Jup) return (int64_t)J * (sp[xd] + sp[xl]);
+        return (int64_t)Jup[xd] * sp[xd] + (int64_t)Jr[xl] * sp[xl];
+    } else {
+        int xu = ((r + 1) % L) * L + c, xr = r * L + (c + 1) % L;
+        if (!Jup) return (int64_t)J * (sp[xu] + sp[xr]);
+        return (int64_t)Jup[x] * sp[xu] + (int64_t)Jr[x] * sp[xr];
+    }
 }
 
 /* new value of one site at half-step s, read from configuration `in` */
-int oracle_torus_site(int L, int J, double lam, double q, double beta, uint64_t seed,
-                      uint32_t replica, uint32_t s, const int8_t *in, int r, int c)
+int oracle_torus_site_j(int L, int J, const int8_t *Jup, const int8_t *Jr, double lam,
+                        double q, double beta, uint64_t seed, uint32_t replica, uint32_t s,
+                        const int8_t *in, int r, int c)
 {
-    int64_t S = (int64_t)J * torus_nsum(L, in, r, c, (int)(s & 1u));
+    int64_t S = torus_fsum(L, J, Jup, Jr, in, r, c, (int)(s & 1u));
     double h = oracle_field(S, in[r * L + c], q, lam);
     uint64_t T = oracle_threshold(h, beta);
     uint32_t u = oracle_torus_uniform(L, seed, replica, s, r, c);
     return ((uint64_t)u < T) ? 1 : -1;
 }
 
+int oracle_torus_site(int L, int J, double lam, double q, double beta, uint64_t seed,
+                      uint32_t replica, uint32_t s, const int8_t *in, int r, int c)
+{
+    return oracle_torus_site_j(L, J, NULL, NULL, lam, q, beta, seed, replica, s, in, r, c);
+}
+
 /* one half-step: every site redrawn from `in` into `out` (in != out) */
-void oracle_torus_half_step(int L, int J, double lam, double q, double beta,
-                            uint64_t seed, uint32_t replica, uint32_t s,
-                            const int8_t *in, int8_t *out)
+void oracle_torus_half_step_j(int L, int J, const int8_t *Jup, const int8_t *Jr, double lam,
+                              double q, double beta, uint64_t seed, uint32_t replica,
+                              uint32_t s, const int8_t *in, int8_t *out)
 {
     int W = torus_words(L), r, wd, b;
     uint32_t R[32];
@@ -178,7 +197,7 @@ void oracle_torus_half_step(int L, int J, double lam, double q, double beta,
             torus_levels(seed, replica, s, (uint32_t)(r * W + wd), R);
             for (b = 0; b < 32 && 32 * wd + b < L; ++b) {
                 int c = 32 * wd + b;
-                int64_t S = (int64_t)J * torus_nsum(L, in, r, c, (int)(s & 1u));
+                int64_t S = torus_fsum(L, J, Jup, Jr, in, r, c, (int)(s & 1u));
                 double h = oracle_field(S, in[r * L + c], q, lam);
                 uint64_t T = oracle_threshold(h, beta);
                 uint32_t u = torus_u_from_levels(R, b);
@@ -187,29 +206,43 @@ void oracle_torus_half_step(int L, int J, double lam, double q, double beta,
         }
 }
 
+void oracle_torus_half_step(int L, int J, double lam, double q, double beta,
+                            uint64_t seed, uint32_t replica, uint32_t s,
+                            const int8_t *in, int8_t *out)
+{
+    oracle_torus_half_step_j(L, J, NULL, NULL, lam, q, beta, seed, replica, s, in, out);
+}
+
 /* E_J over the oriented edge set {(x, x_up), (x, x_right)} and M */
-void oracle_torus_observe(int L, int J, const int8_t *sp, int64_t *EJ, int64_t *M)
+void oracle_torus_observe_j(int L, int J, const int8_t *Jup, const int8_t *Jr,
+                            const int8_t *sp, int64_t *EJ, int64_t *M)
 {
     int64_t e = 0, m = 0;
     int r, c;
     for (r = 0; r < L; ++r)
         for (c = 0; c < L; ++c) {
-            int x = sp[r * L + c];
-            e += (int64_t)J * x * sp[((r + 1) % L) * L + c];
-            e += (int64_t)J * x * sp[r * L + (c + 1) % L];
-            m += x;
+            int x = r * L + c;
+            int ju = Jup ? Jup[x] : J, jr = Jup ? Jr[x] : J;
+            e += (int64_t)ju * sp[x] * sp[((r + 1) % L) * L + c];
+            e += (int64_t)jr * sp[x] * sp[r * L + (c + 1) % L];
+            m += sp[x];
         }
     *EJ = e;
     *M = m;
+}
+
+void oracle_torus_observe(int L, int J, const int8_t *sp, int64_t *EJ, int64_t *M)
+{
+    oracle_torus_observe_j(L, J, NULL, NULL, sp, EJ, M);
 }
 
 /* n_full full steps from half-step index s0 (must be even); spins updated in
  * place (through a private second buffer); logs hold n_full+1 entries
  * (configuration at the start and after every full step); NULL skips a log.
  * Returns 0, or -1 on allocation failure / odd s0. */
-int oracle_torus_run(int L, int J, double lam, double q, double beta, uint64_t seed,
-                     uint32_t replica, uint32_t s0, int8_t *spins, int64_t n_full,
-                     int64_t *EJ_log, int64_t *M_log)
+int oracle_torus_run_j(int L, int J, const int8_t *Jup, const int8_t *Jr, double lam,
+                       double q, double beta, uint64_t seed, uint32_t replica, uint32_t s0,
+                       int8_t *spins, int64_t n_full, int64_t *EJ_log, int64_t *M_log)
 {
     int8_t *tmp;
     int64_t t;
@@ -220,17 +253,25 @@ int oracle_torus_run(int L, int J, double lam, double q, double beta, uint64_t s
     for (t = 0; t <= n_full; ++t) {
         int64_t e, m;
         if (EJ_log || M_log) {
-            oracle_torus_observe(L, J, spins, &e, &m);
+            oracle_torus_observe_j(L, J, Jup, Jr, spins, &e, &m);
             if (EJ_log) EJ_log[t] = e;
             if (M_log) M_log[t] = m;
         }
         if (t == n_full) break;
-        oracle_torus_half_step(L, J, lam, q, beta, seed, replica, s, spins, tmp);
-        oracle_torus_half_step(L, J, lam, q, beta, seed, replica, s + 1, tmp, spins);
+        oracle_torus_half_step_j(L, J, Jup, Jr, lam, q, beta, seed, replica, s, spins, tmp);
+        oracle_torus_half_step_j(L, J, Jup, Jr, lam, q, beta, seed, replica, s + 1, tmp, spins);
         s += 2;
     }
     free(tmp);
     return 0;
+}
+
+int oracle_torus_run(int L, int J, double lam, double q, double beta, uint64_t seed,
+                     uint32_t replica, uint32_t s0, int8_t *spins, int64_t n_full,
+                     int64_t *EJ_log, int64_t *M_log)
+{
+    return oracle_torus_run_j(L, J, NULL, NULL, lam, q, beta, seed, replica, s0, spins, n_full,
+                              EJ_log, M_log);
 }
 
 /* ----------------------------------------------------------------- graph -- */
