@@ -153,16 +153,19 @@ typedef struct shaken_ctx shaken_ctx;
  * q >= 0 (Definition 2.2 takes q > 0; q = 0 is accepted) and inverse
  * temperature beta >= 0 (both finite), Philox key `seed`.
  *   J: host int8 per oriented edge (m entries), or NULL = all +1.  For the
- *      torus J is per oriented edge too (2*L*L entries: index 2x is the edge
- *      (x, x_up), 2x+1 is (x, x_right)) and must currently be uniform; NULL
- *      means +1.
+ *      torus J is per oriented edge too (2*L*L entries, x = row*L + col:
+ *      index 2x is the edge (x, x_up), 2x+1 is (x, x_right)); every entry
+ *      must have the same magnitude: a uniform coupling, or +-J with any
+ *      signs (the Edwards-Anderson couplings of section 6, kept as two sign
+ *      bit-planes); NULL means +1.
  *   opts: NULL = defaults (AUTO format, random init, replica 0, current
  *      device, null stream).
  * The threshold table covers every local field the graph can produce; its
  * size is (2*Smax+1) * 2 * n_classes entries with Smax the largest sum of
  * |J| over a half-neighbourhood; more than 2^24 entries is SHAKEN_EINVAL.
  * Errors: SHAKEN_EINVAL (bad graph, q/beta negative or not finite, torus with
- * a non-uniform J or field), SHAKEN_ENOMEM, SHAKEN_EDEVICE. */
+ * couplings of different magnitudes or a non-uniform field), SHAKEN_ENOMEM,
+ * SHAKEN_EDEVICE. */
 shaken_status shaken_init(shaken_ctx **out, const shaken_graph *g, const int8_t *J,
                           const shaken_field *lambda, double q, double beta,
                           uint64_t seed, const shaken_opts *opts);

@@ -222,6 +222,12 @@ class Chain:
             self.n = int(n)
         else:
             raise ValueError("kind must be 'torus' or 'graph'")
+        if kind == "torus" and isinstance(J, tuple):
+            # (Jup, Jright), each [L, L]: interleave into the per-edge order
+            # of the C ABI (2x = (x, x_up), 2x+1 = (x, x_right))
+            ju = np.asarray(J[0], dtype=np.int8).reshape(-1)
+            jr = np.asarray(J[1], dtype=np.int8).reshape(-1)
+            J = np.stack([ju, jr], axis=1).reshape(-1)
         Jarr = None if J is None else np.ascontiguousarray(J, dtype=np.int8)
         field = None
         if lam_values is not None:

@@ -133,6 +133,7 @@ struct shaken_ctx {
     uint8_t *cls_dev = nullptr;
     uint32_t *ell_dev = nullptr;
     uint64_t *pell_dev = nullptr;
+    uint32_t *jneg_dev = nullptr;  // +-J torus sign planes (2 x L x W words)
     int ell_k = 0;
     int64_t ell_stride = 0;
     int64_t *log_dev = nullptr;
@@ -166,6 +167,7 @@ void release(shaken_ctx *c) {
     dfree(c->cls_dev);
     dfree(c->ell_dev);
     dfree(c->pell_dev);
+    dfree(c->jneg_dev);
     dfree(c->log_dev);
     dfree(c->obs_dev);
     dfree(c->dd);
@@ -334,6 +336,7 @@ struct HostLayout {
     std::vector<int8_t> jw[2];
     std::vector<uint32_t> ell;  // slot-major, ell_k * ell_stride entries
     std::vector<uint64_t> pell; // packed record per vertex, ell_stride entries
+    std::vector<uint32_t> jneg; // +-J torus: sign planes of J(x, x_up) and J(x, x_right)
     int ell_k = 0;
     int64_t ell_stride = 0;
 };
@@ -425,10 +428,29 @@ shaken_status init_host(shaken_ctx *c, const shaken_graph *g, const int8_t *J,
         c->m = 2 * (int64_t)c->n;
         c->J = 1;
         if (J) {
-            for (int64_t e = 1; e < c->m; ++e)
-                if (J[e] != J[0])
-                    return fail(SHAKEN_EINVAL, "torus: couplings must be uniform (pass a non-uniform torus as SHAKEN_EDGES)");
+            // uniform coupling, or +-J (one magnitude, any signs: the
+            // Edwards-Anderson couplings of section 6) as two sign planes
+            const int mag = std::abs((int)J[0]);
+            bool mixed = false;
+            for (int64_t e = 1; e < c->m; ++e) {
+                if (std::abs((int)J[e]) != mag)
+                    return fail(SHAKEN_EINVAL, "torus: every coupling must have the same magnitude "
+                                               "(uniform or +-J; pass other tori as SHAKEN_EDGES)");
+                mixed |= J[e] != J[0];
+            }
             c->J = J[0];
+            if (mixed) {
+                c->J = mag;
+                const int L = c->L, W = c->W;
+                hl.jneg.assign((size_t)2 * L * W, 0u);
+                for (int r = 0; r < L; ++r)
+                    for (int col = 0; col < L; ++col) {
+                        const int64_t x = (int64_t)r * L + col;
+                        const uint32_t bit = 1u << (col & 31);
+                        if (J[2 * x] < 0) hl.jneg[(size_t)r * W + (col >> 5)] |= bit;
+                        if (J[2 * x + 1] < 0) hl.jneg[(size_t)L * W + (size_t)r * W + (col >> 5)] |= bit;
+                    }
+            }
         }
         c->smax = 2 * std::abs(c->J);
         c->maxdeg = 2;
@@ -527,6 +549,10 @@ shaken_status init_device(shaken_ctx *c, const shaken_opts *o, HostLayout &hl) {
             HIPCHK(hipMemcpyAsync(c->pell_dev, hl.pell.data(), hl.pell.size() * 8, hipMemcpyHostToDevice, c->stream));
         }
     }
+    if (!hl.jneg.empty()) {
+        CHK(dalloc(&c->jneg_dev, hl.jneg.size()));
+        HIPCHK(hipMemcpyAsync(c->jneg_dev, hl.jneg.data(), hl.jneg.size() * 4, hipMemcpyHostToDevice, c->stream));
+    }
 
     // descriptor
     ChainDesc &d = c->hd;
@@ -553,6 +579,7 @@ shaken_status init_device(shaken_ctx *c, const shaken_opts *o, HostLayout &hl) {
     d.ell_k = c->ell_k;
     d.ell_stride = c->ell_stride;
     d.pell = c->pell_dev;
+    d.jneg = c->jneg_dev;
     d.log_line = c->line();
     d.log_stride = c->stride();
     for (size_t k = 0; k < c->lam.size() && k < 16; ++k) {

@@ -77,6 +77,7 @@ __device__ void torus_lds_half(const ChainDesc &d, const uint32_t *src, uint32_t
             const uint32_t carry = wd > 0 ? (src[r * W + wd - 1] >> 31)
                                           : ((src[r * W + W - 1] >> lastbits) & 1u);
             b = (own << 1) | carry;
+            if (d.jneg) bp_jflip(d.jneg, L, W, r, wd, 0, a, b);
             if (obs) {
                 e_acc += d.J * (2 * __popc(vm) - 2 * __popc((own ^ a) & vm) - 2 * __popc((own ^ b) & vm));
                 p_acc += __popc(own & vm);
@@ -88,6 +89,7 @@ __device__ void torus_lds_half(const ChainDesc &d, const uint32_t *src, uint32_t
             a = src[(r == L - 1 ? 0 : r + 1) * W + wd];
             b = wd < W - 1 ? ((own >> 1) | (src[r * W + wd + 1] << 31))
                            : ((own >> 1) | ((src[r * W] & 1u) << lastbits));
+            if (d.jneg) bp_jflip(d.jneg, L, W, r, wd, 1, a, b);
         }
         dst[w] = bp_word<FOLD3>(a, b, own, vm, (uint32_t)w, s, d.replica, k0, k1, d.tsmall, d.sgn);
     }

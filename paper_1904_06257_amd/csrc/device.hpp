@@ -161,6 +161,35 @@ __device__ __forceinline__ uint32_t bp_word(uint32_t a, uint32_t b, uint32_t c, 
     return (res ^ p.smask) & vm;
 }
 
+// +-J torus: flip the neighbour planes a (vertical) and b (horizontal) of
+// word (r, wd) where the coupling of the edge to that neighbour is negative.
+// dl (phase 0): the edges come from the row below, (x_down, x), and from the
+// left, (x_left, x), so the right-edge plane is shifted like b; ur (phase 1):
+// the edges (x, x_up) and (x, x_right) belong to the word itself.
+__device__ __forceinline__ void bp_jflip(const uint32_t *__restrict__ jn, int L, int W, int r,
+                                         int wd, int phase, uint32_t &a, uint32_t &b) {
+    const uint32_t *__restrict__ up = jn;
+    const uint32_t *__restrict__ rt = jn + (size_t)L * W;
+    if (phase == 0) {
+        const int rd = (r == 0) ? L - 1 : r - 1;
+        a ^= up[rd * W + wd];
+        const uint32_t carry = wd > 0 ? (rt[r * W + wd - 1] >> 31)
+                                      : ((rt[r * W + W - 1] >> ((L - 1) & 31)) & 1u);
+        b ^= (rt[r * W + wd] << 1) | carry;
+    } else {
+        a ^= up[r * W + wd];
+        b ^= rt[r * W + wd];
+    }
+}
+
+// sign (+1 / -1) of the coupling of torus site (r, c) to its up (plane 0) or
+// right (plane 1) neighbour; +1 without sign planes
+__device__ __forceinline__ int torus_jsign(const uint32_t *__restrict__ jn, int L, int W, int plane,
+                                           int r, int c) {
+    if (!jn) return 1;
+    return ((jn[(size_t)plane * L * W + r * W + (c >> 5)] >> (c & 31)) & 1u) ? -1 : 1;
+}
+
 __device__ __forceinline__ uint32_t bp_valid(int L, int W, int wd) {
     const int rem = L & 31;
     return (wd == W - 1 && rem) ? ((1u << rem) - 1u) : 0xFFFFFFFFu;

@@ -87,7 +87,7 @@ __device__ __noinline__ uint32_t bp_finish(uint32_t a, uint32_t b, uint32_t c, u
 // not idle while its slowest lane runs the rare deep levels.
 constexpr int kQCap = 512;
 
-template <bool OBS, bool FOLD3>
+template <bool OBS, bool FOLD3, bool JPL>
 __global__ __launch_bounds__(256) void k_torus_bp(const ChainDesc *__restrict__ descs, StepArgs sa) {
     __shared__ uint32_t q_w[kQCap], q_a[kQCap], q_b[kQCap], q_c[kQCap], q_und[kQCap], q_res[kQCap];
     __shared__ int q_n;
@@ -149,6 +149,7 @@ __global__ __launch_bounds__(256) void k_torus_bp(const ChainDesc *__restrict__ 
                 b = wd < W - 1 ? ((own[i] >> 1) | (side[i] << 31))
                                : ((own[i] >> 1) | ((side[i] & 1u) << lastbits));
             }
+            if (JPL && d.jneg) bp_jflip(d.jneg, L, W, r0 + i, wd, phase, a, b);
             p = bp_planes(a, b, own[i], sgn);
             und = vm;
             bp_groups<FOLD3, 0, 2>(p, und, res, (uint32_t)widx, s, rep, k0, k1, ts);
@@ -228,11 +229,12 @@ __global__ __launch_bounds__(256) void k_torus_i8(const ChainDesc *__restrict__ 
         const int r = gid / L, c = gid - r * L;
         int n1, n2;
         if ((s & 1u) == 0) {
-            n1 = in[(r == 0 ? L - 1 : r - 1) * L + c];
-            n2 = in[r * L + (c == 0 ? L - 1 : c - 1)];
+            const int rd = r == 0 ? L - 1 : r - 1, cl = c == 0 ? L - 1 : c - 1;
+            n1 = in[rd * L + c] * torus_jsign(d.jneg, L, d.W, 0, rd, c);
+            n2 = in[r * L + cl] * torus_jsign(d.jneg, L, d.W, 1, r, cl);
         } else {
-            n1 = in[(r == L - 1 ? 0 : r + 1) * L + c];
-            n2 = in[r * L + (c == L - 1 ? 0 : c + 1)];
+            n1 = in[(r == L - 1 ? 0 : r + 1) * L + c] * torus_jsign(d.jneg, L, d.W, 0, r, c);
+            n2 = in[r * L + (c == L - 1 ? 0 : c + 1)] * torus_jsign(d.jneg, L, d.W, 1, r, c);
         }
         const int own = in[gid];
         const int S = d.J * (n1 + n2);
@@ -519,6 +521,7 @@ __global__ __launch_bounds__(256) void k_observe(const ChainDesc *__restrict__ d
             const uint32_t own = sp[gid];
             uint32_t a, b;
             bp_neighbours(sp, d.L, d.W, r, wd, 0, own, a, b);
+            if (d.jneg) bp_jflip(d.jneg, d.L, d.W, r, wd, 0, a, b);
             const uint32_t vm = bp_valid(d.L, d.W, wd);
             e_acc = d.J * (2 * __popc(vm) - 2 * __popc((own ^ a) & vm) - 2 * __popc((own ^ b) & vm));
             p_acc = __popc(own & vm);
@@ -532,7 +535,9 @@ __global__ __launch_bounds__(256) void k_observe(const ChainDesc *__restrict__ d
             const int8_t *sp = (const int8_t *)d.spin[idx];
             const int L = d.L, r = gid / L, c = gid - r * L;
             const int own = sp[gid];
-            e_acc = d.J * own * (sp[(r == 0 ? L - 1 : r - 1) * L + c] + sp[r * L + (c == 0 ? L - 1 : c - 1)]);
+            const int rd = r == 0 ? L - 1 : r - 1, cl = c == 0 ? L - 1 : c - 1;
+            e_acc = d.J * own * (sp[rd * L + c] * torus_jsign(d.jneg, L, d.W, 0, rd, c) +
+                                 sp[r * L + cl] * torus_jsign(d.jneg, L, d.W, 1, r, cl));
             p_acc = own > 0;
         }
         if (active_block) block_accumulate2(e_acc, p_acc, lg);
@@ -631,24 +636,28 @@ hipError_t launch_half_step_grid(const ChainDesc *dev_descs, const ChainDesc *ho
     if (nchains <= 0) return hipSuccess;
     // the chains of one launch share a kind and a format (the runtime groups them)
     const ChainDesc &h0 = host_descs[0];
-    int maxu = 0, fold = 1, maxcls = 1;
+    int maxu = 0, fold = 1, maxcls = 1, jpl = 0;
     for (int i = 0; i < nchains; ++i) {
         maxu = maxu > units_of(host_descs[i]) ? maxu : units_of(host_descs[i]);
         fold &= host_descs[i].fold3;
         maxcls = maxcls > host_descs[i].ncls ? maxcls : host_descs[i].ncls;
+        jpl |= host_descs[i].jneg != nullptr;
     }
     const bool obs = log_on && even;
     const StepArgs sa{dstate, s_add, s_log0, log_on};
     const int b = block > 0 ? block : 256;
     const dim3 grid((maxu + b - 1) / b, nchains);
     if (h0.kind == KIND_TORUS && h0.format == FMT_BITPACKED) {
-        if (obs) {
-            if (fold) hipLaunchKernelGGL((k_torus_bp<true, true>), grid, dim3(b), 0, stream, dev_descs, sa);
-            else hipLaunchKernelGGL((k_torus_bp<true, false>), grid, dim3(b), 0, stream, dev_descs, sa);
+#define SHAKEN_BP(O, F, JP) hipLaunchKernelGGL((k_torus_bp<O, F, JP>), grid, dim3(b), 0, stream, dev_descs, sa)
+        if (jpl) {
+            // +-J sign planes (chains without planes in the same launch skip them)
+            if (obs) { if (fold) SHAKEN_BP(true, true, true); else SHAKEN_BP(true, false, true); }
+            else { if (fold) SHAKEN_BP(false, true, true); else SHAKEN_BP(false, false, true); }
         } else {
-            if (fold) hipLaunchKernelGGL((k_torus_bp<false, true>), grid, dim3(b), 0, stream, dev_descs, sa);
-            else hipLaunchKernelGGL((k_torus_bp<false, false>), grid, dim3(b), 0, stream, dev_descs, sa);
+            if (obs) { if (fold) SHAKEN_BP(true, true, false); else SHAKEN_BP(true, false, false); }
+            else { if (fold) SHAKEN_BP(false, true, false); else SHAKEN_BP(false, false, false); }
         }
+#undef SHAKEN_BP
     } else if (h0.kind == KIND_TORUS) {
         if (obs) hipLaunchKernelGGL((k_torus_i8<true>), grid, dim3(b), 0, stream, dev_descs, sa);
         else hipLaunchKernelGGL((k_torus_i8<false>), grid, dim3(b), 0, stream, dev_descs, sa);

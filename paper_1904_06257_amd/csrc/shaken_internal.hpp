@@ -55,6 +55,13 @@ struct ChainDesc {
     // 54+k: J < 0; bits 57-60 field class.  Unused slots and padding vertices
     // have index 0 and no half bit.
     const uint64_t *pell;
+    // +-J torus (couplings of one magnitude J, any signs): two L x W bit planes,
+    // plane 0 bit (r, c) set iff J((r,c), up) < 0, plane 1 iff J((r,c), right)
+    // < 0; null for a uniform coupling.  Flipping a neighbour's bit where its
+    // edge is negative turns the field into J (2 n_plus - 2) + q sigma + lambda
+    // with n_plus counted on the flipped bits, so the classes and thresholds of
+    // the uniform torus apply unchanged.
+    const uint32_t *jneg;
     // observables log: slot t is kLogParts lines of log_line int64; line p holds
     // partial sums [E_J, plus_0 .. plus_{ncls-1}] (a block adds into line
     // blockIdx % kLogParts, so that thousands of blocks do not queue on one

@@ -46,7 +46,7 @@ def _init_status(**kw):
     (dict(kind="torus", L=8, q=-1.0), "q must be"),
     (dict(kind="torus", L=8, beta=float("nan")), "beta must be"),
     (dict(kind="torus", L=8, lam_values=[0.1, 0.2]), "uniform"),
-    (dict(kind="torus", L=4, J=np.r_[np.ones(31), -np.ones(1)]), "uniform"),
+    (dict(kind="torus", L=4, J=np.r_[np.ones(31), 2 * np.ones(1)]), "same magnitude"),
     (dict(kind="graph", n=4, src=[0, 1], dst=[1, 1]), "self-loop"),
     (dict(kind="graph", n=4, src=[0, 1], dst=[1, 0]), "twice"),
     (dict(kind="graph", n=4, src=[0, 5], dst=[1, 2]), "out of range"),
@@ -104,3 +104,18 @@ def test_packed_layout_rejected_when_it_does_not_apply():
             assert _init_status(layout="auto", **kw)[0] == sk.SHAKEN_EDEVICE
         st, _ = _init_status(layout="packed", kind="graph", n=4, src=[0, 1], dst=[1, 2])
         assert st == sk.SHAKEN_EDEVICE
+
+
+def test_pm_j_torus_passes_host_validation():
+    """Couplings of one magnitude with mixed signs (+-J) are accepted for both
+    torus formats; without a GPU the call then fails only at the device step."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    import paper_1904_06257_amd as sk
+    rng = np.random.Generator(np.random.PCG64(1))
+    ju = np.where(rng.integers(0, 2, (5, 5)) == 1, 2, -2).astype(np.int8)
+    jr = np.where(rng.integers(0, 2, (5, 5)) == 1, 2, -2).astype(np.int8)
+    for fmt in ("bitpacked", "int8"):
+        st, msg = _init_status(kind="torus", L=5, J=(ju, jr), fmt=fmt)
+        assert st == sk.SHAKEN_EDEVICE, msg
