@@ -33,8 +33,8 @@ sys.path.insert(0, ROOT)
 VALU_PEAK = 256 * 64 * 2.4e9
 HBM_PEAK_GBS = 8000.0
 
-# Algorithmic ALU work of one bit-packed site-update, in VALU lane-cycles
-# (derivation in the design doc): per 32-site word, E[G] = 1.999 Philox4x32-10
+# Algorithmic ALU work of one bit-packed site-update, in VALU lane-cycles:
+# per 32-site word, E[G] = 1.999 Philox4x32-10
 # calls (the MSB-first compare stops once all 32 sites of the word are
 # decided; levels come in groups of 4), 40 lane-cycles per call (20
 # v_mad_u64_u32 + 20 three-input xors, both full rate on gfx950), 4 E[G]
@@ -43,6 +43,8 @@ HBM_PEAK_GBS = 8000.0
 PHILOX_LC = 40.0
 BP_ALU_PER_SITE = (1.999 * PHILOX_LC + 4 * 1.999 * 6 + 15) / 32.0
 BP_BYTES_PER_SITE = 0.25  # read 1 bit, write 1 bit
+# +-J torus: two more xors per word flip the neighbour planes by the coupling signs
+BP_ALU_PER_SITE_PMJ = BP_ALU_PER_SITE + 2.0 / 32.0
 
 
 def kernel_source_hash():
@@ -241,6 +243,67 @@ def bench_batch(args, sk):
     return value, wall, cfg, roof, "u1 (bit-packed spins in LDS)"
 
 
+def ea_couplings(L, seed):
+    """+-1 couplings of an Edwards-Anderson torus: (J_up, J_right), each [L, L]"""
+    import numpy as np
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return tuple(np.where(rng.integers(0, 2, (L, L)) == 1, 1, -1).astype(np.int8) for _ in range(2))
+
+
+def bench_ea(args, sk):
+    """The paper's benchmarked workload (section 6): 2-D Edwards-Anderson +-J
+    tori, lambda = 0, q > 2, L = 256.  1024 independent spin glasses (own
+    couplings, seed and beta; beta geometric from 0.5 to 2.0) batched on the
+    grid kernels (the faster strategy for tori) under a HIP graph,
+    observables recorded every full step."""
+    import numpy as np
+    import torch
+    L, n_chains, q = 256, 1024, 2.5
+    betas = np.geomspace(0.5, 2.0, n_chains)
+    chains = [sk.Chain.torus(L, J=ea_couplings(L, 10_000 + i), q=q, beta=float(betas[i]),
+                             seed=20_000 + i, replica=i) for i in range(n_chains)]
+    batch = sk.Batch(chains, strategy="grid", use_hipgraph=True, record=True, autotune=True,
+                     log_reserve=max(args.steps, args.warmup))
+    batch.sweep(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.sweep(args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    _, ev_ms = batch.info()
+    batch.close()
+    for c in chains:
+        c.close()
+    sites = n_chains * L * L
+    value = 2.0 * sites * args.steps / wall
+    per_launch_s = ev_ms * 1e-3 / (2 * args.steps)   # one k_torus_bp launch per half-step
+    achieved = sites * BP_ALU_PER_SITE_PMJ / per_launch_s
+    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
+            "unit": "T lane-cycles/s", "frac": achieved / VALU_PEAK, "traffic": None,
+            "kernel": "k_torus_bp", "launch_us": per_launch_s * 1e6,
+            "note": "coupling-sign planes: 2 more words read per spin word (L2-resident)"}
+    cfg = {"workload": "1024 Edwards-Anderson +-J tori 256x256 (lambda=0, q=2.5, beta geometric "
+                       "0.5..2.0, own couplings and seed each), grid batch under a HIP graph",
+           "L": L, "chains": n_chains, "q": q, "strategy": "grid + hipGraph", "observables": "every full step"}
+    return value, wall, cfg, roof, "u1 (bit-packed spins)"
+
+
+def cpu_baseline_ea():
+    """The oracle as it stands on one 256^2 +-J torus: 2500 full steps,
+    single-threaded C (about 10 s of host time)."""
+    import oracle
+    L, steps = 256, 2500
+    J = ea_couplings(L, 10_000)
+    sp = oracle.torus_init_random(L, 20_000, 0)
+    t0 = time.perf_counter()
+    oracle.torus_run(sp, J, 0.0, 2.5, 0.5, 20_000, 0, steps, log=False)
+    dt = time.perf_counter() - t0
+    n = 2 * L * L * steps
+    return {"value": n / dt, "unit": "site-updates/s", "cores": 1, "kind": "oracle",
+            "sample": "%d full steps of one 256^2 +-J torus chain (q=2.5, beta=0.5), %.1f s on one "
+                      "host core" % (steps, dt)}
+
+
 def bench_copycal(args):
     """Plain device copy of a known size: the calibration of the FETCH_SIZE /
     WRITE_SIZE counters (bytes they report per byte copied)."""
@@ -329,12 +392,12 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="torus4096",
-                    choices=["torus4096", "graph", "batch", "copycal"])
+                    choices=["torus4096", "graph", "batch", "ea", "copycal"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(each chain is independent; see DESIGN.md for how the work would shard)",
+              "(chains are independent: the work would shard by chain, one process per GPU)",
               file=sys.stderr)
         sys.exit(2)
     import torch
@@ -355,6 +418,10 @@ def main():
         value, wall, cfg, roof, dtype = bench_graph(args, sk)
         metric = "vertex updates/s (3-regular graph, n=2^20)"
         cpu = None
+    elif args.workload == "ea":
+        value, wall, cfg, roof, dtype = bench_ea(args, sk)
+        metric = "spin-site updates/s (1024 +-J Edwards-Anderson tori 256^2, batched)"
+        cpu = None if args.no_cpu_baseline else cpu_baseline_ea()
     else:
         value, wall, cfg, roof, dtype = bench_batch(args, sk)
         metric = "aggregate site updates/s (2048 mixed chains, persistent batch)"

@@ -240,7 +240,10 @@ shaken_status shaken_synchronize(shaken_ctx *ctx);
  *                            keeps their spins in LDS for all the steps.  Tori
  *                            need the bit-packed format and L <= 256; graphs
  *                            n <= 65536 and at most 16 field classes.
- *   SHAKEN_BATCH_AUTO:       persistent when every chain fits, else grid. */
+ *   SHAKEN_BATCH_AUTO:       persistent when every chain fits and the batch
+ *                            holds a graph (or asks for tracking), else grid
+ *                            (batches of tori run faster on the grid
+ *                            kernels). */
 enum { SHAKEN_BATCH_AUTO = 0, SHAKEN_BATCH_GRID = 1, SHAKEN_BATCH_PERSISTENT = 2 };
 
 typedef struct shaken_batch_opts {

@@ -428,3 +428,29 @@ def test_graph_ell_equals_csr_equals_oracle(sk, n, deg):
             assert np.array_equal(h, _h_from_plus(inst, ej, plus)), (layout, strat)
             b.close()
             ch.close()
+
+
+def test_batch_auto_strategy_choice(sk):
+    """AUTO: grid for batches of tori only, persistent as soon as a graph is in
+    the batch or tracking is asked for; both give the oracle's trajectory."""
+    tori = [sk.Chain.torus(L, q=1.0, beta=0.4, seed=60 + L, replica=L) for L in (16, 40)]
+    b = sk.Batch(tori)
+    assert b.info()[0] == sk.SHAKEN_BATCH_GRID
+    b.close()
+    b = sk.Batch(tori, track=True)
+    assert b.info()[0] == sk.SHAKEN_BATCH_PERSISTENT
+    b.close()
+    inst = synth.oriented_instance(100, 3, 61, lam_values=(0.0,), pm_j=True)
+    g = sk.Chain.graph(inst.n, inst.src, inst.dst, J=inst.J, q=1.0, beta=0.4, seed=61, replica=7)
+    b = sk.Batch(tori + [g])
+    assert b.info()[0] == sk.SHAKEN_BATCH_PERSISTENT
+    b.sweep(5)
+    b.close()
+    for ch, L in zip(tori, (16, 40)):
+        want, _, _ = oracle.torus_run(oracle.torus_init_random(L, 60 + L, L), 1, 0.0, 1.0, 0.4, 60 + L, L, 5)
+        assert np.array_equal(ch.spins(), want)
+        ch.close()
+    og = oracle.Graph(inst.n, inst.src, inst.dst, inst.J, inst.cls, inst.lam_values)
+    want, _, _ = oracle.graph_run(og, oracle.graph_init_random(inst.n, 61, 7), 1.0, 0.4, 61, 7, 5)
+    assert np.array_equal(g.spins(), want)
+    g.close()
