@@ -142,8 +142,20 @@ typedef struct shaken_opts {
     int32_t device;            /* HIP device ordinal; -1 = current device     */
     void *stream;              /* hipStream_t; NULL = the null stream         */
     int32_t graph_layout;      /* SHAKEN_LAYOUT_* (graphs only)               */
-    int32_t reserved;
+    int32_t flags;             /* SHAKEN_GRAPH_* bits (graphs only), else 0    */
 } shaken_opts;
+
+/* opts.flags.  SHAKEN_GRAPH_SPLIT: the generalised split of section 5 -- an
+ * undirected pair {x, y} may be given in both orientations, (x, y) and (y, x),
+ * each with its own coupling, so that the Ising coupling is the sum
+ * (matrix form J = J^o + J^o^T).  Each oriented edge then feeds its own half
+ * only (in-half of its head, out-half of its tail), e.g. J^o = J / 2 on every
+ * orientation gives the symmetric split, whose two half-steps are the same
+ * kernel.  Without the flag a pair given twice is SHAKEN_EINVAL (Definition
+ * 2.1 orients each undirected edge once); the same oriented edge given twice
+ * is SHAKEN_EINVAL either way.  Half-integer splits: scale J, q and lambda by
+ * 2 and beta by 1/2. */
+enum { SHAKEN_GRAPH_SPLIT = 1 };
 
 typedef struct shaken_ctx shaken_ctx;
 

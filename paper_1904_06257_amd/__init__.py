@@ -44,6 +44,7 @@ _FMT = {"auto": SHAKEN_FMT_AUTO, "int8": SHAKEN_FMT_INT8, "bitpacked": SHAKEN_FM
 _STRAT = {"auto": SHAKEN_BATCH_AUTO, "grid": SHAKEN_BATCH_GRID,
           "persistent": SHAKEN_BATCH_PERSISTENT}
 SHAKEN_LAYOUT_AUTO, SHAKEN_LAYOUT_CSR, SHAKEN_LAYOUT_ELL, SHAKEN_LAYOUT_PACKED = 0, 1, 2, 3
+SHAKEN_GRAPH_SPLIT = 1
 _LAYOUT = {"auto": SHAKEN_LAYOUT_AUTO, "csr": SHAKEN_LAYOUT_CSR, "ell": SHAKEN_LAYOUT_ELL,
            "packed": SHAKEN_LAYOUT_PACKED}
 
@@ -63,7 +64,7 @@ class shaken_opts(ctypes.Structure):
     _fields_ = [("format", ctypes.c_int32), ("init", ctypes.c_int32),
                 ("init_spins", ctypes.POINTER(ctypes.c_int8)), ("replica", ctypes.c_uint32),
                 ("device", ctypes.c_int32), ("stream", ctypes.c_void_p),
-                ("graph_layout", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("graph_layout", ctypes.c_int32), ("flags", ctypes.c_int32)]
 
 
 class shaken_obs(ctypes.Structure):
@@ -205,7 +206,7 @@ class Chain:
 
     def __init__(self, kind, *, L=0, n=0, src=None, dst=None, J=None, lam_values=None,
                  lam_class=None, q=1.0, beta=1.0, seed=0, replica=0, init="random",
-                 init_spins=None, fmt="auto", device=-1, stream=None, layout="auto"):
+                 init_spins=None, fmt="auto", device=-1, stream=None, layout="auto", split=False):
         g = shaken_graph()
         self._keep = []
         if kind == "torus":
@@ -252,6 +253,7 @@ class Chain:
         o.device = int(device)
         o.stream = _stream_handle(stream)
         o.graph_layout = _LAYOUT[layout]
+        o.flags = SHAKEN_GRAPH_SPLIT if split else 0
         self.kind = kind
         self.handle = shaken_init(g, Jarr, field, q, beta, seed, o)
         self._keep = None

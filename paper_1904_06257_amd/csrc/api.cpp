@@ -278,7 +278,7 @@ void convert_log(const shaken_ctx *c, const std::vector<int64_t> &raw, int64_t s
 }
 
 // Validate and lay out an oriented graph as in-half and out-half CSR.
-shaken_status build_graph(shaken_ctx *c, const shaken_graph *g, const int8_t *J,
+shaken_status build_graph(shaken_ctx *c, const shaken_graph *g, const int8_t *J, bool split,
                           std::vector<int32_t> rp[2], std::vector<int32_t> col[2],
                           std::vector<int8_t> jw[2]) {
     const int n = g->n;
@@ -293,12 +293,15 @@ shaken_status build_graph(shaken_ctx *c, const shaken_graph *g, const int8_t *J,
         if (a < 0 || a >= n || b < 0 || b >= n)
             return fail(SHAKEN_EINVAL, "graph: vertex id out of range at edge " + std::to_string(e));
         if (a == b) return fail(SHAKEN_EINVAL, "graph: self-loop at edge " + std::to_string(e));
-        key[e] = (int64_t)std::min(a, b) * n + std::max(a, b);
+        // the generalised split keys the oriented pair, Definition 2.1 the undirected one
+        key[e] = split ? (int64_t)a * n + b : (int64_t)std::min(a, b) * n + std::max(a, b);
     }
     std::sort(key.begin(), key.end());
     for (int64_t e = 1; e < m; ++e)
         if (key[e] == key[e - 1])
-            return fail(SHAKEN_EINVAL, "graph: an edge is given twice (the graph must be simple)");
+            return fail(SHAKEN_EINVAL, split ? "graph: an oriented edge is given twice"
+                                             : "graph: an edge is given twice (the graph must be simple; "
+                                               "SHAKEN_GRAPH_SPLIT allows both orientations of a pair)");
     // half 0: in-half (row = head dst, entries = tails src); half 1: out-half
     for (int h = 0; h < 2; ++h) {
         rp[h].assign((size_t)n + 1, 0);
@@ -419,6 +422,7 @@ shaken_status init_host(shaken_ctx *c, const shaken_graph *g, const int8_t *J,
     }
     if (g->kind == SHAKEN_TORUS) {
         if (g->L < 3 || g->L > 32768) return fail(SHAKEN_EINVAL, "torus: L must be in [3, 32768]");
+        if (o->flags) return fail(SHAKEN_EINVAL, "opts.flags apply to graphs only");
         if (lambda && (lambda->n_classes != 1 || lambda->class_of_vertex))
             return fail(SHAKEN_EINVAL, "torus: the field must be uniform (one class, no class map)");
         c->kind = KIND_TORUS;
@@ -470,7 +474,8 @@ shaken_status init_host(shaken_ctx *c, const shaken_graph *g, const int8_t *J,
         if (o->format != SHAKEN_FMT_AUTO && o->format != SHAKEN_FMT_INT8)
             return fail(SHAKEN_EINVAL, "unknown format");
         c->format = FMT_INT8;
-        CHK(build_graph(c, g, J, rp, col, jw));
+        if (o->flags & ~SHAKEN_GRAPH_SPLIT) return fail(SHAKEN_EINVAL, "unknown opts.flags bits");
+        CHK(build_graph(c, g, J, (o->flags & SHAKEN_GRAPH_SPLIT) != 0, rp, col, jw));
         if (o->graph_layout < SHAKEN_LAYOUT_AUTO || o->graph_layout > SHAKEN_LAYOUT_PACKED)
             return fail(SHAKEN_EINVAL, "unknown graph layout");
         if (o->graph_layout != SHAKEN_LAYOUT_CSR) {

@@ -119,3 +119,20 @@ def test_pm_j_torus_passes_host_validation():
     for fmt in ("bitpacked", "int8"):
         st, msg = _init_status(kind="torus", L=5, J=(ju, jr), fmt=fmt)
         assert st == sk.SHAKEN_EDEVICE, msg
+
+
+def test_split_edges_need_the_flag():
+    """Both orientations of a pair are the generalised split of section 5:
+    rejected by default (Definition 2.1), accepted with split=True; the same
+    oriented edge twice is rejected either way."""
+    import torch
+    import paper_1904_06257_amd as sk
+    anti = dict(kind="graph", n=3, src=[0, 1, 1], dst=[1, 0, 2], J=[1, 1, -1])
+    st, msg = _init_status(**anti)
+    assert st == sk.SHAKEN_EINVAL and "both orientations" in msg
+    st, msg = _init_status(split=True, kind="graph", n=3, src=[0, 0], dst=[1, 1])
+    assert st == sk.SHAKEN_EINVAL and "oriented edge" in msg
+    st, msg = _init_status(split=True, kind="torus", L=4)
+    assert st == sk.SHAKEN_EINVAL and "graphs only" in msg
+    if not torch.cuda.is_available():
+        assert _init_status(split=True, **anti)[0] == sk.SHAKEN_EDEVICE

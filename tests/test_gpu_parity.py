@@ -454,3 +454,32 @@ def test_batch_auto_strategy_choice(sk):
     want, _, _ = oracle.graph_run(og, oracle.graph_init_random(inst.n, 61, 7), 1.0, 0.4, 61, 7, 5)
     assert np.array_equal(g.spins(), want)
     g.close()
+
+
+@pytest.mark.parametrize("n,deg,strategy", [(1000, 3, "grid"), (1000, 3, "persistent"),
+                                             (2002, 2, "grid"), (2002, 2, "persistent")])
+def test_split_graph_parity(sk, n, deg, strategy):
+    """Generalised split (section 5): every edge of a random regular graph given
+    in both orientations with independent +-1 couplings (degree 2: the ELL
+    layout applies); bit-exact with the oracle, logs included."""
+    T = 40
+    _print_case("split graph", n, deg, strategy)
+    inst = synth.oriented_instance(n, deg, 500 + n + deg, lam_values=(-0.5, 0.5), pm_j=True)
+    rng = np.random.Generator(np.random.PCG64(n + deg))
+    src = np.concatenate([inst.src, inst.dst]).astype(np.int32)
+    dst = np.concatenate([inst.dst, inst.src]).astype(np.int32)
+    J = np.where(rng.integers(0, 2, src.shape[0]) == 1, 1, -1).astype(np.int8)
+    g = oracle.Graph(n, src, dst, J, inst.cls, inst.lam_values)
+    sp0 = oracle.graph_init_random(n, 8, 2)
+    want, ej, plus = oracle.graph_run(g, sp0, 1.3, 0.7, 8, 2, T)
+    ch = sk.Chain.graph(n, src, dst, J=J, lam_values=inst.lam_values, lam_class=inst.cls, q=1.3,
+                        beta=0.7, seed=8, replica=2, split=True)
+    b = sk.Batch([ch], strategy=strategy, record=True)
+    b.sweep(T)
+    h, m = b.log(0)
+    assert np.array_equal(ch.spins(), want)
+    ncls = np.bincount(inst.cls, minlength=2)
+    assert np.array_equal(m, (2 * plus - ncls[None, :]).sum(axis=1))
+    assert np.array_equal(h, _h_from_plus(inst, ej, plus))
+    b.close()
+    ch.close()
