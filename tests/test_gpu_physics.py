@@ -158,3 +158,32 @@ def test_long_run_state_histogram_chi2(sk, case, T):
     print("%s: chi2 p-value vs pi %.3g, vs Gibbs %.3g" % (case, p, p_gibbs), flush=True)
     assert p > 1e-4
     assert p_gibbs < 1e-10
+
+
+def test_large_q_onsager_at_4096(sk):
+    """The headline lattice: 4096^2 tori, beta = 0.30, random start, q in
+    {4, 6, 8}, grid batch.  After 2000 burn-in steps the energy per site
+    averaged over 1000 steps (statistical error ~1e-5 at this size) approaches
+    Onsager's as q grows, within the first-order bound 0.75 eps."""
+    L, beta, qs = 4096, 0.30, (4.0, 6.0, 8.0)
+    chains = [sk.Chain.torus(L, q=q, beta=beta, seed=300 + k, replica=k) for k, q in enumerate(qs)]
+    b = sk.Batch(chains, strategy="grid", use_hipgraph=True, record=True, log_reserve=2000)
+    b.sweep(2000)
+    b.sweep(1000)
+    u0 = onsager_u(beta)
+    devs, ratios = [], []
+    for k, q in enumerate(qs):
+        h, _ = b.log(k)
+        u = h[1:].astype(np.float64).mean() / (L * L)
+        eps = np.exp(-2 * beta * (q - 2.0))
+        devs.append(abs(u - u0))
+        ratios.append((u - u0) / eps)
+        print("4096^2, beta %.2f q %.0f: u %.6f (Onsager %.6f, dev %.6f, eps %.4f, dev/eps %.3f)"
+              % (beta, q, u, u0, u - u0, eps, (u - u0) / eps), flush=True)
+        assert abs(u - u0) <= 0.75 * eps + 2e-4
+    assert devs[0] > devs[1] > devs[2]
+    # first order in eps: the ratio is nearly the same at every q
+    assert max(ratios) - min(ratios) < 0.15
+    b.close()
+    for c in chains:
+        c.close()
