@@ -187,3 +187,38 @@ def test_large_q_onsager_at_4096(sk):
     b.close()
     for c in chains:
         c.close()
+
+
+def test_first_exit_from_all_minus_is_geometric(sk):
+    """Metastability set-up of section 3 (start -1, small q, lambda > 0): the
+    number of full steps until the chain first leaves -1 is geometric with
+    parameter 1 - P^sh(-1, -1), computed exactly by enumeration (3 x 3 torus,
+    q = 0.1, lambda = 0.15, beta = 1.3; 16384 replicas, exit read from the
+    magnetisation log)."""
+    from scipy import stats
+    from oracle import enumeration as en
+    L, q, lam, beta, T, reps = 3, 0.1, 0.15, 1.3, 60, 16384
+    s, d = en.torus_edges(L)
+    m = en.Model(L * L, s, d, lam=np.full(L * L, lam), q=q, beta=beta)
+    stay = m.Psh()[0, 0]                      # state index 0 = all -1
+    chains = [sk.Chain.torus(L, q=q, beta=beta, lam_values=[lam], init="all_down", seed=7, replica=r)
+              for r in range(reps)]
+    b = sk.Batch(chains, record=True, use_hipgraph=True)
+    b.sweep(T)
+    times = np.full(reps, T + 1)
+    for i in range(reps):
+        _, mlog = b.log(i, with_H=False)
+        assert mlog[0] == -L * L
+        out = np.nonzero(mlog[1:] != -L * L)[0]
+        if out.size:
+            times[i] = out[0] + 1
+    b.close()
+    for c in chains:
+        c.close()
+    kmax = 30
+    counts = np.array([(times == k).sum() for k in range(1, kmax)] + [(times >= kmax).sum()])
+    probs = np.array([stay ** (k - 1) * (1 - stay) for k in range(1, kmax)] + [stay ** (kmax - 1)])
+    p = stats.chisquare(counts, probs * reps).pvalue
+    print("first exit: mean %.3f steps (geometric %.3f), chi2 p %.3g" % (times.mean(), 1 / (1 - stay), p),
+          flush=True)
+    assert p > 1e-4
