@@ -134,40 +134,52 @@ def bench_torus4096(args, sk):
     return value, wall, cfg, roof, "u1 (bit-packed spins)"
 
 
-def bench_graph(args, sk):
-    import numpy as np
-    import synth
+def _graph_run(sk, inst, n, steps, warmup, reps=1, fmt="int8"):
+    """grid batch of `reps` chains of the graph (own seeds), HIP graph replay;
+    returns (wall seconds, event seconds) of the timed call"""
     import torch
-    n = 1 << 20
-    inst = synth.oriented_instance(n, 3, 3, lam_values=(-0.5, 0.0, 0.5), pm_j=True)
-    ch = sk.Chain.graph(n, inst.src, inst.dst, J=inst.J, lam_values=inst.lam_values,
-                        lam_class=inst.cls, q=1.5, beta=0.8, seed=1, layout="csr")
-    batch = sk.Batch([ch], strategy="grid", use_hipgraph=True, record=True, autotune=True,
-                     log_reserve=max(args.steps, args.warmup))
-    batch.sweep(args.warmup)
+    chains = [sk.Chain.graph(n, inst.src, inst.dst, J=inst.J, lam_values=inst.lam_values,
+                             lam_class=inst.cls, q=1.5, beta=0.8, seed=1 + r, replica=r, layout="csr",
+                             fmt=fmt) for r in range(reps)]
+    batch = sk.Batch(chains, strategy="grid", use_hipgraph=True, record=True, autotune=True,
+                     log_reserve=max(steps, warmup))
+    batch.sweep(warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    batch.sweep(args.steps)
+    batch.sweep(steps)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     _, ev_ms = batch.info()
+    batch.close()
+    for c in chains:
+        c.close()
+    return wall, ev_ms * 1e-3
+
+
+def bench_graph(args, sk):
+    """One chain of the n = 2^20 random 3-regular +-J graph (CSR, int8 spins);
+    the same graph with bit-packed spins and 8 replicas are reported beside."""
+    import synth
+    n = 1 << 20
+    inst = synth.oriented_instance(n, 3, 3, lam_values=(-0.5, 0.0, 0.5), pm_j=True)
+    wall, ev_s = _graph_run(sk, inst, n, args.steps, args.warmup)
     value = 2.0 * n * args.steps / wall
-    per_launch_s = ev_ms * 1e-3 / (2 * args.steps)
+    per_launch_s = ev_s / (2 * args.steps)
     m = inst.src.shape[0]
     # algorithmic bytes per half-step: rowptr (n+1) + col + J (m) + own spin,
     # gathered spins (m), field class, written spin
     bytes_launch = 4 * (n + 1) + 5 * m + n + m + n + n
     achieved = bytes_launch / per_launch_s / 1e9
-    traffic = read_traffic("k_persistent", per="full_step")
-    if traffic is not None:
-        traffic *= args.steps
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": read_traffic("k_graph"),
             "kernel": "k_graph", "launch_us": per_launch_s * 1e6}
-    ch.close()
-    batch.close()
+    extra_steps = max(1, args.steps // 2)
+    wall_bp, _ = _graph_run(sk, inst, n, extra_steps, args.warmup, fmt="bitpacked")
+    wall_8, _ = _graph_run(sk, inst, n, extra_steps, args.warmup, reps=8)
     cfg = {"workload": "random 3-regular +-J graph, n=2^20, coin orientation, CSR int32, int8 spins",
-           "n": n, "q": 1.5, "beta": 0.8, "lambda": [-0.5, 0.0, 0.5]}
+           "n": n, "q": 1.5, "beta": 0.8, "lambda": [-0.5, 0.0, 0.5],
+           "bitpacked_spins_vertex_updates_per_s": 2.0 * n * extra_steps / wall_bp,
+           "int8_8_replicas_vertex_updates_per_s": 2.0 * n * 8 * extra_steps / wall_8}
     return value, wall, cfg, roof, "int8"
 
 

@@ -108,7 +108,10 @@ typedef struct shaken_field {
 enum {
     SHAKEN_FMT_AUTO = 0,       /* torus: bit-packed; graph: int8              */
     SHAKEN_FMT_INT8 = 1,       /* one int8 (+1 / -1) per site                 */
-    SHAKEN_FMT_BITPACKED = 2   /* torus only: uint32[L][ceil(L/32)], bit = +1 */
+    SHAKEN_FMT_BITPACKED = 2   /* one bit per site, set = +1: torus
+                                  uint32[L][ceil(L/32)] (bit c & 31 of word
+                                  (r, c >> 5)); graph uint32[ceil(n/32)] (bit
+                                  v & 31 of word v >> 5)                      */
 };
 
 enum {

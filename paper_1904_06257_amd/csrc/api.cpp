@@ -145,7 +145,7 @@ struct shaken_ctx {
     int block = 256;
 
     size_t spin_bytes() const {
-        if (kind == KIND_TORUS && format == FMT_BITPACKED) return (size_t)L * W * 4;
+        if (format == FMT_BITPACKED) return (kind == KIND_TORUS ? (size_t)L * W : ((size_t)n + 31) / 32) * 4;
         return (size_t)n;
     }
     int64_t nvals() const { return 1 + (int64_t)lam.size(); }               // values per slot
@@ -239,18 +239,29 @@ shaken_status ensure_log(shaken_ctx *c, int64_t slots) {
     return SHAKEN_OK;
 }
 
-// pack / unpack host int8 <-> bit-packed torus
-void pack_torus(const int8_t *in, int L, int W, std::vector<uint32_t> &out) {
-    out.assign((size_t)L * W, 0u);
-    for (int r = 0; r < L; ++r)
-        for (int c = 0; c < L; ++c)
-            if (in[(size_t)r * L + c] > 0) out[(size_t)r * W + (c >> 5)] |= 1u << (c & 31);
+// pack / unpack host int8 <-> bit-packed rows (rows x cols spins, W words per
+// row; the torus is L x L, a graph one row of n)
+void pack_rows(const int8_t *in, int rows, int cols, int W, std::vector<uint32_t> &out) {
+    out.assign((size_t)rows * W, 0u);
+    for (int r = 0; r < rows; ++r)
+        for (int c = 0; c < cols; ++c)
+            if (in[(size_t)r * cols + c] > 0) out[(size_t)r * W + (c >> 5)] |= 1u << (c & 31);
 }
 
-void unpack_torus(const std::vector<uint32_t> &in, int L, int W, int8_t *out) {
-    for (int r = 0; r < L; ++r)
-        for (int c = 0; c < L; ++c)
-            out[(size_t)r * L + c] = ((in[(size_t)r * W + (c >> 5)] >> (c & 31)) & 1u) ? 1 : -1;
+void unpack_rows(const std::vector<uint32_t> &in, int rows, int cols, int W, int8_t *out) {
+    for (int r = 0; r < rows; ++r)
+        for (int c = 0; c < cols; ++c)
+            out[(size_t)r * cols + c] = ((in[(size_t)r * W + (c >> 5)] >> (c & 31)) & 1u) ? 1 : -1;
+}
+
+void pack_torus(const int8_t *in, int L, int W, std::vector<uint32_t> &out) { pack_rows(in, L, L, W, out); }
+void unpack_torus(const std::vector<uint32_t> &in, int L, int W, int8_t *out) { unpack_rows(in, L, L, W, out); }
+
+// the spins of a context as bit-packed rows: (rows, cols, words per row)
+void spin_rows(const shaken_ctx *c, int &rows, int &cols, int &W) {
+    rows = c->kind == KIND_TORUS ? c->L : 1;
+    cols = c->kind == KIND_TORUS ? c->L : c->n;
+    W = c->kind == KIND_TORUS ? c->W : (c->n + 31) / 32;
 }
 
 // Convert a device log (slots x stride) to H and M per slot.
@@ -469,11 +480,10 @@ shaken_status init_host(shaken_ctx *c, const shaken_graph *g, const int8_t *J,
         c->kind = KIND_GRAPH;
         c->n = g->n;
         c->m = g->m;
-        if (o->format == SHAKEN_FMT_BITPACKED)
-            return fail(SHAKEN_EINVAL, "graph: only the int8 format is available");
-        if (o->format != SHAKEN_FMT_AUTO && o->format != SHAKEN_FMT_INT8)
+        if (o->format != SHAKEN_FMT_AUTO && o->format != SHAKEN_FMT_INT8 && o->format != SHAKEN_FMT_BITPACKED)
             return fail(SHAKEN_EINVAL, "unknown format");
-        c->format = FMT_INT8;
+        c->format = o->format == SHAKEN_FMT_BITPACKED ? FMT_BITPACKED : FMT_INT8;
+        c->W = (g->n + 31) / 32;
         if (o->flags & ~SHAKEN_GRAPH_SPLIT) return fail(SHAKEN_EINVAL, "unknown opts.flags bits");
         CHK(build_graph(c, g, J, (o->flags & SHAKEN_GRAPH_SPLIT) != 0, rp, col, jw));
         if (o->graph_layout < SHAKEN_LAYOUT_AUTO || o->graph_layout > SHAKEN_LAYOUT_PACKED)
@@ -798,11 +808,13 @@ shaken_status shaken_get_spins(shaken_ctx *ctx, int8_t *out) {
     if (!ctx || !out) return fail(SHAKEN_EINVAL, "ctx and out must be non-NULL");
     DeviceGuard guard(ctx->device);
     const void *src = ctx->spin[ctx->s & 1u];
-    if (ctx->kind == KIND_TORUS && ctx->format == FMT_BITPACKED) {
-        std::vector<uint32_t> w((size_t)ctx->L * ctx->W);
+    if (ctx->format == FMT_BITPACKED) {
+        int rows, cols, W;
+        spin_rows(ctx, rows, cols, W);
+        std::vector<uint32_t> w((size_t)rows * W);
         HIPCHK(hipMemcpyAsync(w.data(), src, w.size() * 4, hipMemcpyDeviceToHost, ctx->stream));
         HIPCHK(hipStreamSynchronize(ctx->stream));
-        unpack_torus(w, ctx->L, ctx->W, out);
+        unpack_rows(w, rows, cols, W, out);
     } else {
         HIPCHK(hipMemcpyAsync(out, src, (size_t)ctx->n, hipMemcpyDeviceToHost, ctx->stream));
         HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -816,9 +828,11 @@ shaken_status shaken_set_spins(shaken_ctx *ctx, const int8_t *in) {
         if (in[i] != 1 && in[i] != -1) return fail(SHAKEN_EINVAL, "spins must be +1 or -1");
     DeviceGuard guard(ctx->device);
     void *dst = ctx->spin[ctx->s & 1u];
-    if (ctx->kind == KIND_TORUS && ctx->format == FMT_BITPACKED) {
+    if (ctx->format == FMT_BITPACKED) {
+        int rows, cols, W;
+        spin_rows(ctx, rows, cols, W);
         std::vector<uint32_t> w;
-        pack_torus(in, ctx->L, ctx->W, w);
+        pack_rows(in, rows, cols, W, w);
         HIPCHK(hipMemcpyAsync(dst, w.data(), w.size() * 4, hipMemcpyHostToDevice, ctx->stream));
         HIPCHK(hipStreamSynchronize(ctx->stream));
     } else {

@@ -343,14 +343,20 @@ __device__ void run_graph(const ChainDesc &d, uint32_t (*buf)[kPWords], uint32_t
         lut = sh_lut;
     }
     if constexpr (LAY != GL_CSR) lut = sh_lut;  // always LDS (checked on the host)
-    const int8_t *g = (const int8_t *)d.spin[0];
-    for (int w = threadIdx.x; w < nw; w += kPBlock) {
-        uint32_t word = 0;
-        for (int b = 0; b < 32; ++b) {
-            const int v = 32 * w + b;
-            if (v < n && g[v] > 0) word |= 1u << b;
+    const bool bp = d.format == FMT_BITPACKED;
+    if (bp) {
+        const uint32_t *g = (const uint32_t *)d.spin[0];
+        for (int w = threadIdx.x; w < nw; w += kPBlock) buf[0][w] = g[w];
+    } else {
+        const int8_t *g = (const int8_t *)d.spin[0];
+        for (int w = threadIdx.x; w < nw; w += kPBlock) {
+            uint32_t word = 0;
+            for (int b = 0; b < 32; ++b) {
+                const int v = 32 * w + b;
+                if (v < n && g[v] > 0) word |= 1u << b;
+            }
+            buf[0][w] = word;
         }
-        buf[0][w] = word;
     }
     __syncthreads();
     int64_t best_h = INT64_MAX, last_h = 0;
@@ -373,8 +379,14 @@ __device__ void run_graph(const ChainDesc &d, uint32_t (*buf)[kPWords], uint32_t
             d.track[1] = best_h;
         }
     }
-    int8_t *go = (int8_t *)d.spin[0];
-    for (int v = threadIdx.x; v < n; v += kPBlock) go[v] = (int8_t)lds_spin(buf[0], v);
+    if (bp) {
+        uint32_t *go = (uint32_t *)d.spin[0];
+        for (int w = threadIdx.x; w < nw; w += kPBlock)
+            go[w] = buf[0][w] & (32 * w + 32 <= n ? 0xFFFFFFFFu : ((1u << (n & 31)) - 1u));
+    } else {
+        int8_t *go = (int8_t *)d.spin[0];
+        for (int v = threadIdx.x; v < n; v += kPBlock) go[v] = (int8_t)lds_spin(buf[0], v);
+    }
 }
 
 // ------------------------------------------------------------------ kernel

@@ -262,7 +262,59 @@ __global__ __launch_bounds__(256) void k_torus_i8(const ChainDesc *__restrict__ 
 constexpr int kEdgeChunk = 8;
 constexpr int kLdsLut = 512;  // threshold entries kept in LDS
 
-template <bool OBS>
+// Spins of a graph chain: int8 (+1/-1 per vertex) or bit-packed (bit v & 31
+// of word v >> 5; the whole configuration of 2^20 vertices is 128 KiB and
+// stays in every XCD's L2).  A bit-packed word is written by the 8 lanes of
+// its 32 vertices together (4-bit pieces merged with lane shuffles).
+template <bool BP>
+__device__ __forceinline__ int graph_spin(const void *sp, int v) {
+    if (BP) return ((((const uint32_t *)sp)[v >> 5] >> (v & 31)) & 1u) ? 1 : -1;
+    return (int)((const int8_t *)sp)[v];
+}
+
+// own spins of vertices v0..v0+3 (v0 + 3 < n unless `full` is false)
+template <bool BP>
+__device__ __forceinline__ void graph_own4(const void *sp, int v0, int n, bool full, int own[4]) {
+    if (BP) {
+        const uint32_t w = ((const uint32_t *)sp)[v0 >> 5] >> (v0 & 31);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) own[j] = ((w >> j) & 1u) ? 1 : -1;
+    } else if (full) {
+        const uint32_t o4 = *(const uint32_t *)((const int8_t *)sp + v0);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) own[j] = (int)(int8_t)(o4 >> (8 * j));
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) own[j] = v0 + j < n ? ((const int8_t *)sp)[v0 + j] : 1;
+    }
+}
+
+// store the new spins of v0..v0+3: `up` bit j = vertex v0+j is +1.  Every lane
+// of the wavefront must call this (bit-packed words are merged by shuffles).
+template <bool BP>
+__device__ __forceinline__ void graph_store4(void *sp, int q4, int n, uint32_t up) {
+    const int v0 = 4 * q4;
+    if (BP) {
+        uint32_t val = (v0 < n ? up : 0u) << (4 * (q4 & 7));
+        val |= __shfl_xor(val, 1, 64);
+        val |= __shfl_xor(val, 2, 64);
+        val |= __shfl_xor(val, 4, 64);
+        if ((q4 & 7) == 0 && v0 < n) ((uint32_t *)sp)[q4 >> 3] = val;
+        return;
+    }
+    if (v0 >= n) return;
+    uint32_t packed = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) packed |= (((up >> j) & 1u) ? 0x01u : 0xFFu) << (8 * j);
+    int8_t *out = (int8_t *)sp;
+    if (v0 + 3 < n) {
+        *(uint32_t *)(out + v0) = packed;
+    } else {
+        for (int j = 0; j < 4 && v0 + j < n; ++j) out[v0 + j] = (int8_t)(packed >> (8 * j));
+    }
+}
+
+template <bool OBS, bool BP>
 __global__ __launch_bounds__(256) void k_graph(const ChainDesc *__restrict__ descs, StepArgs sa) {
     const ChainDesc &d = descs[blockIdx.y];
     const uint32_t s = step_s(sa);
@@ -271,8 +323,8 @@ __global__ __launch_bounds__(256) void k_graph(const ChainDesc *__restrict__ des
     const int n = d.n;
     const int q4 = blockIdx.x * blockDim.x + threadIdx.x;
     const int v0 = q4 * 4;
-    const int8_t *__restrict__ in = (const int8_t *)d.spin[half];
-    int8_t *__restrict__ out = (int8_t *)d.spin[half ^ 1];
+    const void *__restrict__ in = d.spin[half];
+    void *__restrict__ out = d.spin[half ^ 1];
     const int32_t *__restrict__ rp = d.rowptr[half];
     const int32_t *__restrict__ col = d.col[half];
     const int8_t *__restrict__ jw = d.jw[half];
@@ -309,20 +361,14 @@ __global__ __launch_bounds__(256) void k_graph(const ChainDesc *__restrict__ des
 #pragma unroll
             for (int j = 0; j < 5; ++j) rpv[j] = rp[min(v0 + j, n)];
         }
+        graph_own4<BP>(in, v0, n, full, own);
         if (full) {
-            const uint32_t o4 = *(const uint32_t *)(in + v0);
             const uint32_t c4 = *(const uint32_t *)(cls + v0);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                own[j] = (int)(int8_t)(o4 >> (8 * j));
-                cl[j] = (int)((c4 >> (8 * j)) & 0xFFu);
-            }
+            for (int j = 0; j < 4; ++j) cl[j] = (int)((c4 >> (8 * j)) & 0xFFu);
         } else {
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                own[j] = v0 + j < n ? in[v0 + j] : 1;
-                cl[j] = v0 + j < n ? cls[v0 + j] : 0;
-            }
+            for (int j = 0; j < 4; ++j) cl[j] = v0 + j < n ? cls[v0 + j] : 0;
         }
         r = philox10((uint32_t)q4, s, d.replica, kGraphStream, (uint32_t)d.seed,
                      (uint32_t)(d.seed >> 32));
@@ -338,7 +384,7 @@ __global__ __launch_bounds__(256) void k_graph(const ChainDesc *__restrict__ des
                 jj[k] = (int)jw[e];
             }
 #pragma unroll
-            for (int k = 0; k < kEdgeChunk; ++k) sv[k] = (int)in[cc[k]];
+            for (int k = 0; k < kEdgeChunk; ++k) sv[k] = graph_spin<BP>(in, cc[k]);
 #pragma unroll
             for (int k = 0; k < kEdgeChunk; ++k) {
                 const int e = base + k;
@@ -355,27 +401,21 @@ __global__ __launch_bounds__(256) void k_graph(const ChainDesc *__restrict__ des
         Sv[3] = S3;
     }
     __syncthreads();
+    uint32_t up = 0;
     if (active) {
-        const bool full = v0 + 3 < n;
         const uint32_t u[4] = {r.x, r.y, r.z, r.w};
-        uint32_t packed = 0;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int key = ((Sv[j] + smax) * 2 + (own[j] > 0)) * ncls + cl[j];
             const uint64_t T = lut_lds ? sh_lut[key] : d.lut[key];
-            const uint32_t nv = ((uint64_t)u[j] < T) ? 0x01u : 0xFFu;
-            packed |= nv << (8 * j);
+            if (v0 + j < n && (uint64_t)u[j] < T) up |= 1u << j;
             if (OBS && v0 + j < n) {
                 e_acc += own[j] * Sv[j];
                 if (own[j] > 0) atomicAdd(&sh_plus[cl[j]], 1);
             }
         }
-        if (full) {
-            *(uint32_t *)(out + v0) = packed;
-        } else {
-            for (int j = 0; j < 4 && v0 + j < n; ++j) out[v0 + j] = (int8_t)(packed >> (8 * j));
-        }
     }
+    graph_store4<BP>(out, q4, n, up);
     if (OBS && blockIdx.x < (unsigned)((n + 4 * blockDim.x - 1) / (4 * blockDim.x))) {
         int64_t *lg = log_part(d, slot, blockIdx.x);
         __shared__ int sh_e[16];
@@ -398,7 +438,7 @@ __global__ __launch_bounds__(256) void k_graph(const ChainDesc *__restrict__ des
 // neighbour spin at once (empty slots point to the vertex itself) and keeps
 // those of the half being updated.  Two dependent memory levels instead of
 // three (no row pointers).
-template <bool OBS, int K>
+template <bool OBS, int K, bool BP>
 __global__ __launch_bounds__(256) void k_graph_ell(const ChainDesc *__restrict__ descs, StepArgs sa) {
     const ChainDesc &d = descs[blockIdx.y];
     const uint32_t s = step_s(sa);
@@ -408,8 +448,8 @@ __global__ __launch_bounds__(256) void k_graph_ell(const ChainDesc *__restrict__
     const int n = d.n;
     const int q4 = blockIdx.x * blockDim.x + threadIdx.x;
     const int v0 = q4 * 4;
-    const int8_t *__restrict__ in = (const int8_t *)d.spin[half];
-    int8_t *__restrict__ out = (int8_t *)d.spin[half ^ 1];
+    const void *__restrict__ in = d.spin[half];
+    void *__restrict__ out = d.spin[half ^ 1];
     const uint32_t *__restrict__ ell = d.ell;
     const int64_t stride = d.ell_stride;
     const uint8_t *__restrict__ cls = d.cls;
@@ -426,36 +466,31 @@ __global__ __launch_bounds__(256) void k_graph_ell(const ChainDesc *__restrict__
         for (int i = threadIdx.x; i < ncls; i += blockDim.x) sh_plus[i] = 0;
     }
     __syncthreads();
+    uint32_t up = 0;
     if (v0 < n) {
         const bool full = v0 + 3 < n;
         uint4 rec[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) rec[k] = *(const uint4 *)(ell + k * stride + v0);
         int own[4], cl[4];
+        graph_own4<BP>(in, v0, n, full, own);
         if (full) {
-            const uint32_t o4 = *(const uint32_t *)(in + v0);
             const uint32_t c4 = *(const uint32_t *)(cls + v0);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                own[j] = (int)(int8_t)(o4 >> (8 * j));
-                cl[j] = (int)((c4 >> (8 * j)) & 0xFFu);
-            }
+            for (int j = 0; j < 4; ++j) cl[j] = (int)((c4 >> (8 * j)) & 0xFFu);
         } else {
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                own[j] = v0 + j < n ? in[v0 + j] : 1;
-                cl[j] = v0 + j < n ? cls[v0 + j] : 0;
-            }
+            for (int j = 0; j < 4; ++j) cl[j] = v0 + j < n ? cls[v0 + j] : 0;
         }
         const U4 r = philox10((uint32_t)q4, s, d.replica, kGraphStream, (uint32_t)d.seed,
                               (uint32_t)(d.seed >> 32));
         int sv[K][4];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            sv[k][0] = in[rec[k].x & 0x1FFFFFFFu];
-            sv[k][1] = in[rec[k].y & 0x1FFFFFFFu];
-            sv[k][2] = in[rec[k].z & 0x1FFFFFFFu];
-            sv[k][3] = in[rec[k].w & 0x1FFFFFFFu];
+            sv[k][0] = graph_spin<BP>(in, (int)(rec[k].x & 0x1FFFFFFFu));
+            sv[k][1] = graph_spin<BP>(in, (int)(rec[k].y & 0x1FFFFFFFu));
+            sv[k][2] = graph_spin<BP>(in, (int)(rec[k].z & 0x1FFFFFFFu));
+            sv[k][3] = graph_spin<BP>(in, (int)(rec[k].w & 0x1FFFFFFFu));
         }
         int Sv[4] = {0, 0, 0, 0};
 #pragma unroll
@@ -468,24 +503,18 @@ __global__ __launch_bounds__(256) void k_graph_ell(const ChainDesc *__restrict__
             }
         }
         const uint32_t u[4] = {r.x, r.y, r.z, r.w};
-        uint32_t packed = 0;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int key = ((Sv[j] + smax) * 2 + (own[j] > 0)) * ncls + cl[j];
             const uint64_t T = lut_lds ? sh_lut[key] : d.lut[key];
-            const uint32_t nv = ((uint64_t)u[j] < T) ? 0x01u : 0xFFu;
-            packed |= nv << (8 * j);
+            if (v0 + j < n && (uint64_t)u[j] < T) up |= 1u << j;
             if (OBS && v0 + j < n) {
                 e_acc += own[j] * Sv[j];
                 if (own[j] > 0) atomicAdd(&sh_plus[cl[j]], 1);
             }
         }
-        if (full) {
-            *(uint32_t *)(out + v0) = packed;
-        } else {
-            for (int j = 0; j < 4 && v0 + j < n; ++j) out[v0 + j] = (int8_t)(packed >> (8 * j));
-        }
     }
+    graph_store4<BP>(out, q4, n, up);
     if (OBS && blockIdx.x < (unsigned)((n + 4 * blockDim.x - 1) / (4 * blockDim.x))) {
         int64_t *lg = log_part(d, slot, blockIdx.x);
         __shared__ int sh_e[16];
@@ -550,10 +579,12 @@ __global__ __launch_bounds__(256) void k_observe(const ChainDesc *__restrict__ d
     for (int i = threadIdx.x; i < ncls; i += blockDim.x) sh_cls[i] = 0;
     __syncthreads();
     if (gid < d.n) {
-        const int8_t *sp = (const int8_t *)d.spin[idx];
+        const void *sp = d.spin[idx];
+        const bool bp = d.format == FMT_BITPACKED;
         int S = 0;
-        for (int e = d.rowptr[0][gid]; e < d.rowptr[0][gid + 1]; ++e) S += d.jw[0][e] * sp[d.col[0][e]];
-        const int own = sp[gid];
+        for (int e = d.rowptr[0][gid]; e < d.rowptr[0][gid + 1]; ++e)
+            S += d.jw[0][e] * (bp ? graph_spin<true>(sp, d.col[0][e]) : graph_spin<false>(sp, d.col[0][e]));
+        const int own = bp ? graph_spin<true>(sp, gid) : graph_spin<false>(sp, gid);
         e_acc = own * S;
         if (own > 0) atomicAdd(&sh_cls[d.cls[gid]], 1);
     }
@@ -588,6 +619,27 @@ __global__ void k_init(ChainDesc d, void *dst, int mode) {
         ((uint32_t *)dst)[gid] = v & vm;
         return;
     }
+    if (d.kind == KIND_GRAPH && d.format == FMT_BITPACKED) {
+        // word gid: vertices 32 gid .. 32 gid + 31, each +1 iff bit 31 of its u
+        const int nwords = (d.n + 31) / 32;
+        if (gid >= nwords) return;
+        uint32_t v = 0;
+        for (int b = 0; b < 32; ++b) {
+            const int x = 32 * gid + b;
+            if (x >= d.n) break;
+            bool upx;
+            if (mode == 0) {
+                const U4 r = philox10((uint32_t)(x >> 2), kInitStep, d.replica, kGraphStream, k0, k1);
+                const uint32_t u[4] = {r.x, r.y, r.z, r.w};
+                upx = (u[x & 3] >> 31) != 0;
+            } else {
+                upx = mode == 1;
+            }
+            if (upx) v |= 1u << b;
+        }
+        ((uint32_t *)dst)[gid] = v;
+        return;
+    }
     if (gid >= d.n) return;
     int8_t v;
     if (mode == 0) {
@@ -617,7 +669,7 @@ hipError_t launch_fill_i64(int64_t *p, int64_t count, int64_t value, hipStream_t
 }
 
 hipError_t launch_init(const ChainDesc &d, void *dst, int mode, hipStream_t stream) {
-    const int total = (d.kind == KIND_TORUS && d.format == FMT_BITPACKED) ? d.L * d.W : d.n;
+    const int total = d.format != FMT_BITPACKED ? d.n : (d.kind == KIND_TORUS ? d.L * d.W : (d.n + 31) / 32);
     const int b = 256;
     hipLaunchKernelGGL(k_init, dim3((total + b - 1) / b), dim3(b), 0, stream, d, dst, mode);
     return hipGetLastError();
@@ -666,15 +718,19 @@ hipError_t launch_half_step_grid(const ChainDesc *dev_descs, const ChainDesc *ho
         int ellk = host_descs[0].ell_k;
         for (int i = 0; i < nchains; ++i)
             if (host_descs[i].ell_k != ellk || !host_descs[i].ell) ellk = 0;
-#define SHAKEN_ELL(KK)                                                                          \
-    if (obs) hipLaunchKernelGGL((k_graph_ell<true, KK>), grid, dim3(b), shm, stream, dev_descs, sa); \
-    else hipLaunchKernelGGL((k_graph_ell<false, KK>), grid, dim3(b), 0, stream, dev_descs, sa);
-        if (ellk == 1) { SHAKEN_ELL(1) }
-        else if (ellk == 2) { SHAKEN_ELL(2) }
-        else if (ellk == 3) { SHAKEN_ELL(3) }
-        else if (ellk == 4) { SHAKEN_ELL(4) }
-        else if (obs) hipLaunchKernelGGL((k_graph<true>), grid, dim3(b), shm, stream, dev_descs, sa);
-        else hipLaunchKernelGGL((k_graph<false>), grid, dim3(b), 0, stream, dev_descs, sa);
+#define SHAKEN_ELL(KK, BPF)                                                                            \
+    if (obs) hipLaunchKernelGGL((k_graph_ell<true, KK, BPF>), grid, dim3(b), shm, stream, dev_descs, sa); \
+    else hipLaunchKernelGGL((k_graph_ell<false, KK, BPF>), grid, dim3(b), 0, stream, dev_descs, sa);
+#define SHAKEN_GRAPH(BPF)                                                                              \
+    if (ellk == 1) { SHAKEN_ELL(1, BPF) }                                                              \
+    else if (ellk == 2) { SHAKEN_ELL(2, BPF) }                                                         \
+    else if (ellk == 3) { SHAKEN_ELL(3, BPF) }                                                         \
+    else if (ellk == 4) { SHAKEN_ELL(4, BPF) }                                                         \
+    else if (obs) hipLaunchKernelGGL((k_graph<true, BPF>), grid, dim3(b), shm, stream, dev_descs, sa); \
+    else hipLaunchKernelGGL((k_graph<false, BPF>), grid, dim3(b), 0, stream, dev_descs, sa);
+        if (h0.format == FMT_BITPACKED) { SHAKEN_GRAPH(true) }
+        else { SHAKEN_GRAPH(false) }
+#undef SHAKEN_GRAPH
 #undef SHAKEN_ELL
     }
     return hipGetLastError();

@@ -51,7 +51,6 @@ def _init_status(**kw):
     (dict(kind="graph", n=4, src=[0, 1], dst=[1, 0]), "twice"),
     (dict(kind="graph", n=4, src=[0, 5], dst=[1, 2]), "out of range"),
     (dict(kind="graph", n=0, src=[], dst=[]), "n must be"),
-    (dict(kind="graph", n=3, src=[0], dst=[1], fmt="bitpacked"), "int8"),
     (dict(kind="graph", n=3, src=[0], dst=[1], lam_values=[0.0], lam_class=[0, 1, 0]), "class id"),
     (dict(kind="torus", L=3, init_spins=np.zeros(9)), "+1 or -1"),
 ])
@@ -136,3 +135,12 @@ def test_split_edges_need_the_flag():
     assert st == sk.SHAKEN_EINVAL and "graphs only" in msg
     if not torch.cuda.is_available():
         assert _init_status(split=True, **anti)[0] == sk.SHAKEN_EDEVICE
+
+
+def test_graph_bitpacked_passes_host_validation():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    import paper_1904_06257_amd as sk
+    st, msg = _init_status(kind="graph", n=70, src=[0, 5, 69], dst=[1, 6, 0], fmt="bitpacked")
+    assert st == sk.SHAKEN_EDEVICE, msg
