@@ -168,11 +168,13 @@ static int64_t torus_fsum(int L, int J, const int8_t *Jup, const int8_t *Jr,
 }
 
 /* new value of one site at half-step s, read from configuration `in` */
-int oracle_torus_site_j(int L, int J, const int8_t *Jup, const int8_t *Jr, double lam,
+/* rev = 1: the reversed order P^{sh'} = P^{ur} P^{dl} (section 3): the half
+ * read at half-step s is (s & 1) ^ 1, i.e. the out-half (ur) at even s. */
+int oracle_torus_site_j(int L, int J, const int8_t *Jup, const int8_t *Jr, int rev, double lam,
                         double q, double beta, uint64_t seed, uint32_t replica, uint32_t s,
                         const int8_t *in, int r, int c)
 {
-    int64_t S = torus_fsum(L, J, Jup, Jr, in, r, c, (int)(s & 1u));
+    int64_t S = torus_fsum(L, J, Jup, Jr, in, r, c, (int)(s & 1u) ^ (rev != 0));
     double h = oracle_field(S, in[r * L + c], q, lam);
     uint64_t T = oracle_threshold(h, beta);
     uint32_t u = oracle_torus_uniform(L, seed, replica, s, r, c);
@@ -182,12 +184,12 @@ int oracle_torus_site_j(int L, int J, const int8_t *Jup, const int8_t *Jr, doubl
 int oracle_torus_site(int L, int J, double lam, double q, double beta, uint64_t seed,
                       uint32_t replica, uint32_t s, const int8_t *in, int r, int c)
 {
-    return oracle_torus_site_j(L, J, NULL, NULL, lam, q, beta, seed, replica, s, in, r, c);
+    return oracle_torus_site_j(L, J, NULL, NULL, 0, lam, q, beta, seed, replica, s, in, r, c);
 }
 
 /* one half-step: every site redrawn from `in` into `out` (in != out) */
-void oracle_torus_half_step_j(int L, int J, const int8_t *Jup, const int8_t *Jr, double lam,
-                              double q, double beta, uint64_t seed, uint32_t replica,
+void oracle_torus_half_step_j(int L, int J, const int8_t *Jup, const int8_t *Jr, int rev,
+                              double lam, double q, double beta, uint64_t seed, uint32_t replica,
                               uint32_t s, const int8_t *in, int8_t *out)
 {
     int W = torus_words(L), r, wd, b;
@@ -197,7 +199,7 @@ void oracle_torus_half_step_j(int L, int J, const int8_t *Jup, const int8_t *Jr,
             torus_levels(seed, replica, s, (uint32_t)(r * W + wd), R);
             for (b = 0; b < 32 && 32 * wd + b < L; ++b) {
                 int c = 32 * wd + b;
-                int64_t S = torus_fsum(L, J, Jup, Jr, in, r, c, (int)(s & 1u));
+                int64_t S = torus_fsum(L, J, Jup, Jr, in, r, c, (int)(s & 1u) ^ (rev != 0));
                 double h = oracle_field(S, in[r * L + c], q, lam);
                 uint64_t T = oracle_threshold(h, beta);
                 uint32_t u = torus_u_from_levels(R, b);
@@ -210,7 +212,7 @@ void oracle_torus_half_step(int L, int J, double lam, double q, double beta,
                             uint64_t seed, uint32_t replica, uint32_t s,
                             const int8_t *in, int8_t *out)
 {
-    oracle_torus_half_step_j(L, J, NULL, NULL, lam, q, beta, seed, replica, s, in, out);
+    oracle_torus_half_step_j(L, J, NULL, NULL, 0, lam, q, beta, seed, replica, s, in, out);
 }
 
 /* E_J over the oriented edge set {(x, x_up), (x, x_right)} and M */
@@ -240,7 +242,7 @@ void oracle_torus_observe(int L, int J, const int8_t *sp, int64_t *EJ, int64_t *
  * place (through a private second buffer); logs hold n_full+1 entries
  * (configuration at the start and after every full step); NULL skips a log.
  * Returns 0, or -1 on allocation failure / odd s0. */
-int oracle_torus_run_j(int L, int J, const int8_t *Jup, const int8_t *Jr, double lam,
+int oracle_torus_run_j(int L, int J, const int8_t *Jup, const int8_t *Jr, int rev, double lam,
                        double q, double beta, uint64_t seed, uint32_t replica, uint32_t s0,
                        int8_t *spins, int64_t n_full, int64_t *EJ_log, int64_t *M_log)
 {
@@ -258,8 +260,8 @@ int oracle_torus_run_j(int L, int J, const int8_t *Jup, const int8_t *Jr, double
             if (M_log) M_log[t] = m;
         }
         if (t == n_full) break;
-        oracle_torus_half_step_j(L, J, Jup, Jr, lam, q, beta, seed, replica, s, spins, tmp);
-        oracle_torus_half_step_j(L, J, Jup, Jr, lam, q, beta, seed, replica, s + 1, tmp, spins);
+        oracle_torus_half_step_j(L, J, Jup, Jr, rev, lam, q, beta, seed, replica, s, spins, tmp);
+        oracle_torus_half_step_j(L, J, Jup, Jr, rev, lam, q, beta, seed, replica, s + 1, tmp, spins);
         s += 2;
     }
     free(tmp);
@@ -270,7 +272,7 @@ int oracle_torus_run(int L, int J, double lam, double q, double beta, uint64_t s
                      uint32_t replica, uint32_t s0, int8_t *spins, int64_t n_full,
                      int64_t *EJ_log, int64_t *M_log)
 {
-    return oracle_torus_run_j(L, J, NULL, NULL, lam, q, beta, seed, replica, s0, spins, n_full,
+    return oracle_torus_run_j(L, J, NULL, NULL, 0, lam, q, beta, seed, replica, s0, spins, n_full,
                               EJ_log, M_log);
 }
 
