@@ -145,7 +145,7 @@ typedef struct shaken_opts {
     int32_t device;            /* HIP device ordinal; -1 = current device     */
     void *stream;              /* hipStream_t; NULL = the null stream         */
     int32_t graph_layout;      /* SHAKEN_LAYOUT_* (graphs only)               */
-    int32_t flags;             /* SHAKEN_GRAPH_* bits (graphs only), else 0    */
+    int32_t flags;             /* SHAKEN_GRAPH_SPLIT, SHAKEN_ORDER_REVERSED    */
 } shaken_opts;
 
 /* opts.flags.  SHAKEN_GRAPH_SPLIT: the generalised split of section 5 -- an
@@ -158,7 +158,12 @@ typedef struct shaken_opts {
  * 2.1 orients each undirected edge once); the same oriented edge given twice
  * is SHAKEN_EINVAL either way.  Half-integer splits: scale J, q and lambda by
  * 2 and beta by 1/2. */
-enum { SHAKEN_GRAPH_SPLIT = 1 };
+enum { SHAKEN_GRAPH_SPLIT = 1, SHAKEN_ORDER_REVERSED = 2 };
+/* SHAKEN_ORDER_REVERSED (torus and graph): the reversed order of section 3,
+ * P^{sh'} = P^{2->1} P^{1->2}: the half-step at an even counter reads the
+ * out-half (torus: up and right neighbours, P^ur) and the one at an odd
+ * counter the in-half.  The uniforms stay keyed by (site, s), so a reversed
+ * graph run equals the forward run on the reversed edge set. */
 
 typedef struct shaken_ctx shaken_ctx;
 

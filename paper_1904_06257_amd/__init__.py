@@ -44,7 +44,7 @@ _FMT = {"auto": SHAKEN_FMT_AUTO, "int8": SHAKEN_FMT_INT8, "bitpacked": SHAKEN_FM
 _STRAT = {"auto": SHAKEN_BATCH_AUTO, "grid": SHAKEN_BATCH_GRID,
           "persistent": SHAKEN_BATCH_PERSISTENT}
 SHAKEN_LAYOUT_AUTO, SHAKEN_LAYOUT_CSR, SHAKEN_LAYOUT_ELL, SHAKEN_LAYOUT_PACKED = 0, 1, 2, 3
-SHAKEN_GRAPH_SPLIT = 1
+SHAKEN_GRAPH_SPLIT, SHAKEN_ORDER_REVERSED = 1, 2
 _LAYOUT = {"auto": SHAKEN_LAYOUT_AUTO, "csr": SHAKEN_LAYOUT_CSR, "ell": SHAKEN_LAYOUT_ELL,
            "packed": SHAKEN_LAYOUT_PACKED}
 
@@ -206,7 +206,8 @@ class Chain:
 
     def __init__(self, kind, *, L=0, n=0, src=None, dst=None, J=None, lam_values=None,
                  lam_class=None, q=1.0, beta=1.0, seed=0, replica=0, init="random",
-                 init_spins=None, fmt="auto", device=-1, stream=None, layout="auto", split=False):
+                 init_spins=None, fmt="auto", device=-1, stream=None, layout="auto", split=False,
+                 reversed=False):
         g = shaken_graph()
         self._keep = []
         if kind == "torus":
@@ -253,7 +254,7 @@ class Chain:
         o.device = int(device)
         o.stream = _stream_handle(stream)
         o.graph_layout = _LAYOUT[layout]
-        o.flags = SHAKEN_GRAPH_SPLIT if split else 0
+        o.flags = (SHAKEN_GRAPH_SPLIT if split else 0) | (SHAKEN_ORDER_REVERSED if reversed else 0)
         self.kind = kind
         self.handle = shaken_init(g, Jarr, field, q, beta, seed, o)
         self._keep = None

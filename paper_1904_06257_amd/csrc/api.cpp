@@ -433,7 +433,8 @@ shaken_status init_host(shaken_ctx *c, const shaken_graph *g, const int8_t *J,
     }
     if (g->kind == SHAKEN_TORUS) {
         if (g->L < 3 || g->L > 32768) return fail(SHAKEN_EINVAL, "torus: L must be in [3, 32768]");
-        if (o->flags) return fail(SHAKEN_EINVAL, "opts.flags apply to graphs only");
+        if (o->flags & ~SHAKEN_ORDER_REVERSED)
+            return fail(SHAKEN_EINVAL, "SHAKEN_GRAPH_SPLIT applies to graphs only");
         if (lambda && (lambda->n_classes != 1 || lambda->class_of_vertex))
             return fail(SHAKEN_EINVAL, "torus: the field must be uniform (one class, no class map)");
         c->kind = KIND_TORUS;
@@ -484,7 +485,8 @@ shaken_status init_host(shaken_ctx *c, const shaken_graph *g, const int8_t *J,
             return fail(SHAKEN_EINVAL, "unknown format");
         c->format = o->format == SHAKEN_FMT_BITPACKED ? FMT_BITPACKED : FMT_INT8;
         c->W = (g->n + 31) / 32;
-        if (o->flags & ~SHAKEN_GRAPH_SPLIT) return fail(SHAKEN_EINVAL, "unknown opts.flags bits");
+        if (o->flags & ~(SHAKEN_GRAPH_SPLIT | SHAKEN_ORDER_REVERSED))
+            return fail(SHAKEN_EINVAL, "unknown opts.flags bits");
         CHK(build_graph(c, g, J, (o->flags & SHAKEN_GRAPH_SPLIT) != 0, rp, col, jw));
         if (o->graph_layout < SHAKEN_LAYOUT_AUTO || o->graph_layout > SHAKEN_LAYOUT_PACKED)
             return fail(SHAKEN_EINVAL, "unknown graph layout");
@@ -595,6 +597,7 @@ shaken_status init_device(shaken_ctx *c, const shaken_opts *o, HostLayout &hl) {
     d.ell_stride = c->ell_stride;
     d.pell = c->pell_dev;
     d.jneg = c->jneg_dev;
+    d.rev = (o->flags & SHAKEN_ORDER_REVERSED) ? 1 : 0;
     d.log_line = c->line();
     d.log_stride = c->stride();
     for (size_t k = 0; k < c->lam.size() && k < 16; ++k) {

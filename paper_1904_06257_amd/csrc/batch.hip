@@ -62,7 +62,7 @@ template <bool FOLD3>
 __device__ void torus_lds_half(const ChainDesc &d, const uint32_t *src, uint32_t *dst, uint32_t s,
                                bool obs, int *sh_red, Obs *o) {
     const int L = d.L, W = d.W, nw = L * W;
-    const int phase = (int)(s & 1u);
+    const int phase = (int)(s & 1u) ^ d.rev;  // half read: 0 = dl, 1 = ur
     const uint32_t k0 = (uint32_t)d.seed, k1 = (uint32_t)(d.seed >> 32);
     int e_acc = 0, p_acc = 0;
     for (int w = threadIdx.x; w < nw; w += kPBlock) {
@@ -182,7 +182,7 @@ template <int LAY>
 __device__ void graph_lds_half(const ChainDesc &d, const uint32_t *src, uint32_t *dst, uint32_t s,
                                bool obs, int *sh_red, int *sh_plus, Obs *o, const uint64_t *lut) {
     const int n = d.n;
-    const int half = dst ? (int)(s & 1u) : 0;  // observables use the in-half
+    const int half = dst ? ((int)(s & 1u) ^ d.rev) : 0;  // observables use the in-half
     const int32_t *__restrict__ rp = d.rowptr[half];
     const int32_t *__restrict__ col = d.col[half];
     const int8_t *__restrict__ jw = d.jw[half];
@@ -211,7 +211,7 @@ __device__ void graph_lds_half(const ChainDesc &d, const uint32_t *src, uint32_t
                 const uint4 b = *(const uint4 *)(d.pell + v0 + 2);
                 const uint32_t lo[4] = {a.x, a.z, b.x, b.z};
                 const uint32_t hi[4] = {a.y, a.w, b.y, b.w};
-                const uint32_t selsh = (dst && (s & 1u)) ? 19u : 16u;
+                const uint32_t selsh = half ? 19u : 16u;
                 int t[4];
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
@@ -233,7 +233,7 @@ __device__ void graph_lds_half(const ChainDesc &d, const uint32_t *src, uint32_t
             } else if constexpr (LAY == GL_ELL) {
                 // ELL: one 16-byte record per slot for the 4 vertices, no row pointers
                 const int K = d.ell_k;
-                const uint32_t want = dst ? (uint32_t)((s & 1u) + 1u) : 1u;
+                const uint32_t want = (uint32_t)(half + 1);
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     const uint4 rec = *(const uint4 *)(d.ell + min(k, K - 1) * d.ell_stride + v0);

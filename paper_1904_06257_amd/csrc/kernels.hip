@@ -93,15 +93,16 @@ __global__ __launch_bounds__(256) void k_torus_bp(const ChainDesc *__restrict__ 
     __shared__ int q_n;
     const ChainDesc &d = descs[blockIdx.y];
     const uint32_t s = step_s(sa);
-    const int phase = (int)(s & 1u);
+    const int bufp = (int)(s & 1u);      // configuration at s lives in spin[s & 1]
+    const int phase = bufp ^ d.rev;      // half read: 0 = dl, 1 = ur
     const int slot = OBS ? step_slot(sa, s) : 0;
     const int L = d.L, W = d.W;
     const int nrb = (L + kRows - 1) / kRows;
     const int total = nrb * W;
     const int bx = xcd_block(blockIdx.x, gridDim.x);
     const int gid = bx * blockDim.x + threadIdx.x;
-    const uint32_t *__restrict__ in = (const uint32_t *)d.spin[phase];
-    uint32_t *__restrict__ out = (uint32_t *)d.spin[phase ^ 1];
+    const uint32_t *__restrict__ in = (const uint32_t *)d.spin[bufp];
+    uint32_t *__restrict__ out = (uint32_t *)d.spin[bufp ^ 1];
     const uint32_t k0 = (uint32_t)d.seed, k1 = (uint32_t)(d.seed >> 32);
     const uint32_t rep = d.replica, sgn = d.sgn;
     const uint32_t *ts = d.tsmall;
@@ -228,7 +229,7 @@ __global__ __launch_bounds__(256) void k_torus_i8(const ChainDesc *__restrict__ 
     if (gid < n) {
         const int r = gid / L, c = gid - r * L;
         int n1, n2;
-        if ((s & 1u) == 0) {
+        if (((s & 1u) ^ (uint32_t)d.rev) == 0) {
             const int rd = r == 0 ? L - 1 : r - 1, cl = c == 0 ? L - 1 : c - 1;
             n1 = in[rd * L + c] * torus_jsign(d.jneg, L, d.W, 0, rd, c);
             n2 = in[r * L + cl] * torus_jsign(d.jneg, L, d.W, 1, r, cl);
@@ -318,13 +319,14 @@ template <bool OBS, bool BP>
 __global__ __launch_bounds__(256) void k_graph(const ChainDesc *__restrict__ descs, StepArgs sa) {
     const ChainDesc &d = descs[blockIdx.y];
     const uint32_t s = step_s(sa);
-    const int half = (int)(s & 1u);
+    const int bufp = (int)(s & 1u);
+    const int half = bufp ^ d.rev;   // 0 = in-half, 1 = out-half
     const int slot = OBS ? step_slot(sa, s) : 0;
     const int n = d.n;
     const int q4 = blockIdx.x * blockDim.x + threadIdx.x;
     const int v0 = q4 * 4;
-    const void *__restrict__ in = d.spin[half];
-    void *__restrict__ out = d.spin[half ^ 1];
+    const void *__restrict__ in = d.spin[bufp];
+    void *__restrict__ out = d.spin[bufp ^ 1];
     const int32_t *__restrict__ rp = d.rowptr[half];
     const int32_t *__restrict__ col = d.col[half];
     const int8_t *__restrict__ jw = d.jw[half];
@@ -442,14 +444,15 @@ template <bool OBS, int K, bool BP>
 __global__ __launch_bounds__(256) void k_graph_ell(const ChainDesc *__restrict__ descs, StepArgs sa) {
     const ChainDesc &d = descs[blockIdx.y];
     const uint32_t s = step_s(sa);
-    const int half = (int)(s & 1u);
+    const int bufp = (int)(s & 1u);
+    const int half = bufp ^ d.rev;
     const uint32_t want = (uint32_t)(half + 1);
     const int slot = OBS ? step_slot(sa, s) : 0;
     const int n = d.n;
     const int q4 = blockIdx.x * blockDim.x + threadIdx.x;
     const int v0 = q4 * 4;
-    const void *__restrict__ in = d.spin[half];
-    void *__restrict__ out = d.spin[half ^ 1];
+    const void *__restrict__ in = d.spin[bufp];
+    void *__restrict__ out = d.spin[bufp ^ 1];
     const uint32_t *__restrict__ ell = d.ell;
     const int64_t stride = d.ell_stride;
     const uint8_t *__restrict__ cls = d.cls;

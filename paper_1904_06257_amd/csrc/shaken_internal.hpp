@@ -62,6 +62,9 @@ struct ChainDesc {
     // with n_plus counted on the flipped bits, so the classes and thresholds of
     // the uniform torus apply unchanged.
     const uint32_t *jneg;
+    // 1: reversed order P^{sh'} (section 3): the half read at half-step s is
+    // (s & 1) ^ 1, the out-half (torus ur) first
+    int32_t rev;
     // observables log: slot t is kLogParts lines of log_line int64; line p holds
     // partial sums [E_J, plus_0 .. plus_{ncls-1}] (a block adds into line
     // blockIdx % kLogParts, so that thousands of blocks do not queue on one

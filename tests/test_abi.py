@@ -134,6 +134,9 @@ def test_split_edges_need_the_flag():
     st, msg = _init_status(split=True, kind="torus", L=4)
     assert st == sk.SHAKEN_EINVAL and "graphs only" in msg
     if not torch.cuda.is_available():
+        assert _init_status(reversed=True, kind="torus", L=4)[0] == sk.SHAKEN_EDEVICE
+        assert _init_status(reversed=True, split=True, **anti)[0] == sk.SHAKEN_EDEVICE
+    if not torch.cuda.is_available():
         assert _init_status(split=True, **anti)[0] == sk.SHAKEN_EDEVICE
 
 
