@@ -278,3 +278,48 @@ def graph_run(g: Graph, spins, q, beta, seed, replica, n_full, s0=0, log=True):
 def energy(EJ, lam2_dot_sigma):
     """H(sigma) = -E_J - sum_x 2 lambda_x sigma_x (equation ham1)."""
     return -EJ - lam2_dot_sigma
+
+
+# ------------------------------------------------------------- frozen set B --
+# Section 3.1: the state space X_{Lambda,B} keeps the spins of a set B at +1.
+# The dynamics restricted to it redraws every other spin from its field (the
+# frozen +1 spins enter the fields like any other) and leaves B at +1; the
+# uniforms stay keyed by site and half-step, so a half-step on X_{Lambda,B} is
+# the plain half-step followed by sigma_B := +1.
+
+def torus_run_frozen(spins, frozen, J, lam, q, beta, seed, replica, n_full, s0=0, rev=False):
+    """frozen: bool [L, L].  Returns (final spins, E_J log, M log)."""
+    a = np.ascontiguousarray(spins, dtype=np.int8).copy()
+    fz = np.asarray(frozen, dtype=bool)
+    a[fz] = 1
+    ej = np.zeros(n_full + 1, dtype=np.int64)
+    m = np.zeros(n_full + 1, dtype=np.int64)
+    s = s0
+    for t in range(n_full + 1):
+        ej[t], m[t] = torus_observe(a, J)
+        if t == n_full:
+            break
+        for k in range(2):
+            a = torus_half_step(a, J, lam, q, beta, seed, replica, s + k, rev=rev)
+            a[fz] = 1
+        s += 2
+    return a, ej, m
+
+
+def graph_run_frozen(g: Graph, spins, frozen, q, beta, seed, replica, n_full, s0=0):
+    """frozen: bool [n].  Returns (final spins, E_J log, plus-count log)."""
+    a = np.ascontiguousarray(spins, dtype=np.int8).copy()
+    fz = np.asarray(frozen, dtype=bool)
+    a[fz] = 1
+    ej = np.zeros(n_full + 1, dtype=np.int64)
+    pl = np.zeros((n_full + 1, len(g.lam)), dtype=np.int64)
+    s = s0
+    for t in range(n_full + 1):
+        ej[t], pl[t] = graph_observe(g, a)
+        if t == n_full:
+            break
+        for k in range(2):
+            a = graph_half_step(g, a, q, beta, seed, replica, s + k)
+            a[fz] = 1
+        s += 2
+    return a, ej, pl
