@@ -146,6 +146,11 @@ typedef struct shaken_opts {
     void *stream;              /* hipStream_t; NULL = the null stream         */
     int32_t graph_layout;      /* SHAKEN_LAYOUT_* (graphs only)               */
     int32_t flags;             /* SHAKEN_GRAPH_SPLIT, SHAKEN_ORDER_REVERSED    */
+    const uint8_t *frozen;     /* NULL, or host bytes per site (n; torus row-
+                                  major): nonzero = the site is in the frozen
+                                  set B of section 3.1 and stays +1 (its start
+                                  value and every draw are overridden; it
+                                  enters its neighbours' fields as +1)        */
 } shaken_opts;
 
 /* opts.flags.  SHAKEN_GRAPH_SPLIT: the generalised split of section 5 -- an

@@ -64,7 +64,8 @@ class shaken_opts(ctypes.Structure):
     _fields_ = [("format", ctypes.c_int32), ("init", ctypes.c_int32),
                 ("init_spins", ctypes.POINTER(ctypes.c_int8)), ("replica", ctypes.c_uint32),
                 ("device", ctypes.c_int32), ("stream", ctypes.c_void_p),
-                ("graph_layout", ctypes.c_int32), ("flags", ctypes.c_int32)]
+                ("graph_layout", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("frozen", ctypes.POINTER(ctypes.c_uint8))]
 
 
 class shaken_obs(ctypes.Structure):
@@ -207,7 +208,7 @@ class Chain:
     def __init__(self, kind, *, L=0, n=0, src=None, dst=None, J=None, lam_values=None,
                  lam_class=None, q=1.0, beta=1.0, seed=0, replica=0, init="random",
                  init_spins=None, fmt="auto", device=-1, stream=None, layout="auto", split=False,
-                 reversed=False):
+                 reversed=False, frozen=None):
         g = shaken_graph()
         self._keep = []
         if kind == "torus":
@@ -255,6 +256,12 @@ class Chain:
         o.stream = _stream_handle(stream)
         o.graph_layout = _LAYOUT[layout]
         o.flags = (SHAKEN_GRAPH_SPLIT if split else 0) | (SHAKEN_ORDER_REVERSED if reversed else 0)
+        fz = None
+        if frozen is not None:
+            fz = np.ascontiguousarray(np.asarray(frozen).reshape(-1) != 0, dtype=np.uint8)
+            if fz.shape[0] != self.n:
+                raise ValueError("frozen needs one entry per site")
+            o.frozen = _ptr(fz, ctypes.c_uint8)
         self.kind = kind
         self.handle = shaken_init(g, Jarr, field, q, beta, seed, o)
         self._keep = None

@@ -134,6 +134,8 @@ struct shaken_ctx {
     uint32_t *ell_dev = nullptr;
     uint64_t *pell_dev = nullptr;
     uint32_t *jneg_dev = nullptr;  // +-J torus sign planes (2 x L x W words)
+    uint32_t *frozen_dev = nullptr;  // frozen set B as bits (layout of the bit-packed spins)
+    std::vector<uint8_t> frozen_host;  // per site, nonzero = frozen
     int ell_k = 0;
     int64_t ell_stride = 0;
     int64_t *log_dev = nullptr;
@@ -168,6 +170,7 @@ void release(shaken_ctx *c) {
     dfree(c->ell_dev);
     dfree(c->pell_dev);
     dfree(c->jneg_dev);
+    dfree(c->frozen_dev);
     dfree(c->log_dev);
     dfree(c->obs_dev);
     dfree(c->dd);
@@ -351,6 +354,7 @@ struct HostLayout {
     std::vector<uint32_t> ell;  // slot-major, ell_k * ell_stride entries
     std::vector<uint64_t> pell; // packed record per vertex, ell_stride entries
     std::vector<uint32_t> jneg; // +-J torus: sign planes of J(x, x_up) and J(x, x_right)
+    std::vector<uint32_t> frozen; // frozen set B, bits laid out like bit-packed spins
     int ell_k = 0;
     int64_t ell_stride = 0;
 };
@@ -514,6 +518,19 @@ shaken_status init_host(shaken_ctx *c, const shaken_graph *g, const int8_t *J,
     } else {
         return fail(SHAKEN_EINVAL, "unknown graph kind");
     }
+    if (o->frozen) {
+        // frozen set B (section 3.1): bits in the layout of the bit-packed spins
+        const bool torus = c->kind == KIND_TORUS;
+        const int W = torus ? c->W : (c->n + 31) / 32, rows = torus ? c->L : 1, cols = torus ? c->L : c->n;
+        hl.frozen.assign((size_t)rows * W, 0u);
+        c->frozen_host.assign((size_t)c->n, 0);
+        for (int r = 0; r < rows; ++r)
+            for (int col = 0; col < cols; ++col)
+                if (o->frozen[(size_t)r * cols + col]) {
+                    hl.frozen[(size_t)r * W + (col >> 5)] |= 1u << (col & 31);
+                    c->frozen_host[(size_t)r * cols + col] = 1;
+                }
+    }
     const size_t lut_entries = (size_t)(2 * c->smax + 1) * 2 * c->lam.size();
     if (lut_entries > ((size_t)1 << 24))
         return fail(SHAKEN_EINVAL, "threshold table would exceed 2^24 entries");
@@ -566,6 +583,10 @@ shaken_status init_device(shaken_ctx *c, const shaken_opts *o, HostLayout &hl) {
             HIPCHK(hipMemcpyAsync(c->pell_dev, hl.pell.data(), hl.pell.size() * 8, hipMemcpyHostToDevice, c->stream));
         }
     }
+    if (!hl.frozen.empty()) {
+        CHK(dalloc(&c->frozen_dev, hl.frozen.size()));
+        HIPCHK(hipMemcpyAsync(c->frozen_dev, hl.frozen.data(), hl.frozen.size() * 4, hipMemcpyHostToDevice, c->stream));
+    }
     if (!hl.jneg.empty()) {
         CHK(dalloc(&c->jneg_dev, hl.jneg.size()));
         HIPCHK(hipMemcpyAsync(c->jneg_dev, hl.jneg.data(), hl.jneg.size() * 4, hipMemcpyHostToDevice, c->stream));
@@ -598,6 +619,7 @@ shaken_status init_device(shaken_ctx *c, const shaken_opts *o, HostLayout &hl) {
     d.pell = c->pell_dev;
     d.jneg = c->jneg_dev;
     d.rev = (o->flags & SHAKEN_ORDER_REVERSED) ? 1 : 0;
+    d.frozen = c->frozen_dev;
     d.log_line = c->line();
     d.log_stride = c->stride();
     for (size_t k = 0; k < c->lam.size() && k < 16; ++k) {
@@ -829,6 +851,13 @@ shaken_status shaken_set_spins(shaken_ctx *ctx, const int8_t *in) {
     if (!ctx || !in) return fail(SHAKEN_EINVAL, "ctx and in must be non-NULL");
     for (int64_t i = 0; i < ctx->n; ++i)
         if (in[i] != 1 && in[i] != -1) return fail(SHAKEN_EINVAL, "spins must be +1 or -1");
+    std::vector<int8_t> forced;
+    if (!ctx->frozen_host.empty()) {  // sites of the frozen set stay +1
+        forced.assign(in, in + ctx->n);
+        for (int64_t i = 0; i < ctx->n; ++i)
+            if (ctx->frozen_host[(size_t)i]) forced[(size_t)i] = 1;
+        in = forced.data();
+    }
     DeviceGuard guard(ctx->device);
     void *dst = ctx->spin[ctx->s & 1u];
     if (ctx->format == FMT_BITPACKED) {

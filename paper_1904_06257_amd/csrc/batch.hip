@@ -91,7 +91,8 @@ __device__ void torus_lds_half(const ChainDesc &d, const uint32_t *src, uint32_t
                            : ((own >> 1) | ((src[r * W] & 1u) << lastbits));
             if (d.jneg) bp_jflip(d.jneg, L, W, r, wd, 1, a, b);
         }
-        dst[w] = bp_word<FOLD3>(a, b, own, vm, (uint32_t)w, s, d.replica, k0, k1, d.tsmall, d.sgn);
+        dst[w] = bp_word<FOLD3>(a, b, own, vm, (uint32_t)w, s, d.replica, k0, k1, d.tsmall, d.sgn) |
+                 frozen_word(d, w);
     }
     if (obs) {
         block_sum2(e_acc, p_acc, sh_red);
@@ -299,6 +300,7 @@ __device__ void graph_lds_half(const ChainDesc &d, const uint32_t *src, uint32_t
                         if ((uint64_t)u[j] < T) bits |= 1u << j;
                     }
                 }
+                bits |= frozen4(d, v0);
             }
             if (obs) {
 #pragma unroll

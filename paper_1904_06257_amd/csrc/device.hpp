@@ -190,6 +190,16 @@ __device__ __forceinline__ int torus_jsign(const uint32_t *__restrict__ jn, int 
     return ((jn[(size_t)plane * L * W + r * W + (c >> 5)] >> (c & 31)) & 1u) ? -1 : 1;
 }
 
+// frozen set B: word w of the frozen bit-plane (0 when B is empty)
+__device__ __forceinline__ uint32_t frozen_word(const ChainDesc &d, int w) {
+    return d.frozen ? d.frozen[w] : 0u;
+}
+
+// frozen bits of the four vertices v0..v0+3 of a graph (bit j = v0 + j)
+__device__ __forceinline__ uint32_t frozen4(const ChainDesc &d, int v0) {
+    return d.frozen ? ((d.frozen[v0 >> 5] >> (v0 & 31)) & 0xFu) : 0u;
+}
+
 __device__ __forceinline__ uint32_t bp_valid(int L, int W, int wd) {
     const int rem = L & 31;
     return (wd == W - 1 && rem) ? ((1u << rem) - 1u) : 0xFFFFFFFFu;

@@ -87,7 +87,9 @@ __device__ __noinline__ uint32_t bp_finish(uint32_t a, uint32_t b, uint32_t c, u
 // not idle while its slowest lane runs the rare deep levels.
 constexpr int kQCap = 512;
 
-template <bool OBS, bool FOLD3, bool JPL>
+// EXT: instantiation for chains with +-J sign planes or a frozen set (the
+// plain instantiation reads neither)
+template <bool OBS, bool FOLD3, bool EXT>
 __global__ __launch_bounds__(256) void k_torus_bp(const ChainDesc *__restrict__ descs, StepArgs sa) {
     __shared__ uint32_t q_w[kQCap], q_a[kQCap], q_b[kQCap], q_c[kQCap], q_und[kQCap], q_res[kQCap];
     __shared__ int q_n;
@@ -150,7 +152,7 @@ __global__ __launch_bounds__(256) void k_torus_bp(const ChainDesc *__restrict__ 
                 b = wd < W - 1 ? ((own[i] >> 1) | (side[i] << 31))
                                : ((own[i] >> 1) | ((side[i] & 1u) << lastbits));
             }
-            if (JPL && d.jneg) bp_jflip(d.jneg, L, W, r0 + i, wd, phase, a, b);
+            if (EXT && d.jneg) bp_jflip(d.jneg, L, W, r0 + i, wd, phase, a, b);
             p = bp_planes(a, b, own[i], sgn);
             und = vm;
             bp_groups<FOLD3, 0, 2>(p, und, res, (uint32_t)widx, s, rep, k0, k1, ts);
@@ -168,7 +170,7 @@ __global__ __launch_bounds__(256) void k_torus_bp(const ChainDesc *__restrict__ 
         if (act) {
             const int q = base + (int)__popcll(bal & ((1ull << lane) - 1ull));
             if (!pend) {
-                out[widx] = (res ^ p.smask) & vm;
+                out[widx] = ((res ^ p.smask) & vm) | (EXT ? frozen_word(d, widx) : 0u);
             } else if (q < kQCap) {
                 q_w[q] = (uint32_t)widx;
                 q_a[q] = a;
@@ -177,7 +179,8 @@ __global__ __launch_bounds__(256) void k_torus_bp(const ChainDesc *__restrict__ 
                 q_und[q] = und;
                 q_res[q] = res;
             } else {
-                out[widx] = bp_finish<FOLD3>(a, b, own[i], und, res, vm, (uint32_t)widx, s, rep, k0, k1, ts, sgn);
+                out[widx] = bp_finish<FOLD3>(a, b, own[i], und, res, vm, (uint32_t)widx, s, rep, k0, k1, ts, sgn) |
+                            (EXT ? frozen_word(d, widx) : 0u);
             }
         }
     }
@@ -187,7 +190,7 @@ __global__ __launch_bounds__(256) void k_torus_bp(const ChainDesc *__restrict__ 
         const uint32_t w = q_w[it];
         const uint32_t vw = bp_valid(L, W, (int)(w % (uint32_t)W));
         out[w] = bp_finish<FOLD3>(q_a[it], q_b[it], q_c[it], q_und[it], q_res[it], vw, w, s, rep, k0,
-                                  k1, ts, sgn);
+                                  k1, ts, sgn) | (EXT ? frozen_word(d, (int)w) : 0u);
     }
     if (OBS && bx * (int)blockDim.x < total)
         block_accumulate2(e_acc, p_acc, log_part(d, slot, bx));
@@ -243,7 +246,8 @@ __global__ __launch_bounds__(256) void k_torus_i8(const ChainDesc *__restrict__ 
         const uint32_t w = (uint32_t)(r * d.W + (c >> 5));
         const bool up = sliced_less(T, w, c & 31, s, d.replica, (uint32_t)d.seed,
                                     (uint32_t)(d.seed >> 32));
-        out[gid] = up ? 1 : -1;
+        const bool fz = (frozen_word(d, r * d.W + (c >> 5)) >> (c & 31)) & 1u;
+        out[gid] = (up || fz) ? 1 : -1;
         if (OBS) {
             e_acc = own * S;
             p_acc = own > 0;
@@ -417,6 +421,7 @@ __global__ __launch_bounds__(256) void k_graph(const ChainDesc *__restrict__ des
             }
         }
     }
+    if (v0 < n) up |= frozen4(d, v0);
     graph_store4<BP>(out, q4, n, up);
     if (OBS && blockIdx.x < (unsigned)((n + 4 * blockDim.x - 1) / (4 * blockDim.x))) {
         int64_t *lg = log_part(d, slot, blockIdx.x);
@@ -517,6 +522,7 @@ __global__ __launch_bounds__(256) void k_graph_ell(const ChainDesc *__restrict__
             }
         }
     }
+    if (v0 < n) up |= frozen4(d, v0);
     graph_store4<BP>(out, q4, n, up);
     if (OBS && blockIdx.x < (unsigned)((n + 4 * blockDim.x - 1) / (4 * blockDim.x))) {
         int64_t *lg = log_part(d, slot, blockIdx.x);
@@ -619,7 +625,7 @@ __global__ void k_init(ChainDesc d, void *dst, int mode) {
             v = philox10((uint32_t)gid, kInitStep, d.replica, 0u, k0, k1).x;
         else
             v = (mode == 1) ? 0xFFFFFFFFu : 0u;
-        ((uint32_t *)dst)[gid] = v & vm;
+        ((uint32_t *)dst)[gid] = (v & vm) | frozen_word(d, gid);
         return;
     }
     if (d.kind == KIND_GRAPH && d.format == FMT_BITPACKED) {
@@ -640,7 +646,7 @@ __global__ void k_init(ChainDesc d, void *dst, int mode) {
             }
             if (upx) v |= 1u << b;
         }
-        ((uint32_t *)dst)[gid] = v;
+        ((uint32_t *)dst)[gid] = v | frozen_word(d, gid);
         return;
     }
     if (gid >= d.n) return;
@@ -658,6 +664,9 @@ __global__ void k_init(ChainDesc d, void *dst, int mode) {
     } else {
         v = (mode == 1) ? 1 : -1;
     }
+    const int fw = d.kind == KIND_TORUS ? (gid / d.L) * d.W + ((gid % d.L) >> 5) : gid >> 5;
+    const int fb = d.kind == KIND_TORUS ? (gid % d.L) & 31 : gid & 31;
+    if ((frozen_word(d, fw) >> fb) & 1u) v = 1;
     ((int8_t *)dst)[gid] = v;
 }
 
@@ -696,7 +705,7 @@ hipError_t launch_half_step_grid(const ChainDesc *dev_descs, const ChainDesc *ho
         maxu = maxu > units_of(host_descs[i]) ? maxu : units_of(host_descs[i]);
         fold &= host_descs[i].fold3;
         maxcls = maxcls > host_descs[i].ncls ? maxcls : host_descs[i].ncls;
-        jpl |= host_descs[i].jneg != nullptr;
+        jpl |= host_descs[i].jneg != nullptr || host_descs[i].frozen != nullptr;
     }
     const bool obs = log_on && even;
     const StepArgs sa{dstate, s_add, s_log0, log_on};
@@ -705,7 +714,8 @@ hipError_t launch_half_step_grid(const ChainDesc *dev_descs, const ChainDesc *ho
     if (h0.kind == KIND_TORUS && h0.format == FMT_BITPACKED) {
 #define SHAKEN_BP(O, F, JP) hipLaunchKernelGGL((k_torus_bp<O, F, JP>), grid, dim3(b), 0, stream, dev_descs, sa)
         if (jpl) {
-            // +-J sign planes (chains without planes in the same launch skip them)
+            // +-J sign planes or frozen sets (chains without them in the same
+            // launch skip them)
             if (obs) { if (fold) SHAKEN_BP(true, true, true); else SHAKEN_BP(true, false, true); }
             else { if (fold) SHAKEN_BP(false, true, true); else SHAKEN_BP(false, false, true); }
         } else {

@@ -65,6 +65,10 @@ struct ChainDesc {
     // 1: reversed order P^{sh'} (section 3): the half read at half-step s is
     // (s & 1) ^ 1, the out-half (torus ur) first
     int32_t rev;
+    // frozen set B (section 3.1) as bits in the layout of the bit-packed spins
+    // (torus L x W words, graph ceil(n/32)): these sites are written +1 by
+    // every half-step and by the start; null if B is empty
+    const uint32_t *frozen;
     // observables log: slot t is kLogParts lines of log_line int64; line p holds
     // partial sums [E_J, plus_0 .. plus_{ncls-1}] (a block adds into line
     // blockIdx % kLogParts, so that thousands of blocks do not queue on one
