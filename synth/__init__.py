@@ -139,3 +139,21 @@ def batch_spec(n_tori: int, n_graphs: int, seed: int, l_max: int = 256, n_min: i
             it.graph = oriented_instance(n, 3, gseed, lam_values=(0.0,), pm_j=True)
         items.append(it)
     return items
+
+
+def triangular_torus_edges(L: int):
+    """Triangular lattice on an L x L torus in skewed coordinates (site
+    x = row * L + col): every site has the six neighbours x +- e1, x +- e2,
+    x +- (e1 + e2) with e1 = one column, e2 = one row.  Oriented edges
+    (x, x + e1), (x, x + e2), (x, x + e1 + e2): the in-half of x (its three
+    "left" neighbours) is {x - e1, x - e2, x - e1 - e2}, the out-half the
+    other three (section 4, shaken dynamics on the triangular lattice).
+    Returns (src, dst) int32 arrays of 3 L^2 edges."""
+    r, c = np.divmod(np.arange(L * L), L)
+    x = r * L + c
+    right = r * L + (c + 1) % L
+    up = ((r + 1) % L) * L + c
+    diag = ((r + 1) % L) * L + (c + 1) % L
+    src = np.concatenate([x, x, x]).astype(np.int32)
+    dst = np.concatenate([right, up, diag]).astype(np.int32)
+    return src, dst
