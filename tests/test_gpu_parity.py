@@ -483,3 +483,28 @@ def test_split_graph_parity(sk, n, deg, strategy):
     assert np.array_equal(h, _h_from_plus(inst, ej, plus))
     b.close()
     ch.close()
+
+
+def test_batch_run_one_call(sk):
+    """shaken_batch_run: create, sweep, read the final H, free -- in one call
+    through the C ABI; chains continue on their own afterwards."""
+    T = 20
+    L = 40
+    inst = synth.oriented_instance(1002, 3, 71, lam_values=(-0.5, 0.5), pm_j=True)
+    tor = sk.Chain.torus(L, q=0.9, beta=0.45, seed=71, replica=1, lam_values=[0.5])
+    gr = sk.Chain.graph(inst.n, inst.src, inst.dst, J=inst.J, lam_values=inst.lam_values,
+                        lam_class=inst.cls, q=1.2, beta=0.7, seed=72, replica=2)
+    o = sk.shaken_batch_opts(sk.SHAKEN_BATCH_AUTO, 0, 0, 0, None, 0, 0)
+    H = np.zeros(2, dtype=np.int64)
+    sk.shaken_batch_run([tor.handle, gr.handle], T, o, H)
+    wt, ejt, mmt = oracle.torus_run(oracle.torus_init_random(L, 71, 1), 1, 0.5, 0.9, 0.45, 71, 1, T)
+    og = oracle.Graph(inst.n, inst.src, inst.dst, inst.J, inst.cls, inst.lam_values)
+    wg, ejg, plg = oracle.graph_run(og, oracle.graph_init_random(inst.n, 72, 2), 1.2, 0.7, 72, 2, T)
+    assert np.array_equal(tor.spins(), wt) and np.array_equal(gr.spins(), wg)
+    assert H[0] == -ejt[-1] - mmt[-1]
+    assert H[1] == _h_from_plus(inst, ejg, plg)[-1]
+    tor.sweep(2)
+    wt2, _, _ = oracle.torus_run(wt, 1, 0.5, 0.9, 0.45, 71, 1, 2, s0=2 * T)
+    assert np.array_equal(tor.spins(), wt2)
+    tor.close()
+    gr.close()
