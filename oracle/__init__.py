@@ -83,8 +83,8 @@ def lib():
                                                ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                                ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
                                                _i8p, _i8p]
-        L.oracle_torus_observe_j.argtypes = [ctypes.c_int, ctypes.c_int, _i8p, _i8p, _i8p, _i64p,
-                                             _i64p]
+        L.oracle_torus_observe_j.argtypes = [ctypes.c_int, ctypes.c_int, _i8p, _i8p, ctypes.c_int,
+                                             _i8p, _i64p, _i64p]
         L.oracle_torus_run_j.argtypes = [ctypes.c_int, ctypes.c_int, _i8p, _i8p, ctypes.c_int,
                                          ctypes.c_double,
                                          ctypes.c_double, ctypes.c_double, ctypes.c_uint64,
@@ -158,37 +158,42 @@ def _couplings(J, L):
     return 0, ju, jr
 
 
-def torus_half_step(spins, J, lam, q, beta, seed, replica, s, rev=False) -> np.ndarray:
-    """rev: the reversed order P^{sh'} (out-half, ur, read at even s)"""
+def _mode(rev, tri):
+    return (1 if rev else 0) | (2 if tri else 0)
+
+
+def torus_half_step(spins, J, lam, q, beta, seed, replica, s, rev=False, tri=False) -> np.ndarray:
+    """rev: the reversed order P^{sh'} (out-half, ur, read at even s);
+    tri: the triangular lattice (uniform J)"""
     L = spins.shape[0]
     a = np.ascontiguousarray(spins, dtype=np.int8)
     out = np.zeros_like(a)
     j, ju, jr = _couplings(J, L)
-    lib().oracle_torus_half_step_j(L, j, _p(ju, _i8p), _p(jr, _i8p), int(rev), float(lam), float(q),
+    lib().oracle_torus_half_step_j(L, j, _p(ju, _i8p), _p(jr, _i8p), _mode(rev, tri), float(lam), float(q),
                                    float(beta), ctypes.c_uint64(seed), replica, s & 0xFFFFFFFF,
                                    _p(a, _i8p), _p(out, _i8p))
     return out
 
 
-def torus_site(spins, J, lam, q, beta, seed, replica, s, r, c, rev=False) -> int:
+def torus_site(spins, J, lam, q, beta, seed, replica, s, r, c, rev=False, tri=False) -> int:
     a = np.ascontiguousarray(spins, dtype=np.int8)
     j, ju, jr = _couplings(J, a.shape[0])
-    return int(lib().oracle_torus_site_j(a.shape[0], j, _p(ju, _i8p), _p(jr, _i8p), int(rev), float(lam),
+    return int(lib().oracle_torus_site_j(a.shape[0], j, _p(ju, _i8p), _p(jr, _i8p), _mode(rev, tri), float(lam),
                                          float(q), float(beta), ctypes.c_uint64(seed), replica,
                                          s & 0xFFFFFFFF, _p(a, _i8p), int(r), int(c)))
 
 
-def torus_observe(spins, J=1):
+def torus_observe(spins, J=1, tri=False):
     a = np.ascontiguousarray(spins, dtype=np.int8)
     e = ctypes.c_int64()
     m = ctypes.c_int64()
     j, ju, jr = _couplings(J, a.shape[0])
-    lib().oracle_torus_observe_j(a.shape[0], j, _p(ju, _i8p), _p(jr, _i8p), _p(a, _i8p),
+    lib().oracle_torus_observe_j(a.shape[0], j, _p(ju, _i8p), _p(jr, _i8p), _mode(False, tri), _p(a, _i8p),
                                  ctypes.byref(e), ctypes.byref(m))
     return e.value, m.value
 
 
-def torus_run(spins, J, lam, q, beta, seed, replica, n_full, s0=0, log=True, rev=False):
+def torus_run(spins, J, lam, q, beta, seed, replica, n_full, s0=0, log=True, rev=False, tri=False):
     """Returns (final spins, E_J log, M log); logs have n_full+1 entries.  J is
     an int or a pair (Jup, Jright) of [L, L] int8 arrays."""
     a = np.ascontiguousarray(spins, dtype=np.int8).copy()
@@ -196,7 +201,7 @@ def torus_run(spins, J, lam, q, beta, seed, replica, n_full, s0=0, log=True, rev
     ej = np.zeros(n_full + 1, dtype=np.int64) if log else None
     m = np.zeros(n_full + 1, dtype=np.int64) if log else None
     j, ju, jr = _couplings(J, L)
-    rc = lib().oracle_torus_run_j(L, j, _p(ju, _i8p), _p(jr, _i8p), int(rev), float(lam), float(q),
+    rc = lib().oracle_torus_run_j(L, j, _p(ju, _i8p), _p(jr, _i8p), _mode(rev, tri), float(lam), float(q),
                                   float(beta), ctypes.c_uint64(seed), replica, s0, _p(a, _i8p),
                                   n_full, _p(ej, _i64p), _p(m, _i64p))
     if rc != 0:

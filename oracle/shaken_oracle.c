@@ -151,30 +151,36 @@ void oracle_torus_init_random(int L, uint64_t seed, uint32_t replica, int8_t *sp
  * torus are (x, x_up) with coupling Jup[x] and (x, x_right) with Jr[x]
  * (row-major site index); Jup == NULL means every coupling equals J.
  *   phase 0 (in-half, dl):  Jup[x_down] sigma(x_down) + Jr[x_left] sigma(x_left)
- *   phase 1 (out-half, ur): Jup[x] sigma(x_up) + Jr[x] sigma(x_right)        */
-static int64_t torus_fsum(int L, int J, const int8_t *Jup, const int8_t *Jr,
+ *   phase 1 (out-half, ur): Jup[x] sigma(x_up) + Jr[x] sigma(x_right)
+ * Triangular lattice (section 4; skewed coordinates, uniform J): the third
+ * oriented edge (x, x_up_right) adds the diagonal neighbour, down-left in the
+ * in-half and up-right in the out-half. */
+static int64_t torus_fsum(int L, int J, const int8_t *Jup, const int8_t *Jr, int tri,
                           const int8_t *sp, int r, int c, int phase)
 {
     int x = r * L + c;
     if (phase == 0) {
         int xd = ((r - 1 + L) % L) * L + c, xl = r * L + (c - 1 + L) % L;
+        if (tri) return (int64_t)J * (sp[xd] + sp[xl] + sp[((r - 1 + L) % L) * L + (c - 1 + L) % L]);
         if (!Jup) return (int64_t)J * (sp[xd] + sp[xl]);
         return (int64_t)Jup[xd] * sp[xd] + (int64_t)Jr[xl] * sp[xl];
     } else {
         int xu = ((r + 1) % L) * L + c, xr = r * L + (c + 1) % L;
+        if (tri) return (int64_t)J * (sp[xu] + sp[xr] + sp[((r + 1) % L) * L + (c + 1) % L]);
         if (!Jup) return (int64_t)J * (sp[xu] + sp[xr]);
         return (int64_t)Jup[x] * sp[xu] + (int64_t)Jr[x] * sp[xr];
     }
 }
 
 /* new value of one site at half-step s, read from configuration `in` */
-/* rev = 1: the reversed order P^{sh'} = P^{ur} P^{dl} (section 3): the half
- * read at half-step s is (s & 1) ^ 1, i.e. the out-half (ur) at even s. */
-int oracle_torus_site_j(int L, int J, const int8_t *Jup, const int8_t *Jr, int rev, double lam,
+/* mode bit 0: the reversed order P^{sh'} = P^{ur} P^{dl} (section 3): the half
+ * read at half-step s is (s & 1) ^ 1, i.e. the out-half (ur) at even s.
+ * mode bit 1: the triangular lattice (uniform J; Jup must be NULL). */
+int oracle_torus_site_j(int L, int J, const int8_t *Jup, const int8_t *Jr, int mode, double lam,
                         double q, double beta, uint64_t seed, uint32_t replica, uint32_t s,
                         const int8_t *in, int r, int c)
 {
-    int64_t S = torus_fsum(L, J, Jup, Jr, in, r, c, (int)(s & 1u) ^ (rev != 0));
+    int64_t S = torus_fsum(L, J, Jup, Jr, (mode >> 1) & 1, in, r, c, (int)(s & 1u) ^ (mode & 1));
     double h = oracle_field(S, in[r * L + c], q, lam);
     uint64_t T = oracle_threshold(h, beta);
     uint32_t u = oracle_torus_uniform(L, seed, replica, s, r, c);
@@ -188,7 +194,7 @@ int oracle_torus_site(int L, int J, double lam, double q, double beta, uint64_t 
 }
 
 /* one half-step: every site redrawn from `in` into `out` (in != out) */
-void oracle_torus_half_step_j(int L, int J, const int8_t *Jup, const int8_t *Jr, int rev,
+void oracle_torus_half_step_j(int L, int J, const int8_t *Jup, const int8_t *Jr, int mode,
                               double lam, double q, double beta, uint64_t seed, uint32_t replica,
                               uint32_t s, const int8_t *in, int8_t *out)
 {
@@ -199,7 +205,8 @@ void oracle_torus_half_step_j(int L, int J, const int8_t *Jup, const int8_t *Jr,
             torus_levels(seed, replica, s, (uint32_t)(r * W + wd), R);
             for (b = 0; b < 32 && 32 * wd + b < L; ++b) {
                 int c = 32 * wd + b;
-                int64_t S = torus_fsum(L, J, Jup, Jr, in, r, c, (int)(s & 1u) ^ (rev != 0));
+                int64_t S = torus_fsum(L, J, Jup, Jr, (mode >> 1) & 1, in, r, c,
+                                       (int)(s & 1u) ^ (mode & 1));
                 double h = oracle_field(S, in[r * L + c], q, lam);
                 uint64_t T = oracle_threshold(h, beta);
                 uint32_t u = torus_u_from_levels(R, b);
@@ -216,7 +223,7 @@ void oracle_torus_half_step(int L, int J, double lam, double q, double beta,
 }
 
 /* E_J over the oriented edge set {(x, x_up), (x, x_right)} and M */
-void oracle_torus_observe_j(int L, int J, const int8_t *Jup, const int8_t *Jr,
+void oracle_torus_observe_j(int L, int J, const int8_t *Jup, const int8_t *Jr, int mode,
                             const int8_t *sp, int64_t *EJ, int64_t *M)
 {
     int64_t e = 0, m = 0;
@@ -227,6 +234,7 @@ void oracle_torus_observe_j(int L, int J, const int8_t *Jup, const int8_t *Jr,
             int ju = Jup ? Jup[x] : J, jr = Jup ? Jr[x] : J;
             e += (int64_t)ju * sp[x] * sp[((r + 1) % L) * L + c];
             e += (int64_t)jr * sp[x] * sp[r * L + (c + 1) % L];
+            if (mode & 2) e += (int64_t)J * sp[x] * sp[((r + 1) % L) * L + (c + 1) % L];
             m += sp[x];
         }
     *EJ = e;
@@ -235,14 +243,14 @@ void oracle_torus_observe_j(int L, int J, const int8_t *Jup, const int8_t *Jr,
 
 void oracle_torus_observe(int L, int J, const int8_t *sp, int64_t *EJ, int64_t *M)
 {
-    oracle_torus_observe_j(L, J, NULL, NULL, sp, EJ, M);
+    oracle_torus_observe_j(L, J, NULL, NULL, 0, sp, EJ, M);
 }
 
 /* n_full full steps from half-step index s0 (must be even); spins updated in
  * place (through a private second buffer); logs hold n_full+1 entries
  * (configuration at the start and after every full step); NULL skips a log.
  * Returns 0, or -1 on allocation failure / odd s0. */
-int oracle_torus_run_j(int L, int J, const int8_t *Jup, const int8_t *Jr, int rev, double lam,
+int oracle_torus_run_j(int L, int J, const int8_t *Jup, const int8_t *Jr, int mode, double lam,
                        double q, double beta, uint64_t seed, uint32_t replica, uint32_t s0,
                        int8_t *spins, int64_t n_full, int64_t *EJ_log, int64_t *M_log)
 {
@@ -255,13 +263,13 @@ int oracle_torus_run_j(int L, int J, const int8_t *Jup, const int8_t *Jr, int re
     for (t = 0; t <= n_full; ++t) {
         int64_t e, m;
         if (EJ_log || M_log) {
-            oracle_torus_observe_j(L, J, Jup, Jr, spins, &e, &m);
+            oracle_torus_observe_j(L, J, Jup, Jr, mode, spins, &e, &m);
             if (EJ_log) EJ_log[t] = e;
             if (M_log) M_log[t] = m;
         }
         if (t == n_full) break;
-        oracle_torus_half_step_j(L, J, Jup, Jr, rev, lam, q, beta, seed, replica, s, spins, tmp);
-        oracle_torus_half_step_j(L, J, Jup, Jr, rev, lam, q, beta, seed, replica, s + 1, tmp, spins);
+        oracle_torus_half_step_j(L, J, Jup, Jr, mode, lam, q, beta, seed, replica, s, spins, tmp);
+        oracle_torus_half_step_j(L, J, Jup, Jr, mode, lam, q, beta, seed, replica, s + 1, tmp, spins);
         s += 2;
     }
     free(tmp);

@@ -3,11 +3,12 @@
  * torus wrap-around at L = 3 and 33, +-J couplings, an empty edge list, split
  * (anti-parallel) edges and zero temperature.  Exits non-zero on any
  * inconsistency; the sanitizers abort on any invalid access.  The +-J cases
- * also run the reversed order. */
+ * also run the reversed order; the triangular lattice runs too. */
 #include "../oracle/shaken_oracle.c"
 
 #include <stdio.h>
 
+/* pm: 0 uniform J, 1 +-J couplings with the reversed order, 2 triangular */
 static int check_torus(int L, int pm)
 {
     int8_t *sp = malloc((size_t)L * L), *a = malloc((size_t)L * L), *b = malloc((size_t)L * L);
@@ -20,22 +21,22 @@ static int check_torus(int L, int pm)
     }
     oracle_torus_init_random(L, 9, 1, sp);
     memcpy(a, sp, (size_t)L * L);
-    if (oracle_torus_run_j(L, 1, pm ? ju : NULL, pm ? jr : NULL, pm, 0.25, 0.7, 0.6, 9, 1, 0, a, 5, ej, m))
+    if (oracle_torus_run_j(L, 1, pm == 1 ? ju : NULL, pm == 1 ? jr : NULL, pm, 0.25, 0.7, 0.6, 9, 1, 0, a, 5, ej, m))
         return 1;
     /* the same five steps as ten half-steps */
     memcpy(b, sp, (size_t)L * L);
     for (i = 0; i < 10; ++i) {
         int8_t *t = malloc((size_t)L * L);
-        oracle_torus_half_step_j(L, 1, pm ? ju : NULL, pm ? jr : NULL, pm, 0.25, 0.7, 0.6, 9, 1,
+        oracle_torus_half_step_j(L, 1, pm == 1 ? ju : NULL, pm == 1 ? jr : NULL, pm, 0.25, 0.7, 0.6, 9, 1,
                                  (uint32_t)i, b, t);
         memcpy(b, t, (size_t)L * L);
         free(t);
     }
     if (memcmp(a, b, (size_t)L * L)) rc = 2;
-    oracle_torus_observe_j(L, 1, pm ? ju : NULL, pm ? jr : NULL, a, &e1, &m1);
+    oracle_torus_observe_j(L, 1, pm == 1 ? ju : NULL, pm == 1 ? jr : NULL, pm, a, &e1, &m1);
     if (e1 != ej[5] || m1 != m[5]) rc = 3;
     /* zero temperature and a single site */
-    (void)oracle_torus_site_j(L, 1, pm ? ju : NULL, pm ? jr : NULL, pm, 0.1, 0.3, 1e9, 9, 1, 4, a,
+    (void)oracle_torus_site_j(L, 1, pm == 1 ? ju : NULL, pm == 1 ? jr : NULL, pm, 0.1, 0.3, 1e9, 9, 1, 4, a,
                               L - 1, L - 1);
     free(sp); free(a); free(b); free(ju); free(jr);
     return rc;
@@ -64,7 +65,7 @@ int main(void)
 {
     int L[4] = {3, 4, 33, 65}, i, pm, rc;
     for (i = 0; i < 4; ++i)
-        for (pm = 0; pm < 2; ++pm)
+        for (pm = 0; pm < 3; ++pm)
             if ((rc = check_torus(L[i], pm)) != 0) {
                 printf("torus L=%d pm=%d: %d\n", L[i], pm, rc);
                 return rc;

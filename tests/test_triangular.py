@@ -90,3 +90,50 @@ def test_order_on_both_sides_of_the_critical_curve():
     bt.close()
     for c in chains:
         c.close()
+
+
+# --------------------------------------------------- oracle's triangular torus
+# The oracle's bit-sliced torus randomness with the third (diagonal) oriented
+# edge; pinned against the enumeration model built from the same edge list.
+
+def _rand_spins(rng, n):
+    return np.where(rng.integers(0, 2, n) == 1, 1, -1).astype(np.int8)
+
+
+@pytest.mark.parametrize("L", [3, 4, 5])
+def test_oracle_triangular_zero_temperature_fields(L):
+    import oracle
+    from oracle import enumeration as en
+    q, lam = 0.5, 0.25
+    src, dst = synth.triangular_torus_edges(L)
+    m = en.Model(L * L, src, dst, lam=np.full(L * L, lam), q=q, beta=1.0)
+    rng = np.random.Generator(np.random.PCG64(90 + L))
+    for _ in range(20):
+        sp = _rand_spins(rng, L * L)
+        g1 = oracle.torus_half_step(sp.reshape(L, L), 1, lam, q, 1000.0, 3, 0, 0, tri=True).reshape(-1)
+        assert np.array_equal(g1, np.sign(m.field12_of(sp)).astype(np.int8))
+        g2 = oracle.torus_half_step(g1.reshape(L, L), 1, lam, q, 1000.0, 3, 0, 1, tri=True).reshape(-1)
+        assert np.array_equal(g2, np.sign(m.field21_of(g1)).astype(np.int8))
+        ej, mm = oracle.torus_observe(sp.reshape(L, L), 1, tri=True)
+        assert -ej - 2 * lam * mm == pytest.approx(m.gibbs_H_of(sp), abs=1e-12)
+
+
+def test_oracle_triangular_one_step_law():
+    import oracle
+    from oracle import enumeration as en
+    from scipy import stats
+    L, q, lam, b = 3, 0.7, 0.1, 0.4
+    src, dst = synth.triangular_torus_edges(L)
+    m = en.Model(L * L, src, dst, lam=np.full(L * L, lam), q=q, beta=b)
+    sp = np.array([1, -1, -1, 1, 1, -1, 1, -1, 1], dtype=np.int8).reshape(L, L)
+    i0 = en.index_of(sp.reshape(-1))
+    full = np.zeros(2 ** (L * L))
+    for r in range(30000):
+        a = oracle.torus_half_step(sp, 1, lam, q, b, 8, r, 0, tri=True)
+        c = oracle.torus_half_step(a, 1, lam, q, b, 8, r, 1, tri=True)
+        full[en.index_of(c.reshape(-1))] += 1
+    probs = m.Psh()[i0]
+    keep = probs * full.sum() >= 5
+    obs = np.append(full[keep], full[~keep].sum())
+    exp = np.append(probs[keep], probs[~keep].sum()) * full.sum()
+    assert stats.chisquare(obs, exp).pvalue > 1e-4
