@@ -7,9 +7,10 @@ step (half-step dl with the fused observables of the configuration it reads,
 then half-step ur) of all 24 chains; it is replayed from a captured HIP
 graph.  Inputs are resident in device memory before the timed region.
 
-Other workloads (``--workload``): ``graph`` (3-regular +-J graph, n = 2^20,
-CSR, int8), ``batch`` (2048 mixed tori and 3-regular graphs, persistent
-launch), ``torus64`` (one 64 x 64 chain).
+Other workloads (``--workload``): ``tri4096`` (the same 24 runs on the
+triangular-lattice torus of section 4), ``graph`` (3-regular +-J graph,
+n = 2^20, CSR, int8), ``batch`` (2048 mixed tori and 3-regular graphs,
+persistent launch), ``ea`` (1024 +-J Edwards-Anderson tori 256^2).
 
 Prints one JSON line: metric, value (site-updates/s), roofline of the
 dominant kernel (HIP-event time per launch, algorithmic work per launch) and
@@ -45,6 +46,11 @@ BP_ALU_PER_SITE = (1.999 * PHILOX_LC + 4 * 1.999 * 6 + 15) / 32.0
 BP_BYTES_PER_SITE = 0.25  # read 1 bit, write 1 bit
 # +-J torus: two more xors per word flip the neighbour planes by the coupling signs
 BP_ALU_PER_SITE_PMJ = BP_ALU_PER_SITE + 2.0 / 32.0
+# triangular lattice (three neighbour planes a, b, e): the diagonal plane e
+# (shift and insert, 2), the count planes n1 = a^b^e and n2 = maj(a, b, e)
+# (one three-input op each, 2) and the agreement planes of the folded table
+# (3): 7 more lane-cycles per word; the folded compare keeps 6 per level.
+TRI_ALU_PER_SITE = BP_ALU_PER_SITE + 7.0 / 32.0
 
 
 def kernel_source_hash():
@@ -74,30 +80,31 @@ def read_traffic(kernel_key, per="launch"):
     return float(v) if v else None
 
 
-def cpu_baseline_torus():
+def cpu_baseline_torus(triangular=False):
     """The oracle as it stands: ten full steps (twenty half-steps) of one
     4096^2 chain, single-threaded C (about 10 s of host time)."""
     import oracle
     L, steps = 4096, 10
     sp = oracle.torus_init_random(L, 2)
     t0 = time.perf_counter()
-    oracle.torus_run(sp, 1, 0.0, 1.0, 0.44, 2, 0, steps, log=False)
+    oracle.torus_run(sp, 1, 0.0, 1.0, 0.44, 2, 0, steps, log=False, tri=triangular)
     dt = time.perf_counter() - t0
     n = 2 * L * L * steps
     return {"value": n / dt, "unit": "site-updates/s", "cores": 1, "kind": "oracle",
-            "sample": "%d full steps of one 4096^2 torus chain (q=1, beta=0.44, random init), "
-                      "%.1f s on one host core" % (steps, dt)}
+            "sample": "%d full steps of one 4096^2 %s chain (q=1, beta=0.44, random init), "
+                      "%.1f s on one host core" % (steps, "triangular-lattice torus" if triangular
+                                                   else "torus", dt)}
 
 
-def bench_torus4096(args, sk):
+def bench_torus4096(args, sk, triangular=False):
     import synth
     import torch
     L = 4096
     runs = synth.torus_runs()
+    make = sk.Chain.triangular if triangular else sk.Chain.torus
     chains = []
     for i, r in enumerate(runs):
-        chains.append(sk.Chain.torus(L, q=r["q"], beta=r["beta"], seed=r["seed"], replica=i,
-                                     init=r["init"]))
+        chains.append(make(L, q=r["q"], beta=r["beta"], seed=r["seed"], replica=i, init=r["init"]))
     # log space for the longest call reserved up-front: the timed call neither
     # allocates nor re-captures its HIP graph
     batch = sk.Batch(chains, strategy="grid", use_hipgraph=True, record=True, autotune=True,
@@ -116,18 +123,21 @@ def bench_torus4096(args, sk):
     # remaining launches per step (1/16 of a counter increment) are < 0.1 %
     per_launch_s = ev_ms * 1e-3 / (2 * args.steps)
     units_per_launch = n_chains * L * L
-    achieved_alu = units_per_launch * BP_ALU_PER_SITE / per_launch_s
-    traffic = read_traffic("k_torus_bp")
+    kernel = "k_tri_bp" if triangular else "k_torus_bp"
+    alu_per_site = TRI_ALU_PER_SITE if triangular else BP_ALU_PER_SITE
+    achieved_alu = units_per_launch * alu_per_site / per_launch_s
+    traffic = read_traffic(kernel)
     roof = {"bound": "alu", "achieved": achieved_alu / 1e12, "peak": VALU_PEAK / 1e12,
             "unit": "T lane-cycles/s", "frac": achieved_alu / VALU_PEAK,
-            "traffic": traffic, "kernel": "k_torus_bp",
+            "traffic": traffic, "kernel": kernel,
             "launch_us": per_launch_s * 1e6,
             "alg_bytes_GBs": units_per_launch * BP_BYTES_PER_SITE / per_launch_s / 1e9,
             "hbm_frac": units_per_launch * BP_BYTES_PER_SITE / per_launch_s / 1e9 / HBM_PEAK_GBS}
     for c in chains:
         c.close()
     batch.close()
-    cfg = {"workload": "4096x4096 bit-packed torus, 24 chains (q x beta x init) batched",
+    lattice = "triangular-lattice torus (section 4)" if triangular else "torus"
+    cfg = {"workload": "4096x4096 bit-packed %s, 24 chains (q x beta x init) batched" % lattice,
            "L": L, "chains": n_chains, "J": 1, "lambda": 0.0, "q": [0.5, 1.0, 2.0],
            "beta": [0.30, 0.40, 0.44, 0.50], "init": ["all_up", "random"],
            "strategy": "grid + hipGraph", "observables": "fused, every full step"}
@@ -404,7 +414,7 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="torus4096",
-                    choices=["torus4096", "graph", "batch", "ea", "copycal"])
+                    choices=["torus4096", "tri4096", "graph", "batch", "ea", "copycal"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -426,6 +436,10 @@ def main():
         value, wall, cfg, roof, dtype = bench_torus4096(args, sk)
         metric = "spin-site updates/s (4096^2 torus, batched)"
         cpu = None if args.no_cpu_baseline else cpu_baseline_torus()
+    elif args.workload == "tri4096":
+        value, wall, cfg, roof, dtype = bench_torus4096(args, sk, triangular=True)
+        metric = "spin-site updates/s (4096^2 triangular-lattice torus, batched)"
+        cpu = None if args.no_cpu_baseline else cpu_baseline_torus(triangular=True)
     elif args.workload == "graph":
         value, wall, cfg, roof, dtype = bench_graph(args, sk)
         metric = "vertex updates/s (3-regular graph, n=2^20)"

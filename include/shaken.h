@@ -72,12 +72,20 @@ typedef enum shaken_status {
 /* ------------------------------------------------------------------ inputs */
 
 typedef enum shaken_graph_kind {
-    SHAKEN_TORUS = 0,   /* L x L periodic square lattice, E^o = up/right edges */
-    SHAKEN_EDGES = 1    /* arbitrary simple graph given as oriented edges      */
+    SHAKEN_TORUS = 0,      /* L x L periodic square lattice, E^o = up/right edges */
+    SHAKEN_EDGES = 1,      /* arbitrary simple graph given as oriented edges      */
+    SHAKEN_TRIANGULAR = 2  /* L x L periodic triangular lattice (section 4)       */
 } shaken_graph_kind;
 
 /* The interaction graph with its orientation (Definition 2.1).
  *   kind == SHAKEN_TORUS: L is the side, 3 <= L <= 32768; n, m, src, dst unused.
+ *   kind == SHAKEN_TRIANGULAR: L as for the torus; the triangular lattice in
+ *     skewed coordinates, site x = (row, col) with the six neighbours x +- e1
+ *     (one column), x +- e2 (one row), x +- (e1 + e2); E^o = {(x, x + e1),
+ *     (x, x + e2), (x, x + e1 + e2)}, so half-step 1 reads the left, down and
+ *     down-left neighbours and half-step 2 the other three.  J: NULL or 3*L*L
+ *     uniform entries (index 3x + k, k = right, up, diagonal).  Same spin
+ *     layouts, randomness and options as the square torus, except +-J.
  *   kind == SHAKEN_EDGES: n vertices (1 <= n < 2^31), m oriented edges; edge e
  *     is (src[e], dst[e]) in E^o, i.e. dst[e] reads src[e] in half-step 1 and
  *     src[e] reads dst[e] in half-step 2.  Host arrays of m int32 each.

@@ -33,7 +33,7 @@ if not os.path.exists(LIB_PATH):
 _lib = ctypes.CDLL(LIB_PATH)
 
 SHAKEN_OK, SHAKEN_EINVAL, SHAKEN_ENOMEM, SHAKEN_EDEVICE, SHAKEN_ESTATE = range(5)
-SHAKEN_TORUS, SHAKEN_EDGES = 0, 1
+SHAKEN_TORUS, SHAKEN_EDGES, SHAKEN_TRIANGULAR = 0, 1, 2
 SHAKEN_FMT_AUTO, SHAKEN_FMT_INT8, SHAKEN_FMT_BITPACKED = 0, 1, 2
 SHAKEN_INIT_RANDOM, SHAKEN_INIT_ALL_UP, SHAKEN_INIT_ALL_DOWN, SHAKEN_INIT_USER = 0, 1, 2, 3
 SHAKEN_BATCH_AUTO, SHAKEN_BATCH_GRID, SHAKEN_BATCH_PERSISTENT = 0, 1, 2
@@ -211,8 +211,8 @@ class Chain:
                  reversed=False, frozen=None):
         g = shaken_graph()
         self._keep = []
-        if kind == "torus":
-            g.kind, g.L = SHAKEN_TORUS, int(L)
+        if kind in ("torus", "triangular"):
+            g.kind, g.L = (SHAKEN_TORUS if kind == "torus" else SHAKEN_TRIANGULAR), int(L)
             self.shape = (int(L), int(L))
             self.n = int(L) * int(L)
         elif kind == "graph":
@@ -224,7 +224,7 @@ class Chain:
             self.shape = (int(n),)
             self.n = int(n)
         else:
-            raise ValueError("kind must be 'torus' or 'graph'")
+            raise ValueError("kind must be 'torus', 'triangular' or 'graph'")
         if kind == "torus" and isinstance(J, tuple):
             # (Jup, Jright), each [L, L]: interleave into the per-edge order
             # of the C ABI (2x = (x, x_up), 2x+1 = (x, x_right))
@@ -269,6 +269,11 @@ class Chain:
     @classmethod
     def torus(cls, L, **kw):
         return cls("torus", L=L, **kw)
+
+    @classmethod
+    def triangular(cls, L, **kw):
+        """L x L triangular-lattice torus (section 4), skewed coordinates"""
+        return cls("triangular", L=L, **kw)
 
     @classmethod
     def graph(cls, n, src, dst, **kw):

@@ -135,6 +135,7 @@ struct shaken_ctx {
     uint64_t *pell_dev = nullptr;
     uint32_t *jneg_dev = nullptr;  // +-J torus sign planes (2 x L x W words)
     uint32_t *frozen_dev = nullptr;  // frozen set B as bits (layout of the bit-packed spins)
+    bool tri = false;                // triangular torus
     std::vector<uint8_t> frozen_host;  // per site, nonzero = frozen
     int ell_k = 0;
     int64_t ell_stride = 0;
@@ -193,10 +194,13 @@ void build_tables(shaken_ctx *c) {
                 c->lut[((size_t)(S + c->smax) * 2 + sb) * ncls + k] = threshold_T(h, c->beta);
             }
     if (c->kind == KIND_TORUS) {
+        // classes j = n_plus + k (own spin +1), k = 3 (square: 2 neighbours per
+        // half) or 4 (triangular: 3 neighbours)
+        const int nb = c->tri ? 3 : 2, ncl = 2 * (nb + 1);
         uint32_t sgn = 0;
-        for (int j = 0; j < 6; ++j) {
-            const int nplus = j % 3, cb = j / 3;
-            const int64_t S = (int64_t)c->J * (2 * nplus - 2);
+        for (int j = 0; j < ncl; ++j) {
+            const int nplus = j % (nb + 1), cb = j / (nb + 1);
+            const int64_t S = (int64_t)c->J * (2 * nplus - nb);
             const double h = field_h(S, cb ? 1 : -1, c->q, c->lam[0]);
             const uint64_t T = threshold_T(h, c->beta);
             const uint64_t t = (h >= 0.0) ? ((uint64_t)1 << 32) - T : T;
@@ -205,7 +209,9 @@ void build_tables(shaken_ctx *c) {
         }
         c->hd.sgn = sgn;
         const uint32_t *t = c->hd.tsmall;
-        c->hd.fold3 = (t[0] == t[5] && t[2] == t[3] && t[1] == t[4]) ? 1 : 0;
+        bool fold = true;
+        for (int j = 0; j < ncl / 2; ++j) fold = fold && t[j] == t[ncl - 1 - j];
+        c->hd.fold3 = fold ? 1 : 0;
     }
 }
 
@@ -435,7 +441,9 @@ shaken_status init_host(shaken_ctx *c, const shaken_graph *g, const int8_t *J,
         else
             c->lam2[k] = (int64_t)v2;
     }
-    if (g->kind == SHAKEN_TORUS) {
+    if (g->kind == SHAKEN_TORUS || g->kind == SHAKEN_TRIANGULAR) {
+        const bool tri = g->kind == SHAKEN_TRIANGULAR;
+        c->tri = tri;
         if (g->L < 3 || g->L > 32768) return fail(SHAKEN_EINVAL, "torus: L must be in [3, 32768]");
         if (o->flags & ~SHAKEN_ORDER_REVERSED)
             return fail(SHAKEN_EINVAL, "SHAKEN_GRAPH_SPLIT applies to graphs only");
@@ -445,9 +453,15 @@ shaken_status init_host(shaken_ctx *c, const shaken_graph *g, const int8_t *J,
         c->L = g->L;
         c->W = (g->L + 31) / 32;
         c->n = g->L * g->L;
-        c->m = 2 * (int64_t)c->n;
+        c->m = (tri ? 3 : 2) * (int64_t)c->n;
         c->J = 1;
-        if (J) {
+        if (J && tri) {
+            for (int64_t e = 1; e < c->m; ++e)
+                if (J[e] != J[0])
+                    return fail(SHAKEN_EINVAL, "triangular torus: the coupling must be uniform "
+                                               "(pass other couplings as SHAKEN_EDGES)");
+            c->J = J[0];
+        } else if (J) {
             // uniform coupling, or +-J (one magnitude, any signs: the
             // Edwards-Anderson couplings of section 6) as two sign planes
             const int mag = std::abs((int)J[0]);
@@ -472,8 +486,8 @@ shaken_status init_host(shaken_ctx *c, const shaken_graph *g, const int8_t *J,
                     }
             }
         }
-        c->smax = 2 * std::abs(c->J);
-        c->maxdeg = 2;
+        c->smax = (tri ? 3 : 2) * std::abs(c->J);
+        c->maxdeg = tri ? 3 : 2;
         if (o->format == SHAKEN_FMT_INT8)
             c->format = FMT_INT8;
         else if (o->format == SHAKEN_FMT_AUTO || o->format == SHAKEN_FMT_BITPACKED)
@@ -619,6 +633,7 @@ shaken_status init_device(shaken_ctx *c, const shaken_opts *o, HostLayout &hl) {
     d.pell = c->pell_dev;
     d.jneg = c->jneg_dev;
     d.rev = (o->flags & SHAKEN_ORDER_REVERSED) ? 1 : 0;
+    d.tri = c->tri ? 1 : 0;
     d.frozen = c->frozen_dev;
     d.log_line = c->line();
     d.log_stride = c->stride();
@@ -939,7 +954,7 @@ int32_t shaken_version(void) { return (SHAKEN_VERSION_MAJOR << 16) | SHAKEN_VERS
 namespace {
 
 struct Group {
-    int kind = 0, format = 0;
+    int kind = 0, format = 0, tri = 0;
     std::vector<int> members;  // indices into the batch's contexts
     std::vector<ChainDesc> hd;
     ChainDesc *dd = nullptr;
@@ -1252,12 +1267,13 @@ shaken_status shaken_batch_create(shaken_batch **out, shaken_ctx *const *ctx, in
         for (int i = 0; i < n; ++i) {
             Group *g = nullptr;
             for (auto &x : b->groups)
-                if (x.kind == ctx[i]->kind && x.format == ctx[i]->format) g = &x;
+                if (x.kind == ctx[i]->kind && x.format == ctx[i]->format && x.tri == (int)ctx[i]->tri) g = &x;
             if (!g) {
                 b->groups.emplace_back();
                 g = &b->groups.back();
                 g->kind = ctx[i]->kind;
                 g->format = ctx[i]->format;
+                g->tri = ctx[i]->tri;
             }
             g->members.push_back(i);
             g->hd.push_back(ctx[i]->hd);

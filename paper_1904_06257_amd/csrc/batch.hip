@@ -58,8 +58,8 @@ struct Obs {
     int plus[kPClasses];
 };
 
-template <bool FOLD3>
-__device__ void torus_lds_half(const ChainDesc &d, const uint32_t *src, uint32_t *dst, uint32_t s,
+template <bool FOLD3, bool TRI, bool EXT>
+__device__ __forceinline__ void torus_lds_half(const ChainDesc &d, const uint32_t *src, uint32_t *dst, uint32_t s,
                                bool obs, int *sh_red, Obs *o) {
     const int L = d.L, W = d.W, nw = L * W;
     const int phase = (int)(s & 1u) ^ d.rev;  // half read: 0 = dl, 1 = ur
@@ -69,30 +69,43 @@ __device__ void torus_lds_half(const ChainDesc &d, const uint32_t *src, uint32_t
         const int r = w / W, wd = w - r * W;
         const uint32_t own = src[w];
         const uint32_t vm = bp_valid(L, W, wd);
-        uint32_t a, b;
+        uint32_t a, b, e = 0;
+        const int lastbits = (L - 1) & 31;
         if (obs || phase == 0) {
-            // down and left neighbours (the in-half)
-            const int lastbits = (L - 1) & 31;
-            a = src[(r == 0 ? L - 1 : r - 1) * W + wd];
+            // down and left neighbours (the in-half); triangular: down-left too
+            const int rd = r == 0 ? L - 1 : r - 1;
+            a = src[rd * W + wd];
             const uint32_t carry = wd > 0 ? (src[r * W + wd - 1] >> 31)
                                           : ((src[r * W + W - 1] >> lastbits) & 1u);
             b = (own << 1) | carry;
-            if (d.jneg) bp_jflip(d.jneg, L, W, r, wd, 0, a, b);
+            if (TRI) {
+                const uint32_t as = wd > 0 ? src[rd * W + wd - 1] : src[rd * W + W - 1];
+                e = (a << 1) | (wd > 0 ? (as >> 31) : ((as >> lastbits) & 1u));
+            }
+            if (EXT && !TRI && d.jneg) bp_jflip(d.jneg, L, W, r, wd, 0, a, b);
             if (obs) {
                 e_acc += d.J * (2 * __popc(vm) - 2 * __popc((own ^ a) & vm) - 2 * __popc((own ^ b) & vm));
+                if (TRI) e_acc += d.J * (__popc(vm) - 2 * __popc((own ^ e) & vm));
                 p_acc += __popc(own & vm);
             }
         }
         if (!dst) continue;
         if (phase == 1) {
-            const int lastbits = (L - 1) & 31;
-            a = src[(r == L - 1 ? 0 : r + 1) * W + wd];
+            const int ru = r == L - 1 ? 0 : r + 1;
+            a = src[ru * W + wd];
             b = wd < W - 1 ? ((own >> 1) | (src[r * W + wd + 1] << 31))
                            : ((own >> 1) | ((src[r * W] & 1u) << lastbits));
-            if (d.jneg) bp_jflip(d.jneg, L, W, r, wd, 1, a, b);
+            if (TRI)
+                e = wd < W - 1 ? ((a >> 1) | (src[ru * W + wd + 1] << 31))
+                               : ((a >> 1) | ((src[ru * W] & 1u) << lastbits));
+            if (EXT && !TRI && d.jneg) bp_jflip(d.jneg, L, W, r, wd, 1, a, b);
         }
-        dst[w] = bp_word<FOLD3>(a, b, own, vm, (uint32_t)w, s, d.replica, k0, k1, d.tsmall, d.sgn) |
-                 frozen_word(d, w);
+        uint32_t nw_bits;
+        if constexpr (TRI)
+            nw_bits = tri_word<FOLD3>(a, b, e, own, vm, (uint32_t)w, s, d.replica, k0, k1, d.tsmall, d.sgn);
+        else
+            nw_bits = bp_word<FOLD3>(a, b, own, vm, (uint32_t)w, s, d.replica, k0, k1, d.tsmall, d.sgn);
+        dst[w] = EXT ? (nw_bits | frozen_word(d, w)) : nw_bits;
     }
     if (obs) {
         block_sum2(e_acc, p_acc, sh_red);
@@ -133,9 +146,35 @@ __device__ void observe_step(const ChainDesc &d, const Obs &o, int64_t *log_slot
     __syncthreads();
 }
 
-template <bool FOLD3>
-__device__ void run_torus(const ChainDesc &d, uint32_t (*buf)[kPWords], uint32_t s0, int64_t n_full,
-                          int record, int track, int *sh_red, int *sh_flag, Obs &o) {
+// A descriptor reference made wave-uniform and constant-addressed.  Inside a
+// called (not inlined) function the compiler cannot see that an argument is
+// the same for every lane; without this it loads every field into vector
+// registers.
+// The builtin returns a signed int: each half goes through uint32_t before it
+// is widened, or the low half would be sign-extended into the high one.
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t x) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)x);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+    return ((uint64_t)hi << 32) | (uint64_t)lo;
+}
+
+__device__ __forceinline__ const ChainDesc &uniform_desc(const ChainDesc &d) {
+    const uint64_t u = uniform_u64(reinterpret_cast<uint64_t>(&d));
+    typedef const __attribute__((address_space(4))) ChainDesc *ConstDescPtr;
+    return *(const ChainDesc *)(ConstDescPtr)u;
+}
+
+__device__ __forceinline__ int64_t uniform_i64(int64_t x) { return (int64_t)uniform_u64((uint64_t)x); }
+
+template <bool FOLD3, bool TRI, bool EXT>
+__device__ __attribute__((noinline)) void run_torus(const ChainDesc &d_arg, uint32_t (*buf)[kPWords], uint32_t s0_arg,
+                                                    int64_t n_full_arg, int record_arg, int track_arg,
+                                                    int *sh_red, int *sh_flag, Obs &o) {
+    const ChainDesc &d = uniform_desc(d_arg);
+    const uint32_t s0 = (uint32_t)__builtin_amdgcn_readfirstlane(s0_arg);
+    const int64_t n_full = uniform_i64(n_full_arg);
+    const int record = __builtin_amdgcn_readfirstlane(record_arg);
+    const int track = __builtin_amdgcn_readfirstlane(track_arg);
     const int nw = d.L * d.W;
     const bool obs = record || track;
     const uint32_t *g = (const uint32_t *)d.spin[0];
@@ -144,16 +183,16 @@ __device__ void run_torus(const ChainDesc &d, uint32_t (*buf)[kPWords], uint32_t
     int64_t best_h = INT64_MAX, last_h = 0;
     for (int64_t t = 0; t < n_full; ++t) {
         const uint32_t s = s0 + 2u * (uint32_t)t;
-        torus_lds_half<FOLD3>(d, buf[0], buf[1], s, obs, sh_red, &o);
+        torus_lds_half<FOLD3, TRI, EXT>(d, buf[0], buf[1], s, obs, sh_red, &o);
         if (obs)
             observe_step(d, o, record ? d.log + t * d.log_stride : nullptr, track, &best_h, &last_h,
                          buf[0], nw, sh_flag);
         __syncthreads();
-        torus_lds_half<FOLD3>(d, buf[1], buf[0], s + 1u, false, sh_red, nullptr);
+        torus_lds_half<FOLD3, TRI, EXT>(d, buf[1], buf[0], s + 1u, false, sh_red, nullptr);
         __syncthreads();
     }
     if (obs) {
-        torus_lds_half<FOLD3>(d, buf[0], nullptr, s0, true, sh_red, &o);
+        torus_lds_half<FOLD3, TRI, EXT>(d, buf[0], nullptr, s0, true, sh_red, &o);
         observe_step(d, o, record ? d.log + n_full * d.log_stride : nullptr, track, &best_h, &last_h,
                      buf[0], nw, sh_flag);
         if (track && threadIdx.x == 0) {
@@ -180,7 +219,7 @@ __device__ __forceinline__ int lds_spin(const uint32_t *bits, int v) {
 enum GraphLayout : int { GL_CSR = 0, GL_ELL = 1, GL_PACKED = 2 };
 
 template <int LAY>
-__device__ void graph_lds_half(const ChainDesc &d, const uint32_t *src, uint32_t *dst, uint32_t s,
+__device__ __forceinline__ void graph_lds_half(const ChainDesc &d, const uint32_t *src, uint32_t *dst, uint32_t s,
                                bool obs, int *sh_red, int *sh_plus, Obs *o, const uint64_t *lut) {
     const int n = d.n;
     const int half = dst ? ((int)(s & 1u) ^ d.rev) : 0;  // observables use the in-half
@@ -332,9 +371,15 @@ __device__ void graph_lds_half(const ChainDesc &d, const uint32_t *src, uint32_t
 }
 
 template <int LAY>
-__device__ void run_graph(const ChainDesc &d, uint32_t (*buf)[kPWords], uint32_t s0, int64_t n_full,
-                          int record, int track, int *sh_red, int *sh_plus, int *sh_flag,
-                          uint64_t *sh_lut, Obs &o) {
+__device__ __attribute__((noinline)) void run_graph(const ChainDesc &d_arg, uint32_t (*buf)[kPWords], uint32_t s0_arg,
+                                                    int64_t n_full_arg, int record_arg, int track_arg,
+                                                    int *sh_red, int *sh_plus, int *sh_flag,
+                                                    uint64_t *sh_lut, Obs &o) {
+    const ChainDesc &d = uniform_desc(d_arg);
+    const uint32_t s0 = (uint32_t)__builtin_amdgcn_readfirstlane(s0_arg);
+    const int64_t n_full = uniform_i64(n_full_arg);
+    const int record = __builtin_amdgcn_readfirstlane(record_arg);
+    const int track = __builtin_amdgcn_readfirstlane(track_arg);
     const int n = d.n, nw = (n + 31) / 32;
     const bool obs = record || track;
     // the chain's threshold table in LDS when it fits (constant during the call)
@@ -422,10 +467,23 @@ __global__ __launch_bounds__(kPBlock, SHAKEN_PWAVES) void k_persistent(const Cha
         if (item < 0) break;  // queue drained: every wave of the block leaves
         const ChainDesc &d = descs[item];
         if (d.kind == KIND_TORUS) {
-            if (d.fold3)
-                run_torus<true>(d, buf, s0, n_full, record, track, sh_red, &sh_flag, sh_obs);
-            else
-                run_torus<false>(d, buf, s0, n_full, record, track, sh_red, &sh_flag, sh_obs);
+            // the plain square torus reads neither coupling-sign nor frozen planes
+            const bool ext = d.jneg || d.frozen;
+            if (d.tri) {
+                if (d.fold3)
+                    run_torus<true, true, true>(d, buf, s0, n_full, record, track, sh_red, &sh_flag, sh_obs);
+                else
+                    run_torus<false, true, true>(d, buf, s0, n_full, record, track, sh_red, &sh_flag, sh_obs);
+            } else if (ext) {
+                if (d.fold3)
+                    run_torus<true, false, true>(d, buf, s0, n_full, record, track, sh_red, &sh_flag, sh_obs);
+                else
+                    run_torus<false, false, true>(d, buf, s0, n_full, record, track, sh_red, &sh_flag, sh_obs);
+            } else if (d.fold3) {
+                run_torus<true, false, false>(d, buf, s0, n_full, record, track, sh_red, &sh_flag, sh_obs);
+            } else {
+                run_torus<false, false, false>(d, buf, s0, n_full, record, track, sh_red, &sh_flag, sh_obs);
+            }
         } else {
             if (d.pell)
                 run_graph<GL_PACKED>(d, buf, s0, n_full, record, track, sh_red, sh_plus, &sh_flag, sh_lut, sh_obs);

@@ -161,6 +161,95 @@ __device__ __forceinline__ uint32_t bp_word(uint32_t a, uint32_t b, uint32_t c, 
     return (res ^ p.smask) & vm;
 }
 
+// ------------------------------------------ bit-packed triangular lattice
+// Three neighbour planes a, b, e per half (section 4: three "left"
+// neighbours in half-step 1, three "right" ones in half-step 2); a site
+// belongs to class j = n_plus + 4c (n_plus = number of +1 neighbours, c =
+// the site), eight classes.  s1 = a ^ b ^ e (n_plus odd) and s2 = maj(a, b, e)
+// (n_plus >= 2) code n_plus = s1 + 2 s2.  When the thresholds depend on |h|
+// only (lambda = 0), classes (n, c) and (3 - n, 1 - c) share one: the class is
+// then the number k of neighbours that agree with the site, coded the same
+// way by k1, k2 over the agreement planes.
+struct TriPlanes {
+    uint32_t s1, s2, c, smask;
+};
+
+__device__ __forceinline__ uint32_t maj3(uint32_t a, uint32_t b, uint32_t e) {
+    return (a & b) | (a & e) | (b & e);
+}
+
+__device__ __forceinline__ TriPlanes tri_planes(uint32_t a, uint32_t b, uint32_t e, uint32_t c,
+                                                uint32_t sgn, bool fold) {
+    TriPlanes p;
+    p.c = c;
+    const uint32_t n1 = a ^ b ^ e, n2 = maj3(a, b, e);
+    const uint32_t slo = bfi(n2, bfi(n1, bitmask(sgn, 3), bitmask(sgn, 2)),
+                             bfi(n1, bitmask(sgn, 1), bitmask(sgn, 0)));
+    const uint32_t shi = bfi(n2, bfi(n1, bitmask(sgn, 7), bitmask(sgn, 6)),
+                             bfi(n1, bitmask(sgn, 5), bitmask(sgn, 4)));
+    p.smask = bfi(c, shi, slo);
+    if (fold) {
+        // agreement planes: k = n_plus where the site is +1, 3 - n_plus where -1
+        const uint32_t xa = ~(a ^ c), xb = ~(b ^ c), xe = ~(e ^ c);
+        p.s1 = xa ^ xb ^ xe;
+        p.s2 = maj3(xa, xb, xe);
+    } else {
+        p.s1 = n1;
+        p.s2 = n2;
+    }
+    return p;
+}
+
+// MSB-first compare of the 32 bit-sliced uniforms with the eight (or, folded,
+// four) class thresholds, level groups [G0, G1); same contract as bp_groups.
+template <bool FOLD, int G0, int G1>
+__device__ __forceinline__ void tri_groups(const TriPlanes &p, uint32_t &und, uint32_t &res,
+                                           uint32_t w, uint32_t s, uint32_t rep, uint32_t k0,
+                                           uint32_t k1, const uint32_t *__restrict__ ts) {
+    const uint32_t t0 = ts[0], t1 = ts[1], t2 = ts[2], t3 = ts[3];
+    const uint32_t t4 = ts[4], t5 = ts[5], t6 = ts[6], t7 = ts[7];
+#define SHAKEN_TLEVEL(K, R)                                                                       \
+    {                                                                                             \
+        const int sh_ = 31 - (K);                                                                 \
+        uint32_t t_;                                                                              \
+        if (FOLD) {                                                                               \
+            t_ = bfi(p.s2, bfi(p.s1, bitmask(t7, sh_), bitmask(t6, sh_)),                         \
+                     bfi(p.s1, bitmask(t5, sh_), bitmask(t4, sh_)));                              \
+        } else {                                                                                  \
+            const uint32_t lo_ = bfi(p.s2, bfi(p.s1, bitmask(t3, sh_), bitmask(t2, sh_)),         \
+                                     bfi(p.s1, bitmask(t1, sh_), bitmask(t0, sh_)));              \
+            const uint32_t hi_ = bfi(p.s2, bfi(p.s1, bitmask(t7, sh_), bitmask(t6, sh_)),         \
+                                     bfi(p.s1, bitmask(t5, sh_), bitmask(t4, sh_)));              \
+            t_ = bfi(p.c, hi_, lo_);                                                              \
+        }                                                                                         \
+        const uint32_t d_ = (R) ^ p.smask ^ t_;                                                   \
+        res |= und & d_ & t_;                                                                     \
+        und &= ~d_;                                                                               \
+    }
+#pragma unroll
+    for (int g = G0; g < G1; ++g) {
+        const U4 r = philox10(w, s, rep, (uint32_t)g, k0, k1);
+        SHAKEN_TLEVEL(4 * g + 0, r.x)
+        SHAKEN_TLEVEL(4 * g + 1, r.y)
+        SHAKEN_TLEVEL(4 * g + 2, r.z)
+        SHAKEN_TLEVEL(4 * g + 3, r.w)
+        if (und == 0) break;
+    }
+#undef SHAKEN_TLEVEL
+}
+
+// new word of 32 triangular-lattice sites (neighbour planes a, b, e)
+template <bool FOLD>
+__device__ __forceinline__ uint32_t tri_word(uint32_t a, uint32_t b, uint32_t e, uint32_t c,
+                                             uint32_t vm, uint32_t w, uint32_t s, uint32_t rep,
+                                             uint32_t k0, uint32_t k1,
+                                             const uint32_t *__restrict__ ts, uint32_t sgn) {
+    const TriPlanes p = tri_planes(a, b, e, c, sgn, FOLD);
+    uint32_t und = vm, res = 0;
+    tri_groups<FOLD, 0, 8>(p, und, res, w, s, rep, k0, k1, ts);
+    return (res ^ p.smask) & vm;
+}
+
 // +-J torus: flip the neighbour planes a (vertical) and b (horizontal) of
 // word (r, wd) where the coupling of the edge to that neighbour is negative.
 // dl (phase 0): the edges come from the row below, (x_down, x), and from the

@@ -196,6 +196,129 @@ __global__ __launch_bounds__(256) void k_torus_bp(const ChainDesc *__restrict__ 
         block_accumulate2(e_acc, p_acc, log_part(d, slot, bx));
 }
 
+// ------------------------------------------------ triangular bit-packed torus
+// Same strip structure and tail queue as k_torus_bp; the third neighbour plane
+// e is the vertical neighbour row shifted like b (dl: the down-left
+// neighbours, the row below shifted left with the carry of its left word; ur:
+// the up-right neighbours, the row above shifted right with the carry of its
+// right word).
+
+template <bool FOLD>
+__device__ __noinline__ uint32_t tri_finish(uint32_t a, uint32_t b, uint32_t e, uint32_t c,
+                                            uint32_t und, uint32_t res, uint32_t vm, uint32_t w,
+                                            uint32_t s, uint32_t rep, uint32_t k0, uint32_t k1,
+                                            const uint32_t *__restrict__ ts, uint32_t sgn) {
+    const TriPlanes p = tri_planes(a, b, e, c, sgn, FOLD);
+    tri_groups<FOLD, 2, 8>(p, und, res, w, s, rep, k0, k1, ts);
+    return (res ^ p.smask) & vm;
+}
+
+template <bool OBS, bool FOLD>
+__global__ __launch_bounds__(256) void k_tri_bp(const ChainDesc *__restrict__ descs, StepArgs sa) {
+    __shared__ uint32_t q_w[kQCap], q_a[kQCap], q_b[kQCap], q_e[kQCap], q_c[kQCap], q_und[kQCap],
+        q_res[kQCap];
+    __shared__ int q_n;
+    const ChainDesc &d = descs[blockIdx.y];
+    const uint32_t s = step_s(sa);
+    const int bufp = (int)(s & 1u);
+    const int phase = bufp ^ d.rev;
+    const int slot = OBS ? step_slot(sa, s) : 0;
+    const int L = d.L, W = d.W;
+    const int nrb = (L + kRows - 1) / kRows;
+    const int total = nrb * W;
+    const int bx = xcd_block(blockIdx.x, gridDim.x);
+    const int gid = bx * blockDim.x + threadIdx.x;
+    const uint32_t *__restrict__ in = (const uint32_t *)d.spin[bufp];
+    uint32_t *__restrict__ out = (uint32_t *)d.spin[bufp ^ 1];
+    const uint32_t k0 = (uint32_t)d.seed, k1 = (uint32_t)(d.seed >> 32);
+    const uint32_t rep = d.replica, sgn = d.sgn;
+    const uint32_t *ts = d.tsmall;
+    const int lane = threadIdx.x & 63;
+    if (threadIdx.x == 0) q_n = 0;
+    __syncthreads();
+    int e_acc = 0, p_acc = 0;
+    const bool live = gid < total;
+    const int rb = live ? gid / W : 0, wd = live ? gid - rb * W : 0;
+    const int r0 = rb * kRows;
+    const int nr = live ? min(kRows, L - r0) : 0;
+    const uint32_t vm = bp_valid(L, W, wd);
+    const int lastbits = (L - 1) & 31;
+    const int wside = phase == 0 ? (wd > 0 ? wd - 1 : W - 1) : (wd < W - 1 ? wd + 1 : 0);
+    uint32_t own[kRows], side[kRows];
+#pragma unroll
+    for (int i = 0; i < kRows; ++i) {
+        own[i] = i < nr ? in[(r0 + i) * W + wd] : 0u;
+        side[i] = i < nr ? in[(r0 + i) * W + wside] : 0u;
+    }
+    uint32_t halo = 0, halo_side = 0;
+    if (live) {
+        const int rh = phase == 0 ? (r0 == 0 ? L - 1 : r0 - 1) : (r0 + nr == L ? 0 : r0 + nr);
+        halo = in[rh * W + wd];
+        halo_side = in[rh * W + wside];
+    }
+#pragma unroll
+    for (int i = 0; i < kRows; ++i) {
+        const bool act = i < nr;
+        uint32_t a = 0, b = 0, e = 0, und = 0, res = 0;
+        TriPlanes p;
+        const int widx = (r0 + i) * W + wd;
+        if (act) {
+            if (phase == 0) {
+                a = (i == 0) ? halo : own[i > 0 ? i - 1 : 0];
+                const uint32_t as = (i == 0) ? halo_side : side[i > 0 ? i - 1 : 0];
+                b = (own[i] << 1) | (wd > 0 ? (side[i] >> 31) : ((side[i] >> lastbits) & 1u));
+                e = (a << 1) | (wd > 0 ? (as >> 31) : ((as >> lastbits) & 1u));
+            } else {
+                a = (i == nr - 1) ? halo : own[i < kRows - 1 ? i + 1 : 0];
+                const uint32_t as = (i == nr - 1) ? halo_side : side[i < kRows - 1 ? i + 1 : 0];
+                b = wd < W - 1 ? ((own[i] >> 1) | (side[i] << 31))
+                               : ((own[i] >> 1) | ((side[i] & 1u) << lastbits));
+                e = wd < W - 1 ? ((a >> 1) | (as << 31)) : ((a >> 1) | ((as & 1u) << lastbits));
+            }
+            p = tri_planes(a, b, e, own[i], sgn, FOLD);
+            und = vm;
+            tri_groups<FOLD, 0, 2>(p, und, res, (uint32_t)widx, s, rep, k0, k1, ts);
+            if (OBS) {
+                e_acc += d.J * (3 * __popc(vm) - 2 * __popc((own[i] ^ a) & vm) -
+                                2 * __popc((own[i] ^ b) & vm) - 2 * __popc((own[i] ^ e) & vm));
+                p_acc += __popc(own[i] & vm);
+            }
+        }
+        const bool pend = act && und != 0;
+        const unsigned long long bal = __ballot(pend);
+        int base = 0;
+        if (lane == 0 && bal) base = atomicAdd(&q_n, (int)__popcll(bal));
+        base = __shfl(base, 0, 64);
+        if (act) {
+            const int q = base + (int)__popcll(bal & ((1ull << lane) - 1ull));
+            if (!pend) {
+                out[widx] = ((res ^ p.smask) & vm) | frozen_word(d, widx);
+            } else if (q < kQCap) {
+                q_w[q] = (uint32_t)widx;
+                q_a[q] = a;
+                q_b[q] = b;
+                q_e[q] = e;
+                q_c[q] = own[i];
+                q_und[q] = und;
+                q_res[q] = res;
+            } else {
+                out[widx] = tri_finish<FOLD>(a, b, e, own[i], und, res, vm, (uint32_t)widx, s, rep, k0, k1,
+                                             ts, sgn) | frozen_word(d, widx);
+            }
+        }
+    }
+    __syncthreads();
+    const int Q = min(q_n, kQCap);
+    for (int it = threadIdx.x; it < Q; it += blockDim.x) {
+        const uint32_t w = q_w[it];
+        const uint32_t vw = bp_valid(L, W, (int)(w % (uint32_t)W));
+        out[w] = tri_finish<FOLD>(q_a[it], q_b[it], q_e[it], q_c[it], q_und[it], q_res[it], vw, w, s, rep,
+                                  k0, k1, ts, sgn) | frozen_word(d, (int)w);
+    }
+    if (OBS && bx * (int)blockDim.x < total)
+        block_accumulate2(e_acc, p_acc, log_part(d, slot, bx));
+}
+
 // ------------------------------------------------------------- int8 torus
 
 // u < T for the bit-sliced uniform of bit b of RNG word w, decided from the
@@ -231,17 +354,20 @@ __global__ __launch_bounds__(256) void k_torus_i8(const ChainDesc *__restrict__ 
     int e_acc = 0, p_acc = 0;
     if (gid < n) {
         const int r = gid / L, c = gid - r * L;
-        int n1, n2;
+        int n1, n2, n3 = 0;
         if (((s & 1u) ^ (uint32_t)d.rev) == 0) {
             const int rd = r == 0 ? L - 1 : r - 1, cl = c == 0 ? L - 1 : c - 1;
             n1 = in[rd * L + c] * torus_jsign(d.jneg, L, d.W, 0, rd, c);
             n2 = in[r * L + cl] * torus_jsign(d.jneg, L, d.W, 1, r, cl);
+            if (d.tri) n3 = in[rd * L + cl];   // down-left (triangular lattice)
         } else {
-            n1 = in[(r == L - 1 ? 0 : r + 1) * L + c] * torus_jsign(d.jneg, L, d.W, 0, r, c);
-            n2 = in[r * L + (c == L - 1 ? 0 : c + 1)] * torus_jsign(d.jneg, L, d.W, 1, r, c);
+            const int ru = r == L - 1 ? 0 : r + 1, cr = c == L - 1 ? 0 : c + 1;
+            n1 = in[ru * L + c] * torus_jsign(d.jneg, L, d.W, 0, r, c);
+            n2 = in[r * L + cr] * torus_jsign(d.jneg, L, d.W, 1, r, c);
+            if (d.tri) n3 = in[ru * L + cr];   // up-right
         }
         const int own = in[gid];
-        const int S = d.J * (n1 + n2);
+        const int S = d.J * (n1 + n2 + n3);
         const uint64_t T = d.lut[((S + d.smax) * 2 + (own > 0)) * d.ncls];
         const uint32_t w = (uint32_t)(r * d.W + (c >> 5));
         const bool up = sliced_less(T, w, c & 31, s, d.replica, (uint32_t)d.seed,
@@ -562,6 +688,13 @@ __global__ __launch_bounds__(256) void k_observe(const ChainDesc *__restrict__ d
             if (d.jneg) bp_jflip(d.jneg, d.L, d.W, r, wd, 0, a, b);
             const uint32_t vm = bp_valid(d.L, d.W, wd);
             e_acc = d.J * (2 * __popc(vm) - 2 * __popc((own ^ a) & vm) - 2 * __popc((own ^ b) & vm));
+            if (d.tri) {
+                // down-left neighbours: the row below shifted like b
+                const int L = d.L, W = d.W, rd = r == 0 ? L - 1 : r - 1;
+                const uint32_t as = wd > 0 ? sp[rd * W + wd - 1] : sp[rd * W + W - 1];
+                const uint32_t e = (a << 1) | (wd > 0 ? (as >> 31) : ((as >> ((L - 1) & 31)) & 1u));
+                e_acc += d.J * (__popc(vm) - 2 * __popc((own ^ e) & vm));
+            }
             p_acc = __popc(own & vm);
         }
         if (active_block) block_accumulate2(e_acc, p_acc, lg);
@@ -575,7 +708,8 @@ __global__ __launch_bounds__(256) void k_observe(const ChainDesc *__restrict__ d
             const int own = sp[gid];
             const int rd = r == 0 ? L - 1 : r - 1, cl = c == 0 ? L - 1 : c - 1;
             e_acc = d.J * own * (sp[rd * L + c] * torus_jsign(d.jneg, L, d.W, 0, rd, c) +
-                                 sp[r * L + cl] * torus_jsign(d.jneg, L, d.W, 1, r, cl));
+                                 sp[r * L + cl] * torus_jsign(d.jneg, L, d.W, 1, r, cl) +
+                                 (d.tri ? sp[rd * L + cl] : 0));
             p_acc = own > 0;
         }
         if (active_block) block_accumulate2(e_acc, p_acc, lg);
@@ -711,7 +845,13 @@ hipError_t launch_half_step_grid(const ChainDesc *dev_descs, const ChainDesc *ho
     const StepArgs sa{dstate, s_add, s_log0, log_on};
     const int b = block > 0 ? block : 256;
     const dim3 grid((maxu + b - 1) / b, nchains);
-    if (h0.kind == KIND_TORUS && h0.format == FMT_BITPACKED) {
+    if (h0.kind == KIND_TORUS && h0.format == FMT_BITPACKED && h0.tri) {
+        // the runtime groups triangular tori apart from square ones
+        if (obs) { if (fold) hipLaunchKernelGGL((k_tri_bp<true, true>), grid, dim3(b), 0, stream, dev_descs, sa);
+                   else hipLaunchKernelGGL((k_tri_bp<true, false>), grid, dim3(b), 0, stream, dev_descs, sa); }
+        else { if (fold) hipLaunchKernelGGL((k_tri_bp<false, true>), grid, dim3(b), 0, stream, dev_descs, sa);
+               else hipLaunchKernelGGL((k_tri_bp<false, false>), grid, dim3(b), 0, stream, dev_descs, sa); }
+    } else if (h0.kind == KIND_TORUS && h0.format == FMT_BITPACKED) {
 #define SHAKEN_BP(O, F, JP) hipLaunchKernelGGL((k_torus_bp<O, F, JP>), grid, dim3(b), 0, stream, dev_descs, sa)
         if (jpl) {
             // +-J sign planes or frozen sets (chains without them in the same

@@ -29,9 +29,12 @@ struct ChainDesc {
     int32_t n;        // sites (L*L or graph vertices)
     void *spin[2];    // spin[0] holds the configuration read at even offsets
     // bit-packed torus: classes j = (#plus neighbours in the half) + 3*(own spin is +1)
-    uint32_t tsmall[6];  // t of the class: floor(p_small * 2^32), p_small = min(p, 1-p)
+    // triangular torus: j = n_plus + 4*(own spin is +1), eight classes
+    uint32_t tsmall[8];  // t of the class: floor(p_small * 2^32), p_small = min(p, 1-p)
     uint32_t sgn;        // bit j: field of class j is >= 0
-    int32_t fold3;       // tsmall depends on |h| only (3 classes after sign folding)
+    int32_t fold3;       // tsmall depends on |h| only (3 classes after sign folding;
+                         // 4 on the triangular torus)
+    int32_t tri;         // triangular torus (section 4): third oriented edge (x, x + e1 + e2)
     int32_t J;           // uniform torus coupling
     // generic threshold table (int8 torus, graph): ((S+smax)*2 + (sigma>0))*ncls + cls
     const uint64_t *lut;

@@ -65,11 +65,16 @@ def test_order_on_both_sides_of_the_critical_curve():
         cases.append(("tri", q, 1.15 * bc, "all_up", True))
         cases.append(("tri", q, 0.85 * bc, "random", False))
     cases.append(("square", 8.0, 1.15 * beta_c(8.0), "all_up", False))
+    # the same lattice through the dedicated bit-packed triangular kernel
+    cases.append(("tri-torus", 1.0, 1.15 * beta_c(1.0), "all_up", True))
+    cases.append(("tri-torus", 8.0, 0.85 * beta_c(8.0), "random", False))
     chains = []
     for i, (kind, q, b, init, _) in enumerate(cases):
         if kind == "tri":
             chains.append(sk.Chain.graph(L * L, src, dst, q=q, beta=b, seed=40 + i, replica=i, init=init,
                                          fmt="bitpacked"))
+        elif kind == "tri-torus":
+            chains.append(sk.Chain.triangular(L, q=q, beta=b, seed=40 + i, replica=i, init=init))
         else:
             chains.append(sk.Chain.torus(L, q=q, beta=b, seed=40 + i, replica=i, init=init))
     bt = sk.Batch(chains, strategy="persistent", record=True)
@@ -82,7 +87,7 @@ def test_order_on_both_sides_of_the_critical_curve():
             assert mag > 0.6
         else:
             assert mag < 0.15
-        if kind == "tri" and q == 1.0 and ordered:
+        if kind.startswith("tri") and q == 1.0 and ordered:
             # q = J: the pair lattice is the square lattice with coupling J and
             # sigma lives on one of its sublattices, so |m| is Yang's value
             yang = (1 - np.sinh(2 * b) ** -4) ** 0.125
