@@ -273,10 +273,7 @@ shaken_status shaken_synchronize(shaken_ctx *ctx);
  *                            keeps their spins in LDS for all the steps.  Tori
  *                            need the bit-packed format and L <= 256; graphs
  *                            n <= 65536 and at most 16 field classes.
- *   SHAKEN_BATCH_AUTO:       persistent when every chain fits and the batch
- *                            holds a graph (or asks for tracking), else grid
- *                            (batches of tori run faster on the grid
- *                            kernels). */
+ *   SHAKEN_BATCH_AUTO:       persistent when every chain fits, else grid. */
 enum { SHAKEN_BATCH_AUTO = 0, SHAKEN_BATCH_GRID = 1, SHAKEN_BATCH_PERSISTENT = 2 };
 
 typedef struct shaken_batch_opts {
@@ -316,6 +313,23 @@ shaken_status shaken_batch_sweep(shaken_batch *b, int64_t n_full);
  * integer 2*lambda for H).  cap = capacity of H_out / M_out in entries. */
 shaken_status shaken_batch_get_log(shaken_batch *b, int32_t i, int64_t *H_out, int64_t *M_out,
                                    int64_t cap);
+
+/* Same log with the coupling energy E_J(sigma_t) = sum over the undirected
+ * edges of J_xy sigma_x sigma_y (equation ham1 without the field term) in
+ * place of H: exact for any lambda.  EJ_out must be non-NULL, M_out may be
+ * NULL; cap as above.  This is what the metastability runs of section 3.2
+ * read (lambda = 0.15 there, so H is not an integer). */
+shaken_status shaken_batch_get_log_ej(shaken_batch *b, int32_t i, int64_t *EJ_out, int64_t *M_out,
+                                      int64_t cap);
+
+/* Every chain's log of the last sweep at once, read from the device with one
+ * copy: row i (chain i in batch order) of each non-NULL output, row-major
+ * [n_chains][cap], receives that chain's n_full+1 entries of H (integer
+ * 2*lambda on every chain required), M and E_J.  SHAKEN_EINVAL if every
+ * output is NULL or cap < n_full+1; SHAKEN_ESTATE without a recorded sweep.
+ * Host memory: one temporary copy of the call's log space. */
+shaken_status shaken_batch_get_logs(shaken_batch *b, int64_t *H_out, int64_t *M_out, int64_t *EJ_out,
+                                    int64_t cap);
 
 /* Set beta[i] and q[i] (host arrays, one per chain) for the following sweeps
  * of the batch: the thresholds are rebuilt on the host in double exactly as

@@ -105,6 +105,8 @@ _SIGS = {
                             ctypes.POINTER(shaken_batch_opts)],
     "shaken_batch_sweep": [_vp, ctypes.c_int64],
     "shaken_batch_get_log": [_vp, ctypes.c_int32, _i64p, _i64p, ctypes.c_int64],
+    "shaken_batch_get_log_ej": [_vp, ctypes.c_int32, _i64p, _i64p, ctypes.c_int64],
+    "shaken_batch_get_logs": [_vp, _i64p, _i64p, _i64p, ctypes.c_int64],
     "shaken_batch_info": [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)],
     "shaken_batch_free": [_vp],
     "shaken_batch_run": [ctypes.POINTER(_vp), ctypes.c_int32, ctypes.c_int64,
@@ -231,7 +233,13 @@ class Chain:
             ju = np.asarray(J[0], dtype=np.int8).reshape(-1)
             jr = np.asarray(J[1], dtype=np.int8).reshape(-1)
             J = np.stack([ju, jr], axis=1).reshape(-1)
-        Jarr = None if J is None else np.ascontiguousarray(J, dtype=np.int8)
+        # one coupling per oriented edge: 2 L^2 (torus), 3 L^2 (triangular), m (graph)
+        n_edges = {"torus": 2 * self.n, "triangular": 3 * self.n}.get(kind, g.m)
+        if J is not None and np.ndim(J) == 0:
+            J = np.full(n_edges, int(J), dtype=np.int8)
+        Jarr = None if J is None else np.ascontiguousarray(J, dtype=np.int8).reshape(-1)
+        if Jarr is not None and Jarr.shape[0] != n_edges:
+            raise ValueError("J needs one coupling per oriented edge (%d), got %d" % (n_edges, Jarr.shape[0]))
         field = None
         if lam_values is not None:
             lv = np.ascontiguousarray(np.atleast_1d(lam_values), dtype=np.float64)
@@ -377,6 +385,27 @@ class Batch:
         _check(_lib.shaken_batch_get_log(self.handle, int(i), _ptr(H, ctypes.c_int64),
                                          _ptr(M, ctypes.c_int64), n))
         return H, M
+
+    def logs(self, with_H=False, with_EJ=True):
+        """(H, M, E_J) of every chain, each [n_chains, n_full + 1] (None where
+        not asked for), read with one device copy"""
+        n = self._last + 1
+        R = len(self.chains)
+        H = np.zeros((R, n), dtype=np.int64) if with_H else None
+        M = np.zeros((R, n), dtype=np.int64)
+        EJ = np.zeros((R, n), dtype=np.int64) if with_EJ else None
+        _check(_lib.shaken_batch_get_logs(self.handle, _ptr(H, ctypes.c_int64), _ptr(M, ctypes.c_int64),
+                                          _ptr(EJ, ctypes.c_int64), n))
+        return H, M, EJ
+
+    def log_ej(self, i):
+        """(E_J, M) logs of chain i: the coupling energy, exact for any lambda"""
+        n = self._last + 1
+        EJ = np.zeros(n, dtype=np.int64)
+        M = np.zeros(n, dtype=np.int64)
+        _check(_lib.shaken_batch_get_log_ej(self.handle, int(i), _ptr(EJ, ctypes.c_int64),
+                                            _ptr(M, ctypes.c_int64), n))
+        return EJ, M
 
     def set_params(self, beta, q):
         b = np.ascontiguousarray(beta, dtype=np.float64)

@@ -276,9 +276,11 @@ void spin_rows(const shaken_ctx *c, int &rows, int &cols, int &W) {
 // Convert a device log (slots x stride) to H and M per slot.
 // raw holds `parts` partial lines per slot (kLogParts for the grid kernels, 1
 // for the persistent kernel, which owns a chain's whole slot).
+// raw: slots x parts lines of `ln` int64 (ln = 0: the context's line width)
 void convert_log(const shaken_ctx *c, const std::vector<int64_t> &raw, int64_t slots, int parts,
-                 int64_t *H, int64_t *M) {
-    const int64_t ln = c->line(), st = parts * ln;
+                 int64_t *H, int64_t *M, int64_t *EJ_out = nullptr, int64_t ln = 0) {
+    if (ln == 0) ln = c->line();
+    const int64_t st = parts * ln;
     auto val = [&](int64_t t, int64_t v) {
         int64_t a = 0;
         for (int p = 0; p < parts; ++p) a += raw[t * st + p * ln + v];
@@ -294,6 +296,7 @@ void convert_log(const shaken_ctx *c, const std::vector<int64_t> &raw, int64_t s
         }
         if (H) H[t] = -EJ - l2;
         if (M) M[t] = m;
+        if (EJ_out) EJ_out[t] = EJ;
     }
 }
 
@@ -1215,18 +1218,14 @@ shaken_status shaken_batch_create(shaken_batch **out, shaken_ctx *const *ctx, in
         if (hipStreamSynchronize(ctx[i]->stream) != hipSuccess) return bail(fail(SHAKEN_EDEVICE, "stream sync failed"));
     if (hipEventCreate(&b->ev0) != hipSuccess || hipEventCreate(&b->ev1) != hipSuccess)
         return bail(fail(SHAKEN_EDEVICE, "hipEventCreate failed"));
-    bool all_fit = true, any_graph = false;
-    for (int i = 0; i < n; ++i) {
-        all_fit = all_fit && persistent_fits(ctx[i]->hd);
-        any_graph = any_graph || ctx[i]->kind == KIND_GRAPH;
-    }
+    bool all_fit = true;
+    for (int i = 0; i < n; ++i) all_fit = all_fit && persistent_fits(ctx[i]->hd);
     int strat = o.strategy;
-    // AUTO: graphs gain most from LDS-resident spins (measured 4.6x over the
-    // grid kernels on 1024 graphs of 1K-64K vertices); batches of tori only
-    // run faster on the grid kernels (tail compaction, 8-row strips: 1.2-2.4x
-    // on 16^2..256^2 tori); tracking exists on the persistent path only.
-    if (strat == SHAKEN_BATCH_AUTO)
-        strat = all_fit && (any_graph || o.track) ? SHAKEN_BATCH_PERSISTENT : SHAKEN_BATCH_GRID;
+    // AUTO: LDS-resident spins win wherever every chain fits (measured 4.6x
+    // over the grid kernels on 1024 graphs of 1K-64K vertices, 1.2-1.9x on
+    // batches of 32^2..256^2 square, +-J and triangular tori); larger tori
+    // run on the grid kernels.
+    if (strat == SHAKEN_BATCH_AUTO) strat = all_fit ? SHAKEN_BATCH_PERSISTENT : SHAKEN_BATCH_GRID;
     if (strat == SHAKEN_BATCH_PERSISTENT && !all_fit)
         return bail(fail(SHAKEN_EINVAL, "a chain does not fit the persistent strategy"));
     if (b->track && strat != SHAKEN_BATCH_PERSISTENT)
@@ -1362,8 +1361,10 @@ shaken_status shaken_batch_sweep(shaken_batch *b, int64_t n_full) {
     return SHAKEN_OK;
 }
 
-shaken_status shaken_batch_get_log(shaken_batch *b, int32_t i, int64_t *H_out, int64_t *M_out,
-                                   int64_t cap) {
+namespace {
+
+shaken_status batch_read_log(shaken_batch *b, int32_t i, int64_t *H_out, int64_t *M_out, int64_t *EJ_out,
+                             int64_t cap) {
     if (!b || i < 0 || i >= (int32_t)b->ctx.size()) return fail(SHAKEN_EINVAL, "bad batch or index");
     if (!b->record || b->last_n_full < 0) return fail(SHAKEN_ESTATE, "no recorded sweep");
     shaken_ctx *c = b->ctx[i];
@@ -1371,12 +1372,55 @@ shaken_status shaken_batch_get_log(shaken_batch *b, int32_t i, int64_t *H_out, i
     const int64_t slots = b->last_n_full + 1;
     if (cap < slots) return fail(SHAKEN_EINVAL, "capacity too small");
     DeviceGuard guard(b->device);
-    const int64_t width = b->log_parts * c->line();
+    // one line per slot (persistent): only its used values cross the bus
+    const int64_t ln = b->log_parts == 1 ? c->nvals() : c->line();
+    const int64_t width = b->log_parts == 1 ? ln : b->log_parts * c->line();
     std::vector<int64_t> raw((size_t)(slots * width));
     HIPCHK(hipMemcpy2DAsync(raw.data(), (size_t)width * 8, b->log_pool + b->log_off[i], (size_t)b->log_row * 8,
                             (size_t)width * 8, (size_t)slots, hipMemcpyDeviceToHost, b->stream));
     HIPCHK(hipStreamSynchronize(b->stream));
-    convert_log(c, raw, slots, b->log_parts, H_out, M_out);
+    convert_log(c, raw, slots, b->log_parts, H_out, M_out, EJ_out, ln);
+    return SHAKEN_OK;
+}
+
+}  // namespace
+
+shaken_status shaken_batch_get_log(shaken_batch *b, int32_t i, int64_t *H_out, int64_t *M_out,
+                                   int64_t cap) {
+    return batch_read_log(b, i, H_out, M_out, nullptr, cap);
+}
+
+shaken_status shaken_batch_get_log_ej(shaken_batch *b, int32_t i, int64_t *EJ_out, int64_t *M_out,
+                                      int64_t cap) {
+    if (!EJ_out) return fail(SHAKEN_EINVAL, "EJ_out is NULL");
+    return batch_read_log(b, i, nullptr, M_out, EJ_out, cap);
+}
+
+shaken_status shaken_batch_get_logs(shaken_batch *b, int64_t *H_out, int64_t *M_out, int64_t *EJ_out,
+                                    int64_t cap) {
+    if (!b) return fail(SHAKEN_EINVAL, "batch is NULL");
+    if (!H_out && !M_out && !EJ_out) return fail(SHAKEN_EINVAL, "every output is NULL");
+    if (!b->record || b->last_n_full < 0) return fail(SHAKEN_ESTATE, "no recorded sweep");
+    const int64_t slots = b->last_n_full + 1;
+    if (cap < slots) return fail(SHAKEN_EINVAL, "capacity too small");
+    if (H_out)
+        for (auto *c : b->ctx)
+            if (!c->lam2_int) return fail(SHAKEN_EINVAL, "H_out needs every 2*lambda to be an integer");
+    DeviceGuard guard(b->device);
+    // the slots of this call are contiguous in the slot-major pool: one copy
+    std::vector<int64_t> pool((size_t)(slots * b->log_row));
+    HIPCHK(hipMemcpyAsync(pool.data(), b->log_pool, pool.size() * 8, hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    for (size_t i = 0; i < b->ctx.size(); ++i) {
+        shaken_ctx *c = b->ctx[i];
+        const int64_t width = b->log_parts * c->line();
+        std::vector<int64_t> raw((size_t)(slots * width));
+        for (int64_t t = 0; t < slots; ++t)
+            std::copy_n(pool.begin() + t * b->log_row + b->log_off[i], width, raw.begin() + t * width);
+        const int64_t o = (int64_t)i * cap;
+        convert_log(c, raw, slots, b->log_parts, H_out ? H_out + o : nullptr, M_out ? M_out + o : nullptr,
+                    EJ_out ? EJ_out + o : nullptr);
+    }
     return SHAKEN_OK;
 }
 

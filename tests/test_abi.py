@@ -147,3 +147,20 @@ def test_graph_bitpacked_passes_host_validation():
     import paper_1904_06257_amd as sk
     st, msg = _init_status(kind="graph", n=70, src=[0, 5, 69], dst=[1, 6, 0], fmt="bitpacked")
     assert st == sk.SHAKEN_EDEVICE, msg
+
+
+def test_scalar_and_wrong_length_couplings_in_the_binding():
+    """A scalar J is one coupling for every oriented edge (2 L^2 on the torus,
+    3 L^2 on the triangular lattice, m on a graph); an array of another length
+    is refused before the library reads it."""
+    import torch
+    import paper_1904_06257_amd as sk
+    for kind, kw, n_edges in (("torus", dict(L=5), 50), ("triangular", dict(L=5), 75),
+                              ("graph", dict(n=4, src=[0, 1, 2], dst=[1, 2, 3]), 3)):
+        with pytest.raises(ValueError):
+            sk.Chain(kind, J=np.ones(n_edges - 1, np.int8), **kw)
+        if not torch.cuda.is_available():
+            st, msg = _init_status(kind=kind, J=2, **kw)
+            assert st == sk.SHAKEN_EDEVICE, msg
+            st, msg = _init_status(kind=kind, J=np.full(n_edges, -1, np.int8), **kw)
+            assert st == sk.SHAKEN_EDEVICE, msg

@@ -431,15 +431,27 @@ def test_graph_ell_equals_csr_equals_oracle(sk, n, deg):
 
 
 def test_batch_auto_strategy_choice(sk):
-    """AUTO: grid for batches of tori only, persistent as soon as a graph is in
-    the batch or tracking is asked for; both give the oracle's trajectory."""
+    """AUTO: persistent when every chain fits in LDS (tori up to 256^2), grid as
+    soon as one does not; both give the oracle's trajectory."""
     tori = [sk.Chain.torus(L, q=1.0, beta=0.4, seed=60 + L, replica=L) for L in (16, 40)]
     b = sk.Batch(tori)
-    assert b.info()[0] == sk.SHAKEN_BATCH_GRID
-    b.close()
-    b = sk.Batch(tori, track=True)
     assert b.info()[0] == sk.SHAKEN_BATCH_PERSISTENT
     b.close()
+    # 300^2 needs 3000 words of LDS per buffer: the whole batch runs on the grid
+    small = sk.Chain.torus(24, q=1.0, beta=0.4, seed=324, replica=24)
+    big = sk.Chain.torus(300, q=1.0, beta=0.4, seed=600, replica=300)
+    b = sk.Batch([small, big])
+    assert b.info()[0] == sk.SHAKEN_BATCH_GRID
+    b.sweep(5)
+    b.close()
+    for ch, L in ((small, 24), (big, 300)):
+        want, _, _ = oracle.torus_run(oracle.torus_init_random(L, 300 + L, L), 1, 0.0, 1.0, 0.4,
+                                      300 + L, L, 5)
+        assert np.array_equal(ch.spins(), want)
+    with pytest.raises(sk.ShakenError):
+        sk.Batch([small, big], track=True)
+    small.close()
+    big.close()
     inst = synth.oriented_instance(100, 3, 61, lam_values=(0.0,), pm_j=True)
     g = sk.Chain.graph(inst.n, inst.src, inst.dst, J=inst.J, q=1.0, beta=0.4, seed=61, replica=7)
     b = sk.Batch(tori + [g])
