@@ -81,3 +81,32 @@ def test_theorem_3_3_path_on_the_oracle():
         exact = ms.in_diagonal_set(x) and abs(int(x.sum())) != n
         assert exact == bool(sig[t - t_exit]), t
         x, _, _ = oracle.torus_run(x, 1, lam, q, beta, 5, 2, 1, s0=2 * t, log=False)
+
+
+@pytest.mark.parametrize("beta,q,lam", [(0.7, 0.1, 0.15), (1.3, 0.1, 0.15), (0.5, 0.4, 0.6), (1.0, 0.8, 0.3)])
+def test_stationary_law_concentrates_on_all_plus(beta, q, lam):
+    """Section 3.2: for 0 < lambda < J and q > 0 the stationary law of the
+    shaken dynamics puts every configuration other than +1 below
+    exp(-2 beta q) pi(+1).  Exact enumeration of Theorem 2.3's pi on the 3 x 3
+    torus, against the closed form of the ratio: the product over sites of
+    cosh(beta h^dl_x(sigma)) / cosh(beta (2J + q + lambda)) times Theorem 2.3's
+    field factor exp(beta lambda (sum sigma - N))."""
+    from oracle import enumeration as en
+    L, J = 3, 1.0
+    n = L * L
+    src, dst = en.torus_edges(L)
+    m = en.Model(n, src, dst, lam=np.full(n, lam), q=q, beta=beta)
+    pi = m.pi()
+    S = en.states(n)
+    plus = 2 ** n - 1
+    ratio = pi / pi[plus]
+    others = np.arange(2 ** n) != plus
+    assert np.all(ratio[others] <= np.exp(-2 * beta * q) * (1 + 1e-12))
+    # closed form: the dl field collects the tails of the edges pointing at x
+    h = np.zeros_like(S)
+    for a, b in zip(src, dst):
+        h[:, b] += J * S[:, a]
+    h += q * S + lam
+    closed = np.exp(beta * lam * (S.sum(axis=1) - n)) * np.prod(
+        np.cosh(beta * h) / np.cosh(beta * (2 * J + q + lam)), axis=1)
+    assert np.allclose(ratio, closed, rtol=1e-10, atol=0)
