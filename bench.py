@@ -347,11 +347,15 @@ def bench_copycal(args):
     print(json.dumps({"copy_bytes": n, "copies": 3}), flush=True)
 
 
-def _counter_rows(path):
+def _counter_rows(path, grid=None):
+    """counter values per kernel name; grid: keep only dispatches of that
+    grid size (work-items)"""
     import csv
     rows = list(csv.DictReader(open(path)))
     out = {}
     for r in rows:
+        if grid is not None and int(r["Grid_Size"]) != grid:
+            continue
         name = r["Kernel_Name"]
         out.setdefault(name, []).append(float(r["Counter_Value"]))
     return out
@@ -360,12 +364,15 @@ def _counter_rows(path):
 def summarize_traffic(cal_fetch_csv, cal_write_csv, workloads, out_path):
     """profiles/traffic.txt from rocprofv3 --pmc counter CSVs: FETCH_SIZE and
     WRITE_SIZE (KiB per dispatch) of the 1 GiB calibration copy, then per
-    workload (kernel, fetch csv, write csv, full steps per timed launch or 0).
-    Only the named kernel of each workload is summarised; a kernel whose launch
-    covers many full steps (the persistent batch) is reported per full step,
-    from its largest dispatch."""
-    def rows(path):
-        return _counter_rows(path)
+    workload (kernel, fetch csv, write csv, full steps per timed launch or 0,
+    grid size or None, suffix of the kernel's template arguments or "").
+    Only the named kernel of each workload is summarised (only its dispatches
+    of that grid size and with that suffix, where given: a run may launch the
+    kernel for other configurations too); a kernel whose launch covers many
+    full steps (the persistent batch) is reported per full step, from its
+    largest dispatch."""
+    def rows(path, grid=None):
+        return _counter_rows(path, grid)
 
     def short_name(k):
         return k.split("(")[0].replace("void ", "").replace("shaken::", "").split("<")[0]
@@ -381,18 +388,19 @@ def summarize_traffic(cal_fetch_csv, cal_write_csv, workloads, out_path):
              "source_hash = %s" % kernel_source_hash(),
              "calibration_kernel = %s" % ck.split("(")[0],
              "fetch_factor = %.4f" % fetch_factor, "write_factor = %.4f" % write_factor]
-    for kernel, fetch_csv, write_csv, steps in workloads:
-        f, w = rows(fetch_csv), rows(write_csv)
+    for kernel, fetch_csv, write_csv, steps, grid, suffix in workloads:
+        f, w = rows(fetch_csv, grid), rows(write_csv, grid)
         fb_all, wb_all = [], []
         for k in sorted(f):
-            if short_name(k) != kernel:
+            if short_name(k) != kernel or not k.split("(")[0].endswith(suffix):
                 continue
             fv = [x * 1024.0 * fetch_factor for x in f[k]]
             wv = [x * 1024.0 * write_factor for x in w.get(k, [0.0])]
             if steps:
                 fv, wv = [max(fv) / steps], [max(wv) / steps]
-            lines.append("# %s: fetch %.0f B, write %.0f B per %s (%d dispatches)"
-                         % (k.split("(")[0], sum(fv) / len(fv), sum(wv) / len(wv),
+            lines.append("# %s%s: fetch %.0f B, write %.0f B per %s (%d dispatches)"
+                         % (k.split("(")[0], "" if grid is None else " grid %d" % grid,
+                            sum(fv) / len(fv), sum(wv) / len(wv),
                             "full step" if steps else "launch", len(f[k])))
             fb_all += fv
             wb_all += wv
@@ -407,13 +415,15 @@ def summarize_traffic(cal_fetch_csv, cal_write_csv, workloads, out_path):
 
 def main():
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-traffic":
-        # bench.py --summarize-traffic CAL_FETCH CAL_WRITE KERNEL[@STEPS]=FETCH,WRITE ...
+        # bench.py --summarize-traffic CAL_FETCH CAL_WRITE KERNEL[@STEPS][#GRID][~SUFFIX]=FETCH,WRITE ...
         wl = []
         for arg in sys.argv[4:]:
             name, files = arg.split("=", 1)
+            name, _, suffix = name.partition("~")
+            name, _, grid = name.partition("#")
             kernel, _, steps = name.partition("@")
             fetch, write = files.split(",")
-            wl.append((kernel, fetch, write, int(steps or 0)))
+            wl.append((kernel, fetch, write, int(steps or 0), int(grid) if grid else None, suffix))
         summarize_traffic(sys.argv[2], sys.argv[3], wl, os.path.join(ROOT, "profiles", "traffic.txt"))
         return
     ap = argparse.ArgumentParser()
