@@ -187,6 +187,9 @@ def shaken_half_step(ctx, n):
 
 
 def shaken_sweep(ctx, n_full, H_out=None, M_out=None):
+    for a in (H_out, M_out):
+        if a is not None and (a.dtype != np.int64 or not a.flags.c_contiguous or a.size < int(n_full) + 1):
+            raise ValueError("log outputs must be contiguous int64 arrays of n_full + 1 entries")
     _check(_lib.shaken_sweep(ctx, int(n_full), _ptr(H_out, ctypes.c_int64), _ptr(M_out, ctypes.c_int64)))
 
 
@@ -197,6 +200,9 @@ def shaken_observables(ctx):
 
 
 def shaken_batch_run(ctxs, n_full, opts, H_final=None):
+    if H_final is not None and (H_final.dtype != np.int64 or not H_final.flags.c_contiguous
+                                or H_final.size < len(ctxs)):
+        raise ValueError("H_final must be a contiguous int64 array with one entry per context")
     arr = (_vp * len(ctxs))(*[c.value for c in ctxs])
     _check(_lib.shaken_batch_run(arr, len(ctxs), int(n_full), ctypes.byref(opts),
                                  _ptr(H_final, ctypes.c_int64)))
@@ -218,8 +224,10 @@ class Chain:
             self.shape = (int(L), int(L))
             self.n = int(L) * int(L)
         elif kind == "graph":
-            src = np.ascontiguousarray(src, dtype=np.int32)
-            dst = np.ascontiguousarray(dst, dtype=np.int32)
+            src = np.ascontiguousarray(src, dtype=np.int32).reshape(-1)
+            dst = np.ascontiguousarray(dst, dtype=np.int32).reshape(-1)
+            if src.shape != dst.shape:
+                raise ValueError("src and dst must have the same length")
             self._keep += [src, dst]
             g.kind, g.n, g.m = SHAKEN_EDGES, int(n), int(src.shape[0])
             g.src, g.dst = _ptr(src, ctypes.c_int32), _ptr(dst, ctypes.c_int32)
@@ -243,7 +251,9 @@ class Chain:
         field = None
         if lam_values is not None:
             lv = np.ascontiguousarray(np.atleast_1d(lam_values), dtype=np.float64)
-            lc = None if lam_class is None else np.ascontiguousarray(lam_class, dtype=np.uint8)
+            lc = None if lam_class is None else np.ascontiguousarray(lam_class, dtype=np.uint8).reshape(-1)
+            if lc is not None and lc.shape[0] != self.n:
+                raise ValueError("lam_class needs one class per site (%d), got %d" % (self.n, lc.shape[0]))
             self._keep += [lv, lc]
             field = shaken_field(len(lv), _ptr(lv, ctypes.c_double), _ptr(lc, ctypes.c_uint8))
             self.lam_values = lv
@@ -257,6 +267,8 @@ class Chain:
         sp = None
         if init_spins is not None:
             sp = np.ascontiguousarray(init_spins, dtype=np.int8).reshape(-1)
+            if sp.shape[0] != self.n:
+                raise ValueError("init_spins needs one spin per site (%d), got %d" % (self.n, sp.shape[0]))
             o.init = SHAKEN_INIT_USER
             o.init_spins = _ptr(sp, ctypes.c_int8)
         o.replica = int(replica)

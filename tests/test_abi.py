@@ -164,3 +164,27 @@ def test_scalar_and_wrong_length_couplings_in_the_binding():
             assert st == sk.SHAKEN_EDEVICE, msg
             st, msg = _init_status(kind=kind, J=np.full(n_edges, -1, np.int8), **kw)
             assert st == sk.SHAKEN_EDEVICE, msg
+
+
+def test_per_site_arrays_of_wrong_length_refused_in_the_binding():
+    """lam_class and init_spins are read for every site by the library: the
+    binding refuses other lengths before the call"""
+    import paper_1904_06257_amd as sk
+    with pytest.raises(ValueError):
+        sk.Chain("torus", L=4, lam_values=[0.0, 0.5], lam_class=np.zeros(15, np.uint8))
+    with pytest.raises(ValueError):
+        sk.Chain("graph", n=5, src=[0, 1], dst=[1, 2], init_spins=np.ones(4, np.int8))
+    with pytest.raises(ValueError):
+        sk.Chain("torus", L=4, init_spins=np.ones((4, 3), np.int8))
+
+
+def test_edge_and_output_arrays_checked_in_the_binding():
+    import paper_1904_06257_amd as sk
+    with pytest.raises(ValueError):
+        sk.Chain("graph", n=4, src=[0, 1, 2], dst=[1, 2])
+    with pytest.raises(ValueError):
+        sk.shaken_sweep(None, 10, H_out=np.zeros(10, np.int64))
+    with pytest.raises(ValueError):
+        sk.shaken_sweep(None, 10, M_out=np.zeros(11, np.int32))
+    with pytest.raises(ValueError):
+        sk.shaken_batch_run([], 1, None, H_final=np.zeros(3, np.float64))

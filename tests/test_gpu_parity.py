@@ -378,11 +378,16 @@ def test_batch_log_reserve_and_growth(sk, strategy):
     t0 = 0
     for n_full in lengths:
         b.sweep(n_full)
+        _, M_all, EJ_all = b.logs()           # every chain with one device copy
         for i, sp in enumerate(specs):
             h, m = b.log(i, with_H=sp["H"] is not None)
             assert np.array_equal(m, sp["M"][t0:t0 + n_full + 1]), (i, n_full)
             if sp["H"] is not None:
                 assert np.array_equal(h, sp["H"][t0:t0 + n_full + 1]), (i, n_full)
+            ej, m2 = b.log_ej(i)
+            assert np.array_equal(ej, sp["EJ"][t0:t0 + n_full + 1]), (i, n_full)
+            assert np.array_equal(m2, m) and np.array_equal(M_all[i], m), (i, n_full)
+            assert np.array_equal(EJ_all[i], ej), (i, n_full)
         t0 += n_full
     for i, sp in enumerate(specs):
         assert np.array_equal(chains[i].spins().reshape(sp["want"].shape), sp["want"]), i
