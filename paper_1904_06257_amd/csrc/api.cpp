@@ -531,6 +531,13 @@ shaken_status init_host(shaken_ctx *c, const shaken_graph *g, const int8_t *J,
             if (!ok && o->graph_layout == SHAKEN_LAYOUT_PACKED)
                 return fail(SHAKEN_EINVAL, "packed layout needs couplings +-1, at most 3 neighbours per "
                                            "vertex, n <= 65536 and at most 16 field classes");
+            // AUTO on a graph larger than the persistent kernel takes: CSR
+            // (the grid kernels run faster on it than on ELL from 2^17
+            // vertices on, and on every batch of such graphs)
+            if (!ok && o->graph_layout == SHAKEN_LAYOUT_AUTO && c->n > 65536) {
+                hl.ell.clear();
+                hl.ell_k = 0;
+            }
         }
     } else {
         return fail(SHAKEN_EINVAL, "unknown graph kind");
