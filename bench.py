@@ -96,6 +96,53 @@ def cpu_baseline_torus(triangular=False):
                                                    else "torus", dt)}
 
 
+def cpu_baseline_graph():
+    """The oracle as it stands: 100 full steps of the n = 2^20 graph chain,
+    single-threaded C (about 10 s of host time)."""
+    import oracle
+    import synth
+    n, steps = 1 << 20, 100
+    inst = synth.oriented_instance(n, 3, 3, lam_values=(-0.5, 0.0, 0.5), pm_j=True)
+    g = oracle.Graph(n, inst.src, inst.dst, inst.J, inst.cls, inst.lam_values)
+    sp = oracle.graph_init_random(n, 1, 0)
+    t0 = time.perf_counter()
+    oracle.graph_run(g, sp, 1.5, 0.8, 1, 0, steps, log=False)
+    dt = time.perf_counter() - t0
+    return {"value": 2.0 * n * steps / dt, "unit": "vertex-updates/s", "cores": 1, "kind": "oracle",
+            "sample": "%d full steps of the n=2^20 graph chain, %.1f s on one host core" % (steps, dt)}
+
+
+def cpu_baseline_batch():
+    """The oracle as it stands on a sample of the 2048-chain batch: the first
+    8 tori and the first 8 graphs of the batch spec (lambda = 0, as the batch
+    runs them), 120 full steps each, one after the other on one host core
+    (about 10 s)."""
+    import oracle
+    import synth
+    spec = synth.batch_spec(1024, 1024, seed=4)
+    tori = [it for it in spec if it.kind == "torus"][:8]
+    graphs = [it for it in spec if it.kind == "graph"][:8]
+    steps, sites, dt = 120, 0, 0.0
+    for i, it in enumerate(tori + graphs):
+        if it.kind == "torus":
+            sp = oracle.torus_init_random(it.size, it.seed, i)
+            t0 = time.perf_counter()
+            oracle.torus_run(sp, 1, 0.0, it.q, it.beta, it.seed, i, steps, log=False)
+            dt += time.perf_counter() - t0
+            sites += it.size * it.size
+        else:
+            gi = it.graph
+            g = oracle.Graph(gi.n, gi.src, gi.dst, gi.J)
+            sp = oracle.graph_init_random(gi.n, it.seed, i)
+            t0 = time.perf_counter()
+            oracle.graph_run(g, sp, it.q, it.beta, it.seed, i, steps, log=False)
+            dt += time.perf_counter() - t0
+            sites += gi.n
+    return {"value": 2.0 * sites * steps / dt, "unit": "site-updates/s", "cores": 1, "kind": "oracle",
+            "sample": "8 tori and 8 graphs of the batch (%d sites), %d full steps each, %.1f s on one "
+                      "host core" % (sites, steps, dt)}
+
+
 def bench_torus4096(args, sk, triangular=False):
     import synth
     import torch
@@ -460,7 +507,7 @@ def main():
     elif args.workload == "graph":
         value, wall, cfg, roof, dtype = bench_graph(args, sk)
         metric = "vertex updates/s (3-regular graph, n=2^20)"
-        cpu = None
+        cpu = None if args.no_cpu_baseline else cpu_baseline_graph()
     elif args.workload == "ea":
         value, wall, cfg, roof, dtype = bench_ea(args, sk)
         metric = "spin-site updates/s (1024 +-J Edwards-Anderson tori 256^2, batched)"
@@ -468,7 +515,7 @@ def main():
     else:
         value, wall, cfg, roof, dtype = bench_batch(args, sk)
         metric = "aggregate site updates/s (2048 mixed chains, persistent batch)"
-        cpu = None
+        cpu = None if args.no_cpu_baseline else cpu_baseline_batch()
     out = {"metric": metric, "value": value, "unit": "site-updates/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": wall * 1e3 / args.steps, "higher_is_better": True,
