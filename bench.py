@@ -265,7 +265,9 @@ def bench_batch(args, sk):
             # (the in-half and the out-half hold m entries together: m/2 each on average)
             adj_bytes_half += 4 * (g.n + 1) + 5 * (m / 2.0)
     # log space for the longest call is reserved up-front: no allocation in the timed call
-    batch = sk.Batch(chains, strategy="persistent", record=True,
+    # one persistent launch per call, replayed from a captured HIP graph, with
+    # the workgroup count autotuned on the first call (the warm-up)
+    batch = sk.Batch(chains, strategy="persistent", record=True, use_hipgraph=True, autotune=True,
                      log_reserve=max(args.steps, args.warmup))
     batch.sweep(args.warmup)
     torch.cuda.synchronize()

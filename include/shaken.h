@@ -281,9 +281,15 @@ enum { SHAKEN_BATCH_AUTO = 0, SHAKEN_BATCH_GRID = 1, SHAKEN_BATCH_PERSISTENT = 2
 
 typedef struct shaken_batch_opts {
     int32_t strategy;      /* SHAKEN_BATCH_*                                  */
-    int32_t use_hipgraph;  /* grid strategy: capture the half-step launches   */
+    int32_t use_hipgraph;  /* capture the launches in a HIP graph and replay
+                              it: grid strategy, 16 full steps of half-step
+                              launches per replay; persistent strategy, the
+                              whole call (one capture for every n_full)      */
     int32_t autotune;      /* 0: fixed launch shapes; 1: measure candidates
-                              on the first call and keep the fastest         */
+                              on the first call and keep the fastest (grid:
+                              the block size of every group; persistent: the
+                              number of resident workgroups, on trial runs
+                              after which every configuration is restored)   */
     int32_t record;        /* log H and M of every chain at every full step  */
     void *stream;          /* hipStream_t; NULL = the first chain's stream   */
     int32_t track;         /* persistent strategy: keep, per chain, H of the

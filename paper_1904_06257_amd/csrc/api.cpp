@@ -1012,6 +1012,10 @@ struct shaken_batch {
     int32_t *order = nullptr;
     int32_t *counter = nullptr;
     int pblock = 256, pgrid = 0;
+    bool ptuned = false;
+    hipGraphExec_t pgexec = nullptr;  // captured persistent launch (use_hipgraph)
+    hipGraph_t pgraph = nullptr;
+    int pg_grid = 0;                  // workgroup count it was captured with
 };
 
 namespace {
@@ -1028,6 +1032,8 @@ void batch_release(shaken_batch *b) {
     dfree(b->counter);
     if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->pgexec) (void)hipGraphExecDestroy(b->pgexec);
+    if (b->pgraph) (void)hipGraphDestroy(b->pgraph);
     if (b->ev0) (void)hipEventDestroy(b->ev0);
     if (b->ev1) (void)hipEventDestroy(b->ev1);
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
@@ -1150,6 +1156,96 @@ shaken_status batch_build_graph(shaken_batch *b, int chunk) {
     b->graph = gr;
     HIPCHK(hipGraphInstantiate(&b->gexec, gr, nullptr, nullptr, 0));
     b->chunk = chunk;
+    return SHAKEN_OK;
+}
+
+// Persistent strategy: capture the queue reset and the persistent launch; the
+// start half-step and the number of full steps are read from dstate[0..1],
+// so one capture serves every call.
+shaken_status batch_build_pgraph(shaken_batch *b) {
+    if (b->pgexec) (void)hipGraphExecDestroy(b->pgexec);
+    if (b->pgraph) (void)hipGraphDestroy(b->pgraph);
+    b->pgexec = nullptr;
+    b->pgraph = nullptr;
+    HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = launch_set_state((uint32_t *)b->counter, 0u, 0u, b->stream);
+    if (e == hipSuccess)
+        e = launch_persistent(b->pdescs, (int)b->ctx.size(), b->order, b->counter, 0u, b->dstate, 0,
+                              b->record, b->track, b->pblock, b->pgrid, b->stream);
+    hipGraph_t gr = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(b->stream, &gr);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (gr) (void)hipGraphDestroy(gr);
+        return fail(SHAKEN_EDEVICE, std::string("persistent graph capture: ") +
+                                        hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    b->pgraph = gr;
+    HIPCHK(hipGraphInstantiate(&b->pgexec, gr, nullptr, nullptr, 0));
+    b->pg_grid = b->pgrid;
+    return SHAKEN_OK;
+}
+
+// Persistent strategy: pick the number of resident workgroups (the occupancy
+// bound, or one per compute unit) by timing eight full steps of the batch
+// with each; the occupancy bound stays unless the other is at least 3 %
+// faster (run-to-run noise is about that size).  Every chain's configuration
+// is saved before and restored after each trial, so tuning leaves the chains
+// as they were.
+shaken_status batch_autotune_persistent(shaken_batch *b) {
+    const int n = (int)b->ctx.size();
+    int ncu = 256;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, b->device) == hipSuccess) ncu = prop.multiProcessorCount;
+    std::vector<int> cands{b->pgrid};
+    if (std::min(n, ncu) != b->pgrid) cands.push_back(std::min(n, ncu));
+    std::vector<size_t> off;
+    size_t tot = 0;
+    for (auto *c : b->ctx) {
+        off.push_back(tot);
+        tot += (c->spin_bytes() + 255) / 256 * 256;
+    }
+    uint8_t *save = nullptr;
+    CHK(dalloc(&save, tot));
+    auto copy_all = [&](bool to_save) -> hipError_t {
+        for (int i = 0; i < n; ++i) {
+            void *dev = b->ctx[i]->spin[0];
+            const hipError_t e = to_save ? hipMemcpyAsync(save + off[i], dev, b->ctx[i]->spin_bytes(),
+                                                          hipMemcpyDeviceToDevice, b->stream)
+                                         : hipMemcpyAsync(dev, save + off[i], b->ctx[i]->spin_bytes(),
+                                                          hipMemcpyDeviceToDevice, b->stream);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
+    const uint32_t s0 = b->ctx[0]->s;
+    shaken_status st = SHAKEN_OK;
+    hipError_t e = copy_all(true);
+    float best = 1e30f;
+    int best_g = b->pgrid;
+    for (size_t k = 0; k < cands.size() && e == hipSuccess; ++k) {
+        for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {  // the first run warms the caches
+            e = launch_set_state((uint32_t *)b->counter, 0u, 0u, b->stream);
+            if (e == hipSuccess) e = hipEventRecord(b->ev0, b->stream);
+            if (e == hipSuccess)
+                e = launch_persistent(b->pdescs, n, b->order, b->counter, s0, nullptr, 8, 0, 0, b->pblock,
+                                      cands[k], b->stream);
+            if (e == hipSuccess) e = hipEventRecord(b->ev1, b->stream);
+            if (e == hipSuccess) e = copy_all(false);
+            if (e == hipSuccess) e = hipEventSynchronize(b->ev1);
+            float ms = 0;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, b->ev0, b->ev1);
+            if (e == hipSuccess && rep == 1 && (k == 0 || ms < 0.97f * best)) {
+                best = ms;
+                best_g = cands[k];
+            }
+        }
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) st = fail(SHAKEN_EDEVICE, std::string("persistent autotune: ") + hipGetErrorString(e));
+    dfree(save);
+    if (st != SHAKEN_OK) return st;
+    b->pgrid = best_g;
+    b->ptuned = true;
     return SHAKEN_OK;
 }
 
@@ -1344,12 +1440,17 @@ shaken_status shaken_batch_sweep(shaken_batch *b, int64_t n_full) {
             b->gexec = nullptr;
         }
     }
+    if (b->strategy == SHAKEN_BATCH_PERSISTENT && b->autotune && !b->ptuned) CHK(batch_autotune_persistent(b));
     HIPCHK(hipEventRecord(b->ev0, b->stream));
     if (b->strategy == SHAKEN_BATCH_GRID) {
         CHK(batch_sweep_grid(b, n_full));
+    } else if (b->use_graph && n_full > 0) {
+        if (!b->pgexec || b->pg_grid != b->pgrid) CHK(batch_build_pgraph(b));
+        HIPCHK(launch_set_state(b->dstate, s0, (uint32_t)n_full, b->stream));
+        HIPCHK(hipGraphLaunch(b->pgexec, b->stream));
     } else {
         HIPCHK(launch_set_state((uint32_t *)b->counter, 0u, 0u, b->stream));
-        HIPCHK(launch_persistent(b->pdescs, (int)b->ctx.size(), b->order, b->counter, s0, n_full,
+        HIPCHK(launch_persistent(b->pdescs, (int)b->ctx.size(), b->order, b->counter, s0, nullptr, n_full,
                                  b->record, b->track, b->pblock, b->pgrid, b->stream));
     }
     const uint32_t s1 = s0 + (uint32_t)(2 * n_full);

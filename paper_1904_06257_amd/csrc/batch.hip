@@ -447,8 +447,12 @@ __device__ __attribute__((noinline)) void run_graph(const ChainDesc &d_arg, uint
 __global__ __launch_bounds__(kPBlock, SHAKEN_PWAVES) void k_persistent(const ChainDesc *__restrict__ descs,
                                                         int nchains,
                                                         const int32_t *__restrict__ order,
-                                                        int32_t *counter, uint32_t s0,
-                                                        int64_t n_full, int record, int track) {
+                                                        int32_t *counter, uint32_t s0_arg,
+                                                        const uint32_t *__restrict__ sp,
+                                                        int64_t n_full_arg, int record, int track) {
+    // start half-step and full steps from device memory under a replayed HIP graph
+    const uint32_t s0 = sp ? (uint32_t)__builtin_amdgcn_readfirstlane(sp[0]) : s0_arg;
+    const int64_t n_full = sp ? (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane(sp[1]) : n_full_arg;
     __shared__ uint32_t buf[2][kPWords];
     __shared__ int sh_item;
     __shared__ int sh_flag;
@@ -504,13 +508,13 @@ int persistent_resident_blocks() {
 }
 
 hipError_t launch_persistent(const ChainDesc *dev_descs, int nchains, const int32_t *order,
-                             int32_t *counter, uint32_t s0, int64_t n_full, int record, int track,
-                             int block, int grid, hipStream_t stream) {
+                             int32_t *counter, uint32_t s0, const uint32_t *sp, int64_t n_full,
+                             int record, int track, int block, int grid, hipStream_t stream) {
     (void)block;
     if (nchains <= 0) return hipSuccess;
     const int g = grid > 0 ? grid : nchains;
     hipLaunchKernelGGL(k_persistent, dim3(g), dim3(kPBlock), 0, stream, dev_descs, nchains, order,
-                       counter, s0, n_full, record, track);
+                       counter, s0, sp, n_full, record, track);
     return hipGetLastError();
 }
 

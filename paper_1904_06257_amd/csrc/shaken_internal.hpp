@@ -120,12 +120,14 @@ hipError_t launch_observe(const ChainDesc *dev_descs, const ChainDesc *host_desc
 hipError_t launch_fill_i64(int64_t *p, int64_t count, int64_t value, hipStream_t stream);
 
 // persistent batch: run n_full full steps of every chain, starting at
-// half-step s0 with the configuration in spin[0]; chains are taken from a
-// device queue in the order given by `order`; counter must be zero on entry.
-// Writes the final configuration back into spin[0].
+// half-step s0 (when sp is not null, s0 = sp[0] and n_full = sp[1], read on
+// the device: one captured HIP graph serves every call) with the
+// configuration in spin[0]; chains are taken from a device queue in the order
+// given by `order`; counter must be zero on entry.  Writes the final
+// configuration back into spin[0].
 hipError_t launch_persistent(const ChainDesc *dev_descs, int nchains, const int32_t *order,
-                             int32_t *counter, uint32_t s0, int64_t n_full, int record,
-                             int track, int block, int grid, hipStream_t stream);
+                             int32_t *counter, uint32_t s0, const uint32_t *sp, int64_t n_full,
+                             int record, int track, int block, int grid, hipStream_t stream);
 
 // can chain d run in the persistent kernel?
 bool persistent_fits(const ChainDesc &d);

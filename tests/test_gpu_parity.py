@@ -525,3 +525,37 @@ def test_batch_run_one_call(sk):
     assert np.array_equal(tor.spins(), wt2)
     tor.close()
     gr.close()
+
+
+def test_persistent_hipgraph_and_autotune_equal_eager(sk):
+    """Persistent strategy under a captured HIP graph with the workgroup count
+    autotuned: replays of one capture (5 full steps), a re-capture at another
+    length and back, with log reads (eager copies and synchronisations)
+    between the replays; every call equals the eager batch and the oracle."""
+    calls = [5, 5, 5, 8, 5, 5]
+    T = sum(calls)
+    _print_case("persistent hipgraph", calls)
+    specs = _mixed_specs(T, [16, 100, 256], [1024, 2050], seed0=21)
+    a = [_make(sk, sp) for sp in specs]
+    c = [_make(sk, sp) for sp in specs]
+    ba = sk.Batch(a, strategy="persistent", record=True)
+    bc = sk.Batch(c, strategy="persistent", record=True, use_hipgraph=True, autotune=True)
+    assert bc.info()[0] == sk.SHAKEN_BATCH_PERSISTENT
+    t0 = 0
+    for n_full in calls:
+        ba.sweep(n_full)
+        bc.sweep(n_full)
+        _, Ma, EJa = ba.logs()
+        _, Mc, EJc = bc.logs()
+        assert np.array_equal(Ma, Mc) and np.array_equal(EJa, EJc), n_full
+        for i, sp in enumerate(specs):
+            assert np.array_equal(Mc[i], sp["M"][t0:t0 + n_full + 1]), (i, t0)
+            assert np.array_equal(EJc[i], sp["EJ"][t0:t0 + n_full + 1]), (i, t0)
+        t0 += n_full
+    for i, sp in enumerate(specs):
+        assert np.array_equal(c[i].spins().reshape(sp["want"].shape), sp["want"]), i
+        assert np.array_equal(a[i].spins(), c[i].spins()), i
+    ba.close()
+    bc.close()
+    for x in a + c:
+        x.close()
