@@ -114,6 +114,19 @@ __device__ __forceinline__ BpPlanes bp_planes(uint32_t a, uint32_t b, uint32_t c
 // und: sites still undecided; res: sites decided with v < t, where v = u with
 // the bits flipped where h >= 0 (u < 2^32 - t  <=>  not (~u < t)), so only
 // t <= 2^31 is compared.
+// Truth table of a three-input bit function for v_bitop3_b32 (bit a*4 + b*2 + c).
+template <typename F>
+constexpr int bitop3_table(F f) {
+    int t = 0;
+    for (int i = 0; i < 8; ++i)
+        if (f((i >> 2) & 1, (i >> 1) & 1, i & 1)) t |= 1 << i;
+    return t;
+}
+constexpr int kT_nor_and = bitop3_table([](int a, int b, int c) { return !a && !b && c; });
+constexpr int kT_and_or = bitop3_table([](int a, int b, int c) { return (a && b) || c; });
+constexpr int kT_xor3 = bitop3_table([](int a, int b, int c) { return a ^ b ^ c; });
+constexpr int kT_or_and = bitop3_table([](int a, int b, int c) { return a || (b && c); });
+
 template <bool FOLD3, int G0, int G1>
 __device__ __forceinline__ void bp_groups(const BpPlanes &p, uint32_t &und, uint32_t &res,
                                           uint32_t w, uint32_t s, uint32_t rep, uint32_t k0,
@@ -124,7 +137,12 @@ __device__ __forceinline__ void bp_groups(const BpPlanes &p, uint32_t &und, uint
         const int sh_ = 31 - (K);                                                             \
         uint32_t t_;                                                                          \
         if (FOLD3) {                                                                          \
-            t_ = bfi(p.one, bitmask(t1, sh_), bfi(p.al, bitmask(t5, sh_), bitmask(t2, sh_))); \
+            /* one scalar operand per instruction: rest&m2, then |al&m5, then |one&m1 */      \
+            const uint32_t z_ = __builtin_amdgcn_bitop3_b32(p.one, p.al, bitmask(t2, sh_),    \
+                                                            kT_nor_and);                      \
+            const uint32_t w_ = __builtin_amdgcn_bitop3_b32(p.al, bitmask(t5, sh_), z_,       \
+                                                            kT_and_or);                       \
+            t_ = __builtin_amdgcn_bitop3_b32(p.one, bitmask(t1, sh_), w_, kT_and_or);         \
         } else {                                                                              \
             const uint32_t lo_ = bfi(p.both, bitmask(t2, sh_),                                \
                                      bfi(p.one, bitmask(t1, sh_), bitmask(t0, sh_)));         \
@@ -132,8 +150,9 @@ __device__ __forceinline__ void bp_groups(const BpPlanes &p, uint32_t &und, uint
                                      bfi(p.one, bitmask(t4, sh_), bitmask(t3, sh_)));         \
             t_ = bfi(p.c, hi_, lo_);                                                          \
         }                                                                                     \
-        const uint32_t d_ = (R) ^ p.smask ^ t_;                                               \
-        res |= und & d_ & t_;                                                                 \
+        const uint32_t d_ = __builtin_amdgcn_bitop3_b32((R), p.smask, t_, kT_xor3);          \
+        const uint32_t y_ = und & d_; /* decided at this level */                             \
+        res = __builtin_amdgcn_bitop3_b32(res, y_, t_, kT_or_and);                            \
         und &= ~d_;                                                                           \
     }
 #pragma unroll
@@ -172,6 +191,7 @@ __device__ __forceinline__ uint32_t bp_word(uint32_t a, uint32_t b, uint32_t c, 
 // way by k1, k2 over the agreement planes.
 struct TriPlanes {
     uint32_t s1, s2, c, smask;
+    uint32_t k1, k2, k3;  // folded table: one-hot planes of classes 1..3 (class 0 from s1, s2)
 };
 
 __device__ __forceinline__ uint32_t maj3(uint32_t a, uint32_t b, uint32_t e) {
@@ -193,9 +213,13 @@ __device__ __forceinline__ TriPlanes tri_planes(uint32_t a, uint32_t b, uint32_t
         const uint32_t xa = ~(a ^ c), xb = ~(b ^ c), xe = ~(e ^ c);
         p.s1 = xa ^ xb ^ xe;
         p.s2 = maj3(xa, xb, xe);
+        p.k1 = p.s1 & ~p.s2;
+        p.k2 = ~p.s1 & p.s2;
+        p.k3 = p.s1 & p.s2;
     } else {
         p.s1 = n1;
         p.s2 = n2;
+        p.k1 = p.k2 = p.k3 = 0u;
     }
     return p;
 }
@@ -213,8 +237,11 @@ __device__ __forceinline__ void tri_groups(const TriPlanes &p, uint32_t &und, ui
         const int sh_ = 31 - (K);                                                                 \
         uint32_t t_;                                                                              \
         if (FOLD) {                                                                               \
-            t_ = bfi(p.s2, bfi(p.s1, bitmask(t7, sh_), bitmask(t6, sh_)),                         \
-                     bfi(p.s1, bitmask(t5, sh_), bitmask(t4, sh_)));                              \
+            /* one scalar operand per instruction over the one-hot class planes */                \
+            uint32_t x_ = __builtin_amdgcn_bitop3_b32(p.s1, p.s2, bitmask(t4, sh_), kT_nor_and);  \
+            x_ = __builtin_amdgcn_bitop3_b32(p.k1, bitmask(t5, sh_), x_, kT_and_or);              \
+            x_ = __builtin_amdgcn_bitop3_b32(p.k2, bitmask(t6, sh_), x_, kT_and_or);              \
+            t_ = __builtin_amdgcn_bitop3_b32(p.k3, bitmask(t7, sh_), x_, kT_and_or);              \
         } else {                                                                                  \
             const uint32_t lo_ = bfi(p.s2, bfi(p.s1, bitmask(t3, sh_), bitmask(t2, sh_)),         \
                                      bfi(p.s1, bitmask(t1, sh_), bitmask(t0, sh_)));              \
@@ -222,8 +249,9 @@ __device__ __forceinline__ void tri_groups(const TriPlanes &p, uint32_t &und, ui
                                      bfi(p.s1, bitmask(t5, sh_), bitmask(t4, sh_)));              \
             t_ = bfi(p.c, hi_, lo_);                                                              \
         }                                                                                         \
-        const uint32_t d_ = (R) ^ p.smask ^ t_;                                                   \
-        res |= und & d_ & t_;                                                                     \
+        const uint32_t d_ = __builtin_amdgcn_bitop3_b32((R), p.smask, t_, kT_xor3);              \
+        const uint32_t y_ = und & d_; /* decided at this level */                                 \
+        res = __builtin_amdgcn_bitop3_b32(res, y_, t_, kT_or_and);                                \
         und &= ~d_;                                                                               \
     }
 #pragma unroll
