@@ -82,17 +82,35 @@ __device__ __noinline__ uint32_t bp_finish(uint32_t a, uint32_t b, uint32_t c, u
 //
 // Tail compaction: every word first runs level groups 0 and 1 (8 levels, after
 // which a word is still undecided with probability 1 - (1 - 2^-8)^32 = 0.118).
-// Undecided words are appended to a workgroup queue in LDS and finished
-// afterwards by all lanes of the workgroup together, so that a wavefront does
-// not idle while its slowest lane runs the rare deep levels.
+// Undecided words are appended to a queue in LDS and finished afterwards by
+// all lanes of the workgroup together, so that a wavefront does not idle while
+// its slowest lane runs the rare deep levels.  Each wavefront appends to a
+// region of its own at a slot it computes from its ballot (no shared counter,
+// no broadcast); a region that fills up finishes its words in place.
 constexpr int kQCap = 512;
+
+// Tail queue in wavefront regions of qcap_w entries, cnt[r] of them used:
+// the total, and the slot of the it-th entry in region order.
+__device__ __forceinline__ int tail_total(const int *cnt, int nwav) {
+    int t = 0;
+    for (int r = 0; r < nwav; ++r) t += cnt[r];
+    return t;
+}
+__device__ __forceinline__ int tail_slot(const int *cnt, int nwav, int qcap_w, int it) {
+    int r = 0;
+    while (r < nwav - 1 && it >= cnt[r]) {
+        it -= cnt[r];
+        ++r;
+    }
+    return r * qcap_w + it;
+}
 
 // EXT: instantiation for chains with +-J sign planes or a frozen set (the
 // plain instantiation reads neither)
 template <bool OBS, bool FOLD3, bool EXT>
 __global__ __launch_bounds__(256) void k_torus_bp(const ChainDesc *__restrict__ descs, StepArgs sa) {
     __shared__ uint32_t q_w[kQCap], q_a[kQCap], q_b[kQCap], q_c[kQCap], q_und[kQCap], q_res[kQCap];
-    __shared__ int q_n;
+    __shared__ int q_cnt[4];  // entries queued per wavefront region
     const ChainDesc &d = descs[blockIdx.y];
     const uint32_t s = step_s(sa);
     const int bufp = (int)(s & 1u);      // configuration at s lives in spin[s & 1]
@@ -108,9 +126,10 @@ __global__ __launch_bounds__(256) void k_torus_bp(const ChainDesc *__restrict__ 
     const uint32_t k0 = (uint32_t)d.seed, k1 = (uint32_t)(d.seed >> 32);
     const uint32_t rep = d.replica, sgn = d.sgn;
     const uint32_t *ts = d.tsmall;
-    const int lane = threadIdx.x & 63;
-    if (threadIdx.x == 0) q_n = 0;
-    __syncthreads();
+    // tail queue: each wavefront fills a region of its own (no shared counter)
+    const int nwav = (int)(blockDim.x + 63) >> 6, wv = (int)threadIdx.x >> 6;
+    const int qcap_w = kQCap / nwav, qbase = wv * qcap_w;
+    int wq = 0;  // entries this wavefront has queued (the same in every lane)
     int e_acc = 0, p_acc = 0;
     const bool live = gid < total;
     const int rb = live ? gid / W : 0, wd = live ? gid - rb * W : 0;
@@ -164,32 +183,35 @@ __global__ __launch_bounds__(256) void k_torus_bp(const ChainDesc *__restrict__ 
         }
         const bool pend = act && und != 0;
         const unsigned long long bal = __ballot(pend);
-        int base = 0;
-        if (lane == 0 && bal) base = atomicAdd(&q_n, (int)__popcll(bal));
-        base = __shfl(base, 0, 64);
         if (act) {
-            const int q = base + (int)__popcll(bal & ((1ull << lane) - 1ull));
+            // slot in the wavefront's region: entries queued so far + pending lanes below
+            const int q = wq + (int)__builtin_amdgcn_mbcnt_hi(
+                                   (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
             if (!pend) {
                 out[widx] = ((res ^ p.smask) & vm) | (EXT ? frozen_word(d, widx) : 0u);
-            } else if (q < kQCap) {
-                q_w[q] = (uint32_t)widx;
-                q_a[q] = a;
-                q_b[q] = b;
-                q_c[q] = own[i];
-                q_und[q] = und;
-                q_res[q] = res;
+            } else if (q < qcap_w) {
+                const int qs = qbase + q;
+                q_w[qs] = (uint32_t)widx;
+                q_a[qs] = a;
+                q_b[qs] = b;
+                q_c[qs] = own[i];
+                q_und[qs] = und;
+                q_res[qs] = res;
             } else {
                 out[widx] = bp_finish<FOLD3>(a, b, own[i], und, res, vm, (uint32_t)widx, s, rep, k0, k1, ts, sgn) |
                             (EXT ? frozen_word(d, widx) : 0u);
             }
         }
+        wq += (int)__popcll(bal);
     }
+    if ((threadIdx.x & 63) == 0) q_cnt[wv] = min(wq, qcap_w);
     __syncthreads();
-    const int Q = min(q_n, kQCap);
+    const int Q = tail_total(q_cnt, nwav);
     for (int it = threadIdx.x; it < Q; it += blockDim.x) {
-        const uint32_t w = q_w[it];
+        const int qs = tail_slot(q_cnt, nwav, qcap_w, it);
+        const uint32_t w = q_w[qs];
         const uint32_t vw = bp_valid(L, W, (int)(w % (uint32_t)W));
-        out[w] = bp_finish<FOLD3>(q_a[it], q_b[it], q_c[it], q_und[it], q_res[it], vw, w, s, rep, k0,
+        out[w] = bp_finish<FOLD3>(q_a[qs], q_b[qs], q_c[qs], q_und[qs], q_res[qs], vw, w, s, rep, k0,
                                   k1, ts, sgn) | (EXT ? frozen_word(d, (int)w) : 0u);
     }
     if (OBS && bx * (int)blockDim.x < total)
@@ -217,7 +239,7 @@ template <bool OBS, bool FOLD>
 __global__ __launch_bounds__(256) void k_tri_bp(const ChainDesc *__restrict__ descs, StepArgs sa) {
     __shared__ uint32_t q_w[kQCap], q_a[kQCap], q_b[kQCap], q_e[kQCap], q_c[kQCap], q_und[kQCap],
         q_res[kQCap];
-    __shared__ int q_n;
+    __shared__ int q_cnt[4];  // entries queued per wavefront region
     const ChainDesc &d = descs[blockIdx.y];
     const uint32_t s = step_s(sa);
     const int bufp = (int)(s & 1u);
@@ -233,9 +255,10 @@ __global__ __launch_bounds__(256) void k_tri_bp(const ChainDesc *__restrict__ de
     const uint32_t k0 = (uint32_t)d.seed, k1 = (uint32_t)(d.seed >> 32);
     const uint32_t rep = d.replica, sgn = d.sgn;
     const uint32_t *ts = d.tsmall;
-    const int lane = threadIdx.x & 63;
-    if (threadIdx.x == 0) q_n = 0;
-    __syncthreads();
+    // tail queue: each wavefront fills a region of its own (no shared counter)
+    const int nwav = (int)(blockDim.x + 63) >> 6, wv = (int)threadIdx.x >> 6;
+    const int qcap_w = kQCap / nwav, qbase = wv * qcap_w;
+    int wq = 0;  // entries this wavefront has queued (the same in every lane)
     int e_acc = 0, p_acc = 0;
     const bool live = gid < total;
     const int rb = live ? gid / W : 0, wd = live ? gid - rb * W : 0;
@@ -286,33 +309,36 @@ __global__ __launch_bounds__(256) void k_tri_bp(const ChainDesc *__restrict__ de
         }
         const bool pend = act && und != 0;
         const unsigned long long bal = __ballot(pend);
-        int base = 0;
-        if (lane == 0 && bal) base = atomicAdd(&q_n, (int)__popcll(bal));
-        base = __shfl(base, 0, 64);
         if (act) {
-            const int q = base + (int)__popcll(bal & ((1ull << lane) - 1ull));
+            // slot in the wavefront's region: entries queued so far + pending lanes below
+            const int q = wq + (int)__builtin_amdgcn_mbcnt_hi(
+                                   (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
             if (!pend) {
                 out[widx] = ((res ^ p.smask) & vm) | frozen_word(d, widx);
-            } else if (q < kQCap) {
-                q_w[q] = (uint32_t)widx;
-                q_a[q] = a;
-                q_b[q] = b;
-                q_e[q] = e;
-                q_c[q] = own[i];
-                q_und[q] = und;
-                q_res[q] = res;
+            } else if (q < qcap_w) {
+                const int qs = qbase + q;
+                q_w[qs] = (uint32_t)widx;
+                q_a[qs] = a;
+                q_b[qs] = b;
+                q_e[qs] = e;
+                q_c[qs] = own[i];
+                q_und[qs] = und;
+                q_res[qs] = res;
             } else {
                 out[widx] = tri_finish<FOLD>(a, b, e, own[i], und, res, vm, (uint32_t)widx, s, rep, k0, k1,
                                              ts, sgn) | frozen_word(d, widx);
             }
         }
+        wq += (int)__popcll(bal);
     }
+    if ((threadIdx.x & 63) == 0) q_cnt[wv] = min(wq, qcap_w);
     __syncthreads();
-    const int Q = min(q_n, kQCap);
+    const int Q = tail_total(q_cnt, nwav);
     for (int it = threadIdx.x; it < Q; it += blockDim.x) {
-        const uint32_t w = q_w[it];
+        const int qs = tail_slot(q_cnt, nwav, qcap_w, it);
+        const uint32_t w = q_w[qs];
         const uint32_t vw = bp_valid(L, W, (int)(w % (uint32_t)W));
-        out[w] = tri_finish<FOLD>(q_a[it], q_b[it], q_e[it], q_c[it], q_und[it], q_res[it], vw, w, s, rep,
+        out[w] = tri_finish<FOLD>(q_a[qs], q_b[qs], q_e[qs], q_c[qs], q_und[qs], q_res[qs], vw, w, s, rep,
                                   k0, k1, ts, sgn) | frozen_word(d, (int)w);
     }
     if (OBS && bx * (int)blockDim.x < total)
