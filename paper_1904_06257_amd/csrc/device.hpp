@@ -87,33 +87,6 @@ __device__ __forceinline__ int xcd_block(int bx, int nb) {
 
 // ------------------------------------------------------ bit-packed torus
 
-// Bit-planes of a word: the two neighbours of the half (a, b) and the sites
-// themselves (c).  With a uniform coupling a site belongs to class
-// j = n_plus + 3c; the sign plane says where h >= 0 (from the per-chain mask
-// sgn), `al` where the neighbours agree with the site (classes 0 and 5), `one`
-// where exactly one neighbour is +1.
-struct BpPlanes {
-    uint32_t one, both, al, c, smask;
-};
-
-__device__ __forceinline__ BpPlanes bp_planes(uint32_t a, uint32_t b, uint32_t c, uint32_t sgn) {
-    BpPlanes p;
-    p.both = a & b;
-    p.one = a ^ b;
-    const uint32_t slo = bfi(p.both, bitmask(sgn, 2), bfi(p.one, bitmask(sgn, 1), bitmask(sgn, 0)));
-    const uint32_t shi = bfi(p.both, bitmask(sgn, 5), bfi(p.one, bitmask(sgn, 4), bitmask(sgn, 3)));
-    p.smask = bfi(c, shi, slo);
-    p.al = ~(a ^ c) & ~p.one;
-    p.c = c;
-    return p;
-}
-
-// MSB-first comparison of the 32 bit-sliced uniforms of RNG word w with the
-// thresholds of their classes, level groups [G0, G1) (group g = levels
-// 4g..4g+3 = Philox((w, s, rep, g))), stopping once every site is decided.
-// und: sites still undecided; res: sites decided with v < t, where v = u with
-// the bits flipped where h >= 0 (u < 2^32 - t  <=>  not (~u < t)), so only
-// t <= 2^31 is compared.
 // Truth table of a three-input bit function for v_bitop3_b32 (bit a*4 + b*2 + c).
 template <typename F>
 constexpr int bitop3_table(F f) {
@@ -127,6 +100,39 @@ constexpr int kT_and_or = bitop3_table([](int a, int b, int c) { return (a && b)
 constexpr int kT_xor3 = bitop3_table([](int a, int b, int c) { return a ^ b ^ c; });
 constexpr int kT_or_and = bitop3_table([](int a, int b, int c) { return a || (b && c); });
 
+// Bit-planes of a word: the two neighbours of the half (a, b) and the sites
+// themselves (c).  With a uniform coupling a site belongs to class
+// j = n_plus + 3c; the sign plane says where h >= 0 (from the per-chain mask
+// sgn), `al` where the neighbours agree with the site (classes 0 and 5), `one`
+// where exactly one neighbour is +1.
+struct BpPlanes {
+    uint32_t one, both, al, c, smask;
+};
+
+__device__ __forceinline__ BpPlanes bp_planes(uint32_t a, uint32_t b, uint32_t c, uint32_t sgn) {
+    BpPlanes p;
+    p.both = a & b;
+    p.one = a ^ b;
+    // sign of h per class, one scalar operand per instruction: classes with no,
+    // one and two +1 neighbours, then the site's own spin picks the row
+    uint32_t slo = __builtin_amdgcn_bitop3_b32(p.one, p.both, bitmask(sgn, 0), kT_nor_and);
+    slo = __builtin_amdgcn_bitop3_b32(p.one, bitmask(sgn, 1), slo, kT_and_or);
+    slo = __builtin_amdgcn_bitop3_b32(p.both, bitmask(sgn, 2), slo, kT_and_or);
+    uint32_t shi = __builtin_amdgcn_bitop3_b32(p.one, p.both, bitmask(sgn, 3), kT_nor_and);
+    shi = __builtin_amdgcn_bitop3_b32(p.one, bitmask(sgn, 4), shi, kT_and_or);
+    shi = __builtin_amdgcn_bitop3_b32(p.both, bitmask(sgn, 5), shi, kT_and_or);
+    p.smask = bfi(c, shi, slo);
+    p.al = ~(a ^ c) & ~p.one;
+    p.c = c;
+    return p;
+}
+
+// MSB-first comparison of the 32 bit-sliced uniforms of RNG word w with the
+// thresholds of their classes, level groups [G0, G1) (group g = levels
+// 4g..4g+3 = Philox((w, s, rep, g))), stopping once every site is decided.
+// und: sites still undecided; res: sites decided with v < t, where v = u with
+// the bits flipped where h >= 0 (u < 2^32 - t  <=>  not (~u < t)), so only
+// t <= 2^31 is compared.
 template <bool FOLD3, int G0, int G1>
 __device__ __forceinline__ void bp_groups(const BpPlanes &p, uint32_t &und, uint32_t &res,
                                           uint32_t w, uint32_t s, uint32_t rep, uint32_t k0,

@@ -127,8 +127,9 @@ __global__ __launch_bounds__(256) void k_torus_bp(const ChainDesc *__restrict__ 
     const uint32_t rep = d.replica, sgn = d.sgn;
     const uint32_t *ts = d.tsmall;
     // tail queue: each wavefront fills a region of its own (no shared counter)
+    // block sizes are 64, 128 or 256: one, two or four wavefronts
     const int nwav = (int)(blockDim.x + 63) >> 6, wv = (int)threadIdx.x >> 6;
-    const int qcap_w = kQCap / nwav, qbase = wv * qcap_w;
+    const int qcap_w = kQCap >> (nwav == 4 ? 2 : (nwav == 2 ? 1 : 0)), qbase = wv * qcap_w;
     int wq = 0;  // entries this wavefront has queued (the same in every lane)
     int e_acc = 0, p_acc = 0;
     const bool live = gid < total;
@@ -139,6 +140,10 @@ __global__ __launch_bounds__(256) void k_torus_bp(const ChainDesc *__restrict__ 
     const int lastbits = (L - 1) & 31;
     // adjacent word supplying the carry bit: left word (dl) / right word (ur)
     const int wside = phase == 0 ? (wd > 0 ? wd - 1 : W - 1) : (wd < W - 1 ? wd + 1 : 0);
+    // position of the wrap-around bit: the adjacent word's bit brought to bit 0
+    // (dl) or the bit it lands on (ur); 31 inside a row, the last valid bit at
+    // the row's end
+    const int csh = (phase == 0 ? wd > 0 : wd < W - 1) ? 31 : lastbits;
     uint32_t own[kRows], side[kRows];
 #pragma unroll
     for (int i = 0; i < kRows; ++i) {
@@ -164,12 +169,10 @@ __global__ __launch_bounds__(256) void k_torus_bp(const ChainDesc *__restrict__ 
         if (act) {
             if (phase == 0) {
                 a = (i == 0) ? halo : own[i > 0 ? i - 1 : 0];
-                const uint32_t carry = wd > 0 ? (side[i] >> 31) : ((side[i] >> lastbits) & 1u);
-                b = (own[i] << 1) | carry;
+                b = (own[i] << 1) | ((side[i] >> csh) & 1u);
             } else {
                 a = (i == nr - 1) ? halo : own[i < kRows - 1 ? i + 1 : 0];
-                b = wd < W - 1 ? ((own[i] >> 1) | (side[i] << 31))
-                               : ((own[i] >> 1) | ((side[i] & 1u) << lastbits));
+                b = (own[i] >> 1) | ((side[i] & 1u) << csh);
             }
             if (EXT && d.jneg) bp_jflip(d.jneg, L, W, r0 + i, wd, phase, a, b);
             p = bp_planes(a, b, own[i], sgn);
@@ -256,8 +259,9 @@ __global__ __launch_bounds__(256) void k_tri_bp(const ChainDesc *__restrict__ de
     const uint32_t rep = d.replica, sgn = d.sgn;
     const uint32_t *ts = d.tsmall;
     // tail queue: each wavefront fills a region of its own (no shared counter)
+    // block sizes are 64, 128 or 256: one, two or four wavefronts
     const int nwav = (int)(blockDim.x + 63) >> 6, wv = (int)threadIdx.x >> 6;
-    const int qcap_w = kQCap / nwav, qbase = wv * qcap_w;
+    const int qcap_w = kQCap >> (nwav == 4 ? 2 : (nwav == 2 ? 1 : 0)), qbase = wv * qcap_w;
     int wq = 0;  // entries this wavefront has queued (the same in every lane)
     int e_acc = 0, p_acc = 0;
     const bool live = gid < total;
@@ -267,6 +271,10 @@ __global__ __launch_bounds__(256) void k_tri_bp(const ChainDesc *__restrict__ de
     const uint32_t vm = bp_valid(L, W, wd);
     const int lastbits = (L - 1) & 31;
     const int wside = phase == 0 ? (wd > 0 ? wd - 1 : W - 1) : (wd < W - 1 ? wd + 1 : 0);
+    // position of the wrap-around bit: the adjacent word's bit brought to bit 0
+    // (dl) or the bit it lands on (ur); 31 inside a row, the last valid bit at
+    // the row's end
+    const int csh = (phase == 0 ? wd > 0 : wd < W - 1) ? 31 : lastbits;
     uint32_t own[kRows], side[kRows];
 #pragma unroll
     for (int i = 0; i < kRows; ++i) {
@@ -289,14 +297,13 @@ __global__ __launch_bounds__(256) void k_tri_bp(const ChainDesc *__restrict__ de
             if (phase == 0) {
                 a = (i == 0) ? halo : own[i > 0 ? i - 1 : 0];
                 const uint32_t as = (i == 0) ? halo_side : side[i > 0 ? i - 1 : 0];
-                b = (own[i] << 1) | (wd > 0 ? (side[i] >> 31) : ((side[i] >> lastbits) & 1u));
-                e = (a << 1) | (wd > 0 ? (as >> 31) : ((as >> lastbits) & 1u));
+                b = (own[i] << 1) | ((side[i] >> csh) & 1u);
+                e = (a << 1) | ((as >> csh) & 1u);
             } else {
                 a = (i == nr - 1) ? halo : own[i < kRows - 1 ? i + 1 : 0];
                 const uint32_t as = (i == nr - 1) ? halo_side : side[i < kRows - 1 ? i + 1 : 0];
-                b = wd < W - 1 ? ((own[i] >> 1) | (side[i] << 31))
-                               : ((own[i] >> 1) | ((side[i] & 1u) << lastbits));
-                e = wd < W - 1 ? ((a >> 1) | (as << 31)) : ((a >> 1) | ((as & 1u) << lastbits));
+                b = (own[i] >> 1) | ((side[i] & 1u) << csh);
+                e = (a >> 1) | ((as & 1u) << csh);
             }
             p = tri_planes(a, b, e, own[i], sgn, FOLD);
             und = vm;
@@ -870,6 +877,8 @@ hipError_t launch_half_step_grid(const ChainDesc *dev_descs, const ChainDesc *ho
     const bool obs = log_on && even;
     const StepArgs sa{dstate, s_add, s_log0, log_on};
     const int b = block > 0 ? block : 256;
+    // the torus kernels split their tail queue over one, two or four wavefronts
+    if (b != 64 && b != 128 && b != 256) return hipErrorInvalidValue;
     const dim3 grid((maxu + b - 1) / b, nchains);
     if (h0.kind == KIND_TORUS && h0.format == FMT_BITPACKED && h0.tri) {
         // the runtime groups triangular tori apart from square ones
