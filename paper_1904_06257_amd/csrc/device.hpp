@@ -99,6 +99,24 @@ constexpr int kT_nor_and = bitop3_table([](int a, int b, int c) { return !a && !
 constexpr int kT_and_or = bitop3_table([](int a, int b, int c) { return (a && b) || c; });
 constexpr int kT_xor3 = bitop3_table([](int a, int b, int c) { return a ^ b ^ c; });
 constexpr int kT_or_and = bitop3_table([](int a, int b, int c) { return a || (b && c); });
+constexpr int kT_bfi = bitop3_table([](int a, int b, int c) { return a ? b : c; });
+
+// The eight level masks of the folded table's `rest` class (levels 0..7) in
+// vector registers: with one of the three masks of a level there, the class
+// select takes two instructions (each may read only one scalar operand).  A
+// lane permute of the uniform value makes it a per-lane value.
+struct BpRestMasks {
+    uint32_t m[8];
+};
+
+__device__ __forceinline__ BpRestMasks bp_rest_masks(const uint32_t *__restrict__ ts) {
+    BpRestMasks r;
+    const int self = (int)(threadIdx.x & 63u) << 2;
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        r.m[k] = (uint32_t)__builtin_amdgcn_ds_bpermute(self, (int)bitmask(ts[2], 31 - k));
+    return r;
+}
 
 // Bit-planes of a word: the two neighbours of the half (a, b) and the sites
 // themselves (c).  With a uniform coupling a site belongs to class
@@ -171,6 +189,35 @@ __device__ __forceinline__ void bp_groups(const BpPlanes &p, uint32_t &und, uint
         if (und == 0) break;
     }
 #undef SHAKEN_LEVEL
+}
+
+// Folded table, level groups [G0, G1) within the first two, rest-class masks
+// in vector registers (same decisions as bp_groups<true, G0, G1>).
+template <int G0, int G1>
+__device__ __forceinline__ void bp_groups_fold_v(const BpPlanes &p, const BpRestMasks &rm, uint32_t &und,
+                                                 uint32_t &res, uint32_t w, uint32_t s, uint32_t rep,
+                                                 uint32_t k0, uint32_t k1, const uint32_t *__restrict__ ts) {
+    static_assert(G1 <= 2, "rest masks cover levels 0..7");
+    const uint32_t t1 = ts[1], t5 = ts[5];
+#define SHAKEN_VLEVEL(K, R)                                                                    \
+    {                                                                                          \
+        const uint32_t x_ = __builtin_amdgcn_bitop3_b32(p.al, bitmask(t5, 31 - (K)), rm.m[K], kT_bfi); \
+        const uint32_t t_ = __builtin_amdgcn_bitop3_b32(p.one, bitmask(t1, 31 - (K)), x_, kT_bfi);     \
+        const uint32_t d_ = __builtin_amdgcn_bitop3_b32((R), p.smask, t_, kT_xor3);            \
+        const uint32_t y_ = und & d_;                                                          \
+        res = __builtin_amdgcn_bitop3_b32(res, y_, t_, kT_or_and);                             \
+        und &= ~d_;                                                                            \
+    }
+#pragma unroll
+    for (int g = G0; g < G1; ++g) {
+        const U4 r = philox10(w, s, rep, (uint32_t)g, k0, k1);
+        SHAKEN_VLEVEL(4 * g + 0, r.x)
+        SHAKEN_VLEVEL(4 * g + 1, r.y)
+        SHAKEN_VLEVEL(4 * g + 2, r.z)
+        SHAKEN_VLEVEL(4 * g + 3, r.w)
+        if (und == 0) break;
+    }
+#undef SHAKEN_VLEVEL
 }
 
 // New word of 32 sites: a, b neighbour planes of the half, c the sites, vm the

@@ -160,6 +160,8 @@ __global__ __launch_bounds__(256) void k_torus_bp(const ChainDesc *__restrict__ 
         const int rh = phase == 0 ? (r0 == 0 ? L - 1 : r0 - 1) : (r0 + nr == L ? 0 : r0 + nr);
         halo = in[rh * W + wd];
     }
+    BpRestMasks rm;
+    if constexpr (FOLD3) rm = bp_rest_masks(ts);
 #pragma unroll
     for (int i = 0; i < kRows; ++i) {
         const bool act = i < nr;
@@ -177,7 +179,10 @@ __global__ __launch_bounds__(256) void k_torus_bp(const ChainDesc *__restrict__ 
             if (EXT && d.jneg) bp_jflip(d.jneg, L, W, r0 + i, wd, phase, a, b);
             p = bp_planes(a, b, own[i], sgn);
             und = vm;
-            bp_groups<FOLD3, 0, 2>(p, und, res, (uint32_t)widx, s, rep, k0, k1, ts);
+            if constexpr (FOLD3)
+                bp_groups_fold_v<0, 2>(p, rm, und, res, (uint32_t)widx, s, rep, k0, k1, ts);
+            else
+                bp_groups<FOLD3, 0, 2>(p, und, res, (uint32_t)widx, s, rep, k0, k1, ts);
             if (OBS) {
                 e_acc += d.J * (2 * __popc(vm) - 2 * __popc((own[i] ^ a) & vm) -
                                 2 * __popc((own[i] ^ b) & vm));
