@@ -234,6 +234,97 @@ def test_graph_full_size_prefix(sk):
     assert np.array_equal(H, _h_from_plus(inst, ej, plus))
 
 
+def test_graph_full_size_bench_configuration(sk):
+    """The n = 2^20 graph workload as the bench runs it: CSR, int8 spins, a grid
+    batch replayed from a captured HIP graph with autotuned blocks; 100 full
+    steps, every H and M and the final configuration bit-exact."""
+    n, T = 1 << 20, 100
+    _print_case("graph 2^20 bench configuration", T)
+    inst, g = _graph_case(n, 3)
+    sp0 = oracle.graph_init_random(n, 1, 0)
+    want, ej, plus = oracle.graph_run(g, sp0, 1.5, 0.8, 1, 0, T)
+    ch = sk.Chain.graph(n, inst.src, inst.dst, J=inst.J, lam_values=inst.lam_values,
+                        lam_class=inst.cls, q=1.5, beta=0.8, seed=1, replica=0, layout="csr", fmt="int8")
+    b = sk.Batch([ch], strategy="grid", use_hipgraph=True, record=True, autotune=True, log_reserve=T)
+    b.sweep(T)
+    H, M = b.log(0)
+    assert np.array_equal(ch.spins(), want)
+    assert np.array_equal(H, _h_from_plus(inst, ej, plus))
+    ncls = np.bincount(inst.cls, minlength=len(inst.lam_values))
+    assert np.array_equal(M, (2 * plus - ncls[None, :]).sum(axis=1))
+    b.close()
+    ch.close()
+
+
+def _acceptance_z(keys, up, probs):
+    """binomial z-score of the +1 frequency per key (keys with >= 1000 sites)"""
+    zs = []
+    for k in np.unique(keys):
+        sel = keys == k
+        nk = int(sel.sum())
+        p = probs[k]
+        if nk < 1000 or p <= 0.0 or p >= 1.0:
+            if p <= 0.0:
+                assert not np.any(up[sel]), k
+            if p >= 1.0:
+                assert np.all(up[sel]), k
+            continue
+        zs.append((int(up[sel].sum()) - nk * p) / np.sqrt(nk * p * (1 - p)))
+    return np.array(zs)
+
+
+def test_per_class_acceptance_torus(sk):
+    """One half-step of a 1024^2 torus from a random configuration: for every
+    (neighbour sum, own spin) class the frequency of +1 matches the threshold
+    probability T/2^32 of the contract (binomial z-scores)."""
+    L, q, beta, lam = 1024, 1.0, 0.44, 0.0
+    _print_case("acceptance torus", L)
+    ch = sk.Chain.torus(L, q=q, beta=beta, seed=17, replica=3)
+    before = ch.spins().astype(np.int64)
+    ch.half_step(1)
+    after = ch.spins()
+    # half-step 1 (dl): down and left neighbours; row r + 1 is up, column c + 1 right
+    S = np.roll(before, 1, axis=0) + np.roll(before, 1, axis=1)
+    keys = ((S + 2) * 2 + (before > 0)).reshape(-1)
+    probs = {}
+    for Sv in (-2, 0, 2):
+        for sg in (-1, 1):
+            probs[(Sv + 2) * 2 + (sg > 0)] = oracle.threshold_of(Sv, sg, q, lam, beta) / 2.0 ** 32
+    z = _acceptance_z(keys, (after > 0).reshape(-1), probs)
+    print("torus z:", np.round(z, 2), flush=True)
+    assert len(z) == 6 and np.all(np.abs(z) < 5)
+    ch.close()
+
+
+def test_per_class_acceptance_graph(sk):
+    """One half-step of the n = 2^20 graph: +1 frequency per (field sum, own
+    spin, field class) against the threshold probability of the contract."""
+    n, q, beta = 1 << 20, 1.5, 0.8
+    _print_case("acceptance graph", n)
+    inst, g = _graph_case(n, 3)
+    ch = sk.Chain.graph(n, inst.src, inst.dst, J=inst.J, lam_values=inst.lam_values,
+                        lam_class=inst.cls, q=q, beta=beta, seed=5, replica=1)
+    before = ch.spins().astype(np.int64)
+    ch.half_step(1)
+    after = ch.spins()
+    # half-step 1: the in-half, sum over edges (y, x) of J sigma_y
+    S = np.zeros(n, np.int64)
+    np.add.at(S, inst.dst, inst.J.astype(np.int64) * before[inst.src])
+    smax = 3
+    nc = len(inst.lam_values)
+    keys = ((S + smax) * 2 + (before > 0)) * nc + inst.cls
+    probs = {}
+    for Sv in range(-smax, smax + 1):
+        for sg in (-1, 1):
+            for k in range(nc):
+                probs[((Sv + smax) * 2 + (sg > 0)) * nc + k] = oracle.threshold_of(
+                    Sv, sg, q, float(inst.lam_values[k]), beta) / 2.0 ** 32
+    z = _acceptance_z(keys, after > 0, probs)
+    print("graph z:", np.round(z, 2), flush=True)
+    assert len(z) >= 12 and np.all(np.abs(z) < 5)
+    ch.close()
+
+
 def test_graph_lut_matches_oracle(sk):
     inst, g = _graph_case(64, 8)
     ch = sk.Chain.graph(64, inst.src, inst.dst, J=inst.J, lam_values=inst.lam_values,
