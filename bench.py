@@ -14,7 +14,9 @@ persistent launch), ``ea`` (1024 +-J Edwards-Anderson tori 256^2).
 
 Prints one JSON line: metric, value (site-updates/s), roofline of the
 dominant kernel (HIP-event time per launch, algorithmic work per launch) and
-the CPU oracle timed on a bounded sample of the same workload.
+the CPU oracle timed on a bounded sample of the same workload: one sample
+per host core (at most 16), run at once in processes forked before the GPU
+is touched, with the single-process rate beside the aggregate.
 """
 from __future__ import annotations
 
@@ -80,67 +82,108 @@ def read_traffic(kernel_key, per="launch"):
     return float(v) if v else None
 
 
-def cpu_baseline_torus(triangular=False):
-    """The oracle as it stands: ten full steps (twenty half-steps) of one
-    4096^2 chain, single-threaded C (about 10 s of host time)."""
+# ------------------------------------------------------ oracle baselines
+# The oracle as it stands (single-threaded C), timed on the host cores: one
+# independent sample per process, all processes at once (forked before this
+# process touches the GPU); value = all site-updates / the longest process's
+# run time, beside it the median single-process rate.
+
+_BATCH_SPEC = None  # built by the parent before forking, shared by the workers
+
+def _host_cores():
+    n = os.cpu_count() or 1
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit():
+        n = min(n, int(env))
+    return max(1, min(n, 16))
+
+
+def _oracle_torus_sample(args):
     import oracle
-    L, steps = 4096, 10
-    sp = oracle.torus_init_random(L, 2)
+    L, steps, triangular, J, q, beta, seed, rep = args
+    if J == "ea":
+        J = ea_couplings(L, 10_000 + rep)
+    sp = oracle.torus_init_random(L, seed, rep)
     t0 = time.perf_counter()
-    oracle.torus_run(sp, 1, 0.0, 1.0, 0.44, 2, 0, steps, log=False, tri=triangular)
-    dt = time.perf_counter() - t0
-    n = 2 * L * L * steps
-    return {"value": n / dt, "unit": "site-updates/s", "cores": 1, "kind": "oracle",
-            "sample": "%d full steps of one 4096^2 %s chain (q=1, beta=0.44, random init), "
-                      "%.1f s on one host core" % (steps, "triangular-lattice torus" if triangular
-                                                   else "torus", dt)}
+    oracle.torus_run(sp, J, 0.0, q, beta, seed, rep, steps, log=False, tri=triangular)
+    return 2.0 * L * L * steps, time.perf_counter() - t0
+
+
+def _oracle_graph_sample(args):
+    import oracle
+    import synth
+    kind, steps, rep = args
+    if kind == "graph2e20":
+        n = 1 << 20
+        inst = synth.oriented_instance(n, 3, 3, lam_values=(-0.5, 0.0, 0.5), pm_j=True)
+        g = oracle.Graph(n, inst.src, inst.dst, inst.J, inst.cls, inst.lam_values)
+        q, beta, seed = 1.5, 0.8, 1 + rep
+    else:  # one item of the batch spec
+        it = _BATCH_SPEC[kind]
+        if it.kind == "torus":
+            return _oracle_torus_sample((it.size, steps, False, 1, it.q, it.beta, it.seed, kind))
+        gi = it.graph
+        n = gi.n
+        g = oracle.Graph(gi.n, gi.src, gi.dst, gi.J)
+        q, beta, seed = it.q, it.beta, it.seed
+    sp = oracle.graph_init_random(n, seed, rep)
+    t0 = time.perf_counter()
+    oracle.graph_run(g, sp, q, beta, seed, rep, steps, log=False)
+    return 2.0 * n * steps, time.perf_counter() - t0
+
+
+def _run_samples(fn, tasks):
+    import multiprocessing as mp
+    t0 = time.perf_counter()
+    if len(tasks) == 1:
+        res = [fn(tasks[0])]
+    else:
+        with mp.get_context("fork").Pool(len(tasks)) as pool:
+            res = pool.map(fn, tasks)
+    wall = time.perf_counter() - t0
+    work = sum(r[0] for r in res)
+    single = sorted(r[0] / r[1] for r in res)[len(res) // 2]
+    return work / max(r[1] for r in res), single, wall
+
+
+def cpu_baseline_torus(triangular=False):
+    """Five full steps of one 4096^2 chain per host core (about 10-20 s)."""
+    cores = _host_cores()
+    tasks = [(4096, 5, triangular, 1, 1.0, 0.44, 2, r) for r in range(cores)]
+    value, single, wall = _run_samples(_oracle_torus_sample, tasks)
+    lattice = "triangular-lattice torus" if triangular else "torus"
+    return {"value": value, "unit": "site-updates/s", "cores": cores, "kind": "oracle",
+            "single_core_value": single,
+            "sample": "%d processes, each 5 full steps of its own 4096^2 %s chain (q=1, beta=0.44, "
+                      "random init), %.1f s wall" % (cores, lattice, wall)}
 
 
 def cpu_baseline_graph():
-    """The oracle as it stands: 100 full steps of the n = 2^20 graph chain,
-    single-threaded C (about 10 s of host time)."""
-    import oracle
-    import synth
-    n, steps = 1 << 20, 100
-    inst = synth.oriented_instance(n, 3, 3, lam_values=(-0.5, 0.0, 0.5), pm_j=True)
-    g = oracle.Graph(n, inst.src, inst.dst, inst.J, inst.cls, inst.lam_values)
-    sp = oracle.graph_init_random(n, 1, 0)
-    t0 = time.perf_counter()
-    oracle.graph_run(g, sp, 1.5, 0.8, 1, 0, steps, log=False)
-    dt = time.perf_counter() - t0
-    return {"value": 2.0 * n * steps / dt, "unit": "vertex-updates/s", "cores": 1, "kind": "oracle",
-            "sample": "%d full steps of the n=2^20 graph chain, %.1f s on one host core" % (steps, dt)}
+    """100 full steps of the n = 2^20 graph chain per host core (about 10-20 s)."""
+    cores = _host_cores()
+    value, single, wall = _run_samples(_oracle_graph_sample, [("graph2e20", 100, r) for r in range(cores)])
+    return {"value": value, "unit": "vertex-updates/s", "cores": cores, "kind": "oracle",
+            "single_core_value": single,
+            "sample": "%d processes, each 100 full steps of its own chain of the n=2^20 graph, %.1f s "
+                      "wall" % (cores, wall)}
 
 
 def cpu_baseline_batch():
-    """The oracle as it stands on a sample of the 2048-chain batch: the first
-    8 tori and the first 8 graphs of the batch spec (lambda = 0, as the batch
-    runs them), 120 full steps each, one after the other on one host core
-    (about 10 s)."""
-    import oracle
+    """Chains of the 2048-chain batch (lambda = 0, as the batch runs them),
+    alternately tori and graphs from the front of the spec, one per host core,
+    800 full steps each (about 10 s)."""
     import synth
-    spec = synth.batch_spec(1024, 1024, seed=4)
-    tori = [it for it in spec if it.kind == "torus"][:8]
-    graphs = [it for it in spec if it.kind == "graph"][:8]
-    steps, sites, dt = 120, 0, 0.0
-    for i, it in enumerate(tori + graphs):
-        if it.kind == "torus":
-            sp = oracle.torus_init_random(it.size, it.seed, i)
-            t0 = time.perf_counter()
-            oracle.torus_run(sp, 1, 0.0, it.q, it.beta, it.seed, i, steps, log=False)
-            dt += time.perf_counter() - t0
-            sites += it.size * it.size
-        else:
-            gi = it.graph
-            g = oracle.Graph(gi.n, gi.src, gi.dst, gi.J)
-            sp = oracle.graph_init_random(gi.n, it.seed, i)
-            t0 = time.perf_counter()
-            oracle.graph_run(g, sp, it.q, it.beta, it.seed, i, steps, log=False)
-            dt += time.perf_counter() - t0
-            sites += gi.n
-    return {"value": 2.0 * sites * steps / dt, "unit": "site-updates/s", "cores": 1, "kind": "oracle",
-            "sample": "8 tori and 8 graphs of the batch (%d sites), %d full steps each, %.1f s on one "
-                      "host core" % (sites, steps, dt)}
+    global _BATCH_SPEC
+    cores = _host_cores()
+    spec = _BATCH_SPEC = synth.batch_spec(1024, 1024, seed=4)
+    tori = [i for i, it in enumerate(spec) if it.kind == "torus"]
+    graphs = [i for i, it in enumerate(spec) if it.kind == "graph"]
+    pick = [(tori if k % 2 == 0 else graphs)[k // 2] for k in range(cores)]
+    value, single, wall = _run_samples(_oracle_graph_sample, [(i, 800, i) for i in pick])
+    return {"value": value, "unit": "site-updates/s", "cores": cores, "kind": "oracle",
+            "single_core_value": single,
+            "sample": "%d chains of the batch (tori and graphs alternately), one per process, 800 "
+                      "full steps each, %.1f s wall" % (cores, wall)}
 
 
 def bench_torus4096(args, sk, triangular=False):
@@ -247,7 +290,8 @@ def bench_batch(args, sk):
     import numpy as np
     import synth
     import torch
-    spec = synth.batch_spec(1024, 1024, seed=4)
+    # the same spec as the oracle baseline's (built once)
+    spec = _BATCH_SPEC if _BATCH_SPEC is not None else synth.batch_spec(1024, 1024, seed=4)
     chains = []
     sites = 0
     adj_bytes_half = 0
@@ -367,19 +411,14 @@ def bench_ea(args, sk):
 
 
 def cpu_baseline_ea():
-    """The oracle as it stands on one 256^2 +-J torus: 2500 full steps,
-    single-threaded C (about 10 s of host time)."""
-    import oracle
-    L, steps = 256, 2500
-    J = ea_couplings(L, 10_000)
-    sp = oracle.torus_init_random(L, 20_000, 0)
-    t0 = time.perf_counter()
-    oracle.torus_run(sp, J, 0.0, 2.5, 0.5, 20_000, 0, steps, log=False)
-    dt = time.perf_counter() - t0
-    n = 2 * L * L * steps
-    return {"value": n / dt, "unit": "site-updates/s", "cores": 1, "kind": "oracle",
-            "sample": "%d full steps of one 256^2 +-J torus chain (q=2.5, beta=0.5), %.1f s on one "
-                      "host core" % (steps, dt)}
+    """1200 full steps of one 256^2 +-J torus per host core (about 10-20 s)."""
+    cores = _host_cores()
+    tasks = [(256, 1200, False, "ea", 2.5, 0.5, 20_000, r) for r in range(cores)]
+    value, single, wall = _run_samples(_oracle_torus_sample, tasks)
+    return {"value": value, "unit": "site-updates/s", "cores": cores, "kind": "oracle",
+            "single_core_value": single,
+            "sample": "%d processes, each 1200 full steps of its own 256^2 +-J torus (q=2.5, beta=0.5), "
+                      "%.1f s wall" % (cores, wall)}
 
 
 def bench_copycal(args):
@@ -488,6 +527,13 @@ def main():
               "(chains are independent: the work would shard by chain, one process per GPU)",
               file=sys.stderr)
         sys.exit(2)
+    # the oracle baseline runs first, in processes forked before this process
+    # initialises the GPU
+    baselines = {"torus4096": cpu_baseline_torus, "tri4096": lambda: cpu_baseline_torus(triangular=True),
+                 "graph": cpu_baseline_graph, "ea": cpu_baseline_ea, "batch": cpu_baseline_batch}
+    cpu = None
+    if not args.no_cpu_baseline and args.workload in baselines:
+        cpu = baselines[args.workload]()
     import torch
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
@@ -501,23 +547,18 @@ def main():
     if args.workload == "torus4096":
         value, wall, cfg, roof, dtype = bench_torus4096(args, sk)
         metric = "spin-site updates/s (4096^2 torus, batched)"
-        cpu = None if args.no_cpu_baseline else cpu_baseline_torus()
     elif args.workload == "tri4096":
         value, wall, cfg, roof, dtype = bench_torus4096(args, sk, triangular=True)
         metric = "spin-site updates/s (4096^2 triangular-lattice torus, batched)"
-        cpu = None if args.no_cpu_baseline else cpu_baseline_torus(triangular=True)
     elif args.workload == "graph":
         value, wall, cfg, roof, dtype = bench_graph(args, sk)
         metric = "vertex updates/s (3-regular graph, n=2^20)"
-        cpu = None if args.no_cpu_baseline else cpu_baseline_graph()
     elif args.workload == "ea":
         value, wall, cfg, roof, dtype = bench_ea(args, sk)
         metric = "spin-site updates/s (1024 +-J Edwards-Anderson tori 256^2, batched)"
-        cpu = None if args.no_cpu_baseline else cpu_baseline_ea()
     else:
         value, wall, cfg, roof, dtype = bench_batch(args, sk)
         metric = "aggregate site updates/s (2048 mixed chains, persistent batch)"
-        cpu = None if args.no_cpu_baseline else cpu_baseline_batch()
     out = {"metric": metric, "value": value, "unit": "site-updates/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": wall * 1e3 / args.steps, "higher_is_better": True,
