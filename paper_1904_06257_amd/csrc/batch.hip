@@ -235,6 +235,10 @@ __device__ __forceinline__ void graph_lds_half(const ChainDesc &d, const uint32_
         __syncthreads();
     }
     int e_acc = 0;
+    // +1 counts per field class: in registers for up to four classes (one LDS
+    // atomic per wavefront and class at the end), else LDS atomics per vertex
+    int pc[4] = {0, 0, 0, 0};
+    const bool pc_reg = ncls <= 4;
     for (int q4 = threadIdx.x; q4 < nq_pad; q4 += kPBlock) {
         uint32_t bits = 0;
         if (q4 < nq) {
@@ -347,7 +351,14 @@ __device__ __forceinline__ void graph_lds_half(const ChainDesc &d, const uint32_
                     if (v0 + j < n) {
                         const bool up = (ownw >> j) & 1u;
                         e_acc += up ? Sv[j] : -Sv[j];
-                        if (up) atomicAdd(&sh_plus[cl[j]], 1);
+                        if (up) {
+                            if (pc_reg) {
+#pragma unroll
+                                for (int k = 0; k < 4; ++k) pc[k] += cl[j] == k;
+                            } else {
+                                atomicAdd(&sh_plus[cl[j]], 1);
+                            }
+                        }
                     }
                 }
             }
@@ -361,6 +372,14 @@ __device__ __forceinline__ void graph_lds_half(const ChainDesc &d, const uint32_
         }
     }
     if (obs) {
+        if (pc_reg) {
+            const int lane = threadIdx.x & 63;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int t = wave_sum(pc[k]);
+                if (lane == 0 && k < ncls && t) atomicAdd(&sh_plus[k], t);
+            }
+        }
         int dummy = 0;
         block_sum2(e_acc, dummy, sh_red);  // ends with a barrier: sh_plus is complete
         if (threadIdx.x == 0) {
