@@ -198,19 +198,37 @@ void build_tables(shaken_ctx *c) {
         // half) or 4 (triangular: 3 neighbours)
         const int nb = c->tri ? 3 : 2, ncl = 2 * (nb + 1);
         uint32_t sgn = 0;
+        uint64_t Tc[8];
         for (int j = 0; j < ncl; ++j) {
             const int nplus = j % (nb + 1), cb = j / (nb + 1);
             const int64_t S = (int64_t)c->J * (2 * nplus - nb);
             const double h = field_h(S, cb ? 1 : -1, c->q, c->lam[0]);
             const uint64_t T = threshold_T(h, c->beta);
             const uint64_t t = (h >= 0.0) ? ((uint64_t)1 << 32) - T : T;
+            Tc[j] = T;
             c->hd.tsmall[j] = (uint32_t)t;
             if (h >= 0.0) sgn |= 1u << j;
         }
-        c->hd.sgn = sgn;
+        // Folded table: mirror classes j and ncl-1-j (one neighbour count
+        // reversed, the site flipped) with equal t.  On the square lattice the
+        // folded kernels also take the two signs to be opposite; a class with
+        // T = 2^31 has t = 2^31 and decides alike with either sign, so it
+        // takes the sign opposite to its mirror's.
         const uint32_t *t = c->hd.tsmall;
+        const uint64_t half = (uint64_t)1 << 31;
         bool fold = true;
-        for (int j = 0; j < ncl / 2; ++j) fold = fold && t[j] == t[ncl - 1 - j];
+        for (int j = 0; j < ncl / 2; ++j) {
+            const int k = ncl - 1 - j;
+            fold = fold && t[j] == t[k];
+            if (((sgn >> j) ^ (sgn >> k)) & 1u) continue;
+            if (Tc[k] == half)
+                sgn ^= 1u << k;
+            else if (Tc[j] == half)
+                sgn ^= 1u << j;
+            else if (!c->tri)
+                fold = false;
+        }
+        c->hd.sgn = sgn;
         c->hd.fold3 = fold ? 1 : 0;
     }
 }

@@ -6,6 +6,19 @@
 
 namespace shaken {
 
+// words in the global address space
+typedef __attribute__((address_space(1))) uint32_t gmem_u32;
+typedef __attribute__((address_space(1))) char gmem_char;
+
+// word idx of a global array through a 32-bit byte offset (idx < 2^30), so
+// that the access takes the scalar-base form
+__device__ __forceinline__ gmem_u32 &gword(gmem_u32 *base, uint32_t idx) {
+    return *(gmem_u32 *)((gmem_char *)base + (idx << 2));
+}
+__device__ __forceinline__ uint32_t gload(const gmem_u32 *base, uint32_t idx) {
+    return *(const gmem_u32 *)((const gmem_char *)base + (idx << 2));
+}
+
 // ------------------------------------------------------------------ Philox
 
 struct U4 {
@@ -101,7 +114,7 @@ constexpr int kT_xor3 = bitop3_table([](int a, int b, int c) { return a ^ b ^ c;
 constexpr int kT_or_and = bitop3_table([](int a, int b, int c) { return a || (b && c); });
 constexpr int kT_bfi = bitop3_table([](int a, int b, int c) { return a ? b : c; });
 
-// The eight level masks of the folded table's `rest` class (levels 0..7) in
+// The eight level masks of the folded table's rest class (levels 0..7) in
 // vector registers: with one of the three masks of a level there, the class
 // select takes two instructions (each may read only one scalar operand).  A
 // lane permute of the uniform value makes it a per-lane value.
@@ -109,22 +122,21 @@ struct BpRestMasks {
     uint32_t m[8];
 };
 
-__device__ __forceinline__ BpRestMasks bp_rest_masks(const uint32_t *__restrict__ ts) {
+__device__ __forceinline__ BpRestMasks bp_rest_masks(uint32_t rest) {
     BpRestMasks r;
     const int self = (int)(threadIdx.x & 63u) << 2;
 #pragma unroll
     for (int k = 0; k < 8; ++k)
-        r.m[k] = (uint32_t)__builtin_amdgcn_ds_bpermute(self, (int)bitmask(ts[2], 31 - k));
+        r.m[k] = (uint32_t)__builtin_amdgcn_ds_bpermute(self, (int)bitmask(rest, 31 - k));
     return r;
 }
 
-// Bit-planes of a word: the two neighbours of the half (a, b) and the sites
-// themselves (c).  With a uniform coupling a site belongs to class
-// j = n_plus + 3c; the sign plane says where h >= 0 (from the per-chain mask
-// sgn), `al` where the neighbours agree with the site (classes 0 and 5), `one`
-// where exactly one neighbour is +1.
+// Bit-planes of a word for the six-class table: the two neighbours of the
+// half (a, b) and the sites themselves (c).  With a uniform coupling a site
+// belongs to class j = n_plus + 3c; the sign plane says where h >= 0 (from
+// the per-chain mask sgn).
 struct BpPlanes {
-    uint32_t one, both, al, c, smask;
+    uint32_t one, both, c, smask;
 };
 
 __device__ __forceinline__ BpPlanes bp_planes(uint32_t a, uint32_t b, uint32_t c, uint32_t sgn) {
@@ -140,7 +152,6 @@ __device__ __forceinline__ BpPlanes bp_planes(uint32_t a, uint32_t b, uint32_t c
     shi = __builtin_amdgcn_bitop3_b32(p.one, bitmask(sgn, 4), shi, kT_and_or);
     shi = __builtin_amdgcn_bitop3_b32(p.both, bitmask(sgn, 5), shi, kT_and_or);
     p.smask = bfi(c, shi, slo);
-    p.al = ~(a ^ c) & ~p.one;
     p.c = c;
     return p;
 }
@@ -151,7 +162,7 @@ __device__ __forceinline__ BpPlanes bp_planes(uint32_t a, uint32_t b, uint32_t c
 // und: sites still undecided; res: sites decided with v < t, where v = u with
 // the bits flipped where h >= 0 (u < 2^32 - t  <=>  not (~u < t)), so only
 // t <= 2^31 is compared.
-template <bool FOLD3, int G0, int G1>
+template <int G0, int G1>
 __device__ __forceinline__ void bp_groups(const BpPlanes &p, uint32_t &und, uint32_t &res,
                                           uint32_t w, uint32_t s, uint32_t rep, uint32_t k0,
                                           uint32_t k1, const uint32_t *__restrict__ ts) {
@@ -159,21 +170,11 @@ __device__ __forceinline__ void bp_groups(const BpPlanes &p, uint32_t &und, uint
 #define SHAKEN_LEVEL(K, R)                                                                    \
     {                                                                                         \
         const int sh_ = 31 - (K);                                                             \
-        uint32_t t_;                                                                          \
-        if (FOLD3) {                                                                          \
-            /* one scalar operand per instruction: rest&m2, then |al&m5, then |one&m1 */      \
-            const uint32_t z_ = __builtin_amdgcn_bitop3_b32(p.one, p.al, bitmask(t2, sh_),    \
-                                                            kT_nor_and);                      \
-            const uint32_t w_ = __builtin_amdgcn_bitop3_b32(p.al, bitmask(t5, sh_), z_,       \
-                                                            kT_and_or);                       \
-            t_ = __builtin_amdgcn_bitop3_b32(p.one, bitmask(t1, sh_), w_, kT_and_or);         \
-        } else {                                                                              \
-            const uint32_t lo_ = bfi(p.both, bitmask(t2, sh_),                                \
-                                     bfi(p.one, bitmask(t1, sh_), bitmask(t0, sh_)));         \
-            const uint32_t hi_ = bfi(p.both, bitmask(t5, sh_),                                \
-                                     bfi(p.one, bitmask(t4, sh_), bitmask(t3, sh_)));         \
-            t_ = bfi(p.c, hi_, lo_);                                                          \
-        }                                                                                     \
+        const uint32_t lo_ = bfi(p.both, bitmask(t2, sh_),                                    \
+                                 bfi(p.one, bitmask(t1, sh_), bitmask(t0, sh_)));             \
+        const uint32_t hi_ = bfi(p.both, bitmask(t5, sh_),                                    \
+                                 bfi(p.one, bitmask(t4, sh_), bitmask(t3, sh_)));             \
+        const uint32_t t_ = bfi(p.c, hi_, lo_);                                               \
         const uint32_t d_ = __builtin_amdgcn_bitop3_b32((R), p.smask, t_, kT_xor3);          \
         const uint32_t y_ = und & d_; /* decided at this level */                             \
         res = __builtin_amdgcn_bitop3_b32(res, y_, t_, kT_or_and);                            \
@@ -191,33 +192,134 @@ __device__ __forceinline__ void bp_groups(const BpPlanes &p, uint32_t &und, uint
 #undef SHAKEN_LEVEL
 }
 
-// Folded table, level groups [G0, G1) within the first two, rest-class masks
-// in vector registers (same decisions as bp_groups<true, G0, G1>).
+// ------------------------------------------- folded table (uniform coupling)
+// With the thresholds equal in mirror classes j and 5 - j three classes
+// remain: `one` (exactly one +1 neighbour: classes 1 and 4), `al` (the
+// neighbours agree with the site: 0 and 5) and `rest` (2 and 3).  The host
+// keeps this table only where mirror classes also have opposite signs of h
+// (a class with T = 2^31 decides alike with either sign), so the flip plane
+// is smask = c ^ F(class), F the sign bit of the member whose site is -1.
+// F is folded into the class words, tf = t ^ F, and a site compares u with
+// y = tf ^ c = t ^ smask: u < T holds exactly when (u ^ smask) < t, whose
+// value is t's bit at the most significant level where the two differ, that
+// is y's bit at the most significant level where u and y differ (smask when
+// all 32 levels agree).
+struct FoldT {
+    uint32_t one, al, rest;
+};
+
+__device__ __forceinline__ FoldT fold_t(const uint32_t *__restrict__ ts, uint32_t sgn) {
+    return FoldT{ts[1] ^ bitmask(sgn, 1), ts[0] ^ bitmask(sgn, 0), ts[2] ^ bitmask(sgn, 2)};
+}
+
+struct FoldPlanes {
+    uint32_t one, al, c;
+};
+
+constexpr int kT_al = bitop3_table([](int a, int c, int one) { return a == c && !one; });
+// o' = y where u and y differ, else o
+constexpr int kT_first = bitop3_table([](int u, int y, int o) { return u != y ? y : o; });
+// eq' = eq where u and y agree
+constexpr int kT_and_eq = bitop3_table([](int e, int u, int y) { return e && u == y; });
+// out' = out, or ~u where newly decided (there y = ~u)
+constexpr int kT_or_andn = bitop3_table([](int o, int e, int u) { return o || (e && !u); });
+
+__device__ __forceinline__ FoldPlanes fold_planes(uint32_t a, uint32_t b, uint32_t c) {
+    FoldPlanes p;
+    p.one = a ^ b;
+    p.al = __builtin_amdgcn_bitop3_b32(a, c, p.one, kT_al);
+    p.c = c;
+    return p;
+}
+
+// tf's bit `sh` of each site's class, one scalar operand per instruction
+__device__ __forceinline__ uint32_t fold_select(const FoldPlanes &p, const FoldT &ft, int sh) {
+    uint32_t x = __builtin_amdgcn_bitop3_b32(p.one, p.al, bitmask(ft.rest, sh), kT_nor_and);
+    x = __builtin_amdgcn_bitop3_b32(p.al, bitmask(ft.al, sh), x, kT_and_or);
+    return __builtin_amdgcn_bitop3_b32(p.one, bitmask(ft.one, sh), x, kT_and_or);
+}
+
+// the flip plane smask, needed only where all 32 levels agree
+__device__ __forceinline__ uint32_t fold_smask(const FoldPlanes &p, uint32_t sgn) {
+    uint32_t f = __builtin_amdgcn_bitop3_b32(p.one, p.al, bitmask(sgn, 2), kT_nor_and);
+    f = __builtin_amdgcn_bitop3_b32(p.al, bitmask(sgn, 0), f, kT_and_or);
+    f = __builtin_amdgcn_bitop3_b32(p.one, bitmask(sgn, 1), f, kT_and_or);
+    return f ^ p.c;
+}
+
+// Levels 0..7 (groups 0 and 1) least significant first: afterwards o holds
+// y's bit at the most significant differing level of every site whose top
+// eight bits of u and y differ, and eq marks the sites where all eight agree
+// (o is not meaningful there).  A level costs the class select, y = tf ^ c
+// and one instruction each for o and eq; the MSB-first form needs one more
+// (decided sites, result, undecided sites).  VREST: rest-class words in
+// vector registers (two-instruction select).
+template <bool VREST>
+__device__ __forceinline__ void fold_top8(const FoldPlanes &p, const FoldT &ft, const BpRestMasks &rm,
+                                          uint32_t &o, uint32_t &eq, uint32_t w, uint32_t s,
+                                          uint32_t rep, uint32_t k0, uint32_t k1) {
+#define SHAKEN_FLEVEL(K, R)                                                                       \
+    {                                                                                             \
+        uint32_t t_;                                                                              \
+        if (VREST) {                                                                              \
+            const uint32_t x_ = __builtin_amdgcn_bitop3_b32(p.al, bitmask(ft.al, 31 - (K)),       \
+                                                            rm.m[K], kT_bfi);                     \
+            t_ = __builtin_amdgcn_bitop3_b32(p.one, bitmask(ft.one, 31 - (K)), x_, kT_bfi);       \
+        } else {                                                                                  \
+            t_ = fold_select(p, ft, 31 - (K));                                                    \
+        }                                                                                         \
+        const uint32_t y_ = t_ ^ p.c;                                                             \
+        o = __builtin_amdgcn_bitop3_b32((R), y_, o, kT_first);                                    \
+        eq = __builtin_amdgcn_bitop3_b32(eq, (R), y_, kT_and_eq);                                 \
+    }
+    const U4 r1 = philox10(w, s, rep, 1u, k0, k1);
+    SHAKEN_FLEVEL(7, r1.w)
+    SHAKEN_FLEVEL(6, r1.z)
+    SHAKEN_FLEVEL(5, r1.y)
+    SHAKEN_FLEVEL(4, r1.x)
+    const U4 r0 = philox10(w, s, rep, 0u, k0, k1);
+    SHAKEN_FLEVEL(3, r0.w)
+    SHAKEN_FLEVEL(2, r0.z)
+    SHAKEN_FLEVEL(1, r0.y)
+    SHAKEN_FLEVEL(0, r0.x)
+#undef SHAKEN_FLEVEL
+}
+
+// Levels of groups [G0, G1) most significant first for the sites in und;
+// out collects the new spins of the sites decided.
 template <int G0, int G1>
-__device__ __forceinline__ void bp_groups_fold_v(const BpPlanes &p, const BpRestMasks &rm, uint32_t &und,
-                                                 uint32_t &res, uint32_t w, uint32_t s, uint32_t rep,
-                                                 uint32_t k0, uint32_t k1, const uint32_t *__restrict__ ts) {
-    static_assert(G1 <= 2, "rest masks cover levels 0..7");
-    const uint32_t t1 = ts[1], t5 = ts[5];
-#define SHAKEN_VLEVEL(K, R)                                                                    \
-    {                                                                                          \
-        const uint32_t x_ = __builtin_amdgcn_bitop3_b32(p.al, bitmask(t5, 31 - (K)), rm.m[K], kT_bfi); \
-        const uint32_t t_ = __builtin_amdgcn_bitop3_b32(p.one, bitmask(t1, 31 - (K)), x_, kT_bfi);     \
-        const uint32_t d_ = __builtin_amdgcn_bitop3_b32((R), p.smask, t_, kT_xor3);            \
-        const uint32_t y_ = und & d_;                                                          \
-        res = __builtin_amdgcn_bitop3_b32(res, y_, t_, kT_or_and);                             \
-        und &= ~d_;                                                                            \
+__device__ __forceinline__ void fold_groups(const FoldPlanes &p, const FoldT &ft, uint32_t &und,
+                                            uint32_t &out, uint32_t w, uint32_t s, uint32_t rep,
+                                            uint32_t k0, uint32_t k1) {
+#define SHAKEN_GLEVEL(K, R)                                                                       \
+    {                                                                                             \
+        const uint32_t t_ = fold_select(p, ft, 31 - (K));                                         \
+        const uint32_t d_ = __builtin_amdgcn_bitop3_b32((R), p.c, t_, kT_xor3); /* u != y */      \
+        const uint32_t e_ = und & d_;                                                             \
+        out = __builtin_amdgcn_bitop3_b32(out, e_, (R), kT_or_andn);                              \
+        und &= ~d_;                                                                               \
     }
 #pragma unroll
     for (int g = G0; g < G1; ++g) {
         const U4 r = philox10(w, s, rep, (uint32_t)g, k0, k1);
-        SHAKEN_VLEVEL(4 * g + 0, r.x)
-        SHAKEN_VLEVEL(4 * g + 1, r.y)
-        SHAKEN_VLEVEL(4 * g + 2, r.z)
-        SHAKEN_VLEVEL(4 * g + 3, r.w)
+        SHAKEN_GLEVEL(4 * g + 0, r.x)
+        SHAKEN_GLEVEL(4 * g + 1, r.y)
+        SHAKEN_GLEVEL(4 * g + 2, r.z)
+        SHAKEN_GLEVEL(4 * g + 3, r.w)
         if (und == 0) break;
     }
-#undef SHAKEN_VLEVEL
+#undef SHAKEN_GLEVEL
+}
+
+// Finish a word on the folded table from level group G0 on: und the sites
+// still undecided, out the new spins of the others.
+template <int G0>
+__device__ __forceinline__ uint32_t fold_finish(const FoldPlanes &p, const FoldT &ft, uint32_t und,
+                                                uint32_t out, uint32_t vm, uint32_t w, uint32_t s,
+                                                uint32_t rep, uint32_t k0, uint32_t k1, uint32_t sgn) {
+    fold_groups<G0, 8>(p, ft, und, out, w, s, rep, k0, k1);
+    if (und) out |= und & fold_smask(p, sgn);
+    return out & vm;
 }
 
 // New word of 32 sites: a, b neighbour planes of the half, c the sites, vm the
@@ -227,10 +329,20 @@ __device__ __forceinline__ uint32_t bp_word(uint32_t a, uint32_t b, uint32_t c, 
                                             uint32_t w, uint32_t s, uint32_t rep, uint32_t k0,
                                             uint32_t k1, const uint32_t *__restrict__ ts,
                                             uint32_t sgn) {
-    const BpPlanes p = bp_planes(a, b, c, sgn);
-    uint32_t und = vm, res = 0;
-    bp_groups<FOLD3, 0, 8>(p, und, res, w, s, rep, k0, k1, ts);
-    return (res ^ p.smask) & vm;
+    if constexpr (FOLD3) {
+        const FoldPlanes p = fold_planes(a, b, c);
+        const FoldT ft = fold_t(ts, sgn);
+        uint32_t o = 0, eq = ~0u;
+        fold_top8<false>(p, ft, BpRestMasks{}, o, eq, w, s, rep, k0, k1);
+        const uint32_t und = eq & vm;
+        if (und == 0) return o & vm;
+        return fold_finish<2>(p, ft, und, o & ~eq, vm, w, s, rep, k0, k1, sgn);
+    } else {
+        const BpPlanes p = bp_planes(a, b, c, sgn);
+        uint32_t und = vm, res = 0;
+        bp_groups<0, 8>(p, und, res, w, s, rep, k0, k1, ts);
+        return (res ^ p.smask) & vm;
+    }
 }
 
 // ------------------------------------------ bit-packed triangular lattice

@@ -64,15 +64,22 @@ __device__ __forceinline__ int step_slot(const StepArgs &a, uint32_t s) {
     return (int)((s - (a.dstate ? a.dstate[1] : a.s_log0)) >> 1);
 }
 
-// Finish a word whose first level groups left sites undecided (groups 2..7).
-template <bool FOLD3>
+// Finish a word whose first level groups left sites undecided (groups
+// G0..7).  Six-class table: res holds the sites decided with v < t; folded
+// table: the new spins of the sites decided.
+template <bool FOLD3, int G0 = 2>
 __device__ __noinline__ uint32_t bp_finish(uint32_t a, uint32_t b, uint32_t c, uint32_t und,
                                            uint32_t res, uint32_t vm, uint32_t w, uint32_t s,
                                            uint32_t rep, uint32_t k0, uint32_t k1,
                                            const uint32_t *__restrict__ ts, uint32_t sgn) {
-    const BpPlanes p = bp_planes(a, b, c, sgn);
-    bp_groups<FOLD3, 2, 8>(p, und, res, w, s, rep, k0, k1, ts);
-    return (res ^ p.smask) & vm;
+    if constexpr (FOLD3) {
+        return fold_finish<G0>(fold_planes(a, b, c), fold_t(ts, sgn), und, res, vm, w, s, rep, k0, k1, sgn);
+    } else {
+        static_assert(G0 == 2, "six-class words are finished from group 2");
+        const BpPlanes p = bp_planes(a, b, c, sgn);
+        bp_groups<2, 8>(p, und, res, w, s, rep, k0, k1, ts);
+        return (res ^ p.smask) & vm;
+    }
 }
 
 // One lane owns a strip of kRows words of one word column: it loads the strip,
@@ -88,6 +95,13 @@ __device__ __noinline__ uint32_t bp_finish(uint32_t a, uint32_t b, uint32_t c, u
 // region of its own at a slot it computes from its ballot (no shared counter,
 // no broadcast); a region that fills up finishes its words in place.
 constexpr int kQCap = 512;
+// Folded table: words still undecided after level group 2 of the tail move to
+// a second, short queue (about 1 in 15 of the first queue's), so that the rare
+// deeper groups run in one wavefront instead of in all of them.
+constexpr int kQ2Cap = 128;
+// A queued word index carries this flag where the word is the last of its row
+// with bits past the side (its valid-bit mask is the row end's).
+constexpr uint32_t kLastWord = 0x80000000u;
 
 // Tail queue in wavefront regions of qcap_w entries, cnt[r] of them used:
 // the total, and the slot of the it-th entry in region order.
@@ -108,9 +122,12 @@ __device__ __forceinline__ int tail_slot(const int *cnt, int nwav, int qcap_w, i
 // EXT: instantiation for chains with +-J sign planes or a frozen set (the
 // plain instantiation reads neither)
 template <bool OBS, bool FOLD3, bool EXT>
-__global__ __launch_bounds__(256) void k_torus_bp(const ChainDesc *__restrict__ descs, StepArgs sa) {
+__global__ __launch_bounds__(256, (OBS && FOLD3 && !EXT) ? 5 : 1) void k_torus_bp(const ChainDesc *__restrict__ descs, StepArgs sa) {
     __shared__ uint32_t q_w[kQCap], q_a[kQCap], q_b[kQCap], q_c[kQCap], q_und[kQCap], q_res[kQCap];
     __shared__ int q_cnt[4];  // entries queued per wavefront region
+    __shared__ uint32_t q2_w[FOLD3 ? kQ2Cap : 1], q2_a[FOLD3 ? kQ2Cap : 1], q2_b[FOLD3 ? kQ2Cap : 1],
+        q2_c[FOLD3 ? kQ2Cap : 1], q2_und[FOLD3 ? kQ2Cap : 1], q2_res[FOLD3 ? kQ2Cap : 1];
+    __shared__ int q2_cnt;
     const ChainDesc &d = descs[blockIdx.y];
     const uint32_t s = step_s(sa);
     const int bufp = (int)(s & 1u);      // configuration at s lives in spin[s & 1]
@@ -121,8 +138,10 @@ __global__ __launch_bounds__(256) void k_torus_bp(const ChainDesc *__restrict__ 
     const int total = nrb * W;
     const int bx = xcd_block(blockIdx.x, gridDim.x);
     const int gid = bx * blockDim.x + threadIdx.x;
-    const uint32_t *__restrict__ in = (const uint32_t *)d.spin[bufp];
-    uint32_t *__restrict__ out = (uint32_t *)d.spin[bufp ^ 1];
+    // global (not generic) pointers: stores and loads address through a
+    // scalar base, and they do not count against the LDS wait counter
+    const gmem_u32 *__restrict__ in = (const gmem_u32 *)d.spin[bufp];
+    gmem_u32 *__restrict__ out = (gmem_u32 *)d.spin[bufp ^ 1];
     const uint32_t k0 = (uint32_t)d.seed, k1 = (uint32_t)(d.seed >> 32);
     const uint32_t rep = d.replica, sgn = d.sgn;
     const uint32_t *ts = d.tsmall;
@@ -148,8 +167,8 @@ __global__ __launch_bounds__(256) void k_torus_bp(const ChainDesc *__restrict__ 
 #pragma unroll
     for (int i = 0; i < kRows; ++i) {
         if (i < nr) {
-            own[i] = in[(r0 + i) * W + wd];
-            side[i] = in[(r0 + i) * W + wside];
+            own[i] = gload(in, (uint32_t)((r0 + i) * W + wd));
+            side[i] = gload(in, (uint32_t)((r0 + i) * W + wside));
         } else {
             own[i] = 0u;
             side[i] = 0u;
@@ -158,69 +177,127 @@ __global__ __launch_bounds__(256) void k_torus_bp(const ChainDesc *__restrict__ 
     uint32_t halo = 0;
     if (live) {
         const int rh = phase == 0 ? (r0 == 0 ? L - 1 : r0 - 1) : (r0 + nr == L ? 0 : r0 + nr);
-        halo = in[rh * W + wd];
+        halo = gload(in, (uint32_t)(rh * W + wd));
     }
     BpRestMasks rm;
-    if constexpr (FOLD3) rm = bp_rest_masks(ts);
+    FoldT ft;
+    if constexpr (FOLD3) {
+        ft = fold_t(ts, sgn);
+        rm = bp_rest_masks(ft.rest);
+    }
 #pragma unroll
     for (int i = 0; i < kRows; ++i) {
+        // rows past the strip (and lanes past the grid) are computed with no
+        // valid sites: nothing undecided, nothing stored
         const bool act = i < nr;
-        uint32_t a = 0, b = 0, und = 0, res = 0;
-        BpPlanes p;
+        const uint32_t vmi = act ? vm : 0u;
         const int widx = (r0 + i) * W + wd;
-        if (act) {
-            if (phase == 0) {
-                a = (i == 0) ? halo : own[i > 0 ? i - 1 : 0];
-                b = (own[i] << 1) | ((side[i] >> csh) & 1u);
-            } else {
-                a = (i == nr - 1) ? halo : own[i < kRows - 1 ? i + 1 : 0];
-                b = (own[i] >> 1) | ((side[i] & 1u) << csh);
-            }
-            if (EXT && d.jneg) bp_jflip(d.jneg, L, W, r0 + i, wd, phase, a, b);
-            p = bp_planes(a, b, own[i], sgn);
-            und = vm;
-            if constexpr (FOLD3)
-                bp_groups_fold_v<0, 2>(p, rm, und, res, (uint32_t)widx, s, rep, k0, k1, ts);
-            else
-                bp_groups<FOLD3, 0, 2>(p, und, res, (uint32_t)widx, s, rep, k0, k1, ts);
-            if (OBS) {
-                e_acc += d.J * (2 * __popc(vm) - 2 * __popc((own[i] ^ a) & vm) -
-                                2 * __popc((own[i] ^ b) & vm));
-                p_acc += __popc(own[i] & vm);
+        uint32_t a, b;
+        if (phase == 0) {
+            a = (i == 0) ? halo : own[i > 0 ? i - 1 : 0];
+            b = (own[i] << 1) | ((side[i] >> csh) & 1u);
+        } else {
+            a = (i == nr - 1) ? halo : own[i < kRows - 1 ? i + 1 : 0];
+            b = (own[i] >> 1) | ((side[i] & 1u) << csh);
+        }
+        if (EXT && d.jneg && act) bp_jflip(d.jneg, L, W, r0 + i, wd, phase, a, b);
+        if (OBS) {
+            e_acc += d.J * (2 * __popc(vmi) - 2 * __popc((own[i] ^ a) & vmi) -
+                            2 * __popc((own[i] ^ b) & vmi));
+            p_acc += __popc(own[i] & vmi);
+        }
+        // folded table: res = new spins of the sites decided; six classes:
+        // the sites decided with v < t (the flip plane applied at the store)
+        uint32_t und, res, smask = 0;
+        if constexpr (FOLD3) {
+            uint32_t o = 0, eq = ~0u;
+            fold_top8<true>(fold_planes(a, b, own[i]), ft, rm, o, eq, (uint32_t)widx, s, rep, k0, k1);
+            und = eq & vmi;
+            res = o & ~eq;
+        } else {
+            // under the row's own branch: merged across rows, the scalar
+            // level masks of the six classes would not fit the scalar registers
+            und = 0;
+            res = 0;
+            if (act) {
+                const BpPlanes p = bp_planes(a, b, own[i], sgn);
+                smask = p.smask;
+                und = vm;
+                bp_groups<0, 2>(p, und, res, (uint32_t)widx, s, rep, k0, k1, ts);
             }
         }
-        const bool pend = act && und != 0;
+        const bool pend = und != 0;
         const unsigned long long bal = __ballot(pend);
-        if (act) {
+        if (pend) {
             // slot in the wavefront's region: entries queued so far + pending lanes below
             const int q = wq + (int)__builtin_amdgcn_mbcnt_hi(
                                    (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-            if (!pend) {
-                out[widx] = ((res ^ p.smask) & vm) | (EXT ? frozen_word(d, widx) : 0u);
-            } else if (q < qcap_w) {
+            if (q < qcap_w) {
                 const int qs = qbase + q;
-                q_w[qs] = (uint32_t)widx;
+                q_w[qs] = (uint32_t)widx | (vm != ~0u ? kLastWord : 0u);
                 q_a[qs] = a;
                 q_b[qs] = b;
                 q_c[qs] = own[i];
                 q_und[qs] = und;
                 q_res[qs] = res;
             } else {
-                out[widx] = bp_finish<FOLD3>(a, b, own[i], und, res, vm, (uint32_t)widx, s, rep, k0, k1, ts, sgn) |
+                gword(out, (uint32_t)widx) = bp_finish<FOLD3>(a, b, own[i], und, res, vm, (uint32_t)widx, s, rep, k0, k1, ts, sgn) |
                             (EXT ? frozen_word(d, widx) : 0u);
             }
+        } else if (act) {
+            gword(out, (uint32_t)widx) = ((res ^ smask) & vm) | (EXT ? frozen_word(d, widx) : 0u);
         }
         wq += (int)__popcll(bal);
     }
     if ((threadIdx.x & 63) == 0) q_cnt[wv] = min(wq, qcap_w);
+    if (FOLD3 && threadIdx.x == 0) q2_cnt = 0;
     __syncthreads();
     const int Q = tail_total(q_cnt, nwav);
-    for (int it = threadIdx.x; it < Q; it += blockDim.x) {
-        const int qs = tail_slot(q_cnt, nwav, qcap_w, it);
-        const uint32_t w = q_w[qs];
-        const uint32_t vw = bp_valid(L, W, (int)(w % (uint32_t)W));
-        out[w] = bp_finish<FOLD3>(q_a[qs], q_b[qs], q_c[qs], q_und[qs], q_res[qs], vw, w, s, rep, k0,
-                                  k1, ts, sgn) | (EXT ? frozen_word(d, (int)w) : 0u);
+    const uint32_t vlast = bp_valid(L, W, W - 1);
+    if constexpr (FOLD3) {
+        // stage 1: level group 2 of every queued word
+        for (int it = threadIdx.x; it < Q; it += blockDim.x) {
+            const int qs = tail_slot(q_cnt, nwav, qcap_w, it);
+            const uint32_t wf = q_w[qs], w = wf & ~kLastWord;
+            const uint32_t vw = (wf & kLastWord) ? vlast : ~0u;
+            const uint32_t a = q_a[qs], b = q_b[qs], c = q_c[qs];
+            uint32_t und = q_und[qs], o = q_res[qs];
+            fold_groups<2, 3>(fold_planes(a, b, c), ft, und, o, w, s, rep, k0, k1);
+            if (und == 0) {
+                gword(out, w) = (o & vw) | (EXT ? frozen_word(d, (int)w) : 0u);
+            } else {
+                const int q2 = atomicAdd(&q2_cnt, 1);
+                if (q2 < kQ2Cap) {
+                    q2_w[q2] = wf;
+                    q2_a[q2] = a;
+                    q2_b[q2] = b;
+                    q2_c[q2] = c;
+                    q2_und[q2] = und;
+                    q2_res[q2] = o;
+                } else {
+                    gword(out, w) = bp_finish<true, 3>(a, b, c, und, o, vw, w, s, rep, k0, k1, ts, sgn) |
+                                    (EXT ? frozen_word(d, (int)w) : 0u);
+                }
+            }
+        }
+        __syncthreads();
+        // stage 2: groups 3..7 of the words still undecided
+        const int Q2 = min(q2_cnt, kQ2Cap);
+        for (int it = threadIdx.x; it < Q2; it += blockDim.x) {
+            const uint32_t wf = q2_w[it], w = wf & ~kLastWord;
+            const uint32_t vw = (wf & kLastWord) ? vlast : ~0u;
+            gword(out, w) = bp_finish<true, 3>(q2_a[it], q2_b[it], q2_c[it], q2_und[it], q2_res[it], vw, w, s,
+                                               rep, k0, k1, ts, sgn) |
+                            (EXT ? frozen_word(d, (int)w) : 0u);
+        }
+    } else {
+        for (int it = threadIdx.x; it < Q; it += blockDim.x) {
+            const int qs = tail_slot(q_cnt, nwav, qcap_w, it);
+            const uint32_t wf = q_w[qs], w = wf & ~kLastWord;
+            const uint32_t vw = (wf & kLastWord) ? vlast : ~0u;
+            gword(out, w) = bp_finish<false>(q_a[qs], q_b[qs], q_c[qs], q_und[qs], q_res[qs], vw, w, s, rep, k0,
+                                             k1, ts, sgn) | (EXT ? frozen_word(d, (int)w) : 0u);
+        }
     }
     if (OBS && bx * (int)blockDim.x < total)
         block_accumulate2(e_acc, p_acc, log_part(d, slot, bx));
@@ -258,8 +335,10 @@ __global__ __launch_bounds__(256) void k_tri_bp(const ChainDesc *__restrict__ de
     const int total = nrb * W;
     const int bx = xcd_block(blockIdx.x, gridDim.x);
     const int gid = bx * blockDim.x + threadIdx.x;
-    const uint32_t *__restrict__ in = (const uint32_t *)d.spin[bufp];
-    uint32_t *__restrict__ out = (uint32_t *)d.spin[bufp ^ 1];
+    // global (not generic) pointers: stores and loads address through a
+    // scalar base, and they do not count against the LDS wait counter
+    const gmem_u32 *__restrict__ in = (const gmem_u32 *)d.spin[bufp];
+    gmem_u32 *__restrict__ out = (gmem_u32 *)d.spin[bufp ^ 1];
     const uint32_t k0 = (uint32_t)d.seed, k1 = (uint32_t)(d.seed >> 32);
     const uint32_t rep = d.replica, sgn = d.sgn;
     const uint32_t *ts = d.tsmall;
@@ -283,14 +362,14 @@ __global__ __launch_bounds__(256) void k_tri_bp(const ChainDesc *__restrict__ de
     uint32_t own[kRows], side[kRows];
 #pragma unroll
     for (int i = 0; i < kRows; ++i) {
-        own[i] = i < nr ? in[(r0 + i) * W + wd] : 0u;
-        side[i] = i < nr ? in[(r0 + i) * W + wside] : 0u;
+        own[i] = i < nr ? gload(in, (uint32_t)((r0 + i) * W + wd)) : 0u;
+        side[i] = i < nr ? gload(in, (uint32_t)((r0 + i) * W + wside)) : 0u;
     }
     uint32_t halo = 0, halo_side = 0;
     if (live) {
         const int rh = phase == 0 ? (r0 == 0 ? L - 1 : r0 - 1) : (r0 + nr == L ? 0 : r0 + nr);
-        halo = in[rh * W + wd];
-        halo_side = in[rh * W + wside];
+        halo = gload(in, (uint32_t)(rh * W + wd));
+        halo_side = gload(in, (uint32_t)(rh * W + wside));
     }
 #pragma unroll
     for (int i = 0; i < kRows; ++i) {
@@ -326,10 +405,10 @@ __global__ __launch_bounds__(256) void k_tri_bp(const ChainDesc *__restrict__ de
             const int q = wq + (int)__builtin_amdgcn_mbcnt_hi(
                                    (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
             if (!pend) {
-                out[widx] = ((res ^ p.smask) & vm) | frozen_word(d, widx);
+                gword(out, (uint32_t)widx) = ((res ^ p.smask) & vm) | frozen_word(d, widx);
             } else if (q < qcap_w) {
                 const int qs = qbase + q;
-                q_w[qs] = (uint32_t)widx;
+                q_w[qs] = (uint32_t)widx | (vm != ~0u ? kLastWord : 0u);
                 q_a[qs] = a;
                 q_b[qs] = b;
                 q_e[qs] = e;
@@ -337,7 +416,7 @@ __global__ __launch_bounds__(256) void k_tri_bp(const ChainDesc *__restrict__ de
                 q_und[qs] = und;
                 q_res[qs] = res;
             } else {
-                out[widx] = tri_finish<FOLD>(a, b, e, own[i], und, res, vm, (uint32_t)widx, s, rep, k0, k1,
+                gword(out, (uint32_t)widx) = tri_finish<FOLD>(a, b, e, own[i], und, res, vm, (uint32_t)widx, s, rep, k0, k1,
                                              ts, sgn) | frozen_word(d, widx);
             }
         }
@@ -348,9 +427,9 @@ __global__ __launch_bounds__(256) void k_tri_bp(const ChainDesc *__restrict__ de
     const int Q = tail_total(q_cnt, nwav);
     for (int it = threadIdx.x; it < Q; it += blockDim.x) {
         const int qs = tail_slot(q_cnt, nwav, qcap_w, it);
-        const uint32_t w = q_w[qs];
-        const uint32_t vw = bp_valid(L, W, (int)(w % (uint32_t)W));
-        out[w] = tri_finish<FOLD>(q_a[qs], q_b[qs], q_e[qs], q_c[qs], q_und[qs], q_res[qs], vw, w, s, rep,
+        const uint32_t wf = q_w[qs], w = wf & ~kLastWord;
+        const uint32_t vw = (wf & kLastWord) ? bp_valid(L, W, W - 1) : ~0u;
+        gword(out, w) = tri_finish<FOLD>(q_a[qs], q_b[qs], q_e[qs], q_c[qs], q_und[qs], q_res[qs], vw, w, s, rep,
                                   k0, k1, ts, sgn) | frozen_word(d, (int)w);
     }
     if (OBS && bx * (int)blockDim.x < total)
