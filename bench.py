@@ -36,23 +36,46 @@ sys.path.insert(0, ROOT)
 VALU_PEAK = 256 * 64 * 2.4e9
 HBM_PEAK_GBS = 8000.0
 
-# Algorithmic ALU work of one bit-packed site-update, in VALU lane-cycles:
-# per 32-site word, E[G] = 1.999 Philox4x32-10
-# calls (the MSB-first compare stops once all 32 sites of the word are
-# decided; levels come in groups of 4), 40 lane-cycles per call (20
-# v_mad_u64_u32 + 20 three-input xors, both full rate on gfx950), 4 E[G]
-# compare levels x 6 lane-cycles, 15 lane-cycles of neighbour, class and sign
-# planes per word: (80.0 + 48.0 + 15) / 32 = 4.47.
+# Algorithmic ALU work of one bit-packed site-update, in VALU lane-cycles, per
+# 32-site word on the folded class table (the workloads' lambda = 0):
+#  * levels come in groups of four, one Philox4x32-10 call each; every word
+#    takes groups 0 and 1 (levels 0..7), and group g >= 2 where some site is
+#    still undecided after 4g levels, DEEP_GROUPS = 0.126 groups per word on
+#    average; 40 lane-cycles per call (20 v_mad_u64_u32 + 20 three-input xors,
+#    both full rate on gfx950);
+#  * levels 0..7 least significant first at `level_top` lane-cycles each
+#    (class select, y = tf ^ c, result, agreement); the deeper levels most
+#    significant first at `level_deep` (class select, difference, result and
+#    undecided);
+#  * `planes` lane-cycles of class planes and output per word.
 PHILOX_LC = 40.0
-BP_ALU_PER_SITE = (1.999 * PHILOX_LC + 4 * 1.999 * 6 + 15) / 32.0
+
+
+def _undecided(levels):
+    """P(a 32-site word is still undecided after `levels` levels)."""
+    return 1.0 - (1.0 - 2.0 ** -levels) ** 32
+
+
+DEEP_GROUPS = sum(_undecided(4 * g) for g in range(2, 8))   # 0.126
+
+
+def _alu_per_site(level_top, level_deep, planes):
+    return ((2.0 + DEEP_GROUPS) * PHILOX_LC + 8 * level_top + 4 * DEEP_GROUPS * level_deep
+            + planes) / 32.0
+
+
+# square lattice: select 2 (rest-class words in vector registers), deeper
+# levels select 3; planes `one`, `al` and the output: 4.11
+BP_ALU_PER_SITE = _alu_per_site(5, 7, 3)
 BP_BYTES_PER_SITE = 0.25  # read 1 bit, write 1 bit
-# +-J torus: two more xors per word flip the neighbour planes by the coupling signs
-BP_ALU_PER_SITE_PMJ = BP_ALU_PER_SITE + 2.0 / 32.0
-# triangular lattice (three neighbour planes a, b, e): the diagonal plane e
-# (shift and insert, 2), the count planes n1 = a^b^e and n2 = maj(a, b, e)
-# (one three-input op each, 2) and the agreement planes of the folded table
-# (3): 7 more lane-cycles per word; the folded compare keeps 6 per level.
-TRI_ALU_PER_SITE = BP_ALU_PER_SITE + 7.0 / 32.0
+# tori in the persistent kernel (LDS-resident): the class select takes 3 at
+# every level (no vector-register class words there); +-J couplings: two more
+# xors per word flip the neighbour planes by the coupling signs
+BP_ALU_PER_SITE_PMJ = _alu_per_site(6, 7, 3) + 2.0 / 32.0
+# triangular lattice (three neighbour planes a, b, e, four agreement classes):
+# select 4; planes: the diagonal plane e (shift and insert, 2), the agreement
+# parity and majority (2 each), the one-hot classes (3), the output (1): 4.85
+TRI_ALU_PER_SITE = _alu_per_site(7, 8, 10)
 
 
 def kernel_source_hash():

@@ -209,11 +209,10 @@ void build_tables(shaken_ctx *c) {
             c->hd.tsmall[j] = (uint32_t)t;
             if (h >= 0.0) sgn |= 1u << j;
         }
-        // Folded table: mirror classes j and ncl-1-j (one neighbour count
-        // reversed, the site flipped) with equal t.  On the square lattice the
-        // folded kernels also take the two signs to be opposite; a class with
-        // T = 2^31 has t = 2^31 and decides alike with either sign, so it
-        // takes the sign opposite to its mirror's.
+        // Folded table: mirror classes j and ncl-1-j (the neighbour count
+        // reversed, the site flipped) with equal t and opposite signs.  A
+        // class with T = 2^31 has t = 2^31 and decides alike with either sign,
+        // so it takes the sign opposite to its mirror's.
         const uint32_t *t = c->hd.tsmall;
         const uint64_t half = (uint64_t)1 << 31;
         bool fold = true;
@@ -225,7 +224,7 @@ void build_tables(shaken_ctx *c) {
                 sgn ^= 1u << k;
             else if (Tc[j] == half)
                 sgn ^= 1u << j;
-            else if (!c->tri)
+            else
                 fold = false;
         }
         c->hd.sgn = sgn;

@@ -239,36 +239,42 @@ __device__ __forceinline__ uint32_t fold_select(const FoldPlanes &p, const FoldT
     return __builtin_amdgcn_bitop3_b32(p.one, bitmask(ft.one, sh), x, kT_and_or);
 }
 
-// the flip plane smask, needed only where all 32 levels agree
-__device__ __forceinline__ uint32_t fold_smask(const FoldPlanes &p, uint32_t sgn) {
-    uint32_t f = __builtin_amdgcn_bitop3_b32(p.one, p.al, bitmask(sgn, 2), kT_nor_and);
-    f = __builtin_amdgcn_bitop3_b32(p.al, bitmask(sgn, 0), f, kT_and_or);
-    f = __builtin_amdgcn_bitop3_b32(p.one, bitmask(sgn, 1), f, kT_and_or);
-    return f ^ p.c;
-}
+// Class-word selectors of the folded tables: sel(k) is the bit of level k
+// (0 = most significant) of each site's class word tf, c() the sites, and
+// smask(sgn) the flip plane (needed only where all 32 levels agree).
+struct SqSel {  // square lattice, the three class words scalar
+    FoldPlanes p;
+    FoldT ft;
+    __device__ __forceinline__ uint32_t c() const { return p.c; }
+    __device__ __forceinline__ uint32_t sel(int k) const { return fold_select(p, ft, 31 - k); }
+    __device__ __forceinline__ uint32_t smask(uint32_t sgn) const {
+        uint32_t f = __builtin_amdgcn_bitop3_b32(p.one, p.al, bitmask(sgn, 2), kT_nor_and);
+        f = __builtin_amdgcn_bitop3_b32(p.al, bitmask(sgn, 0), f, kT_and_or);
+        f = __builtin_amdgcn_bitop3_b32(p.one, bitmask(sgn, 1), f, kT_and_or);
+        return f ^ p.c;
+    }
+};
+
+struct SqSelV : SqSel {  // rest-class words of levels 0..7 in vector registers
+    const BpRestMasks *rm;
+    __device__ __forceinline__ uint32_t sel(int k) const {
+        const uint32_t x = __builtin_amdgcn_bitop3_b32(p.al, bitmask(ft.al, 31 - k), rm->m[k], kT_bfi);
+        return __builtin_amdgcn_bitop3_b32(p.one, bitmask(ft.one, 31 - k), x, kT_bfi);
+    }
+};
 
 // Levels 0..7 (groups 0 and 1) least significant first: afterwards o holds
 // y's bit at the most significant differing level of every site whose top
 // eight bits of u and y differ, and eq marks the sites where all eight agree
 // (o is not meaningful there).  A level costs the class select, y = tf ^ c
 // and one instruction each for o and eq; the MSB-first form needs one more
-// (decided sites, result, undecided sites).  VREST: rest-class words in
-// vector registers (two-instruction select).
-template <bool VREST>
-__device__ __forceinline__ void fold_top8(const FoldPlanes &p, const FoldT &ft, const BpRestMasks &rm,
-                                          uint32_t &o, uint32_t &eq, uint32_t w, uint32_t s,
+// (decided sites, result, undecided sites).
+template <class S>
+__device__ __forceinline__ void fold_top8(const S &sl, uint32_t &o, uint32_t &eq, uint32_t w, uint32_t s,
                                           uint32_t rep, uint32_t k0, uint32_t k1) {
 #define SHAKEN_FLEVEL(K, R)                                                                       \
     {                                                                                             \
-        uint32_t t_;                                                                              \
-        if (VREST) {                                                                              \
-            const uint32_t x_ = __builtin_amdgcn_bitop3_b32(p.al, bitmask(ft.al, 31 - (K)),       \
-                                                            rm.m[K], kT_bfi);                     \
-            t_ = __builtin_amdgcn_bitop3_b32(p.one, bitmask(ft.one, 31 - (K)), x_, kT_bfi);       \
-        } else {                                                                                  \
-            t_ = fold_select(p, ft, 31 - (K));                                                    \
-        }                                                                                         \
-        const uint32_t y_ = t_ ^ p.c;                                                             \
+        const uint32_t y_ = sl.sel(K) ^ sl.c();                                                   \
         o = __builtin_amdgcn_bitop3_b32((R), y_, o, kT_first);                                    \
         eq = __builtin_amdgcn_bitop3_b32(eq, (R), y_, kT_and_eq);                                 \
     }
@@ -287,14 +293,12 @@ __device__ __forceinline__ void fold_top8(const FoldPlanes &p, const FoldT &ft, 
 
 // Levels of groups [G0, G1) most significant first for the sites in und;
 // out collects the new spins of the sites decided.
-template <int G0, int G1>
-__device__ __forceinline__ void fold_groups(const FoldPlanes &p, const FoldT &ft, uint32_t &und,
-                                            uint32_t &out, uint32_t w, uint32_t s, uint32_t rep,
-                                            uint32_t k0, uint32_t k1) {
+template <class S, int G0, int G1>
+__device__ __forceinline__ void fold_groups(const S &sl, uint32_t &und, uint32_t &out, uint32_t w,
+                                            uint32_t s, uint32_t rep, uint32_t k0, uint32_t k1) {
 #define SHAKEN_GLEVEL(K, R)                                                                       \
     {                                                                                             \
-        const uint32_t t_ = fold_select(p, ft, 31 - (K));                                         \
-        const uint32_t d_ = __builtin_amdgcn_bitop3_b32((R), p.c, t_, kT_xor3); /* u != y */      \
+        const uint32_t d_ = __builtin_amdgcn_bitop3_b32((R), sl.c(), sl.sel(K), kT_xor3); /* u != y */ \
         const uint32_t e_ = und & d_;                                                             \
         out = __builtin_amdgcn_bitop3_b32(out, e_, (R), kT_or_andn);                              \
         und &= ~d_;                                                                               \
@@ -311,15 +315,26 @@ __device__ __forceinline__ void fold_groups(const FoldPlanes &p, const FoldT &ft
 #undef SHAKEN_GLEVEL
 }
 
-// Finish a word on the folded table from level group G0 on: und the sites
+// Finish a word on a folded table from level group G0 on: und the sites
 // still undecided, out the new spins of the others.
-template <int G0>
-__device__ __forceinline__ uint32_t fold_finish(const FoldPlanes &p, const FoldT &ft, uint32_t und,
-                                                uint32_t out, uint32_t vm, uint32_t w, uint32_t s,
-                                                uint32_t rep, uint32_t k0, uint32_t k1, uint32_t sgn) {
-    fold_groups<G0, 8>(p, ft, und, out, w, s, rep, k0, k1);
-    if (und) out |= und & fold_smask(p, sgn);
+template <class S, int G0>
+__device__ __forceinline__ uint32_t fold_finish(const S &sl, uint32_t und, uint32_t out, uint32_t vm,
+                                                uint32_t w, uint32_t s, uint32_t rep, uint32_t k0,
+                                                uint32_t k1, uint32_t sgn) {
+    fold_groups<S, G0, 8>(sl, und, out, w, s, rep, k0, k1);
+    if (und) out |= und & sl.smask(sgn);
     return out & vm;
+}
+
+// a whole word on a folded table
+template <class S>
+__device__ __forceinline__ uint32_t fold_word(const S &sl, uint32_t vm, uint32_t w, uint32_t s, uint32_t rep,
+                                              uint32_t k0, uint32_t k1, uint32_t sgn) {
+    uint32_t o = 0, eq = ~0u;
+    fold_top8(sl, o, eq, w, s, rep, k0, k1);
+    const uint32_t und = eq & vm;
+    if (und == 0) return o & vm;
+    return fold_finish<S, 2>(sl, und, o & ~eq, vm, w, s, rep, k0, k1, sgn);
 }
 
 // New word of 32 sites: a, b neighbour planes of the half, c the sites, vm the
@@ -330,13 +345,7 @@ __device__ __forceinline__ uint32_t bp_word(uint32_t a, uint32_t b, uint32_t c, 
                                             uint32_t k1, const uint32_t *__restrict__ ts,
                                             uint32_t sgn) {
     if constexpr (FOLD3) {
-        const FoldPlanes p = fold_planes(a, b, c);
-        const FoldT ft = fold_t(ts, sgn);
-        uint32_t o = 0, eq = ~0u;
-        fold_top8<false>(p, ft, BpRestMasks{}, o, eq, w, s, rep, k0, k1);
-        const uint32_t und = eq & vm;
-        if (und == 0) return o & vm;
-        return fold_finish<2>(p, ft, und, o & ~eq, vm, w, s, rep, k0, k1, sgn);
+        return fold_word(SqSel{fold_planes(a, b, c), fold_t(ts, sgn)}, vm, w, s, rep, k0, k1, sgn);
     } else {
         const BpPlanes p = bp_planes(a, b, c, sgn);
         uint32_t und = vm, res = 0;
@@ -356,42 +365,74 @@ __device__ __forceinline__ uint32_t bp_word(uint32_t a, uint32_t b, uint32_t c, 
 // way by k1, k2 over the agreement planes.
 struct TriPlanes {
     uint32_t s1, s2, c, smask;
-    uint32_t k1, k2, k3;  // folded table: one-hot planes of classes 1..3 (class 0 from s1, s2)
 };
 
 __device__ __forceinline__ uint32_t maj3(uint32_t a, uint32_t b, uint32_t e) {
     return (a & b) | (a & e) | (b & e);
 }
 
+// eight-class planes: n_plus coded by s1, s2; the flip plane from sgn
 __device__ __forceinline__ TriPlanes tri_planes(uint32_t a, uint32_t b, uint32_t e, uint32_t c,
-                                                uint32_t sgn, bool fold) {
+                                                uint32_t sgn) {
     TriPlanes p;
     p.c = c;
-    const uint32_t n1 = a ^ b ^ e, n2 = maj3(a, b, e);
-    const uint32_t slo = bfi(n2, bfi(n1, bitmask(sgn, 3), bitmask(sgn, 2)),
-                             bfi(n1, bitmask(sgn, 1), bitmask(sgn, 0)));
-    const uint32_t shi = bfi(n2, bfi(n1, bitmask(sgn, 7), bitmask(sgn, 6)),
-                             bfi(n1, bitmask(sgn, 5), bitmask(sgn, 4)));
+    p.s1 = a ^ b ^ e;
+    p.s2 = maj3(a, b, e);
+    const uint32_t slo = bfi(p.s2, bfi(p.s1, bitmask(sgn, 3), bitmask(sgn, 2)),
+                             bfi(p.s1, bitmask(sgn, 1), bitmask(sgn, 0)));
+    const uint32_t shi = bfi(p.s2, bfi(p.s1, bitmask(sgn, 7), bitmask(sgn, 6)),
+                             bfi(p.s1, bitmask(sgn, 5), bitmask(sgn, 4)));
     p.smask = bfi(c, shi, slo);
-    if (fold) {
-        // agreement planes: k = n_plus where the site is +1, 3 - n_plus where -1
-        const uint32_t xa = ~(a ^ c), xb = ~(b ^ c), xe = ~(e ^ c);
-        p.s1 = xa ^ xb ^ xe;
-        p.s2 = maj3(xa, xb, xe);
-        p.k1 = p.s1 & ~p.s2;
-        p.k2 = ~p.s1 & p.s2;
-        p.k3 = p.s1 & p.s2;
-    } else {
-        p.s1 = n1;
-        p.s2 = n2;
-        p.k1 = p.k2 = p.k3 = 0u;
-    }
     return p;
 }
 
-// MSB-first compare of the 32 bit-sliced uniforms with the eight (or, folded,
-// four) class thresholds, level groups [G0, G1); same contract as bp_groups.
-template <bool FOLD, int G0, int G1>
+// Folded table in the flipped domain (same contract as the square lattice's
+// SqSel): agreement class k holds the mirror classes (3 - k, -1) and (k, +1)
+// of the same t; the host keeps the table only where their signs are
+// opposite, so the flip plane is c ^ F_k with F_k the sign of (3 - k, -1),
+// bit 3 - k of sgn, and the class words are tf_k = t_{4+k} ^ F_k.
+struct TriSel {
+    uint32_t s1, s2, k1, k2, k3, cc;
+    uint32_t tf[4];
+    __device__ __forceinline__ uint32_t c() const { return cc; }
+    __device__ __forceinline__ uint32_t sel(int k) const {
+        const int sh = 31 - k;
+        uint32_t x = __builtin_amdgcn_bitop3_b32(s1, s2, bitmask(tf[0], sh), kT_nor_and);
+        x = __builtin_amdgcn_bitop3_b32(k1, bitmask(tf[1], sh), x, kT_and_or);
+        x = __builtin_amdgcn_bitop3_b32(k2, bitmask(tf[2], sh), x, kT_and_or);
+        return __builtin_amdgcn_bitop3_b32(k3, bitmask(tf[3], sh), x, kT_and_or);
+    }
+    __device__ __forceinline__ uint32_t smask(uint32_t sgn) const {
+        uint32_t f = __builtin_amdgcn_bitop3_b32(s1, s2, bitmask(sgn, 3), kT_nor_and);
+        f = __builtin_amdgcn_bitop3_b32(k1, bitmask(sgn, 2), f, kT_and_or);
+        f = __builtin_amdgcn_bitop3_b32(k2, bitmask(sgn, 1), f, kT_and_or);
+        f = __builtin_amdgcn_bitop3_b32(k3, bitmask(sgn, 0), f, kT_and_or);
+        return f ^ cc;
+    }
+};
+
+constexpr int kT_xnor = bitop3_table([](int a, int b, int) { return a == b; });
+
+// the agreement planes of a word: s1 = odd agreement count, s2 = at least
+// two; n_plus's parity and majority xnor the site (three complements of
+// a ^ c, b ^ c, e ^ c)
+__device__ __forceinline__ TriSel tri_sel(uint32_t a, uint32_t b, uint32_t e, uint32_t c,
+                                          const uint32_t *__restrict__ ts, uint32_t sgn) {
+    TriSel t;
+    t.cc = c;
+    t.s1 = ~(a ^ b ^ e ^ c);
+    t.s2 = __builtin_amdgcn_bitop3_b32(maj3(a, b, e), c, 0u, kT_xnor);
+    t.k1 = t.s1 & ~t.s2;
+    t.k2 = ~t.s1 & t.s2;
+    t.k3 = t.s1 & t.s2;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) t.tf[k] = ts[4 + k] ^ bitmask(sgn, 3 - k);
+    return t;
+}
+
+// MSB-first compare of the 32 bit-sliced uniforms with the eight class
+// thresholds, level groups [G0, G1); same contract as bp_groups.
+template <int G0, int G1>
 __device__ __forceinline__ void tri_groups(const TriPlanes &p, uint32_t &und, uint32_t &res,
                                            uint32_t w, uint32_t s, uint32_t rep, uint32_t k0,
                                            uint32_t k1, const uint32_t *__restrict__ ts) {
@@ -400,20 +441,11 @@ __device__ __forceinline__ void tri_groups(const TriPlanes &p, uint32_t &und, ui
 #define SHAKEN_TLEVEL(K, R)                                                                       \
     {                                                                                             \
         const int sh_ = 31 - (K);                                                                 \
-        uint32_t t_;                                                                              \
-        if (FOLD) {                                                                               \
-            /* one scalar operand per instruction over the one-hot class planes */                \
-            uint32_t x_ = __builtin_amdgcn_bitop3_b32(p.s1, p.s2, bitmask(t4, sh_), kT_nor_and);  \
-            x_ = __builtin_amdgcn_bitop3_b32(p.k1, bitmask(t5, sh_), x_, kT_and_or);              \
-            x_ = __builtin_amdgcn_bitop3_b32(p.k2, bitmask(t6, sh_), x_, kT_and_or);              \
-            t_ = __builtin_amdgcn_bitop3_b32(p.k3, bitmask(t7, sh_), x_, kT_and_or);              \
-        } else {                                                                                  \
-            const uint32_t lo_ = bfi(p.s2, bfi(p.s1, bitmask(t3, sh_), bitmask(t2, sh_)),         \
-                                     bfi(p.s1, bitmask(t1, sh_), bitmask(t0, sh_)));              \
-            const uint32_t hi_ = bfi(p.s2, bfi(p.s1, bitmask(t7, sh_), bitmask(t6, sh_)),         \
-                                     bfi(p.s1, bitmask(t5, sh_), bitmask(t4, sh_)));              \
-            t_ = bfi(p.c, hi_, lo_);                                                              \
-        }                                                                                         \
+        const uint32_t lo_ = bfi(p.s2, bfi(p.s1, bitmask(t3, sh_), bitmask(t2, sh_)),             \
+                                 bfi(p.s1, bitmask(t1, sh_), bitmask(t0, sh_)));                  \
+        const uint32_t hi_ = bfi(p.s2, bfi(p.s1, bitmask(t7, sh_), bitmask(t6, sh_)),             \
+                                 bfi(p.s1, bitmask(t5, sh_), bitmask(t4, sh_)));                  \
+        const uint32_t t_ = bfi(p.c, hi_, lo_);                                                   \
         const uint32_t d_ = __builtin_amdgcn_bitop3_b32((R), p.smask, t_, kT_xor3);              \
         const uint32_t y_ = und & d_; /* decided at this level */                                 \
         res = __builtin_amdgcn_bitop3_b32(res, y_, t_, kT_or_and);                                \
@@ -437,10 +469,14 @@ __device__ __forceinline__ uint32_t tri_word(uint32_t a, uint32_t b, uint32_t e,
                                              uint32_t vm, uint32_t w, uint32_t s, uint32_t rep,
                                              uint32_t k0, uint32_t k1,
                                              const uint32_t *__restrict__ ts, uint32_t sgn) {
-    const TriPlanes p = tri_planes(a, b, e, c, sgn, FOLD);
-    uint32_t und = vm, res = 0;
-    tri_groups<FOLD, 0, 8>(p, und, res, w, s, rep, k0, k1, ts);
-    return (res ^ p.smask) & vm;
+    if constexpr (FOLD) {
+        return fold_word(tri_sel(a, b, e, c, ts, sgn), vm, w, s, rep, k0, k1, sgn);
+    } else {
+        const TriPlanes p = tri_planes(a, b, e, c, sgn);
+        uint32_t und = vm, res = 0;
+        tri_groups<0, 8>(p, und, res, w, s, rep, k0, k1, ts);
+        return (res ^ p.smask) & vm;
+    }
 }
 
 // +-J torus: flip the neighbour planes a (vertical) and b (horizontal) of

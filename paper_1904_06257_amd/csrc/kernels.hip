@@ -73,7 +73,8 @@ __device__ __noinline__ uint32_t bp_finish(uint32_t a, uint32_t b, uint32_t c, u
                                            uint32_t rep, uint32_t k0, uint32_t k1,
                                            const uint32_t *__restrict__ ts, uint32_t sgn) {
     if constexpr (FOLD3) {
-        return fold_finish<G0>(fold_planes(a, b, c), fold_t(ts, sgn), und, res, vm, w, s, rep, k0, k1, sgn);
+        return fold_finish<SqSel, G0>(SqSel{fold_planes(a, b, c), fold_t(ts, sgn)}, und, res, vm, w, s, rep, k0,
+                                      k1, sgn);
     } else {
         static_assert(G0 == 2, "six-class words are finished from group 2");
         const BpPlanes p = bp_planes(a, b, c, sgn);
@@ -211,7 +212,11 @@ __global__ __launch_bounds__(256, (OBS && FOLD3 && !EXT) ? 5 : 1) void k_torus_b
         uint32_t und, res, smask = 0;
         if constexpr (FOLD3) {
             uint32_t o = 0, eq = ~0u;
-            fold_top8<true>(fold_planes(a, b, own[i]), ft, rm, o, eq, (uint32_t)widx, s, rep, k0, k1);
+            SqSelV sl;
+            sl.p = fold_planes(a, b, own[i]);
+            sl.ft = ft;
+            sl.rm = &rm;
+            fold_top8(sl, o, eq, (uint32_t)widx, s, rep, k0, k1);
             und = eq & vmi;
             res = o & ~eq;
         } else {
@@ -262,7 +267,7 @@ __global__ __launch_bounds__(256, (OBS && FOLD3 && !EXT) ? 5 : 1) void k_torus_b
             const uint32_t vw = (wf & kLastWord) ? vlast : ~0u;
             const uint32_t a = q_a[qs], b = q_b[qs], c = q_c[qs];
             uint32_t und = q_und[qs], o = q_res[qs];
-            fold_groups<2, 3>(fold_planes(a, b, c), ft, und, o, w, s, rep, k0, k1);
+            fold_groups<SqSel, 2, 3>(SqSel{fold_planes(a, b, c), ft}, und, o, w, s, rep, k0, k1);
             if (und == 0) {
                 gword(out, w) = (o & vw) | (EXT ? frozen_word(d, (int)w) : 0u);
             } else {
@@ -310,14 +315,19 @@ __global__ __launch_bounds__(256, (OBS && FOLD3 && !EXT) ? 5 : 1) void k_torus_b
 // the up-right neighbours, the row above shifted right with the carry of its
 // right word).
 
-template <bool FOLD>
+template <bool FOLD, int G0 = 2>
 __device__ __noinline__ uint32_t tri_finish(uint32_t a, uint32_t b, uint32_t e, uint32_t c,
                                             uint32_t und, uint32_t res, uint32_t vm, uint32_t w,
                                             uint32_t s, uint32_t rep, uint32_t k0, uint32_t k1,
                                             const uint32_t *__restrict__ ts, uint32_t sgn) {
-    const TriPlanes p = tri_planes(a, b, e, c, sgn, FOLD);
-    tri_groups<FOLD, 2, 8>(p, und, res, w, s, rep, k0, k1, ts);
-    return (res ^ p.smask) & vm;
+    if constexpr (FOLD) {
+        return fold_finish<TriSel, G0>(tri_sel(a, b, e, c, ts, sgn), und, res, vm, w, s, rep, k0, k1, sgn);
+    } else {
+        static_assert(G0 == 2, "eight-class words are finished from group 2");
+        const TriPlanes p = tri_planes(a, b, e, c, sgn);
+        tri_groups<2, 8>(p, und, res, w, s, rep, k0, k1, ts);
+        return (res ^ p.smask) & vm;
+    }
 }
 
 template <bool OBS, bool FOLD>
@@ -325,6 +335,9 @@ __global__ __launch_bounds__(256) void k_tri_bp(const ChainDesc *__restrict__ de
     __shared__ uint32_t q_w[kQCap], q_a[kQCap], q_b[kQCap], q_e[kQCap], q_c[kQCap], q_und[kQCap],
         q_res[kQCap];
     __shared__ int q_cnt[4];  // entries queued per wavefront region
+    __shared__ uint32_t q2_w[FOLD ? kQ2Cap : 1], q2_a[FOLD ? kQ2Cap : 1], q2_b[FOLD ? kQ2Cap : 1],
+        q2_e[FOLD ? kQ2Cap : 1], q2_c[FOLD ? kQ2Cap : 1], q2_und[FOLD ? kQ2Cap : 1], q2_res[FOLD ? kQ2Cap : 1];
+    __shared__ int q2_cnt;
     const ChainDesc &d = descs[blockIdx.y];
     const uint32_t s = step_s(sa);
     const int bufp = (int)(s & 1u);
@@ -373,40 +386,55 @@ __global__ __launch_bounds__(256) void k_tri_bp(const ChainDesc *__restrict__ de
     }
 #pragma unroll
     for (int i = 0; i < kRows; ++i) {
+        // rows past the strip (and lanes past the grid) are computed with no
+        // valid sites: nothing undecided, nothing stored
         const bool act = i < nr;
-        uint32_t a = 0, b = 0, e = 0, und = 0, res = 0;
-        TriPlanes p;
+        const uint32_t vmi = act ? vm : 0u;
         const int widx = (r0 + i) * W + wd;
-        if (act) {
-            if (phase == 0) {
-                a = (i == 0) ? halo : own[i > 0 ? i - 1 : 0];
-                const uint32_t as = (i == 0) ? halo_side : side[i > 0 ? i - 1 : 0];
-                b = (own[i] << 1) | ((side[i] >> csh) & 1u);
-                e = (a << 1) | ((as >> csh) & 1u);
-            } else {
-                a = (i == nr - 1) ? halo : own[i < kRows - 1 ? i + 1 : 0];
-                const uint32_t as = (i == nr - 1) ? halo_side : side[i < kRows - 1 ? i + 1 : 0];
-                b = (own[i] >> 1) | ((side[i] & 1u) << csh);
-                e = (a >> 1) | ((as & 1u) << csh);
-            }
-            p = tri_planes(a, b, e, own[i], sgn, FOLD);
-            und = vm;
-            tri_groups<FOLD, 0, 2>(p, und, res, (uint32_t)widx, s, rep, k0, k1, ts);
-            if (OBS) {
-                e_acc += d.J * (3 * __popc(vm) - 2 * __popc((own[i] ^ a) & vm) -
-                                2 * __popc((own[i] ^ b) & vm) - 2 * __popc((own[i] ^ e) & vm));
-                p_acc += __popc(own[i] & vm);
+        uint32_t a, b, e;
+        if (phase == 0) {
+            a = (i == 0) ? halo : own[i > 0 ? i - 1 : 0];
+            const uint32_t as = (i == 0) ? halo_side : side[i > 0 ? i - 1 : 0];
+            b = (own[i] << 1) | ((side[i] >> csh) & 1u);
+            e = (a << 1) | ((as >> csh) & 1u);
+        } else {
+            a = (i == nr - 1) ? halo : own[i < kRows - 1 ? i + 1 : 0];
+            const uint32_t as = (i == nr - 1) ? halo_side : side[i < kRows - 1 ? i + 1 : 0];
+            b = (own[i] >> 1) | ((side[i] & 1u) << csh);
+            e = (a >> 1) | ((as & 1u) << csh);
+        }
+        if (OBS) {
+            e_acc += d.J * (3 * __popc(vmi) - 2 * __popc((own[i] ^ a) & vmi) -
+                            2 * __popc((own[i] ^ b) & vmi) - 2 * __popc((own[i] ^ e) & vmi));
+            p_acc += __popc(own[i] & vmi);
+        }
+        // folded table: res = new spins of the sites decided; eight classes:
+        // the sites decided with v < t (the flip plane applied at the store)
+        uint32_t und, res, smask = 0;
+        if constexpr (FOLD) {
+            uint32_t o = 0, eq = ~0u;
+            fold_top8(tri_sel(a, b, e, own[i], ts, sgn), o, eq, (uint32_t)widx, s, rep, k0, k1);
+            und = eq & vmi;
+            res = o & ~eq;
+        } else {
+            // under the row's own branch: merged across rows, the scalar
+            // level masks of the eight classes would not fit the scalar registers
+            und = 0;
+            res = 0;
+            if (act) {
+                const TriPlanes p = tri_planes(a, b, e, own[i], sgn);
+                smask = p.smask;
+                und = vm;
+                tri_groups<0, 2>(p, und, res, (uint32_t)widx, s, rep, k0, k1, ts);
             }
         }
-        const bool pend = act && und != 0;
+        const bool pend = und != 0;
         const unsigned long long bal = __ballot(pend);
-        if (act) {
+        if (pend) {
             // slot in the wavefront's region: entries queued so far + pending lanes below
             const int q = wq + (int)__builtin_amdgcn_mbcnt_hi(
                                    (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-            if (!pend) {
-                gword(out, (uint32_t)widx) = ((res ^ p.smask) & vm) | frozen_word(d, widx);
-            } else if (q < qcap_w) {
+            if (q < qcap_w) {
                 const int qs = qbase + q;
                 q_w[qs] = (uint32_t)widx | (vm != ~0u ? kLastWord : 0u);
                 q_a[qs] = a;
@@ -416,21 +444,65 @@ __global__ __launch_bounds__(256) void k_tri_bp(const ChainDesc *__restrict__ de
                 q_und[qs] = und;
                 q_res[qs] = res;
             } else {
-                gword(out, (uint32_t)widx) = tri_finish<FOLD>(a, b, e, own[i], und, res, vm, (uint32_t)widx, s, rep, k0, k1,
-                                             ts, sgn) | frozen_word(d, widx);
+                gword(out, (uint32_t)widx) = tri_finish<FOLD>(a, b, e, own[i], und, res, vm, (uint32_t)widx, s,
+                                                              rep, k0, k1, ts, sgn) | frozen_word(d, widx);
             }
+        } else if (act) {
+            gword(out, (uint32_t)widx) = ((res ^ smask) & vm) | frozen_word(d, widx);
         }
         wq += (int)__popcll(bal);
     }
     if ((threadIdx.x & 63) == 0) q_cnt[wv] = min(wq, qcap_w);
+    if (FOLD && threadIdx.x == 0) q2_cnt = 0;
     __syncthreads();
     const int Q = tail_total(q_cnt, nwav);
-    for (int it = threadIdx.x; it < Q; it += blockDim.x) {
-        const int qs = tail_slot(q_cnt, nwav, qcap_w, it);
-        const uint32_t wf = q_w[qs], w = wf & ~kLastWord;
-        const uint32_t vw = (wf & kLastWord) ? bp_valid(L, W, W - 1) : ~0u;
-        gword(out, w) = tri_finish<FOLD>(q_a[qs], q_b[qs], q_e[qs], q_c[qs], q_und[qs], q_res[qs], vw, w, s, rep,
-                                  k0, k1, ts, sgn) | frozen_word(d, (int)w);
+    const uint32_t vlast = bp_valid(L, W, W - 1);
+    if constexpr (FOLD) {
+        // stage 1: level group 2 of every queued word; the words still
+        // undecided move to the second queue
+        for (int it = threadIdx.x; it < Q; it += blockDim.x) {
+            const int qs = tail_slot(q_cnt, nwav, qcap_w, it);
+            const uint32_t wf = q_w[qs], w = wf & ~kLastWord;
+            const uint32_t vw = (wf & kLastWord) ? vlast : ~0u;
+            const uint32_t a = q_a[qs], b = q_b[qs], e = q_e[qs], c = q_c[qs];
+            uint32_t und = q_und[qs], o = q_res[qs];
+            fold_groups<TriSel, 2, 3>(tri_sel(a, b, e, c, ts, sgn), und, o, w, s, rep, k0, k1);
+            if (und == 0) {
+                gword(out, w) = (o & vw) | frozen_word(d, (int)w);
+            } else {
+                const int q2 = atomicAdd(&q2_cnt, 1);
+                if (q2 < kQ2Cap) {
+                    q2_w[q2] = wf;
+                    q2_a[q2] = a;
+                    q2_b[q2] = b;
+                    q2_e[q2] = e;
+                    q2_c[q2] = c;
+                    q2_und[q2] = und;
+                    q2_res[q2] = o;
+                } else {
+                    gword(out, w) = tri_finish<true, 3>(a, b, e, c, und, o, vw, w, s, rep, k0, k1, ts, sgn) |
+                                    frozen_word(d, (int)w);
+                }
+            }
+        }
+        __syncthreads();
+        // stage 2: groups 3..7 of the words still undecided
+        const int Q2 = min(q2_cnt, kQ2Cap);
+        for (int it = threadIdx.x; it < Q2; it += blockDim.x) {
+            const uint32_t wf = q2_w[it], w = wf & ~kLastWord;
+            const uint32_t vw = (wf & kLastWord) ? vlast : ~0u;
+            gword(out, w) = tri_finish<true, 3>(q2_a[it], q2_b[it], q2_e[it], q2_c[it], q2_und[it], q2_res[it], vw,
+                                                w, s, rep, k0, k1, ts, sgn) |
+                            frozen_word(d, (int)w);
+        }
+    } else {
+        for (int it = threadIdx.x; it < Q; it += blockDim.x) {
+            const int qs = tail_slot(q_cnt, nwav, qcap_w, it);
+            const uint32_t wf = q_w[qs], w = wf & ~kLastWord;
+            const uint32_t vw = (wf & kLastWord) ? vlast : ~0u;
+            gword(out, w) = tri_finish<false>(q_a[qs], q_b[qs], q_e[qs], q_c[qs], q_und[qs], q_res[qs], vw, w, s,
+                                              rep, k0, k1, ts, sgn) | frozen_word(d, (int)w);
+        }
     }
     if (OBS && bx * (int)blockDim.x < total)
         block_accumulate2(e_acc, p_acc, log_part(d, slot, bx));
