@@ -123,7 +123,7 @@ __device__ __forceinline__ int tail_slot(const int *cnt, int nwav, int qcap_w, i
 // EXT: instantiation for chains with +-J sign planes or a frozen set (the
 // plain instantiation reads neither)
 template <bool OBS, bool FOLD3, bool EXT>
-__global__ __launch_bounds__(256, (OBS && FOLD3 && !EXT) ? 5 : 1) void k_torus_bp(const ChainDesc *__restrict__ descs, StepArgs sa) {
+__global__ __launch_bounds__(256) void k_torus_bp(const ChainDesc *__restrict__ descs, StepArgs sa) {
     __shared__ uint32_t q_w[kQCap], q_a[kQCap], q_b[kQCap], q_c[kQCap], q_und[kQCap], q_res[kQCap];
     __shared__ int q_cnt[4];  // entries queued per wavefront region
     __shared__ uint32_t q2_w[FOLD3 ? kQ2Cap : 1], q2_a[FOLD3 ? kQ2Cap : 1], q2_b[FOLD3 ? kQ2Cap : 1],
