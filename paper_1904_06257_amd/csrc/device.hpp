@@ -45,6 +45,27 @@ __device__ __forceinline__ U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, ui
     return U4{c0, c1, c2, c3};
 }
 
+// The same call with words x and z of the result xored with a per-lane word
+// v: the last round's key xor takes (k ^ v) in their place, so the xor costs
+// nothing there.  kx0, kx1 = the tenth round's keys xor v.
+__device__ __forceinline__ U4 philox10_xv(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                          uint32_t k0, uint32_t k1, uint32_t kx0, uint32_t kx1) {
+#pragma unroll
+    for (int i = 0; i < 10; ++i) {
+        const uint64_t a = (uint64_t)c0 * 0xD2511F53u;
+        const uint64_t b = (uint64_t)c2 * 0xCD9E8D57u;
+        const uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(b >> 32), c1, i == 9 ? kx0 : k0, 0x96);
+        const uint32_t n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(a >> 32), c3, i == 9 ? kx1 : k1, 0x96);
+        c1 = (uint32_t)b;
+        c3 = (uint32_t)a;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return U4{c0, c1, c2, c3};
+}
+
 __device__ __forceinline__ uint32_t bfi(uint32_t m, uint32_t x, uint32_t y) {
     return (m & x) | (~m & y);
 }
@@ -269,26 +290,35 @@ struct SqSelV : SqSel {  // rest-class words of levels 0..7 in vector registers
 // (o is not meaningful there).  A level costs the class select, y = tf ^ c
 // and one instruction each for o and eq; the MSB-first form needs one more
 // (decided sites, result, undecided sites).
+//
+// The levels run on x = u ^ c against tf: u and y differ where x and tf do,
+// and the state kept is o ^ c, whose update is then `tf where x != tf`.  Two
+// of the four words of each Philox call come out already xored with c.
 template <class S>
 __device__ __forceinline__ void fold_top8(const S &sl, uint32_t &o, uint32_t &eq, uint32_t w, uint32_t s,
                                           uint32_t rep, uint32_t k0, uint32_t k1) {
-#define SHAKEN_FLEVEL(K, R)                                                                       \
+#define SHAKEN_FLEVEL(K, X)                                                                       \
     {                                                                                             \
-        const uint32_t y_ = sl.sel(K) ^ sl.c();                                                   \
-        o = __builtin_amdgcn_bitop3_b32((R), y_, o, kT_first);                                    \
-        eq = __builtin_amdgcn_bitop3_b32(eq, (R), y_, kT_and_eq);                                 \
+        const uint32_t x_ = (X);                                                                  \
+        const uint32_t t_ = sl.sel(K);                                                            \
+        oc = __builtin_amdgcn_bitop3_b32(x_, t_, oc, kT_first);                                   \
+        eq = __builtin_amdgcn_bitop3_b32(eq, x_, t_, kT_and_eq);                                  \
     }
-    const U4 r1 = philox10(w, s, rep, 1u, k0, k1);
-    SHAKEN_FLEVEL(7, r1.w)
+    const uint32_t c = sl.c();
+    const uint32_t kx0 = (k0 + 9u * 0x9E3779B9u) ^ c, kx1 = (k1 + 9u * 0xBB67AE85u) ^ c;
+    uint32_t oc = 0;
+    const U4 r1 = philox10_xv(w, s, rep, 1u, k0, k1, kx0, kx1);
+    SHAKEN_FLEVEL(7, r1.w ^ c)
     SHAKEN_FLEVEL(6, r1.z)
-    SHAKEN_FLEVEL(5, r1.y)
+    SHAKEN_FLEVEL(5, r1.y ^ c)
     SHAKEN_FLEVEL(4, r1.x)
-    const U4 r0 = philox10(w, s, rep, 0u, k0, k1);
-    SHAKEN_FLEVEL(3, r0.w)
+    const U4 r0 = philox10_xv(w, s, rep, 0u, k0, k1, kx0, kx1);
+    SHAKEN_FLEVEL(3, r0.w ^ c)
     SHAKEN_FLEVEL(2, r0.z)
-    SHAKEN_FLEVEL(1, r0.y)
+    SHAKEN_FLEVEL(1, r0.y ^ c)
     SHAKEN_FLEVEL(0, r0.x)
 #undef SHAKEN_FLEVEL
+    o = oc ^ c;
 }
 
 // Levels of groups [G0, G1) most significant first for the sites in und;
