@@ -78,11 +78,20 @@ BP_ALU_PER_SITE_PMJ = _alu_per_site(6, 7, 3) + 2.0 / 32.0
 TRI_ALU_PER_SITE = _alu_per_site(7, 8, 10)
 
 
+def _code_only(text):
+    """Kernel source without comments and blank space: what the hash of the
+    measured kernels covers (a comment edit leaves the counters valid)."""
+    import re
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
     for f in ("kernels.hip", "batch.hip", "device.hpp", "shaken_internal.hpp"):
-        with open(os.path.join(ROOT, "paper_1904_06257_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1904_06257_amd", "csrc", f), encoding="utf-8") as fh:
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -392,7 +392,7 @@ __device__ __forceinline__ uint32_t bp_word(uint32_t a, uint32_t b, uint32_t c, 
 // (n_plus >= 2) code n_plus = s1 + 2 s2.  When the thresholds depend on |h|
 // only (lambda = 0), classes (n, c) and (3 - n, 1 - c) share one: the class is
 // then the number k of neighbours that agree with the site, coded the same
-// way by k1, k2 over the agreement planes.
+// way over the agreement planes (TriSel below).
 struct TriPlanes {
     uint32_t s1, s2, c, smask;
 };

@@ -32,8 +32,8 @@ struct ChainDesc {
     // triangular torus: j = n_plus + 4*(own spin is +1), eight classes
     uint32_t tsmall[8];  // t of the class: floor(p_small * 2^32), p_small = min(p, 1-p)
     uint32_t sgn;        // bit j: class j compares flipped (field >= 0; either way where T = 2^31)
-    int32_t fold3;       // tsmall depends on |h| only (3 classes after sign folding;
-                         // 4 on the triangular torus)
+    int32_t fold3;       // mirror classes share t and have opposite flips (3 classes
+                         // after folding; 4 on the triangular torus)
     int32_t tri;         // triangular torus (section 4): third oriented edge (x, x + e1 + e2)
     int32_t J;           // uniform torus coupling
     // generic threshold table (int8 torus, graph): ((S+smax)*2 + (sigma>0))*ncls + cls
