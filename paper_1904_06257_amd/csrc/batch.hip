@@ -58,54 +58,129 @@ struct Obs {
     int plus[kPClasses];
 };
 
+// Neighbour planes of word w read in half `phase` (0 = dl, 1 = ur): a the
+// vertical neighbours, b the horizontal ones, e (triangular lattice) the
+// diagonal ones, flipped by the coupling signs where there are any.
+template <bool TRI, bool EXT>
+__device__ __forceinline__ void lds_planes(const ChainDesc &d, const uint32_t *src, int w, int phase,
+                                           uint32_t &a, uint32_t &b, uint32_t &e) {
+    const int L = d.L, W = d.W;
+    const int r = w / W, wd = w - r * W;
+    const uint32_t own = src[w];
+    const int lastbits = (L - 1) & 31;
+    e = 0;
+    if (phase == 0) {
+        // down and left neighbours (the in-half); triangular: down-left too
+        const int rd = r == 0 ? L - 1 : r - 1;
+        a = src[rd * W + wd];
+        const uint32_t carry = wd > 0 ? (src[r * W + wd - 1] >> 31)
+                                      : ((src[r * W + W - 1] >> lastbits) & 1u);
+        b = (own << 1) | carry;
+        if (TRI) {
+            const uint32_t as = wd > 0 ? src[rd * W + wd - 1] : src[rd * W + W - 1];
+            e = (a << 1) | (wd > 0 ? (as >> 31) : ((as >> lastbits) & 1u));
+        }
+    } else {
+        const int ru = r == L - 1 ? 0 : r + 1;
+        a = src[ru * W + wd];
+        b = wd < W - 1 ? ((own >> 1) | (src[r * W + wd + 1] << 31))
+                       : ((own >> 1) | ((src[r * W] & 1u) << lastbits));
+        if (TRI)
+            e = wd < W - 1 ? ((a >> 1) | (src[ru * W + wd + 1] << 31))
+                           : ((a >> 1) | ((src[ru * W] & 1u) << lastbits));
+    }
+    if (EXT && !TRI && d.jneg) bp_jflip(d.jneg, L, W, r, wd, phase, a, b);
+}
+
+// Words of a torus half-step whose top eight levels left sites undecided,
+// finished after the pass over all words by the whole workgroup, so that the
+// rare deeper levels run in a few wavefronts instead of in every one.
+constexpr int kPTail = 512;
+struct TailQ {
+    int n;
+    uint32_t w[kPTail], und[kPTail], out[kPTail];
+    uint32_t a[kPTail], b[kPTail], e[kPTail];  // neighbour planes (no coupling-sign reads in the tail)
+};
+
+// One half-step (or, with dst == nullptr, only the observables of src) of an
+// L x L bit-packed torus held in LDS.
 template <bool FOLD3, bool TRI, bool EXT>
 __device__ __forceinline__ void torus_lds_half(const ChainDesc &d, const uint32_t *src, uint32_t *dst, uint32_t s,
-                               bool obs, int *sh_red, Obs *o) {
+                                               bool obs, int *sh_red, Obs *o, TailQ *tq) {
     const int L = d.L, W = d.W, nw = L * W;
     const int phase = (int)(s & 1u) ^ d.rev;  // half read: 0 = dl, 1 = ur
     const uint32_t k0 = (uint32_t)d.seed, k1 = (uint32_t)(d.seed >> 32);
     int e_acc = 0, p_acc = 0;
     for (int w = threadIdx.x; w < nw; w += kPBlock) {
-        const int r = w / W, wd = w - r * W;
         const uint32_t own = src[w];
-        const uint32_t vm = bp_valid(L, W, wd);
-        uint32_t a, b, e = 0;
-        const int lastbits = (L - 1) & 31;
-        if (obs || phase == 0) {
-            // down and left neighbours (the in-half); triangular: down-left too
-            const int rd = r == 0 ? L - 1 : r - 1;
-            a = src[rd * W + wd];
-            const uint32_t carry = wd > 0 ? (src[r * W + wd - 1] >> 31)
-                                          : ((src[r * W + W - 1] >> lastbits) & 1u);
-            b = (own << 1) | carry;
-            if (TRI) {
-                const uint32_t as = wd > 0 ? src[rd * W + wd - 1] : src[rd * W + W - 1];
-                e = (a << 1) | (wd > 0 ? (as >> 31) : ((as >> lastbits) & 1u));
-            }
-            if (EXT && !TRI && d.jneg) bp_jflip(d.jneg, L, W, r, wd, 0, a, b);
-            if (obs) {
-                e_acc += d.J * (2 * __popc(vm) - 2 * __popc((own ^ a) & vm) - 2 * __popc((own ^ b) & vm));
-                if (TRI) e_acc += d.J * (__popc(vm) - 2 * __popc((own ^ e) & vm));
-                p_acc += __popc(own & vm);
-            }
+        const uint32_t vm = bp_valid(L, W, w - (w / W) * W);
+        uint32_t a, b, e;
+        if (obs) {
+            lds_planes<TRI, EXT>(d, src, w, 0, a, b, e);
+            e_acc += d.J * (2 * __popc(vm) - 2 * __popc((own ^ a) & vm) - 2 * __popc((own ^ b) & vm));
+            if (TRI) e_acc += d.J * (__popc(vm) - 2 * __popc((own ^ e) & vm));
+            p_acc += __popc(own & vm);
         }
         if (!dst) continue;
-        if (phase == 1) {
-            const int ru = r == L - 1 ? 0 : r + 1;
-            a = src[ru * W + wd];
-            b = wd < W - 1 ? ((own >> 1) | (src[r * W + wd + 1] << 31))
-                           : ((own >> 1) | ((src[r * W] & 1u) << lastbits));
-            if (TRI)
-                e = wd < W - 1 ? ((a >> 1) | (src[ru * W + wd + 1] << 31))
-                               : ((a >> 1) | ((src[ru * W] & 1u) << lastbits));
-            if (EXT && !TRI && d.jneg) bp_jflip(d.jneg, L, W, r, wd, 1, a, b);
-        }
+        if (!obs || phase == 1) lds_planes<TRI, EXT>(d, src, w, phase, a, b, e);
         uint32_t nw_bits;
-        if constexpr (TRI)
-            nw_bits = tri_word<FOLD3>(a, b, e, own, vm, (uint32_t)w, s, d.replica, k0, k1, d.tsmall, d.sgn);
-        else
-            nw_bits = bp_word<FOLD3>(a, b, own, vm, (uint32_t)w, s, d.replica, k0, k1, d.tsmall, d.sgn);
+        if constexpr (FOLD3) {
+            uint32_t ob = 0, eq = ~0u;
+            if constexpr (TRI)
+                fold_top8(tri_sel(a, b, e, own, d.tsmall, d.sgn), ob, eq, (uint32_t)w, s, d.replica, k0, k1);
+            else
+                fold_top8(SqSel{fold_planes(a, b, own), fold_t(d.tsmall, d.sgn)}, ob, eq, (uint32_t)w, s,
+                          d.replica, k0, k1);
+            const uint32_t und = eq & vm;
+            nw_bits = ob & vm;
+            if (und != 0) {
+                const int qi = atomicAdd(&tq->n, 1);
+                if (qi < kPTail) {
+                    tq->w[qi] = (uint32_t)w;
+                    tq->und[qi] = und;
+                    tq->out[qi] = ob & ~eq;
+                    tq->a[qi] = a;
+                    tq->b[qi] = b;
+                    if (TRI) tq->e[qi] = e;
+                    continue;
+                }
+                if constexpr (TRI)
+                    nw_bits = fold_finish<TriSel, 2>(tri_sel(a, b, e, own, d.tsmall, d.sgn), und, ob & ~eq, vm,
+                                                     (uint32_t)w, s, d.replica, k0, k1, d.sgn);
+                else
+                    nw_bits = fold_finish<SqSel, 2>(SqSel{fold_planes(a, b, own), fold_t(d.tsmall, d.sgn)}, und,
+                                                    ob & ~eq, vm, (uint32_t)w, s, d.replica, k0, k1, d.sgn);
+            }
+        } else if constexpr (TRI) {
+            nw_bits = tri_word<false>(a, b, e, own, vm, (uint32_t)w, s, d.replica, k0, k1, d.tsmall, d.sgn);
+        } else {
+            nw_bits = bp_word<false>(a, b, own, vm, (uint32_t)w, s, d.replica, k0, k1, d.tsmall, d.sgn);
+        }
         dst[w] = EXT ? (nw_bits | frozen_word(d, w)) : nw_bits;
+    }
+    if (FOLD3 && dst) {
+        // the queued words
+        __syncthreads();
+        const int Q = min(tq->n, kPTail);
+        for (int it = threadIdx.x; it < Q; it += kPBlock) {
+            const int w = (int)tq->w[it];
+            const uint32_t own = src[w];
+            const uint32_t vm = bp_valid(L, W, w - (w / W) * W);
+            const uint32_t a = tq->a[it], b = tq->b[it], e = TRI ? tq->e[it] : 0u;
+            uint32_t nw_bits;
+            if constexpr (TRI)
+                nw_bits = fold_finish<TriSel, 2>(tri_sel(a, b, e, own, d.tsmall, d.sgn), tq->und[it], tq->out[it],
+                                                 vm, (uint32_t)w, s, d.replica, k0, k1, d.sgn);
+            else
+                nw_bits = fold_finish<SqSel, 2>(SqSel{fold_planes(a, b, own), fold_t(d.tsmall, d.sgn)},
+                                                tq->und[it], tq->out[it], vm, (uint32_t)w, s, d.replica, k0, k1,
+                                                d.sgn);
+            dst[w] = EXT ? (nw_bits | frozen_word(d, w)) : nw_bits;
+        }
+        // every lane has read the count: the next half-step starts from zero
+        // (the caller's barrier orders the reset before its first append)
+        __syncthreads();
+        if (threadIdx.x == 0) tq->n = 0;
     }
     if (obs) {
         block_sum2(e_acc, p_acc, sh_red);
@@ -169,7 +244,7 @@ __device__ __forceinline__ int64_t uniform_i64(int64_t x) { return (int64_t)unif
 template <bool FOLD3, bool TRI, bool EXT>
 __device__ __attribute__((noinline)) void run_torus(const ChainDesc &d_arg, uint32_t (*buf)[kPWords], uint32_t s0_arg,
                                                     int64_t n_full_arg, int record_arg, int track_arg,
-                                                    int *sh_red, int *sh_flag, Obs &o) {
+                                                    int *sh_red, int *sh_flag, Obs &o, TailQ *tq) {
     const ChainDesc &d = uniform_desc(d_arg);
     const uint32_t s0 = (uint32_t)__builtin_amdgcn_readfirstlane(s0_arg);
     const int64_t n_full = uniform_i64(n_full_arg);
@@ -179,20 +254,21 @@ __device__ __attribute__((noinline)) void run_torus(const ChainDesc &d_arg, uint
     const bool obs = record || track;
     const uint32_t *g = (const uint32_t *)d.spin[0];
     for (int w = threadIdx.x; w < nw; w += kPBlock) buf[0][w] = g[w];
+    if (threadIdx.x == 0) tq->n = 0;
     __syncthreads();
     int64_t best_h = INT64_MAX, last_h = 0;
     for (int64_t t = 0; t < n_full; ++t) {
         const uint32_t s = s0 + 2u * (uint32_t)t;
-        torus_lds_half<FOLD3, TRI, EXT>(d, buf[0], buf[1], s, obs, sh_red, &o);
+        torus_lds_half<FOLD3, TRI, EXT>(d, buf[0], buf[1], s, obs, sh_red, &o, tq);
         if (obs)
             observe_step(d, o, record ? d.log + t * d.log_stride : nullptr, track, &best_h, &last_h,
                          buf[0], nw, sh_flag);
         __syncthreads();
-        torus_lds_half<FOLD3, TRI, EXT>(d, buf[1], buf[0], s + 1u, false, sh_red, nullptr);
+        torus_lds_half<FOLD3, TRI, EXT>(d, buf[1], buf[0], s + 1u, false, sh_red, nullptr, tq);
         __syncthreads();
     }
     if (obs) {
-        torus_lds_half<FOLD3, TRI, EXT>(d, buf[0], nullptr, s0, true, sh_red, &o);
+        torus_lds_half<FOLD3, TRI, EXT>(d, buf[0], nullptr, s0, true, sh_red, &o, tq);
         observe_step(d, o, record ? d.log + n_full * d.log_stride : nullptr, track, &best_h, &last_h,
                      buf[0], nw, sh_flag);
         if (track && threadIdx.x == 0) {
@@ -479,6 +555,7 @@ __global__ __launch_bounds__(kPBlock, SHAKEN_PWAVES) void k_persistent(const Cha
     __shared__ int sh_plus[kPClasses];
     __shared__ uint64_t sh_lut[kPLut];
     __shared__ Obs sh_obs;  // observables of the current configuration (thread 0)
+    __shared__ TailQ sh_tail;
     for (;;) {
         if (threadIdx.x == 0) {
             const int k = atomicAdd(counter, 1);
@@ -494,18 +571,18 @@ __global__ __launch_bounds__(kPBlock, SHAKEN_PWAVES) void k_persistent(const Cha
             const bool ext = d.jneg || d.frozen;
             if (d.tri) {
                 if (d.fold3)
-                    run_torus<true, true, true>(d, buf, s0, n_full, record, track, sh_red, &sh_flag, sh_obs);
+                    run_torus<true, true, true>(d, buf, s0, n_full, record, track, sh_red, &sh_flag, sh_obs, &sh_tail);
                 else
-                    run_torus<false, true, true>(d, buf, s0, n_full, record, track, sh_red, &sh_flag, sh_obs);
+                    run_torus<false, true, true>(d, buf, s0, n_full, record, track, sh_red, &sh_flag, sh_obs, &sh_tail);
             } else if (ext) {
                 if (d.fold3)
-                    run_torus<true, false, true>(d, buf, s0, n_full, record, track, sh_red, &sh_flag, sh_obs);
+                    run_torus<true, false, true>(d, buf, s0, n_full, record, track, sh_red, &sh_flag, sh_obs, &sh_tail);
                 else
-                    run_torus<false, false, true>(d, buf, s0, n_full, record, track, sh_red, &sh_flag, sh_obs);
+                    run_torus<false, false, true>(d, buf, s0, n_full, record, track, sh_red, &sh_flag, sh_obs, &sh_tail);
             } else if (d.fold3) {
-                run_torus<true, false, false>(d, buf, s0, n_full, record, track, sh_red, &sh_flag, sh_obs);
+                run_torus<true, false, false>(d, buf, s0, n_full, record, track, sh_red, &sh_flag, sh_obs, &sh_tail);
             } else {
-                run_torus<false, false, false>(d, buf, s0, n_full, record, track, sh_red, &sh_flag, sh_obs);
+                run_torus<false, false, false>(d, buf, s0, n_full, record, track, sh_red, &sh_flag, sh_obs, &sh_tail);
             }
         } else {
             if (d.pell)
