@@ -4,16 +4,23 @@ Default workload (the headline): the 24 runs of the 4096 x 4096 bit-packed
 torus -- q in {0.5, 1, 2} x beta in {0.30, 0.40, 0.44, 0.50} x initial state
 {all up, random} -- held as 24 chains of one grid batch.  One step is one full
 step (half-step dl with the fused observables of the configuration it reads,
-then half-step ur) of all 24 chains; it is replayed from a captured HIP
-graph.  Inputs are resident in device memory before the timed region.
+then half-step ur) of all 24 chains; sixteen full steps are replayed per
+captured HIP graph (captured in the warm-up call), the rest of a call runs
+eagerly.  Inputs are resident in device memory before the timed region, and
+the timed call is checked to have captured, allocated and tuned nothing.
 
-Other workloads (``--workload``): ``tri4096`` (the same 24 runs on the
-triangular-lattice torus of section 4), ``graph`` (3-regular +-J graph,
-n = 2^20, CSR, int8), ``batch`` (2048 mixed tori and 3-regular graphs,
-persistent launch), ``ea`` (1024 +-J Edwards-Anderson tori 256^2).
+The default run also times, under ``secondary``, the n = 2^20 random
+3-regular +-J graph (CSR, int8 spins), the 2048-chain mixed batch (one
+persistent launch per call) and the latency of the schedule network's
+forward and backward calls; each graph or batch line has its own roofline and
+oracle baseline.
+
+Other workloads (``--workload``, one line each): ``tri4096`` (the same 24
+runs on the triangular-lattice torus of section 4), ``graph``, ``batch``,
+``ea`` (1024 +-J Edwards-Anderson tori 256^2).
 
 Prints one JSON line: metric, value (site-updates/s), roofline of the
-dominant kernel (HIP-event time per launch, algorithmic work per launch) and
+dominant kernel (HIP-event time per launch, algorithmic bytes per launch) and
 the CPU oracle timed on a bounded sample of the same workload: one sample
 per host core (at most 16), run at once in processes forked before the GPU
 is touched, with the single-process rate beside the aggregate.
@@ -35,6 +42,8 @@ sys.path.insert(0, ROOT)
 # VALU lane-cycles per second.
 VALU_PEAK = 256 * 64 * 2.4e9
 HBM_PEAK_GBS = 8000.0
+# the share of HBM peak the bit-packed torus is asked to reach
+HBM_TARGET_FRAC = 0.60
 
 # Algorithmic ALU work of one bit-packed site-update, in VALU lane-cycles, per
 # 32-site word on the folded class table (the workloads' lambda = 0):
@@ -95,9 +104,11 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def read_traffic(kernel_key, per="launch"):
-    """HBM bytes per launch (or per full step) from the committed rocprofv3
-    counter summary, or None if the kernels changed since it was taken."""
+def read_traffic(kernel_key, per="launch", what="bytes"):
+    """HBM bytes (what="bytes") or VALU lane-instructions
+    (what="valu_lane_instr") per launch (or per full step) from the committed
+    rocprofv3 counter summary, or None if the kernels changed since it was
+    taken."""
     path = os.path.join(ROOT, "profiles", "traffic.txt")
     if not os.path.exists(path):
         return None
@@ -110,8 +121,28 @@ def read_traffic(kernel_key, per="launch"):
             vals[k.strip()] = v.strip()
     if vals.get("source_hash") != kernel_source_hash():
         return None
-    v = vals.get(kernel_key + ".bytes_per_" + per)
+    v = vals.get(kernel_key + "." + what + "_per_" + per)
     return float(v) if v else None
+
+
+def timed_sweep(batch, steps):
+    """Wall time of batch.sweep(steps) between two device synchronisations.
+    The call must do no host-side set-up (graph capture, log allocation,
+    autotuning): that belongs to the warm-up, and the run stops if it
+    happened inside the timed region."""
+    import torch
+    before = batch.counters()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.sweep(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    after = batch.counters()
+    for k in ("captures", "log_allocs", "autotunes"):
+        if after[k] != before[k]:
+            raise SystemExit("bench: the timed call did set-up work (%s %d -> %d)"
+                             % (k, before[k], after[k]))
+    return wall
 
 
 # ------------------------------------------------------ oracle baselines
@@ -220,41 +251,42 @@ def cpu_baseline_batch():
 
 def bench_torus4096(args, sk, triangular=False):
     import synth
-    import torch
     L = 4096
     runs = synth.torus_runs()
     make = sk.Chain.triangular if triangular else sk.Chain.torus
     chains = []
     for i, r in enumerate(runs):
         chains.append(make(L, q=r["q"], beta=r["beta"], seed=r["seed"], replica=i, init=r["init"]))
-    # log space for the longest call reserved up-front: the timed call neither
-    # allocates nor re-captures its HIP graph
+    # log space for the longest call reserved up-front; the HIP graph and the
+    # block sizes are made in the warm-up call
     batch = sk.Batch(chains, strategy="grid", use_hipgraph=True, record=True, autotune=True,
                      log_reserve=max(args.steps, args.warmup))
     batch.sweep(args.warmup)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    batch.sweep(args.steps)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    wall = timed_sweep(batch, args.steps)
     _, ev_ms = batch.info()   # HIP events on the batch stream around the sweep
     n_chains = len(chains)
     site_updates = 2.0 * n_chains * L * L * args.steps
     value = site_updates / wall
     # dominant kernel: the bit-packed half-step, 2 launches per step; the
-    # remaining launches per step (1/16 of a counter increment) are < 0.1 %
+    # remaining launches (one counter increment per 16 steps) are < 0.1 %
     per_launch_s = ev_ms * 1e-3 / (2 * args.steps)
     units_per_launch = n_chains * L * L
     kernel = "k_tri_bp" if triangular else "k_torus_bp"
     alu_per_site = TRI_ALU_PER_SITE if triangular else BP_ALU_PER_SITE
-    achieved_alu = units_per_launch * alu_per_site / per_launch_s
-    traffic = read_traffic(kernel)
-    roof = {"bound": "alu", "achieved": achieved_alu / 1e12, "peak": VALU_PEAK / 1e12,
-            "unit": "T lane-cycles/s", "frac": achieved_alu / VALU_PEAK,
-            "traffic": traffic, "kernel": kernel,
+    achieved = units_per_launch * BP_BYTES_PER_SITE / per_launch_s / 1e9
+    valu = read_traffic(kernel, per="launch", what="valu_lane_instr")
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": read_traffic(kernel), "kernel": kernel,
             "launch_us": per_launch_s * 1e6,
-            "alg_bytes_GBs": units_per_launch * BP_BYTES_PER_SITE / per_launch_s / 1e9,
-            "hbm_frac": units_per_launch * BP_BYTES_PER_SITE / per_launch_s / 1e9 / HBM_PEAK_GBS}
+            "bytes_per_site_update": BP_BYTES_PER_SITE,
+            "target_frac": HBM_TARGET_FRAC,
+            "gap": "%.2f of HBM peak against the 0.60 target: at 0.25 B per site-update the "
+                   "kernel is bound by VALU issue (Philox and the bit-sliced compare), not by "
+                   "HBM; 0.60 would need %.1f site-updates per ns" %
+                   (achieved / HBM_PEAK_GBS, HBM_TARGET_FRAC * HBM_PEAK_GBS / BP_BYTES_PER_SITE),
+            "valu_issue_frac": None if valu is None else valu / (VALU_PEAK * per_launch_s),
+            "valu_lane_instr_per_site_update": None if valu is None else valu / units_per_launch,
+            "alu_model_frac": units_per_launch * alu_per_site / per_launch_s / VALU_PEAK}
     for c in chains:
         c.close()
     batch.close()
@@ -262,25 +294,21 @@ def bench_torus4096(args, sk, triangular=False):
     cfg = {"workload": "4096x4096 bit-packed %s, 24 chains (q x beta x init) batched" % lattice,
            "L": L, "chains": n_chains, "J": 1, "lambda": 0.0, "q": [0.5, 1.0, 2.0],
            "beta": [0.30, 0.40, 0.44, 0.50], "init": ["all_up", "random"],
-           "strategy": "grid + hipGraph", "observables": "fused, every full step"}
+           "strategy": "grid + hipGraph (16 full steps per replay)",
+           "observables": "fused, every full step"}
     return value, wall, cfg, roof, "u1 (bit-packed spins)"
 
 
 def _graph_run(sk, inst, n, steps, warmup, reps=1, fmt="int8"):
     """grid batch of `reps` chains of the graph (own seeds), HIP graph replay;
     returns (wall seconds, event seconds) of the timed call"""
-    import torch
     chains = [sk.Chain.graph(n, inst.src, inst.dst, J=inst.J, lam_values=inst.lam_values,
                              lam_class=inst.cls, q=1.5, beta=0.8, seed=1 + r, replica=r, layout="csr",
                              fmt=fmt) for r in range(reps)]
     batch = sk.Batch(chains, strategy="grid", use_hipgraph=True, record=True, autotune=True,
                      log_reserve=max(steps, warmup))
     batch.sweep(warmup)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    batch.sweep(steps)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    wall = timed_sweep(batch, steps)
     _, ev_ms = batch.info()
     batch.close()
     for c in chains:
@@ -346,11 +374,7 @@ def bench_batch(args, sk):
     batch = sk.Batch(chains, strategy="persistent", record=True, use_hipgraph=True, autotune=True,
                      log_reserve=max(args.steps, args.warmup))
     batch.sweep(args.warmup)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    batch.sweep(args.steps)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    wall = timed_sweep(batch, args.steps)
     _, ev_ms = batch.info()
     value = 2.0 * sites * args.steps / wall
     batch.close()
@@ -413,11 +437,7 @@ def bench_ea(args, sk):
                      log_reserve=max(args.steps, args.warmup))
     strategy = batch.info()[0]
     batch.sweep(args.warmup)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    batch.sweep(args.steps)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    wall = timed_sweep(batch, args.steps)
     _, ev_ms = batch.info()
     batch.close()
     for c in chains:
@@ -533,6 +553,46 @@ def summarize_traffic(cal_fetch_csv, cal_write_csv, workloads, out_path):
     print("\n".join(lines))
 
 
+def bench_mlp(sk, rows=512, reps=200):
+    """Latency of the schedule network's calls at `rows` feature rows (one
+    row per chain): forward; loss + backward (it returns the loss to the host,
+    so each call synchronises); one Adam step.  Microseconds per call over
+    `reps` calls, device synchronised before and after."""
+    import numpy as np
+    import torch
+    from paper_1904_06257_amd import anneal
+    mlp = sk.MLP(device=0)
+    mlp.set_params(anneal.init_params(1))
+    x = torch.randn(rows, sk.MLP_IN, device="cuda")
+    y = torch.empty(rows, sk.MLP_OUT, device="cuda")
+    t = torch.randn(rows, sk.MLP_OUT, device="cuda")
+    out = {"rows": rows, "calls": reps}
+    for name, fn in (("forward_us", lambda: mlp.forward(x, y)),
+                     ("loss_backward_us", lambda: mlp.loss_backward(t)),
+                     ("adam_us", lambda: mlp.adam(1e-4, 1))):
+        for _ in range(10):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        out[name] = (time.perf_counter() - t0) / reps * 1e6
+    # forward FLOPs per row: 2 x (16*128 + 128*128 + 128*128 + 128*16)
+    flops = 2.0 * rows * (16 * 128 + 2 * 128 * 128 + 128 * 16)
+    out["forward_tflops"] = flops / (out["forward_us"] * 1e-6) / 1e12
+    out["note"] = ("latency-bound: %.1f MFLOP per forward call, far below what the matrix cores "
+                   "need to be busy; the figure that matters is microseconds per call" % (flops / 1e6))
+    mlp.close()
+    return out
+
+
+def _line(metric, unit, value, steps, warmup, wall, cfg, roof, cpu, dtype):
+    return {"metric": metric, "value": value, "unit": unit, "steps": steps, "warmup": warmup,
+            "ms_per_step": wall * 1e3 / steps, "dtype": dtype, "config": cfg, "roofline": roof,
+            "cpu_baseline": cpu}
+
+
 def main():
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-traffic":
         # bench.py --summarize-traffic CAL_FETCH CAL_WRITE KERNEL[@STEPS][#GRID][~SUFFIX]=FETCH,WRITE ...
@@ -553,19 +613,30 @@ def main():
     ap.add_argument("--workload", default="torus4096",
                     choices=["torus4096", "tri4096", "graph", "batch", "ea", "copycal"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="default workload only: skip the graph, batch and network lines")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(chains are independent: the work would shard by chain, one process per GPU)",
               file=sys.stderr)
         sys.exit(2)
-    # the oracle baseline runs first, in processes forked before this process
+    secondary = args.workload == "torus4096" and not args.no_secondary
+    # secondary lines: enough steps for the timed region to dwarf the
+    # synchronisation around it (a 2^20 graph half-step is ~15 us)
+    sec_args = {"graph": argparse.Namespace(steps=max(args.steps, 500), warmup=max(args.warmup, 5)),
+                "batch": argparse.Namespace(steps=max(args.steps, 200), warmup=max(args.warmup, 5))}
+    # the oracle baselines run first, in processes forked before this process
     # initialises the GPU
     baselines = {"torus4096": cpu_baseline_torus, "tri4096": lambda: cpu_baseline_torus(triangular=True),
                  "graph": cpu_baseline_graph, "ea": cpu_baseline_ea, "batch": cpu_baseline_batch}
     cpu = None
-    if not args.no_cpu_baseline and args.workload in baselines:
-        cpu = baselines[args.workload]()
+    cpu_sec = {}
+    if not args.no_cpu_baseline:
+        if args.workload in baselines:
+            cpu = baselines[args.workload]()
+        if secondary:
+            cpu_sec = {"graph": cpu_baseline_graph(), "batch": cpu_baseline_batch()}
     import torch
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
@@ -596,6 +667,19 @@ def main():
            "ms_per_step": wall * 1e3 / args.steps, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic",
            "config": cfg, "roofline": roof, "cpu_baseline": cpu}
+    if secondary:
+        sec = {}
+        ga = sec_args["graph"]
+        v, w, c, r, d = bench_graph(ga, sk)
+        sec["graph_2e20"] = _line("vertex updates/s (3-regular graph, n=2^20)", "vertex-updates/s",
+                                  v, ga.steps, ga.warmup, w, c, r, cpu_sec.get("graph"), d)
+        ba = sec_args["batch"]
+        v, w, c, r, d = bench_batch(ba, sk)
+        sec["batch_2048"] = _line("aggregate site updates/s (2048 mixed chains, persistent batch)",
+                                  "site-updates/s", v, ba.steps, ba.warmup, w, c, r,
+                                  cpu_sec.get("batch"), d)
+        sec["mlp_512"] = bench_mlp(sk)
+        out["secondary"] = sec
     print(json.dumps(out), flush=True)
 
 

@@ -283,7 +283,9 @@ typedef struct shaken_batch_opts {
     int32_t strategy;      /* SHAKEN_BATCH_*                                  */
     int32_t use_hipgraph;  /* capture the launches in a HIP graph and replay
                               it: grid strategy, 16 full steps of half-step
-                              launches per replay; persistent strategy, the
+                              launches per replay (captured on the first
+                              sweep, whatever its length; the remainder of
+                              a call runs eagerly); persistent strategy, the
                               whole call (one capture for every n_full)      */
     int32_t autotune;      /* 0: fixed launch shapes; 1: measure candidates
                               on the first call and keep the fastest (grid:
@@ -315,7 +317,9 @@ shaken_status shaken_batch_create(shaken_batch **out, shaken_ctx *const *ctx, in
 
 /* Advance every chain of the batch by n_full full steps.  With record set,
  * each chain's H/M log of this call (n_full+1 entries) can then be read with
- * shaken_batch_get_log.  Asynchronous. */
+ * shaken_batch_get_log.  Every chain's counter must still be the batch's and
+ * even (SHAKEN_ESTATE otherwise: a member stepped on its own, or restored to
+ * an odd counter).  Asynchronous. */
 shaken_status shaken_batch_sweep(shaken_batch *b, int64_t n_full);
 
 /* Copy chain i's log of the last shaken_batch_sweep (requires record and
@@ -361,6 +365,31 @@ shaken_status shaken_batch_get_track(shaken_batch *b, int64_t *H_last, int64_t *
  * device time in milliseconds measured with HIP events on the batch stream
  * (synchronises). */
 shaken_status shaken_batch_info(shaken_batch *b, int32_t *strategy, double *last_ms);
+
+/* Host-side work the batch has done since creation, so that a caller can
+ * check that a call did none of it (a timed call, a serving loop):
+ *   sweeps:     shaken_batch_sweep calls completed;
+ *   captures:   HIP graphs captured and instantiated (grid strategy: one graph
+ *               of 16 full steps, captured on the first sweep whatever its
+ *               length and again only after the log space or the launch
+ *               shapes changed; persistent strategy: one, on the first sweep,
+ *               that serves every later call whatever its n_full);
+ *   log_allocs: device allocations of log space (a recorded sweep longer than
+ *               any before it, beyond opts.log_reserve);
+ *   autotunes:  autotuning passes (the first sweep with opts.autotune);
+ *   uploads:    refreshes of the device chain descriptors (log space moved,
+ *               parameters changed, or a member's spin buffers swapped by
+ *               shaken_set_half_step).
+ * Never fails on a valid batch. */
+typedef struct shaken_batch_counts {
+    int64_t sweeps;
+    int64_t captures;
+    int64_t log_allocs;
+    int64_t autotunes;
+    int64_t uploads;
+} shaken_batch_counts;
+
+shaken_status shaken_batch_counters(shaken_batch *b, shaken_batch_counts *out);
 
 shaken_status shaken_batch_free(shaken_batch *b);
 

@@ -81,6 +81,12 @@ class shaken_batch_opts(ctypes.Structure):
                 ("log_reserve", ctypes.c_int32)]
 
 
+class shaken_batch_counts(ctypes.Structure):
+    _fields_ = [("sweeps", ctypes.c_int64), ("captures", ctypes.c_int64),
+                ("log_allocs", ctypes.c_int64), ("autotunes", ctypes.c_int64),
+                ("uploads", ctypes.c_int64)]
+
+
 _vp = ctypes.c_void_p
 _i64p = ctypes.POINTER(ctypes.c_int64)
 _i8p = ctypes.POINTER(ctypes.c_int8)
@@ -108,6 +114,7 @@ _SIGS = {
     "shaken_batch_get_log_ej": [_vp, ctypes.c_int32, _i64p, _i64p, ctypes.c_int64],
     "shaken_batch_get_logs": [_vp, _i64p, _i64p, _i64p, ctypes.c_int64],
     "shaken_batch_info": [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)],
+    "shaken_batch_counters": [_vp, ctypes.POINTER(shaken_batch_counts)],
     "shaken_batch_free": [_vp],
     "shaken_batch_run": [ctypes.POINTER(_vp), ctypes.c_int32, ctypes.c_int64,
                          ctypes.POINTER(shaken_batch_opts), _i64p],
@@ -442,6 +449,13 @@ class Batch:
         ms = ctypes.c_double()
         _check(_lib.shaken_batch_info(self.handle, ctypes.byref(st), ctypes.byref(ms)))
         return int(st.value), float(ms.value)
+
+    def counters(self):
+        """host-side work done so far: dict of sweeps, captures, log_allocs,
+        autotunes, uploads"""
+        c = shaken_batch_counts()
+        _check(_lib.shaken_batch_counters(self.handle, ctypes.byref(c)))
+        return {k: int(getattr(c, k)) for k, _ in shaken_batch_counts._fields_}
 
     def close(self):
         if getattr(self, "handle", None) is not None:

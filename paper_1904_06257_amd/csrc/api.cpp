@@ -980,6 +980,9 @@ int32_t shaken_version(void) { return (SHAKEN_VERSION_MAJOR << 16) | SHAKEN_VERS
 
 namespace {
 
+// full steps of half-step launches per captured HIP graph (grid strategy)
+constexpr int kGraphChunk = 16;
+
 struct Group {
     int kind = 0, format = 0, tri = 0;
     std::vector<int> members;  // indices into the batch's contexts
@@ -1020,6 +1023,10 @@ struct shaken_batch {
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
     int chunk = 0;          // full steps per graph replay
+    // spin buffers of every chain as the device descriptors hold them
+    std::vector<std::pair<void *, void *>> up_spin;
+    // host-side work done so far (shaken_batch_counters)
+    int64_t n_captures = 0, n_log_allocs = 0, n_autotunes = 0, n_uploads = 0, n_sweeps = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool timed = false;
     int64_t last_n_full = -1;
@@ -1086,11 +1093,15 @@ shaken_status batch_ensure_log(shaken_batch *b, int64_t slots, bool *changed) {
     b->log_row = row;
     CHK(dalloc(&b->log_pool, (size_t)(slots * row)));
     b->log_cap = slots;
+    b->n_log_allocs += 1;
     *changed = true;
     return SHAKEN_OK;
 }
 
 shaken_status batch_upload(shaken_batch *b) {
+    b->up_spin.resize(b->ctx.size());
+    for (size_t i = 0; i < b->ctx.size(); ++i) b->up_spin[i] = {b->ctx[i]->spin[0], b->ctx[i]->spin[1]};
+    b->n_uploads += 1;
     for (auto &g : b->groups) {
         for (size_t i = 0; i < g.members.size(); ++i) g.hd[i] = batch_desc(b, g.members[i]);
         HIPCHK(hipMemcpyAsync(g.dd, g.hd.data(), g.hd.size() * sizeof(ChainDesc),
@@ -1147,6 +1158,7 @@ shaken_status batch_autotune(shaken_batch *b) {
         g.block = best_b;
     }
     b->tuned = true;
+    b->n_autotunes += 1;
     return SHAKEN_OK;
 }
 
@@ -1173,6 +1185,7 @@ shaken_status batch_build_graph(shaken_batch *b, int chunk) {
     b->graph = gr;
     HIPCHK(hipGraphInstantiate(&b->gexec, gr, nullptr, nullptr, 0));
     b->chunk = chunk;
+    b->n_captures += 1;
     return SHAKEN_OK;
 }
 
@@ -1199,6 +1212,7 @@ shaken_status batch_build_pgraph(shaken_batch *b) {
     b->pgraph = gr;
     HIPCHK(hipGraphInstantiate(&b->pgexec, gr, nullptr, nullptr, 0));
     b->pg_grid = b->pgrid;
+    b->n_captures += 1;
     return SHAKEN_OK;
 }
 
@@ -1263,30 +1277,32 @@ shaken_status batch_autotune_persistent(shaken_batch *b) {
     if (st != SHAKEN_OK) return st;
     b->pgrid = best_g;
     b->ptuned = true;
+    b->n_autotunes += 1;
     return SHAKEN_OK;
 }
 
 shaken_status batch_sweep_grid(shaken_batch *b, int64_t n_full) {
     const uint32_t s0 = b->ctx[0]->s;
-    if (b->use_graph && n_full > 0) {
-        const int chunk = (int)std::min<int64_t>(n_full, 16);
-        if (!b->gexec || b->chunk != chunk) CHK(batch_build_graph(b, chunk));
-        HIPCHK(launch_set_state(b->dstate, s0, s0, b->stream));
-        const int64_t reps = n_full / chunk;
-        for (int64_t r = 0; r < reps; ++r) HIPCHK(hipGraphLaunch(b->gexec, b->stream));
-        uint32_t s = s0 + (uint32_t)(2 * chunk * reps);
-        for (int64_t t = reps * chunk; t < n_full; ++t) {
-            CHK(batch_half(b, nullptr, s, s0, true));
-            CHK(batch_half(b, nullptr, s + 1, s0, false));
-            s += 2;
+    uint32_t s = s0;
+    int64_t t = 0;
+    if (b->use_graph) {
+        // one graph of kGraphChunk full steps, captured on the first call
+        // whatever its length, replayed as often as it fits; the remainder
+        // runs eagerly (a call never captures again unless the log space or
+        // the launch shapes changed)
+        if (!b->gexec) CHK(batch_build_graph(b, kGraphChunk));
+        const int64_t reps = n_full / kGraphChunk;
+        if (reps > 0) {
+            HIPCHK(launch_set_state(b->dstate, s0, s0, b->stream));
+            for (int64_t r = 0; r < reps; ++r) HIPCHK(hipGraphLaunch(b->gexec, b->stream));
         }
-    } else {
-        uint32_t s = s0;
-        for (int64_t t = 0; t < n_full; ++t) {
-            CHK(batch_half(b, nullptr, s, s0, true));
-            CHK(batch_half(b, nullptr, s + 1, s0, false));
-            s += 2;
-        }
+        t = reps * kGraphChunk;
+        s = s0 + (uint32_t)(2 * t);
+    }
+    for (; t < n_full; ++t) {
+        CHK(batch_half(b, nullptr, s, s0, true));
+        CHK(batch_half(b, nullptr, s + 1, s0, false));
+        s += 2;
     }
     return SHAKEN_OK;
 }
@@ -1433,8 +1449,16 @@ shaken_status shaken_batch_sweep(shaken_batch *b, int64_t n_full) {
     DeviceGuard guard(b->device);
     const uint32_t s0 = b->ctx[0]->s;
     if ((int64_t)s0 + 2 * n_full >= (int64_t)kInitStep) return fail(SHAKEN_ESTATE, "half-step counter would overflow");
-    for (auto *c : b->ctx)
+    if (s0 & 1u) return fail(SHAKEN_ESTATE, "batches need an even half-step counter");
+    bool moved = false;
+    for (size_t i = 0; i < b->ctx.size(); ++i) {
+        shaken_ctx *c = b->ctx[i];
         if (c->s != s0) return fail(SHAKEN_ESTATE, "a context of the batch was stepped on its own");
+        // a checkpoint restore on a member (shaken_set_half_step) can swap its
+        // two spin buffers: the device descriptors must follow
+        moved |= b->up_spin[i].first != c->spin[0] || b->up_spin[i].second != c->spin[1];
+    }
+    if (moved) CHK(batch_upload(b));
     if (b->record) {
         bool changed = false;
         CHK(batch_ensure_log(b, n_full + 1, &changed));
@@ -1461,7 +1485,9 @@ shaken_status shaken_batch_sweep(shaken_batch *b, int64_t n_full) {
     HIPCHK(hipEventRecord(b->ev0, b->stream));
     if (b->strategy == SHAKEN_BATCH_GRID) {
         CHK(batch_sweep_grid(b, n_full));
-    } else if (b->use_graph && n_full > 0) {
+    } else if (b->use_graph) {
+        // captured on the first call (n_full = 0 included): the start
+        // half-step and the length come from device memory
         if (!b->pgexec || b->pg_grid != b->pgrid) CHK(batch_build_pgraph(b));
         HIPCHK(launch_set_state(b->dstate, s0, (uint32_t)n_full, b->stream));
         HIPCHK(hipGraphLaunch(b->pgexec, b->stream));
@@ -1483,6 +1509,7 @@ shaken_status shaken_batch_sweep(shaken_batch *b, int64_t n_full) {
     b->timed = true;
     for (auto *c : b->ctx) c->s = s1;
     b->last_n_full = n_full;
+    b->n_sweeps += 1;
     return SHAKEN_OK;
 }
 
@@ -1624,6 +1651,16 @@ shaken_status shaken_batch_info(shaken_batch *b, int32_t *strategy, double *last
             *last_ms = ms;
         }
     }
+    return SHAKEN_OK;
+}
+
+shaken_status shaken_batch_counters(shaken_batch *b, shaken_batch_counts *out) {
+    if (!b || !out) return fail(SHAKEN_EINVAL, "batch and out must be non-NULL");
+    out->sweeps = b->n_sweeps;
+    out->captures = b->n_captures;
+    out->log_allocs = b->n_log_allocs;
+    out->autotunes = b->n_autotunes;
+    out->uploads = b->n_uploads;
     return SHAKEN_OK;
 }
 
