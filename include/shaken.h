@@ -224,6 +224,30 @@ shaken_status shaken_half_step(shaken_ctx *ctx, int64_t n);
  * for. */
 shaken_status shaken_sweep(shaken_ctx *ctx, int64_t n_full, int64_t *H_out, int64_t *M_out);
 
+/* Variant of shaken_sweep for callers that cannot allocate memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  The same half-steps and the same logs, but the per-step partial
+ * sums of the observables go to a fixed 4 MiB device buffer of the library
+ * (one per device, its address looked up at shaken_init) instead of log space
+ * grown on demand, and the logs are written to device memory.  The call
+ * allocates nothing, on the device or on the host, and only enqueues work on
+ * the context's stream (the one exception: after shaken_batch_set_params
+ * changed this context's parameters, the first call re-uploads its tables and
+ * synchronises).
+ *   H_dev, M_dev: NULL, or device int64 arrays of n_full+1 entries that
+ *     receive H(sigma_t) and M(sigma_t), t = 0..n_full, exactly as H_out and
+ *     M_out of shaken_sweep (H_dev needs every 2*lambda to be an integer).
+ *     With both NULL nothing is logged and the buffer is not used.
+ * Limits with logs: at most 32 field classes, and n_full + 1 slots of
+ * 8 * 16 * ceil((1 + n_classes) / 16) int64 each within the 2^19 int64 of
+ * the buffer -- 4095 full steps per call for up to 15 classes, 2047 for 16 to
+ * 31; beyond that SHAKEN_EINVAL, with the bound in the message.
+ * The buffer is shared by every context on a device and keeps the last call's
+ * contents (each call clears the part it uses first): calls that overlap on
+ * one device -- from different streams or threads -- race and corrupt each
+ * other's logs.  Other errors as shaken_sweep. */
+shaken_status shaken_sweep_noalloc(shaken_ctx *ctx, int64_t n_full, int64_t *H_dev, int64_t *M_dev);
+
 /* Observables of the current configuration. */
 typedef struct shaken_obs {
     int64_t half_step;   /* the counter s                                    */

@@ -98,6 +98,7 @@ _SIGS = {
     "shaken_free": [_vp],
     "shaken_half_step": [_vp, ctypes.c_int64],
     "shaken_sweep": [_vp, ctypes.c_int64, _i64p, _i64p],
+    "shaken_sweep_noalloc": [_vp, ctypes.c_int64, _vp, _vp],
     "shaken_observables": [_vp, ctypes.POINTER(shaken_obs)],
     "shaken_set_params": [_vp, ctypes.c_double, ctypes.c_double],
     "shaken_get_spins": [_vp, _i8p],
@@ -328,6 +329,18 @@ class Chain:
         M = np.zeros(n_full + 1, dtype=np.int64)
         shaken_sweep(self.handle, n_full, H, M)
         return H, M
+
+    def sweep_noalloc(self, n_full, H=None, M=None):
+        """shaken_sweep_noalloc: n_full full steps; H, M are None or int64
+        device tensors of n_full + 1 entries that receive the logs (the call
+        only enqueues work: synchronise before reading them)"""
+        for t in (H, M):
+            if t is not None and (not t.is_cuda or not t.is_contiguous() or t.numel() < n_full + 1
+                                  or str(t.dtype) != "torch.int64"):
+                raise ValueError("logs must be contiguous int64 device tensors of n_full + 1 entries")
+        _check(_lib.shaken_sweep_noalloc(self.handle, int(n_full),
+                                         None if H is None else ctypes.c_void_p(H.data_ptr()),
+                                         None if M is None else ctypes.c_void_p(M.data_ptr())))
 
     def sweep_m(self, n_full):
         """magnetisation log only (works for any lambda)"""

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libshaken.so")
-SOURCES = ["api.cpp", "kernels.hip", "batch.hip", "mlp.hip"]
+SOURCES = ["api.cpp", "kernels.hip", "batch.hip", "mlp.hip", "noalloc.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -4,6 +4,7 @@
 // kernels.hip; this file only prepares data and enqueues launches.
 #include "shaken.h"
 #include "shaken_internal.hpp"
+#include "noalloc.hpp"
 
 #include <algorithm>
 #include <cmath>
@@ -145,6 +146,10 @@ struct shaken_ctx {
     bool lut_stale = false;  // a batch changed beta/q: re-upload before a call of its own
     ChainDesc hd{};
     ChainDesc *dd = nullptr;
+    // the same descriptor with its log pointer at the device's fixed buffer
+    // (shaken_sweep_noalloc); kept in step with dd by upload_desc
+    ChainDesc *dd_static = nullptr;
+    int64_t *scratch = nullptr;  // device address of that buffer (not owned)
     int block = 256;
 
     size_t spin_bytes() const {
@@ -175,6 +180,7 @@ void release(shaken_ctx *c) {
     dfree(c->log_dev);
     dfree(c->obs_dev);
     dfree(c->dd);
+    dfree(c->dd_static);
 }
 
 size_t bit_words(const shaken_ctx *c) {
@@ -232,12 +238,21 @@ void build_tables(shaken_ctx *c) {
     }
 }
 
+// copy the host descriptor to the device: dd as it is, dd_static with the log
+// pointed at the fixed buffer (synchronises the stream)
+shaken_status upload_desc(shaken_ctx *c) {
+    ChainDesc ds = c->hd;
+    ds.log = c->scratch;
+    HIPCHK(hipMemcpyAsync(c->dd, &c->hd, sizeof(ChainDesc), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->dd_static, &ds, sizeof(ChainDesc), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return SHAKEN_OK;
+}
+
 shaken_status upload_tables(shaken_ctx *c) {
     HIPCHK(hipMemcpyAsync(c->lut_dev, c->lut.data(), c->lut.size() * sizeof(uint64_t),
                           hipMemcpyHostToDevice, c->stream));
-    HIPCHK(hipMemcpyAsync(c->dd, &c->hd, sizeof(ChainDesc), hipMemcpyHostToDevice, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
-    return SHAKEN_OK;
+    return upload_desc(c);
 }
 
 // refresh the device tables of a chain whose parameters a batch changed
@@ -260,9 +275,7 @@ shaken_status ensure_log(shaken_ctx *c, int64_t slots) {
     CHK(dalloc(&c->log_dev, (size_t)(slots * c->stride())));
     c->log_cap = slots;
     refresh_desc_spins(c);
-    HIPCHK(hipMemcpyAsync(c->dd, &c->hd, sizeof(ChainDesc), hipMemcpyHostToDevice, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
-    return SHAKEN_OK;
+    return upload_desc(c);
 }
 
 // pack / unpack host int8 <-> bit-packed rows (rows x cols spins, W words per
@@ -600,6 +613,9 @@ shaken_status init_device(shaken_ctx *c, const shaken_opts *o, HostLayout &hl) {
     CHK(dalloc(&c->lut_dev, lut_entries));
     CHK(dalloc(&c->obs_dev, (size_t)c->stride()));
     CHK(dalloc(&c->dd, 1));
+    CHK(dalloc(&c->dd_static, 1));
+    // set-up of the fixed buffer's device address (the device is current)
+    HIPCHK(noalloc_scratch(c->device, &c->scratch));
     if (c->kind == KIND_GRAPH) {
         for (int h = 0; h < 2; ++h) {
             CHK(dalloc(&c->rp[h], rp[h].size()));
@@ -689,11 +705,12 @@ shaken_status init_device(shaken_ctx *c, const shaken_opts *o, HostLayout &hl) {
     return SHAKEN_OK;
 }
 
-// one half-step at the context's counter
-shaken_status half_step_once(shaken_ctx *c, int log_on, uint32_t s_log0) {
+// one half-step at the context's counter (descriptor dd, or dd_static with
+// the log in the fixed buffer)
+shaken_status half_step_once(shaken_ctx *c, int log_on, uint32_t s_log0, bool fixed_log = false) {
     if (c->s >= kInitStep - 1) return fail(SHAKEN_ESTATE, "half-step counter exhausted");
     CHK(refresh_if_stale(c));
-    HIPCHK(launch_half_step_grid(c->dd, &c->hd, 1, nullptr, c->s, s_log0, log_on,
+    HIPCHK(launch_half_step_grid(fixed_log ? c->dd_static : c->dd, &c->hd, 1, nullptr, c->s, s_log0, log_on,
                                  (c->s & 1u) == 0, c->block, c->stream));
     c->s += 1;
     return SHAKEN_OK;
@@ -813,6 +830,46 @@ shaken_status shaken_sweep(shaken_ctx *ctx, int64_t n_full, int64_t *H_out, int6
     return SHAKEN_OK;
 }
 
+shaken_status shaken_sweep_noalloc(shaken_ctx *ctx, int64_t n_full, int64_t *H_dev, int64_t *M_dev) {
+    if (!ctx) return fail(SHAKEN_EINVAL, "ctx is NULL");
+    if (n_full < 0) return fail(SHAKEN_EINVAL, "n_full must be >= 0");
+    if (ctx->s & 1u) return fail(SHAKEN_ESTATE, "shaken_sweep_noalloc needs an even half-step counter");
+    if (H_dev && !ctx->lam2_int) return fail(SHAKEN_EINVAL, "H_dev needs every 2*lambda to be an integer");
+    if ((int64_t)ctx->s + 2 * n_full >= (int64_t)kInitStep) return fail(SHAKEN_ESTATE, "half-step counter would overflow");
+    if (!ctx->scratch || !ctx->dd_static) return fail(SHAKEN_ESTATE, "context has no fixed log buffer");
+    const bool logs = H_dev || M_dev;
+    const int64_t max_full = noalloc_capacity() / ctx->stride() - 1;
+    if (logs) {
+        if ((int64_t)ctx->lam.size() > kNoallocClasses)
+            return fail(SHAKEN_EINVAL, "shaken_sweep_noalloc logs at most " + std::to_string(kNoallocClasses) +
+                                           " field classes");
+        if (n_full > max_full)
+            return fail(SHAKEN_EINVAL, "n_full = " + std::to_string(n_full) + " exceeds the fixed log buffer: at most " +
+                                           std::to_string(max_full) + " full steps per call with logs for this context");
+    }
+    DeviceGuard guard(ctx->device);
+    const uint32_t s0 = ctx->s;
+    const int64_t slots = n_full + 1;
+    // partial sums accumulate into the slots: clear them with a fill kernel
+    if (logs) HIPCHK(launch_fill_i64(ctx->scratch, slots * ctx->stride(), 0, ctx->stream));
+    for (int64_t t = 0; t < n_full; ++t) {
+        CHK(half_step_once(ctx, logs ? 1 : 0, s0, true));
+        CHK(half_step_once(ctx, 0, s0, true));
+    }
+    if (logs) {
+        HIPCHK(launch_observe(ctx->dd_static, &ctx->hd, 1, (int)(ctx->s & 1u), (int)n_full, ctx->stream));
+        LogReduceArgs a{};
+        a.ncls = (int32_t)ctx->lam.size();
+        a.n = ctx->n;
+        for (size_t k = 0; k < ctx->lam.size(); ++k) {
+            a.lam2[k] = ctx->lam2_int ? ctx->lam2[k] : 0;
+            a.c0 += a.lam2[k] * ctx->class_size[k];
+        }
+        HIPCHK(launch_log_reduce(ctx->scratch, slots, ctx->line(), a, H_dev, M_dev, ctx->stream));
+    }
+    return SHAKEN_OK;
+}
+
 shaken_status shaken_observables(shaken_ctx *ctx, shaken_obs *out) {
     if (!ctx || !out) return fail(SHAKEN_EINVAL, "ctx and out must be non-NULL");
     DeviceGuard guard(ctx->device);
@@ -925,8 +982,7 @@ shaken_status shaken_set_half_step(shaken_ctx *ctx, int64_t s) {
         // keep the configuration where the new parity expects it
         std::swap(ctx->spin[0], ctx->spin[1]);
         refresh_desc_spins(ctx);
-        HIPCHK(hipMemcpyAsync(ctx->dd, &ctx->hd, sizeof(ChainDesc), hipMemcpyHostToDevice, ctx->stream));
-        HIPCHK(hipStreamSynchronize(ctx->stream));
+        CHK(upload_desc(ctx));
     }
     ctx->s = (uint32_t)s;
     return SHAKEN_OK;
