@@ -417,11 +417,6 @@ shaken_status shaken_batch_counters(shaken_batch *b, shaken_batch_counts *out);
 
 shaken_status shaken_batch_free(shaken_batch *b);
 
-/* One-call convenience: create a batch over ctx[0..n-1], run n_full full
- * steps, optionally copy each chain's final H into H_final (n entries),
- * free the batch.  Synchronises. */
-shaken_status shaken_batch_run(shaken_ctx *const *ctx, int32_t n, int64_t n_full,
-                               const shaken_batch_opts *opts, int64_t *H_final);
 
 /* ------------------------------------------------- annealing schedule network
  *
@@ -479,6 +474,86 @@ shaken_status shaken_mlp_get_grads(shaken_mlp *m, float *host, size_t n);
  * the bias corrections), then refresh the BF16 copies. */
 shaken_status shaken_mlp_adam(shaken_mlp *m, float lr, float beta1, float beta2, float eps,
                               int32_t t);
+
+/* ------------------------------------------------------ one-call batch runs
+ *
+ * shaken_batch_run creates a batch over ctx[0..n-1], runs n_full full steps
+ * under an optional annealing schedule, fills the requested results and frees
+ * the batch; the contexts keep their final configurations (and, with a
+ * schedule, the last beta and q).  This is the minimisation use of the
+ * dynamics (section 6): at low temperature the pair law concentrates on the
+ * minimisers of the pair Hamiltonian, which lie on the diagonal -- minimisers
+ * of H -- once q exceeds every half-neighbourhood coupling sum (Theorem 6.1,
+ * read as q > max_x sum_{(x,y) in E^o} |J_xy| + |lambda_x|).  The schedule
+ * only chooses (beta, q) between chunks of full steps; the sampler's
+ * arithmetic is unchanged, and every energy reported is that of a
+ * configuration the dynamics reached. */
+enum {
+    SHAKEN_SCHEDULE_NONE = 0,       /* every chain keeps its own beta and q     */
+    SHAKEN_SCHEDULE_GEOMETRIC = 1,  /* beta geometric from beta0 to beta1, q
+                                       constant, the same for every chain      */
+    SHAKEN_SCHEDULE_MLP = 2         /* the schedule network picks (beta, q) for
+                                       every chain and chunk; the geometric
+                                       schedule stands in for any chain whose
+                                       network output is not finite            */
+};
+
+typedef struct shaken_schedule {
+    int32_t kind;            /* SHAKEN_SCHEDULE_*                               */
+    int32_t chunk_sweeps;    /* full steps per chunk (>= 1, n_full a multiple of
+                                it; kinds GEOMETRIC and MLP): (beta, q) change
+                                only between chunks                          */
+    double beta0, beta1;     /* geometric schedule (> 0, finite): chunk c of C
+                                runs at beta = exp(log beta0 + ((c + 1/2) / C)
+                                * (log beta1 - log beta0)) (libm log and exp)  */
+    double q;                /* geometric schedule: q (>= 0, finite)           */
+    shaken_mlp *mlp;         /* kind MLP: the network (same device)            */
+} shaken_schedule;
+
+/* The schedule network's inputs, one row of 16 FP32 per chain and chunk c of
+ * C (features of the chain before the chunk, zero beyond entry 8):
+ *   0  log2(sites) / 16
+ *   1  mean degree / 4                (in-half + out-half sizes)
+ *   2  std(in-half size - out-half size) / 2, over the sites
+ *   3  c / C
+ *   4  H(current configuration) / sites
+ *   5  lowest H so far / sites
+ *   6  log beta of the previous chunk / 3   (0 before the first chunk)
+ *   7  log q of the previous chunk / 3      (0 before the first chunk)
+ *   8  1
+ * each computed in double and rounded to FP32.  Outputs 0 and 1 are
+ * (log beta, log q); after the fallback for non-finite rows both are clamped
+ * to [log 0.05, log 20] and [log 0.05, log 8]. */
+
+typedef struct shaken_run_result {
+    int64_t *H_final;     /* NULL or n: H of each chain's final configuration */
+    int64_t *H_best;      /* NULL or n: lowest H over each chain's full-step
+                             configurations of the run (the start included) */
+    int8_t *best_spins;   /* NULL or, concatenated in chain order, the
+                             configuration that first reached H_best (n or
+                             L*L int8 each); needs the persistent strategy   */
+    double *beta_used;    /* NULL or [chunks][n]: beta of each chain in each
+                             chunk (kinds GEOMETRIC and MLP)                 */
+    double *q_used;       /* NULL or [chunks][n]: q likewise                  */
+    int64_t chunks;       /* out: number of chunks run                        */
+    int64_t fallbacks;    /* out: (chunk, chain) pairs where the network's
+                             output was not finite                           */
+} shaken_run_result;
+
+/* Run n_full full steps of the chains ctx[0..n-1] as one batch (opts as for
+ * shaken_batch_create, NULL = defaults; AUTO picks the persistent kernel
+ * when every chain fits it) under `sched` (NULL = SHAKEN_SCHEDULE_NONE), and
+ * fill what `res` asks for (res may be NULL).  Energies (H_final, H_best,
+ * best_spins, and the MLP's features) need every 2*lambda to be an integer;
+ * they are tracked on the device (persistent strategy) or read from the
+ * observables log (grid strategy).  Allocates the batch and, for the MLP,
+ * two small feature buffers; synchronises.  Errors: SHAKEN_EINVAL (bad
+ * schedule, n_full not a multiple of chunk_sweeps, best_spins without the
+ * persistent strategy, network on another device), SHAKEN_ESTATE, and those
+ * of the batch calls. */
+shaken_status shaken_batch_run(shaken_ctx *const *ctx, int32_t n, int64_t n_full,
+                               const shaken_batch_opts *opts, const shaken_schedule *sched,
+                               shaken_run_result *res);
 
 /* -------------------------------------------------------------- diagnostics */
 

@@ -90,6 +90,20 @@ class shaken_batch_counts(ctypes.Structure):
 _vp = ctypes.c_void_p
 _i64p = ctypes.POINTER(ctypes.c_int64)
 _i8p = ctypes.POINTER(ctypes.c_int8)
+_f64p = ctypes.POINTER(ctypes.c_double)
+
+SHAKEN_SCHEDULE_NONE, SHAKEN_SCHEDULE_GEOMETRIC, SHAKEN_SCHEDULE_MLP = 0, 1, 2
+_SCHED = {"none": SHAKEN_SCHEDULE_NONE, "geometric": SHAKEN_SCHEDULE_GEOMETRIC, "mlp": SHAKEN_SCHEDULE_MLP}
+
+
+class shaken_schedule(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("chunk_sweeps", ctypes.c_int32), ("beta0", ctypes.c_double),
+                ("beta1", ctypes.c_double), ("q", ctypes.c_double), ("mlp", ctypes.c_void_p)]
+
+
+class shaken_run_result(ctypes.Structure):
+    _fields_ = [("H_final", _i64p), ("H_best", _i64p), ("best_spins", _i8p), ("beta_used", _f64p),
+                ("q_used", _f64p), ("chunks", ctypes.c_int64), ("fallbacks", ctypes.c_int64)]
 
 _SIGS = {
     "shaken_init": [ctypes.POINTER(_vp), ctypes.POINTER(shaken_graph), _i8p,
@@ -118,7 +132,8 @@ _SIGS = {
     "shaken_batch_counters": [_vp, ctypes.POINTER(shaken_batch_counts)],
     "shaken_batch_free": [_vp],
     "shaken_batch_run": [ctypes.POINTER(_vp), ctypes.c_int32, ctypes.c_int64,
-                         ctypes.POINTER(shaken_batch_opts), _i64p],
+                         ctypes.POINTER(shaken_batch_opts), ctypes.POINTER(shaken_schedule),
+                         ctypes.POINTER(shaken_run_result)],
     "shaken_batch_set_params": [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
     "shaken_batch_get_track": [_vp, _i64p, _i64p, _i8p],
     "shaken_mlp_create": [ctypes.POINTER(_vp), ctypes.c_int32, _vp],
@@ -207,13 +222,13 @@ def shaken_observables(ctx):
     return o
 
 
-def shaken_batch_run(ctxs, n_full, opts, H_final=None):
-    if H_final is not None and (H_final.dtype != np.int64 or not H_final.flags.c_contiguous
-                                or H_final.size < len(ctxs)):
-        raise ValueError("H_final must be a contiguous int64 array with one entry per context")
+def shaken_batch_run(ctxs, n_full, opts=None, sched=None, res=None):
+    """raw call: ctxs are context handles, opts / sched / res ctypes structs
+    or None (res arrays are filled in place)"""
     arr = (_vp * len(ctxs))(*[c.value for c in ctxs])
-    _check(_lib.shaken_batch_run(arr, len(ctxs), int(n_full), ctypes.byref(opts),
-                                 _ptr(H_final, ctypes.c_int64)))
+    _check(_lib.shaken_batch_run(arr, len(ctxs), int(n_full), None if opts is None else ctypes.byref(opts),
+                                 None if sched is None else ctypes.byref(sched),
+                                 None if res is None else ctypes.byref(res)))
 
 
 # ------------------------------------------------------------------ classes
@@ -480,6 +495,46 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+class RunOutput:
+    """Results of batch_run: H_final, H_best (int64 per chain), best_spins
+    (list of per-chain int8 configurations, or None), beta_used and q_used
+    ([chunks, chains] or None), chunks, fallbacks."""
+
+    def __init__(self, **kw):
+        self.__dict__.update(kw)
+
+
+def batch_run(chains, n_full, schedule="none", chunk_sweeps=0, beta0=1.0, beta1=1.0, q=1.0, mlp=None,
+              strategy="auto", use_hipgraph=False, autotune=False, best_spins=False, energies=True,
+              stream=None):
+    """shaken_batch_run over `chains`: n_full full steps under a schedule
+    ("none", "geometric", "mlp"), the chunk loop run by the library; returns a
+    RunOutput (energies need every 2*lambda integer; energies=False asks for
+    none of them)."""
+    n = len(chains)
+    kind = _SCHED[schedule]
+    if n < 1:
+        raise ValueError("batch_run needs at least one chain")
+    o = shaken_batch_opts(_STRAT[strategy], int(use_hipgraph), int(autotune), 0, _stream_handle(stream), 0, 0)
+    sc = shaken_schedule(kind, int(chunk_sweeps), float(beta0), float(beta1), float(q),
+                         None if mlp is None else mlp.handle)
+    chunks = 0 if schedule == "none" or chunk_sweeps < 1 else int(n_full) // int(chunk_sweeps)
+    hf = np.zeros(n, dtype=np.int64) if energies else None
+    hb = np.zeros(n, dtype=np.int64) if energies else None
+    sp = np.zeros(sum(c.n for c in chains), dtype=np.int8) if best_spins else None
+    bu = np.zeros((chunks, n), dtype=np.float64) if chunks else None
+    qu = np.zeros((chunks, n), dtype=np.float64) if chunks else None
+    r = shaken_run_result(_ptr(hf, ctypes.c_int64), _ptr(hb, ctypes.c_int64), _ptr(sp, ctypes.c_int8),
+                          _ptr(bu, ctypes.c_double), _ptr(qu, ctypes.c_double), 0, 0)
+    shaken_batch_run([c.handle for c in chains], n_full, o, sc, r)
+    spins = None
+    if best_spins:
+        off = np.cumsum([0] + [c.n for c in chains])
+        spins = [sp[off[i]:off[i + 1]].reshape(chains[i].shape).copy() for i in range(n)]
+    return RunOutput(H_final=hf, H_best=hb, best_spins=spins, beta_used=bu, q_used=qu,
+                     chunks=int(r.chunks), fallbacks=int(r.fallbacks))
 
 
 # ---------------------------------------------------------- schedule network

@@ -14,28 +14,43 @@ Policies map per-chain features to (beta, q) once per chunk of sweeps:
   * ``MLPPolicy``       -- the network of the library (BF16/FP32 MFMA kernels)
     maps the features to (log beta, log q).
 
+Two drivers of the chunk loop:
+  * ``run_native`` -- the library's own loop (``shaken_batch_run`` with a
+    geometric or network schedule): what evaluation and users run;
+  * ``run`` -- the same loop written here around any policy, for the
+    perturbed schedules the network is trained on.  With ``GeometricPolicy``
+    or ``MLPPolicy`` it computes exactly what the library does (same features,
+    libm log and exp, same clamps and fallback), which the tests check bit
+    for bit.
+
 This module only orchestrates: sampling, thresholds, tracking and the network
 all run in libshaken.
 """
 from __future__ import annotations
 
 import dataclasses
+import math
 
 import numpy as np
 
-from . import Batch, Chain, MLP
+from . import Batch, Chain, MLP, batch_run
 
 NFEAT = 16
-LOG_BETA_RANGE = (np.log(0.05), np.log(20.0))
-LOG_Q_RANGE = (np.log(0.05), np.log(8.0))
+# libm log, as the library's clamps
+LOG_BETA_RANGE = (math.log(0.05), math.log(20.0))
+LOG_Q_RANGE = (math.log(0.05), math.log(8.0))
 
 
 def graph_stats(inst):
-    """(log2 n / 16, mean degree / 4, std of in-degree minus out-degree / 2)"""
+    """(log2 n / 16, mean degree / 4, std of in-degree minus out-degree / 2),
+    from integer sums (the differences sum to zero over the vertices), as the
+    library computes them"""
     n = inst.n
-    deg_in = np.bincount(inst.dst, minlength=n)
-    deg_out = np.bincount(inst.src, minlength=n)
-    return (np.log2(n) / 16.0, (deg_in + deg_out).mean() / 4.0, (deg_in - deg_out).std() / 2.0)
+    deg_in = np.bincount(inst.dst, minlength=n).astype(np.int64)
+    deg_out = np.bincount(inst.src, minlength=n).astype(np.int64)
+    d = deg_in - deg_out
+    return (math.log2(n) / 16.0, float(int((deg_in + deg_out).sum())) / n / 4.0,
+            math.sqrt(float(int((d * d).sum())) / n) / 2.0)
 
 
 def features(stats, frac, e_cur, e_best, n, log_beta, log_q):
@@ -58,11 +73,16 @@ class GeometricPolicy:
     beta1: float
     q: float
 
-    def __call__(self, F, c, n_chunks):
+    def at(self, c, n_chunks):
+        """(log beta, log q) of chunk c of n_chunks (libm log)"""
         t = (c + 0.5) / n_chunks
-        lb = np.log(self.beta0) + t * (np.log(self.beta1) - np.log(self.beta0))
+        l0, l1 = math.log(self.beta0), math.log(self.beta1)
+        return l0 + t * (l1 - l0), math.log(self.q)
+
+    def __call__(self, F, c, n_chunks):
+        lb, lq = self.at(c, n_chunks)
         rows = F.shape[0]
-        return np.full(rows, lb), np.full(rows, np.log(self.q))
+        return np.full(rows, lb), np.full(rows, lq)
 
 
 class PerturbedPolicy:
@@ -90,11 +110,17 @@ class PerturbedPolicy:
 
 
 class MLPPolicy:
-    def __init__(self, mlp: MLP, device="cuda"):
+    """The network's (log beta, log q) per chain; rows whose output is not
+    finite take the geometric schedule `fallback` instead (counted in
+    `fallbacks`)."""
+
+    def __init__(self, mlp: MLP, fallback: GeometricPolicy, device="cuda"):
         import torch
         self.mlp = mlp
+        self.fallback = fallback
         self.torch = torch
         self.device = device
+        self.fallbacks = 0
 
     def __call__(self, F, c, n_chunks):
         torch = self.torch
@@ -104,8 +130,10 @@ class MLPPolicy:
         out = y[:, :2].double().cpu().numpy()
         lb, lq = out[:, 0], out[:, 1]
         bad = ~np.isfinite(lb) | ~np.isfinite(lq)
-        lb = np.clip(np.where(bad, 0.0, lb), *LOG_BETA_RANGE)
-        lq = np.clip(np.where(bad, 0.0, lq), *LOG_Q_RANGE)
+        self.fallbacks += int(bad.sum())
+        glb, glq = self.fallback.at(c, n_chunks)
+        lb = np.clip(np.where(bad, glb, lb), *LOG_BETA_RANGE)
+        lq = np.clip(np.where(bad, glq, lq), *LOG_Q_RANGE)
         return lb, lq
 
 
@@ -130,10 +158,43 @@ class RunResult:
     last: np.ndarray          # H of the final configuration
     best_spins: list          # configuration that reached `best`, per chain
     final_spins: list
-    feats: np.ndarray         # [chunks, chains, 16]
-    log_beta: np.ndarray      # [chunks, chains]
+    feats: np.ndarray         # [chunks, chains, 16] (None from the library's loop)
+    log_beta: np.ndarray      # [chunks, chains] (clamped; exp gives beta)
     log_q: np.ndarray
     seconds: float
+    beta: np.ndarray = None   # [chunks, chains]: the beta and q the chains ran
+    q: np.ndarray = None
+    fallbacks: int = 0
+
+
+def _exp(a):
+    """libm exp elementwise (the library's)"""
+    return np.array([math.exp(float(v)) for v in np.ravel(a)], dtype=np.float64).reshape(np.shape(a))
+
+
+def _chains(instances, seeds, replica0):
+    return [Chain.graph(inst.n, inst.src, inst.dst, J=inst.J, q=1.0, beta=0.1, seed=int(seeds[i]),
+                        replica=replica0 + i) for i, inst in enumerate(instances)]
+
+
+def run_native(instances, seeds, schedule, sweeps, chunk, geometric, mlp=None, replica0=0,
+               keep_spins=False):
+    """Anneal every instance once with the library's chunk loop
+    (shaken_batch_run): schedule "geometric" (the GeometricPolicy
+    `geometric`) or "mlp" (network `mlp`, `geometric` as its fallback)."""
+    import time
+    chains = _chains(instances, seeds, replica0)
+    t0 = time.perf_counter()
+    out = batch_run(chains, sweeps, schedule=schedule, chunk_sweeps=chunk, beta0=geometric.beta0,
+                    beta1=geometric.beta1, q=geometric.q, mlp=mlp, strategy="persistent",
+                    best_spins=keep_spins)
+    secs = time.perf_counter() - t0
+    final = [ch.spins() for ch in chains] if keep_spins else []
+    for ch in chains:
+        ch.close()
+    return RunResult(out.H_best, out.H_final, out.best_spins if keep_spins else [], final, None,
+                     np.log(out.beta_used), np.log(out.q_used), secs, beta=out.beta_used, q=out.q_used,
+                     fallbacks=out.fallbacks)
 
 
 def run(instances, seeds, policy, sweeps, chunk, replica0=0, keep_spins=False):
@@ -141,10 +202,7 @@ def run(instances, seeds, policy, sweeps, chunk, replica0=0, keep_spins=False):
     `policy`; chains start from the random state of their seed."""
     import time
     n_chunks = sweeps // chunk
-    chains = []
-    for i, inst in enumerate(instances):
-        chains.append(Chain.graph(inst.n, inst.src, inst.dst, J=inst.J, q=1.0, beta=0.1,
-                                  seed=int(seeds[i]), replica=replica0 + i))
+    chains = _chains(instances, seeds, replica0)
     stats = [graph_stats(inst) for inst in instances]
     ns = np.array([inst.n for inst in instances], dtype=np.float64)
     batch = Batch(chains, strategy="persistent", track=True)
@@ -161,14 +219,17 @@ def run(instances, seeds, policy, sweeps, chunk, replica0=0, keep_spins=False):
     e_best = e_best.astype(np.float64)
     lb_prev = np.zeros(len(chains))
     lq_prev = np.zeros(len(chains))
-    feats, lbs, lqs = [], [], []
+    feats, lbs, lqs, bs, qs = [], [], [], [], []
     t0 = time.perf_counter()
     for c in range(n_chunks):
         F = features(stats, c / n_chunks, e_cur, e_best, ns, lb_prev, lq_prev)
         lb, lq = policy(F, c, n_chunks)
         lb = np.clip(lb, *LOG_BETA_RANGE)
         lq = np.clip(lq, *LOG_Q_RANGE)
-        batch.set_params(np.exp(lb), np.exp(lq))
+        beta, q = _exp(lb), _exp(lq)
+        bs.append(beta)
+        qs.append(q)
+        batch.set_params(beta, q)
         batch.sweep(chunk)
         if keep_spins:
             hl, hb, sp = batch.track(best_spins=True)
@@ -188,7 +249,8 @@ def run(instances, seeds, policy, sweeps, chunk, replica0=0, keep_spins=False):
     for ch in chains:
         ch.close()
     return RunResult(e_best, e_cur, best_spins, final, np.array(feats), np.array(lbs),
-                     np.array(lqs), secs)
+                     np.array(lqs), secs, beta=np.array(bs), q=np.array(qs),
+                     fallbacks=getattr(policy, "fallbacks", 0))
 
 
 def train_mlp(mlp: MLP, X, Y, w, epochs, batch_rows, lr, seed=0, device="cuda", log=None):

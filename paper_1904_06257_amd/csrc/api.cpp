@@ -144,6 +144,9 @@ struct shaken_ctx {
     int64_t log_cap = 0;  // slots
     int64_t *obs_dev = nullptr;
     bool lut_stale = false;  // a batch changed beta/q: re-upload before a call of its own
+    // degree statistics over the sites (schedule network features): mean of
+    // in-half + out-half size, root mean square of in-half - out-half size
+    double deg_mean = 0, deg_spread = 0;
     ChainDesc hd{};
     ChainDesc *dd = nullptr;
     // the same descriptor with its log pointer at the device's fixed buffer
@@ -688,6 +691,23 @@ shaken_status init_device(shaken_ctx *c, const shaken_opts *o, HostLayout &hl) {
     build_tables(c);
     CHK(upload_tables(c));
 
+    // degree statistics (integer sums; the in - out differences sum to zero
+    // over the sites, so their root mean square is their standard deviation)
+    if (c->kind == KIND_GRAPH) {
+        int64_t sdeg = 0, s2 = 0;
+        for (int v = 0; v < c->n; ++v) {
+            const int64_t din = rp[0][(size_t)v + 1] - rp[0][(size_t)v];
+            const int64_t dout = rp[1][(size_t)v + 1] - rp[1][(size_t)v];
+            sdeg += din + dout;
+            s2 += (din - dout) * (din - dout);
+        }
+        c->deg_mean = (double)sdeg / (double)c->n;
+        c->deg_spread = std::sqrt((double)s2 / (double)c->n);
+    } else {
+        c->deg_mean = c->tri ? 6.0 : 4.0;
+        c->deg_spread = 0.0;
+    }
+
     // initial state into spin[0] (s = 0)
     switch (o->init) {
     case SHAKEN_INIT_RANDOM:
@@ -1183,10 +1203,9 @@ shaken_status batch_half(shaken_batch *b, const uint32_t *dstate, uint32_t s_add
 
 // time `reps` repeated launches of the same half-step (idempotent: same input,
 // same output buffer) for one group and block size
-shaken_status time_group(shaken_batch *b, Group &g, int block, uint32_t s, float *ms) {
-    const int reps = 5;
-    HIPCHK(launch_half_step_grid(g.dd, g.hd.data(), (int)g.hd.size(), nullptr, s, s, 0, (s & 1u) == 0,
-                                 block, b->stream));
+shaken_status time_group(shaken_batch *b, Group &g, int block, uint32_t s, int reps, float *ms) {
+    HIPCHK(launch_half_step_grid(g.dd, g.hd.data(), (int)g.hd.size(), nullptr, s, s, 0, (s & 1u) == 0, block,
+                                 b->stream));
     HIPCHK(hipEventRecord(b->ev0, b->stream));
     for (int i = 0; i < reps; ++i)
         HIPCHK(launch_half_step_grid(g.dd, g.hd.data(), (int)g.hd.size(), nullptr, s, s, 0,
@@ -1197,15 +1216,33 @@ shaken_status time_group(shaken_batch *b, Group &g, int block, uint32_t s, float
     return SHAKEN_OK;
 }
 
+// GPU time the autotuners spend on trial launches before they compare
+// candidates: an idle GPU takes some tens of milliseconds of work to reach its
+// steady clocks (measured on MI355X: half-step launches of the 4096^2 x 24
+// batch run 74 us at first, 66 us after ~30 ms, 63 us in long runs), and a
+// comparison made while the clocks rise favours whichever candidate runs last.
+constexpr float kWarmMs = 40.0f;
+constexpr int kWarmMaxTrials = 400;
+
 shaken_status batch_autotune(shaken_batch *b) {
     const uint32_t s = b->ctx[0]->s;
+    const int cands[3] = {64, 128, 256};
+    // Trial launches are half-steps at the batch's (even) counter: they read
+    // spin[0] and write spin[1], so the chains' configurations are untouched.
+    // Warm phase first, with the default shape.
+    float warm = 0;
+    for (int k = 0; k < kWarmMaxTrials && warm < kWarmMs; ++k)
+        for (auto &g : b->groups) {
+            float ms = 0;
+            CHK(time_group(b, g, g.block, s, 5, &ms));
+            warm += ms;
+        }
     for (auto &g : b->groups) {
-        const int cands[3] = {64, 128, 256};
         float best = 1e30f;
         int best_b = g.block;
         for (int cb : cands) {
             float ms = 0;
-            CHK(time_group(b, g, cb, s, &ms));
+            CHK(time_group(b, g, cb, s, 10, &ms));
             if (ms < best) {
                 best = ms;
                 best_b = cb;
@@ -1307,6 +1344,22 @@ shaken_status batch_autotune_persistent(shaken_batch *b) {
     const uint32_t s0 = b->ctx[0]->s;
     shaken_status st = SHAKEN_OK;
     hipError_t e = copy_all(true);
+    // warm phase (steady clocks before the comparison): trial runs with the
+    // occupancy-bound grid, each followed by the restore
+    float warm = 0;
+    for (int k = 0; k < kWarmMaxTrials && warm < kWarmMs && e == hipSuccess; ++k) {
+        e = launch_set_state((uint32_t *)b->counter, 0u, 0u, b->stream);
+        if (e == hipSuccess) e = hipEventRecord(b->ev0, b->stream);
+        if (e == hipSuccess)
+            e = launch_persistent(b->pdescs, n, b->order, b->counter, s0, nullptr, 8, 0, 0, b->pblock, b->pgrid,
+                                  b->stream);
+        if (e == hipSuccess) e = hipEventRecord(b->ev1, b->stream);
+        if (e == hipSuccess) e = copy_all(false);
+        if (e == hipSuccess) e = hipEventSynchronize(b->ev1);
+        float ms = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, b->ev0, b->ev1);
+        warm += ms;
+    }
     float best = 1e30f;
     int best_g = b->pgrid;
     for (size_t k = 0; k < cands.size() && e == hipSuccess; ++k) {
@@ -1729,24 +1782,218 @@ shaken_status shaken_batch_free(shaken_batch *b) {
     return SHAKEN_OK;
 }
 
-shaken_status shaken_batch_run(shaken_ctx *const *ctx, int32_t n, int64_t n_full,
-                               const shaken_batch_opts *opts, int64_t *H_final) {
-    shaken_batch *b = nullptr;
-    CHK(shaken_batch_create(&b, ctx, n, opts));
-    shaken_status st = shaken_batch_sweep(b, n_full);
-    if (st == SHAKEN_OK) {
-        DeviceGuard guard(b->device);
-        if (hipStreamSynchronize(b->stream) != hipSuccess) st = fail(SHAKEN_EDEVICE, "stream sync failed");
+}  // extern "C"
+
+// =========================================================== one-call runs
+
+namespace shaken {
+// the network's device and stream (defined with the network)
+int mlp_device(const shaken_mlp *m);
+hipStream_t mlp_stream(const shaken_mlp *m);
+}  // namespace shaken
+
+namespace {
+
+constexpr int kFeat = SHAKEN_MLP_IN;
+
+// the geometric schedule at chunk c of C: (log beta, log q)
+void geometric_at(const shaken_schedule &s, int64_t c, int64_t C, double *lb, double *lq) {
+    const double t = ((double)c + 0.5) / (double)C;
+    const double l0 = std::log(s.beta0), l1 = std::log(s.beta1);
+    *lb = l0 + t * (l1 - l0);
+    *lq = std::log(s.q);
+}
+
+// energies after a sweep: H of the last configuration and the lowest H over
+// the call's full-step configurations, per chain (track on the persistent
+// strategy, the observables log on the grid strategy)
+shaken_status call_energies(shaken_batch *b, int64_t n_full, std::vector<int64_t> &last,
+                            std::vector<int64_t> &best) {
+    const size_t n = b->ctx.size();
+    last.resize(n);
+    best.resize(n);
+    if (b->track) return shaken_batch_get_track(b, last.data(), best.data(), nullptr);
+    const int64_t cap = n_full + 1;
+    std::vector<int64_t> H((size_t)(n * cap));
+    CHK(shaken_batch_get_logs(b, H.data(), nullptr, nullptr, cap));
+    for (size_t i = 0; i < n; ++i) {
+        const int64_t *h = H.data() + i * cap;
+        last[i] = h[cap - 1];
+        best[i] = *std::min_element(h, h + cap);
     }
-    shaken_batch_free(b);
-    if (st != SHAKEN_OK) return st;
-    if (H_final) {
-        for (int i = 0; i < n; ++i) {
-            shaken_obs ob;
-            CHK(shaken_observables(ctx[i], &ob));
-            if (!(ob.flags & 1)) return fail(SHAKEN_EINVAL, "H_final needs every 2*lambda to be an integer");
-            H_final[i] = (int64_t)ob.H;
+    return SHAKEN_OK;
+}
+
+struct RunState {
+    shaken_batch *b = nullptr;
+    float *x = nullptr, *y = nullptr;  // network features and outputs (device)
+    ~RunState() {
+        if (b) shaken_batch_free(b);
+        dfree(x);
+        dfree(y);
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+shaken_status shaken_batch_run(shaken_ctx *const *ctx, int32_t n, int64_t n_full,
+                               const shaken_batch_opts *opts, const shaken_schedule *sched,
+                               shaken_run_result *res) {
+    g_err.clear();
+    if (!ctx || n < 1) return fail(SHAKEN_EINVAL, "need ctx and n >= 1");
+    if (n_full < 0) return fail(SHAKEN_EINVAL, "n_full must be >= 0");
+    for (int i = 0; i < n; ++i)
+        if (!ctx[i]) return fail(SHAKEN_EINVAL, "ctx[" + std::to_string(i) + "] is NULL");
+    shaken_schedule sc{};
+    if (sched) sc = *sched;
+    if (sc.kind < SHAKEN_SCHEDULE_NONE || sc.kind > SHAKEN_SCHEDULE_MLP)
+        return fail(SHAKEN_EINVAL, "unknown schedule kind");
+    const bool scheduled = sc.kind != SHAKEN_SCHEDULE_NONE;
+    int64_t chunk = n_full, chunks = 1;
+    if (scheduled) {
+        if (sc.chunk_sweeps < 1) return fail(SHAKEN_EINVAL, "chunk_sweeps must be >= 1");
+        if (n_full % sc.chunk_sweeps) return fail(SHAKEN_EINVAL, "n_full must be a multiple of chunk_sweeps");
+        chunk = sc.chunk_sweeps;
+        chunks = n_full / chunk;
+        if (!(std::isfinite(sc.beta0) && sc.beta0 > 0 && std::isfinite(sc.beta1) && sc.beta1 > 0))
+            return fail(SHAKEN_EINVAL, "geometric schedule: beta0 and beta1 must be finite and > 0");
+        if (!finite_nonneg(sc.q) || sc.q == 0.0)
+            return fail(SHAKEN_EINVAL, "geometric schedule: q must be finite and > 0");
+        if (sc.kind == SHAKEN_SCHEDULE_MLP) {
+            if (!sc.mlp) return fail(SHAKEN_EINVAL, "schedule MLP needs the network");
+            if (shaken::mlp_device(sc.mlp) != ctx[0]->device)
+                return fail(SHAKEN_EINVAL, "the network is on another device");
         }
+    }
+    const bool want_best = res && (res->H_best || res->best_spins);
+    const bool energies = (res && (res->H_final || want_best)) || sc.kind == SHAKEN_SCHEDULE_MLP;
+    shaken_batch_opts o{};
+    if (opts) o = *opts;
+    if (energies) {
+        for (int i = 0; i < n; ++i)
+            if (!ctx[i]->lam2_int) return fail(SHAKEN_EINVAL, "energies need every 2*lambda to be an integer");
+        bool all_fit = true;
+        for (int i = 0; i < n; ++i) all_fit = all_fit && persistent_fits(ctx[i]->hd);
+        int strat = o.strategy == SHAKEN_BATCH_AUTO ? (all_fit ? SHAKEN_BATCH_PERSISTENT : SHAKEN_BATCH_GRID)
+                                                    : o.strategy;
+        o.strategy = strat;
+        if (strat == SHAKEN_BATCH_PERSISTENT) {
+            o.track = 1;
+        } else {
+            if (res && res->best_spins) return fail(SHAKEN_EINVAL, "best_spins needs the persistent strategy");
+            o.record = 1;
+            o.log_reserve = (int32_t)std::min<int64_t>(std::max<int64_t>(o.log_reserve, chunk), INT32_MAX);
+        }
+    }
+    RunState rs;
+    CHK(shaken_batch_create(&rs.b, ctx, n, &o));
+    shaken_batch *b = rs.b;
+    DeviceGuard guard(b->device);
+    const size_t N = (size_t)n;
+    // the run's energies: current and lowest so far, and the best configurations
+    std::vector<int64_t> e_cur(N, 0), e_best(N, 0), last, best;
+    std::vector<int8_t> best_sp;
+    std::vector<size_t> sp_off(N + 1, 0);
+    for (size_t i = 0; i < N; ++i) sp_off[i + 1] = sp_off[i] + (size_t)ctx[i]->n;
+    auto take_best = [&](bool first) -> shaken_status {
+        bool improved = first;
+        for (size_t i = 0; i < N && !improved; ++i) improved = best[i] < e_best[i];
+        if (res && res->best_spins && improved) {
+            std::vector<int8_t> sp(sp_off[N]);
+            CHK(shaken_batch_get_track(b, nullptr, nullptr, sp.data()));
+            for (size_t i = 0; i < N; ++i)
+                if (first || best[i] < e_best[i])
+                    std::copy(sp.begin() + (ptrdiff_t)sp_off[i], sp.begin() + (ptrdiff_t)sp_off[i + 1],
+                              best_sp.begin() + (ptrdiff_t)sp_off[i]);
+        }
+        for (size_t i = 0; i < N; ++i) e_best[i] = first ? best[i] : std::min(e_best[i], best[i]);
+        for (size_t i = 0; i < N; ++i) e_cur[i] = last[i];
+        return SHAKEN_OK;
+    };
+    if (res && res->best_spins) best_sp.assign(sp_off[N], 0);
+    if (energies) {
+        // energies of the start (a sweep of no steps)
+        CHK(shaken_batch_sweep(b, 0));
+        CHK(call_energies(b, 0, last, best));
+        CHK(take_best(true));
+    }
+    const bool use_mlp = sc.kind == SHAKEN_SCHEDULE_MLP;
+    std::vector<float> F, Y;
+    hipStream_t ms = nullptr;
+    if (use_mlp) {
+        F.assign(N * kFeat, 0.f);
+        Y.assign(N * kFeat, 0.f);
+        CHK(dalloc(&rs.x, N * kFeat));
+        CHK(dalloc(&rs.y, N * kFeat));
+        ms = shaken::mlp_stream(sc.mlp);
+    }
+    const double lb_lo = std::log(0.05), lb_hi = std::log(20.0);
+    const double lq_lo = std::log(0.05), lq_hi = std::log(8.0);
+    std::vector<double> lb_prev(N, 0.0), lq_prev(N, 0.0), beta(N), q(N);
+    int64_t fallbacks = 0;
+    for (int64_t c = 0; c < chunks; ++c) {
+        if (scheduled) {
+            double glb, glq;
+            geometric_at(sc, c, chunks, &glb, &glq);
+            std::vector<double> lb(N, glb), lq(N, glq);
+            if (use_mlp) {
+                for (size_t i = 0; i < N; ++i) {
+                    const shaken_ctx *x = ctx[i];
+                    const double sites = (double)x->n;
+                    float *f = F.data() + i * kFeat;
+                    f[0] = (float)(std::log2(sites) / 16.0);
+                    f[1] = (float)(x->deg_mean / 4.0);
+                    f[2] = (float)(x->deg_spread / 2.0);
+                    f[3] = (float)((double)c / (double)chunks);
+                    f[4] = (float)((double)e_cur[i] / sites);
+                    f[5] = (float)((double)e_best[i] / sites);
+                    f[6] = (float)(lb_prev[i] / 3.0);
+                    f[7] = (float)(lq_prev[i] / 3.0);
+                    f[8] = 1.0f;
+                }
+                HIPCHK(hipMemcpyAsync(rs.x, F.data(), F.size() * 4, hipMemcpyHostToDevice, ms));
+                CHK(shaken_mlp_forward(sc.mlp, rs.x, n, rs.y));
+                HIPCHK(hipMemcpyAsync(Y.data(), rs.y, Y.size() * 4, hipMemcpyDeviceToHost, ms));
+                HIPCHK(hipStreamSynchronize(ms));
+                for (size_t i = 0; i < N; ++i) {
+                    const double a = (double)Y[i * kFeat], bq = (double)Y[i * kFeat + 1];
+                    if (std::isfinite(a) && std::isfinite(bq)) {
+                        lb[i] = a;
+                        lq[i] = bq;
+                    } else {
+                        ++fallbacks;
+                    }
+                }
+            }
+            for (size_t i = 0; i < N; ++i) {
+                lb[i] = std::min(std::max(lb[i], lb_lo), lb_hi);
+                lq[i] = std::min(std::max(lq[i], lq_lo), lq_hi);
+                beta[i] = std::exp(lb[i]);
+                q[i] = std::exp(lq[i]);
+                if (res && res->beta_used) res->beta_used[(size_t)c * N + i] = beta[i];
+                if (res && res->q_used) res->q_used[(size_t)c * N + i] = q[i];
+            }
+            CHK(shaken_batch_set_params(b, beta.data(), q.data()));
+            lb_prev = lb;
+            lq_prev = lq;
+        }
+        CHK(shaken_batch_sweep(b, chunk));
+        if (energies) {
+            CHK(call_energies(b, chunk, last, best));
+            CHK(take_best(false));
+        }
+    }
+    if (!energies || chunks == 0) HIPCHK(hipStreamSynchronize(b->stream));
+    if (res) {
+        res->chunks = scheduled ? chunks : (n_full > 0 ? 1 : 0);
+        res->fallbacks = fallbacks;
+        for (size_t i = 0; i < N; ++i) {
+            if (res->H_final) res->H_final[i] = e_cur[i];
+            if (res->H_best) res->H_best[i] = e_best[i];
+        }
+        if (res->best_spins) std::copy(best_sp.begin(), best_sp.end(), res->best_spins);
     }
     return SHAKEN_OK;
 }

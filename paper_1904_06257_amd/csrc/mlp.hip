@@ -437,3 +437,8 @@ shaken_status shaken_mlp_adam(shaken_mlp *m, float lr, float beta1, float beta2,
 }
 
 }  // extern "C"
+
+namespace shaken {
+int mlp_device(const shaken_mlp *m) { return m->device; }
+hipStream_t mlp_stream(const shaken_mlp *m) { return m->stream; }
+}  // namespace shaken

@@ -140,7 +140,7 @@ def train(args):
         _log("round %d (noise scale %.2f): %d rows" % (rnd, scale, X.shape[0]))
         losses = anneal.train_mlp(mlp, X, Y, np.ones(X.shape[0]), args.epochs, 512, args.lr,
                                   seed=rnd, log=None)
-        policy = anneal.MLPPolicy(mlp)
+        policy = anneal.MLPPolicy(mlp, base)
         # learned vs plain on the validation instances (disjoint from training and evaluation)
         val, _, _ = compare(val_insts, val_seeds, mlp, base, args.sweeps, args.chunk)
         gain = val["all"]["gain_mean"]
@@ -170,10 +170,11 @@ def load(path):
 
 def compare(insts, seeds, mlp, geo, sweeps, chunk):
     """Learned and plain schedule on the same instances with the same Philox
-    seeds (common random numbers); paired statistics per size class."""
+    seeds (common random numbers), each run by the library's chunk loop;
+    paired statistics per size class."""
     from scipy import stats
-    rl = anneal.run(insts, seeds, anneal.MLPPolicy(mlp), sweeps, chunk)
-    rp = anneal.run(insts, seeds, geo, sweeps, chunk)
+    rl = anneal.run_native(insts, seeds, "mlp", sweeps, chunk, geo, mlp=mlp)
+    rp = anneal.run_native(insts, seeds, "geometric", sweeps, chunk, geo)
     ns = np.array([g.n for g in insts], dtype=np.float64)
     out = {}
     for n in sorted(set(ns.astype(int))):

@@ -187,4 +187,6 @@ def test_edge_and_output_arrays_checked_in_the_binding():
     with pytest.raises(ValueError):
         sk.shaken_sweep(None, 10, M_out=np.zeros(11, np.int32))
     with pytest.raises(ValueError):
-        sk.shaken_batch_run([], 1, None, H_final=np.zeros(3, np.float64))
+        sk.batch_run([], 1)
+    with pytest.raises(KeyError):
+        sk.batch_run([None], 1, schedule="cosine")

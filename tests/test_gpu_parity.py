@@ -604,13 +604,18 @@ def test_batch_run_one_call(sk):
                         lam_class=inst.cls, q=1.2, beta=0.7, seed=72, replica=2)
     o = sk.shaken_batch_opts(sk.SHAKEN_BATCH_AUTO, 0, 0, 0, None, 0, 0)
     H = np.zeros(2, dtype=np.int64)
-    sk.shaken_batch_run([tor.handle, gr.handle], T, o, H)
+    Hb = np.zeros(2, dtype=np.int64)
+    res = sk.shaken_run_result(H_final=H.ctypes.data_as(sk._i64p), H_best=Hb.ctypes.data_as(sk._i64p))
+    sk.shaken_batch_run([tor.handle, gr.handle], T, o, None, res)
+    assert res.chunks == 1 and res.fallbacks == 0
     wt, ejt, mmt = oracle.torus_run(oracle.torus_init_random(L, 71, 1), 1, 0.5, 0.9, 0.45, 71, 1, T)
     og = oracle.Graph(inst.n, inst.src, inst.dst, inst.J, inst.cls, inst.lam_values)
     wg, ejg, plg = oracle.graph_run(og, oracle.graph_init_random(inst.n, 72, 2), 1.2, 0.7, 72, 2, T)
     assert np.array_equal(tor.spins(), wt) and np.array_equal(gr.spins(), wg)
     assert H[0] == -ejt[-1] - mmt[-1]
     assert H[1] == _h_from_plus(inst, ejg, plg)[-1]
+    assert Hb[0] == (-ejt - mmt).min()
+    assert Hb[1] == _h_from_plus(inst, ejg, plg).min()
     tor.sweep(2)
     wt2, _, _ = oracle.torus_run(wt, 1, 0.5, 0.9, 0.45, 71, 1, 2, s0=2 * T)
     assert np.array_equal(tor.spins(), wt2)
