@@ -174,7 +174,14 @@ typedef struct shaken_opts {
  * 2.1 orients each undirected edge once); the same oriented edge given twice
  * is SHAKEN_EINVAL either way.  Half-integer splits: scale J, q and lambda by
  * 2 and beta by 1/2. */
-enum { SHAKEN_GRAPH_SPLIT = 1, SHAKEN_ORDER_REVERSED = 2 };
+enum { SHAKEN_GRAPH_SPLIT = 1, SHAKEN_ORDER_REVERSED = 2, SHAKEN_GRAPH_LDS = 4, SHAKEN_GRAPH_NO_LDS = 8 };
+/* SHAKEN_GRAPH_LDS / SHAKEN_GRAPH_NO_LDS (graphs, grid launches): run the
+ * half-steps in the kernel that first copies the bit-packed configuration
+ * into LDS, so that every neighbour gather is an LDS read instead of a
+ * random global load (graphs of at most 1,179,648 vertices; int8 chains then
+ * keep a packed mirror of their spins), or never.  Default: that kernel from
+ * 131,072 vertices on.  A batch group takes it when all its chains do; with
+ * autotune a batch measures both.  Results are identical either way. */
 /* SHAKEN_ORDER_REVERSED (torus and graph): the reversed order of section 3,
  * P^{sh'} = P^{2->1} P^{1->2}: the half-step at an even counter reads the
  * out-half (torus: up and right neighbours, P^ur) and the one at an odd

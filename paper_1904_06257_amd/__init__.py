@@ -44,7 +44,8 @@ _FMT = {"auto": SHAKEN_FMT_AUTO, "int8": SHAKEN_FMT_INT8, "bitpacked": SHAKEN_FM
 _STRAT = {"auto": SHAKEN_BATCH_AUTO, "grid": SHAKEN_BATCH_GRID,
           "persistent": SHAKEN_BATCH_PERSISTENT}
 SHAKEN_LAYOUT_AUTO, SHAKEN_LAYOUT_CSR, SHAKEN_LAYOUT_ELL, SHAKEN_LAYOUT_PACKED = 0, 1, 2, 3
-SHAKEN_GRAPH_SPLIT, SHAKEN_ORDER_REVERSED = 1, 2
+SHAKEN_GRAPH_SPLIT, SHAKEN_ORDER_REVERSED, SHAKEN_GRAPH_LDS, SHAKEN_GRAPH_NO_LDS = 1, 2, 4, 8
+_GKERNEL = {"auto": 0, "lds": SHAKEN_GRAPH_LDS, "plain": SHAKEN_GRAPH_NO_LDS}
 _LAYOUT = {"auto": SHAKEN_LAYOUT_AUTO, "csr": SHAKEN_LAYOUT_CSR, "ell": SHAKEN_LAYOUT_ELL,
            "packed": SHAKEN_LAYOUT_PACKED}
 
@@ -239,7 +240,7 @@ class Chain:
     def __init__(self, kind, *, L=0, n=0, src=None, dst=None, J=None, lam_values=None,
                  lam_class=None, q=1.0, beta=1.0, seed=0, replica=0, init="random",
                  init_spins=None, fmt="auto", device=-1, stream=None, layout="auto", split=False,
-                 reversed=False, frozen=None):
+                 reversed=False, frozen=None, graph_kernel="auto"):
         g = shaken_graph()
         self._keep = []
         if kind in ("torus", "triangular"):
@@ -298,7 +299,8 @@ class Chain:
         o.device = int(device)
         o.stream = _stream_handle(stream)
         o.graph_layout = _LAYOUT[layout]
-        o.flags = (SHAKEN_GRAPH_SPLIT if split else 0) | (SHAKEN_ORDER_REVERSED if reversed else 0)
+        o.flags = (SHAKEN_GRAPH_SPLIT if split else 0) | (SHAKEN_ORDER_REVERSED if reversed else 0) | \
+            _GKERNEL[graph_kernel]
         fz = None
         if frozen is not None:
             fz = np.ascontiguousarray(np.asarray(frozen).reshape(-1) != 0, dtype=np.uint8)

@@ -136,6 +136,7 @@ struct shaken_ctx {
     uint64_t *pell_dev = nullptr;
     uint32_t *jneg_dev = nullptr;  // +-J torus sign planes (2 x L x W words)
     uint32_t *frozen_dev = nullptr;  // frozen set B as bits (layout of the bit-packed spins)
+    uint32_t *mirror[2] = {nullptr, nullptr};  // packed copies of int8 graph spins (LDS-staged kernel)
     bool tri = false;                // triangular torus
     std::vector<uint8_t> frozen_host;  // per site, nonzero = frozen
     int ell_k = 0;
@@ -180,6 +181,8 @@ void release(shaken_ctx *c) {
     dfree(c->pell_dev);
     dfree(c->jneg_dev);
     dfree(c->frozen_dev);
+    dfree(c->mirror[0]);
+    dfree(c->mirror[1]);
     dfree(c->log_dev);
     dfree(c->obs_dev);
     dfree(c->dd);
@@ -482,7 +485,7 @@ shaken_status init_host(shaken_ctx *c, const shaken_graph *g, const int8_t *J,
         c->tri = tri;
         if (g->L < 3 || g->L > 32768) return fail(SHAKEN_EINVAL, "torus: L must be in [3, 32768]");
         if (o->flags & ~SHAKEN_ORDER_REVERSED)
-            return fail(SHAKEN_EINVAL, "SHAKEN_GRAPH_SPLIT applies to graphs only");
+            return fail(SHAKEN_EINVAL, "SHAKEN_GRAPH_SPLIT, SHAKEN_GRAPH_LDS and SHAKEN_GRAPH_NO_LDS apply to graphs only");
         if (lambda && (lambda->n_classes != 1 || lambda->class_of_vertex))
             return fail(SHAKEN_EINVAL, "torus: the field must be uniform (one class, no class map)");
         c->kind = KIND_TORUS;
@@ -539,8 +542,10 @@ shaken_status init_host(shaken_ctx *c, const shaken_graph *g, const int8_t *J,
             return fail(SHAKEN_EINVAL, "unknown format");
         c->format = o->format == SHAKEN_FMT_BITPACKED ? FMT_BITPACKED : FMT_INT8;
         c->W = (g->n + 31) / 32;
-        if (o->flags & ~(SHAKEN_GRAPH_SPLIT | SHAKEN_ORDER_REVERSED))
+        if (o->flags & ~(SHAKEN_GRAPH_SPLIT | SHAKEN_ORDER_REVERSED | SHAKEN_GRAPH_LDS | SHAKEN_GRAPH_NO_LDS))
             return fail(SHAKEN_EINVAL, "unknown opts.flags bits");
+        if ((o->flags & SHAKEN_GRAPH_LDS) && (o->flags & SHAKEN_GRAPH_NO_LDS))
+            return fail(SHAKEN_EINVAL, "SHAKEN_GRAPH_LDS and SHAKEN_GRAPH_NO_LDS exclude each other");
         CHK(build_graph(c, g, J, (o->flags & SHAKEN_GRAPH_SPLIT) != 0, rp, col, jw));
         if (o->graph_layout < SHAKEN_LAYOUT_AUTO || o->graph_layout > SHAKEN_LAYOUT_PACKED)
             return fail(SHAKEN_EINVAL, "unknown graph layout");
@@ -604,6 +609,8 @@ shaken_status init_host(shaken_ctx *c, const shaken_graph *g, const int8_t *J,
 }
 
 // Device phase of shaken_init: buffers, uploads, descriptor, initial state.
+int default_block(const ChainDesc &d);
+
 shaken_status init_device(shaken_ctx *c, const shaken_opts *o, HostLayout &hl) {
     std::vector<uint8_t> &cls_host = hl.cls_host;
     std::vector<int32_t> *rp = hl.rp, *col = hl.col;
@@ -611,8 +618,11 @@ shaken_status init_device(shaken_ctx *c, const shaken_opts *o, HostLayout &hl) {
     const size_t lut_entries = (size_t)(2 * c->smax + 1) * 2 * c->lam.size();
 
     // device buffers
-    CHK(dalloc((uint8_t **)&c->spin[0], c->spin_bytes()));
-    CHK(dalloc((uint8_t **)&c->spin[1], c->spin_bytes()));
+    // whole 16-byte units (the LDS-staged graph kernel reads bit-packed
+    // configurations four words at a time)
+    const size_t sbytes = (c->spin_bytes() + 15) / 16 * 16;
+    CHK(dalloc((uint8_t **)&c->spin[0], sbytes));
+    CHK(dalloc((uint8_t **)&c->spin[1], sbytes));
     CHK(dalloc(&c->lut_dev, lut_entries));
     CHK(dalloc(&c->obs_dev, (size_t)c->stride()));
     CHK(dalloc(&c->dd, 1));
@@ -620,18 +630,26 @@ shaken_status init_device(shaken_ctx *c, const shaken_opts *o, HostLayout &hl) {
     // set-up of the fixed buffer's device address (the device is current)
     HIPCHK(noalloc_scratch(c->device, &c->scratch));
     if (c->kind == KIND_GRAPH) {
+        // padding read by the LDS-staged kernel's unconditional vector loads:
+        // row pointers to a multiple of four vertices plus one (value m_h,
+        // empty rows), eight zero edges, class bytes to a multiple of four
+        const size_t n4 = ((size_t)c->n + 3) / 4 * 4;
+        for (int h = 0; h < 2; ++h) {
+            rp[h].resize(n4 + 1, rp[h][(size_t)c->n]);
+            col[h].resize(col[h].size() + 8, 0);
+            jw[h].resize(jw[h].size() + 8, 0);
+        }
+        cls_host.resize(n4, 0);
         for (int h = 0; h < 2; ++h) {
             CHK(dalloc(&c->rp[h], rp[h].size()));
             CHK(dalloc(&c->col[h], col[h].size()));
             CHK(dalloc(&c->jw[h], jw[h].size()));
             HIPCHK(hipMemcpyAsync(c->rp[h], rp[h].data(), rp[h].size() * 4, hipMemcpyHostToDevice, c->stream));
-            if (c->m > 0) {
-                HIPCHK(hipMemcpyAsync(c->col[h], col[h].data(), col[h].size() * 4, hipMemcpyHostToDevice, c->stream));
-                HIPCHK(hipMemcpyAsync(c->jw[h], jw[h].data(), jw[h].size(), hipMemcpyHostToDevice, c->stream));
-            }
+            HIPCHK(hipMemcpyAsync(c->col[h], col[h].data(), col[h].size() * 4, hipMemcpyHostToDevice, c->stream));
+            HIPCHK(hipMemcpyAsync(c->jw[h], jw[h].data(), jw[h].size(), hipMemcpyHostToDevice, c->stream));
         }
-        CHK(dalloc(&c->cls_dev, (size_t)c->n));
-        HIPCHK(hipMemcpyAsync(c->cls_dev, cls_host.data(), (size_t)c->n, hipMemcpyHostToDevice, c->stream));
+        CHK(dalloc(&c->cls_dev, cls_host.size()));
+        HIPCHK(hipMemcpyAsync(c->cls_dev, cls_host.data(), cls_host.size(), hipMemcpyHostToDevice, c->stream));
         if (hl.ell_k > 0) {
             CHK(dalloc(&c->ell_dev, hl.ell.size()));
             HIPCHK(hipMemcpyAsync(c->ell_dev, hl.ell.data(), hl.ell.size() * 4, hipMemcpyHostToDevice, c->stream));
@@ -646,6 +664,11 @@ shaken_status init_device(shaken_ctx *c, const shaken_opts *o, HostLayout &hl) {
     if (!hl.frozen.empty()) {
         CHK(dalloc(&c->frozen_dev, hl.frozen.size()));
         HIPCHK(hipMemcpyAsync(c->frozen_dev, hl.frozen.data(), hl.frozen.size() * 4, hipMemcpyHostToDevice, c->stream));
+    }
+    if (c->kind == KIND_GRAPH && c->format != FMT_BITPACKED && (c->n + 31) / 32 <= graph_lds_max_words()) {
+        const size_t mw = ((size_t)(c->n + 31) / 32 + 3) / 4 * 4;
+        CHK(dalloc(&c->mirror[0], mw));
+        CHK(dalloc(&c->mirror[1], mw));
     }
     if (!hl.jneg.empty()) {
         CHK(dalloc(&c->jneg_dev, hl.jneg.size()));
@@ -681,6 +704,8 @@ shaken_status init_device(shaken_ctx *c, const shaken_opts *o, HostLayout &hl) {
     d.rev = (o->flags & SHAKEN_ORDER_REVERSED) ? 1 : 0;
     d.tri = c->tri ? 1 : 0;
     d.frozen = c->frozen_dev;
+    d.mirror[0] = c->mirror[0];
+    d.mirror[1] = c->mirror[1];
     d.log_line = c->line();
     d.log_stride = c->stride();
     for (size_t k = 0; k < c->lam.size() && k < 16; ++k) {
@@ -690,6 +715,9 @@ shaken_status init_device(shaken_ctx *c, const shaken_opts *o, HostLayout &hl) {
     refresh_desc_spins(c);
     build_tables(c);
     CHK(upload_tables(c));
+    c->block = (o->flags & SHAKEN_GRAPH_NO_LDS) ? 256
+               : ((o->flags & SHAKEN_GRAPH_LDS) && graph_lds_fits(c->hd)) ? kLdsGraphBlock
+                                                                          : default_block(c->hd);
 
     // degree statistics (integer sums; the in - out differences sum to zero
     // over the sites, so their root mean square is their standard deviation)
@@ -722,6 +750,24 @@ shaken_status init_device(shaken_ctx *c, const shaken_opts *o, HostLayout &hl) {
         CHK(shaken_set_spins(c, o->init_spins));
         break;
     }
+    return SHAKEN_OK;
+}
+
+// The launch shape a graph chain starts with: the LDS-staged kernel from
+// kLdsGraphMinN vertices on (where staging the packed configuration costs
+// less than the cache lines of its random gathers), else the plain kernel's
+// 256-lane blocks.  Batches with autotuning measure both.
+constexpr int kLdsGraphMinN = 1 << 17;
+
+int default_block(const ChainDesc &d) {
+    return graph_lds_fits(d) && d.n >= kLdsGraphMinN ? kLdsGraphBlock : 256;
+}
+
+// before the first half-step of a call on the LDS-staged kernel: the packed
+// mirror of the configuration it reads (int8 chains)
+shaken_status prepare_mirror(shaken_ctx *c, const ChainDesc *dev) {
+    if (c->block == kLdsGraphBlock && c->mirror[0])
+        HIPCHK(launch_pack_mirror(dev, &c->hd, 1, (int)(c->s & 1u), c->stream));
     return SHAKEN_OK;
 }
 
@@ -819,6 +865,7 @@ shaken_status shaken_half_step(shaken_ctx *ctx, int64_t n) {
     if (n < 0) return fail(SHAKEN_EINVAL, "n must be >= 0");
     DeviceGuard guard(ctx->device);
     if ((int64_t)ctx->s + n >= (int64_t)kInitStep) return fail(SHAKEN_ESTATE, "half-step counter would overflow");
+    if (n > 0) CHK(prepare_mirror(ctx, ctx->dd));
     for (int64_t i = 0; i < n; ++i) CHK(half_step_once(ctx, 0, 0));
     return SHAKEN_OK;
 }
@@ -836,6 +883,7 @@ shaken_status shaken_sweep(shaken_ctx *ctx, int64_t n_full, int64_t *H_out, int6
         CHK(ensure_log(ctx, n_full + 1));
         HIPCHK(launch_fill_i64(ctx->log_dev, (n_full + 1) * ctx->stride(), 0, ctx->stream));
     }
+    if (n_full > 0) CHK(prepare_mirror(ctx, ctx->dd));
     for (int64_t t = 0; t < n_full; ++t) {
         CHK(half_step_once(ctx, logs ? 1 : 0, s0));
         CHK(half_step_once(ctx, 0, s0));
@@ -872,6 +920,7 @@ shaken_status shaken_sweep_noalloc(shaken_ctx *ctx, int64_t n_full, int64_t *H_d
     const int64_t slots = n_full + 1;
     // partial sums accumulate into the slots: clear them with a fill kernel
     if (logs) HIPCHK(launch_fill_i64(ctx->scratch, slots * ctx->stride(), 0, ctx->stream));
+    if (n_full > 0) CHK(prepare_mirror(ctx, ctx->dd_static));
     for (int64_t t = 0; t < n_full; ++t) {
         CHK(half_step_once(ctx, logs ? 1 : 0, s0, true));
         CHK(half_step_once(ctx, 0, s0, true));
@@ -1201,15 +1250,61 @@ shaken_status batch_half(shaken_batch *b, const uint32_t *dstate, uint32_t s_add
     return SHAKEN_OK;
 }
 
-// time `reps` repeated launches of the same half-step (idempotent: same input,
-// same output buffer) for one group and block size
-shaken_status time_group(shaken_batch *b, Group &g, int block, uint32_t s, int reps, float *ms) {
-    HIPCHK(launch_half_step_grid(g.dd, g.hd.data(), (int)g.hd.size(), nullptr, s, s, 0, (s & 1u) == 0, block,
-                                 b->stream));
+// can every chain of the group run in the LDS-staged graph kernel?
+bool group_lds_fits(const Group &g) {
+    for (const auto &d : g.hd)
+        if (!graph_lds_fits(d)) return false;
+    return !g.hd.empty();
+}
+
+// launch shape a group starts with: the LDS-staged kernel when every chain
+// takes it on its own
+int group_default_block(const shaken_batch *b, const Group &g) {
+    for (int i : g.members)
+        if (b->ctx[(size_t)i]->block != kLdsGraphBlock) return 256;
+    return kLdsGraphBlock;
+}
+
+// packed mirrors of the configurations the next half-step reads (groups on
+// the LDS-staged kernel, or all that fit it when `all_fitting`)
+shaken_status batch_pack_mirrors(shaken_batch *b, uint32_t s, bool all_fitting) {
+    for (auto &g : b->groups)
+        if (g.block == kLdsGraphBlock || (all_fitting && group_lds_fits(g)))
+            HIPCHK(launch_pack_mirror(g.dd, g.hd.data(), (int)g.hd.size(), (int)(s & 1u), b->stream));
+    return SHAKEN_OK;
+}
+
+// `reps` launches of the same half-step at the (even) counter s for one
+// group and block size, captured in a HIP graph: trial launches are
+// idempotent (they read spin[0], write spin[1]) and run as a sweep runs them,
+// replayed from a graph (timed eagerly, the host's launch rate would hide
+// differences of a few microseconds per launch)
+struct TrialGraph {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t x = nullptr;
+    ~TrialGraph() {
+        if (x) (void)hipGraphExecDestroy(x);
+        if (g) (void)hipGraphDestroy(g);
+    }
+};
+
+shaken_status trial_graph(shaken_batch *b, Group &g, int block, uint32_t s, int reps, TrialGraph &t) {
+    HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < reps && e == hipSuccess; ++i)
+        e = launch_half_step_grid(g.dd, g.hd.data(), (int)g.hd.size(), nullptr, s, s, 0, (s & 1u) == 0, block,
+                                  b->stream);
+    const hipError_t e2 = hipStreamEndCapture(b->stream, &t.g);
+    if (e != hipSuccess || e2 != hipSuccess)
+        return fail(SHAKEN_EDEVICE, std::string("autotune capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+    HIPCHK(hipGraphInstantiate(&t.x, t.g, nullptr, nullptr, 0));
+    return SHAKEN_OK;
+}
+
+// GPU time of one replay of a trial graph (milliseconds)
+shaken_status time_replay(shaken_batch *b, TrialGraph &t, float *ms) {
     HIPCHK(hipEventRecord(b->ev0, b->stream));
-    for (int i = 0; i < reps; ++i)
-        HIPCHK(launch_half_step_grid(g.dd, g.hd.data(), (int)g.hd.size(), nullptr, s, s, 0,
-                                     (s & 1u) == 0, block, b->stream));
+    HIPCHK(hipGraphLaunch(t.x, b->stream));
     HIPCHK(hipEventRecord(b->ev1, b->stream));
     HIPCHK(hipEventSynchronize(b->ev1));
     HIPCHK(hipEventElapsedTime(ms, b->ev0, b->ev1));
@@ -1226,26 +1321,34 @@ constexpr int kWarmMaxTrials = 400;
 
 shaken_status batch_autotune(shaken_batch *b) {
     const uint32_t s = b->ctx[0]->s;
-    const int cands[3] = {64, 128, 256};
-    // Trial launches are half-steps at the batch's (even) counter: they read
-    // spin[0] and write spin[1], so the chains' configurations are untouched.
-    // Warm phase first, with the default shape.
-    float warm = 0;
-    for (int k = 0; k < kWarmMaxTrials && warm < kWarmMs; ++k)
-        for (auto &g : b->groups) {
+    CHK(batch_pack_mirrors(b, s, true));
+    const int reps = 10;
+    for (auto &g : b->groups) {
+        std::vector<int> cands{64, 128, 256};
+        if (group_lds_fits(g)) cands.push_back(kLdsGraphBlock);
+        std::vector<TrialGraph> tg(cands.size());
+        size_t def = 0;
+        for (size_t k = 0; k < cands.size(); ++k) {
+            CHK(trial_graph(b, g, cands[k], s, reps, tg[k]));
+            if (cands[k] == g.block) def = k;
+        }
+        // warm phase with the default shape, then one untimed and one timed
+        // replay per candidate
+        float warm = 0;
+        for (int k = 0; k < kWarmMaxTrials && warm < kWarmMs; ++k) {
             float ms = 0;
-            CHK(time_group(b, g, g.block, s, 5, &ms));
+            CHK(time_replay(b, tg[def], &ms));
             warm += ms;
         }
-    for (auto &g : b->groups) {
         float best = 1e30f;
         int best_b = g.block;
-        for (int cb : cands) {
+        for (size_t k = 0; k < cands.size(); ++k) {
             float ms = 0;
-            CHK(time_group(b, g, cb, s, 10, &ms));
+            CHK(time_replay(b, tg[k], &ms));
+            CHK(time_replay(b, tg[k], &ms));
             if (ms < best) {
                 best = ms;
-                best_b = cb;
+                best_b = cands[k];
             }
         }
         g.block = best_b;
@@ -1394,6 +1497,7 @@ shaken_status batch_sweep_grid(shaken_batch *b, int64_t n_full) {
     const uint32_t s0 = b->ctx[0]->s;
     uint32_t s = s0;
     int64_t t = 0;
+    if (n_full > 0) CHK(batch_pack_mirrors(b, s0, false));
     if (b->use_graph) {
         // one graph of kGraphChunk full steps, captured on the first call
         // whatever its length, replayed as often as it fits; the remainder
@@ -1522,8 +1626,10 @@ shaken_status shaken_batch_create(shaken_batch **out, shaken_ctx *const *ctx, in
             g->members.push_back(i);
             g->hd.push_back(ctx[i]->hd);
         }
-        for (auto &g : b->groups)
+        for (auto &g : b->groups) {
             if ((st = dalloc(&g.dd, g.hd.size())) != SHAKEN_OK) return bail(st);
+            g.block = group_default_block(b, g);
+        }
     } else {
         b->phd.resize(n);
         if ((st = dalloc(&b->pdescs, (size_t)n)) != SHAKEN_OK) return bail(st);

@@ -760,6 +760,200 @@ __global__ __launch_bounds__(256) void k_graph(const ChainDesc *__restrict__ des
 // neighbour spin at once (empty slots point to the vertex itself) and keeps
 // those of the half being updated.  Two dependent memory levels instead of
 // three (no row pointers).
+// ------------------------------------------- graph, gathers served from LDS
+//
+// Every edge of a half-step gathers one neighbour spin.  From global memory a
+// random gather costs a whole cache line between L2 and the compute unit, so
+// on a large graph those lines, not the bytes of the CSR arrays, bound the
+// kernel.  Here each workgroup first copies the bit-packed configuration
+// (2^20 vertices: 128 KiB) into LDS with coalesced loads, issued while the
+// row pointers and the first edges are still in flight, and the gathers
+// become LDS reads.  The bit-packed source is the state itself (bit-packed
+// chains) or, for int8 chains, its packed mirror: the kernel writes the new
+// int8 spins and the mirror of them, and each call starts by packing the
+// configuration it reads (launch_pack_mirror).  One workgroup of 1024 lanes
+// per compute unit (the LDS holds one configuration), four vertices per lane
+// as in k_graph.
+constexpr int kLdsGraphWords = 36864;                 // 144 KiB: up to 1,179,648 vertices
+constexpr int kLdsGraphStage = kLdsGraphWords / 4 / kLdsGraphBlock;  // uint4 loads per lane
+constexpr int kLdsGraphClasses = 256;
+
+// Loads through the global address space (not flat), unconditional at
+// clamped indices: a load under a divergent branch makes the compiler wait
+// for it before the branch joins, which would serialise the staging.
+typedef uint32_t gl_u32x4 __attribute__((ext_vector_type(4)));
+typedef int32_t gl_i32x4 __attribute__((ext_vector_type(4)));
+
+template <class T>
+__device__ __forceinline__ T gld(const void *base, int64_t i) {
+    return ((const __attribute__((address_space(1))) T *)base)[i];
+}
+
+template <bool OBS, bool BP>
+__global__ __launch_bounds__(kLdsGraphBlock) void k_graph_lds(const ChainDesc *__restrict__ descs, StepArgs sa) {
+    __shared__ gl_u32x4 sh_sp4[kLdsGraphWords / 4];
+    __shared__ uint64_t sh_lut[kLdsLut];
+    __shared__ int sh_plus[kLdsGraphClasses];
+    __shared__ int sh_e[kLdsGraphBlock / 64];
+    const ChainDesc &d = descs[blockIdx.y];
+    const int n = d.n;
+    // a chain smaller than the grid: its surplus workgroups leave at once
+    if ((int)blockIdx.x * (4 * kLdsGraphBlock) >= n) return;
+    const uint32_t s = step_s(sa);
+    const int bufp = (int)(s & 1u);
+    const int half = bufp ^ d.rev;   // 0 = in-half, 1 = out-half
+    const int slot = OBS ? step_slot(sa, s) : 0;
+    const int tid = threadIdx.x;
+    const int q4 = blockIdx.x * kLdsGraphBlock + tid;
+    const int v0 = q4 * 4;
+    void *__restrict__ out = d.spin[bufp ^ 1];
+    const uint32_t *bits_in = BP ? (const uint32_t *)d.spin[bufp] : d.mirror[bufp];
+    uint32_t *__restrict__ bits_out = BP ? (uint32_t *)out : d.mirror[bufp ^ 1];
+    const int ncls = d.ncls, smax = d.smax;
+    const int nw = (n + 31) >> 5;
+    const int ng = (nw + 3) >> 2;     // groups of four words, the last padded
+    const bool active = v0 < n;
+    const int va = active ? v0 : 0;   // row pointers and classes are padded
+                                      // to a multiple of four vertices
+    const int nlut = (2 * smax + 1) * 2 * ncls;
+    const bool lut_lds = nlut <= kLdsLut;
+    // 1. row bounds, classes, the lane's threshold entry and frozen bits
+    const gl_i32x4 r4 = gld<gl_i32x4>(d.rowptr[half], va >> 2);
+    const int rp4 = gld<int32_t>(d.rowptr[half], va + 4);
+    const int rpv[5] = {r4.x, r4.y, r4.z, r4.w, rp4};
+    const uint32_t c4 = gld<uint32_t>(d.cls, va >> 2);
+    const uint64_t lutv = lut_lds ? gld<uint64_t>(d.lut, min(tid, nlut - 1)) : 0;
+    const uint32_t fzw = d.frozen ? gld<uint32_t>(d.frozen, va >> 5) : 0u;
+    // 3. the first chunk of the lane's edges (needs the row bounds; arrays
+    // padded, indices clamped: every load valid)
+    const int last = rpv[4] - 1;
+    int cc[kEdgeChunk], jj[kEdgeChunk];
+#pragma unroll
+    for (int k = 0; k < kEdgeChunk; ++k) {
+        const int e = max(min(rpv[0] + k, last), 0);
+        cc[k] = gld<int32_t>(d.col[half], e);
+        jj[k] = (int)gld<int8_t>(d.jw[half], e);
+    }
+    // 4. the configuration, coalesced, straight into LDS (global_load_lds:
+    // lane l of a wavefront loads 16 bytes into the wavefront's 1 KiB LDS
+    // segment at 16 l, the same offset as in global memory).  Each group of
+    // four words is loaded by exactly one lane, the last group with the
+    // buffer's padding, so no other write to the array is needed -- a wait
+    // on the vector memory counter covers only the waiting wavefront's own
+    // loads, and the barrier below is what orders them for everyone.
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
+#pragma unroll
+    for (int k = 0; k < kLdsGraphStage; ++k) {
+        const int base = k * kLdsGraphBlock + wv * 64;
+        if (base < ng && base + lane < ng)
+            __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)(bits_in + 4 * (base + lane)),
+                                             (__attribute__((address_space(3))) void *)(sh_sp4 + base), 16, 0, 0);
+    }
+    if (OBS)
+        for (int i = tid; i < ncls; i += kLdsGraphBlock) sh_plus[i] = 0;
+    U4 r = {0u, 0u, 0u, 0u};
+    if (active)
+        r = philox10((uint32_t)q4, s, d.replica, kGraphStream, (uint32_t)d.seed, (uint32_t)(d.seed >> 32));
+    // 5. this wavefront's direct loads have landed (vector memory counter),
+    // then the barrier: every lane sees the whole configuration
+    __builtin_amdgcn_s_waitcnt(0);
+    uint32_t *sh_sp = (uint32_t *)sh_sp4;
+    if (lut_lds && tid < nlut) sh_lut[tid] = lutv;
+    __syncthreads();
+    // 6. own spins and field sums from LDS
+    int own[4], cl[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int v = min(v0 + j, n - 1);
+        own[j] = ((sh_sp[v >> 5] >> (v & 31)) & 1u) ? 1 : -1;
+        cl[j] = (int)((c4 >> (8 * j)) & 0xFFu);
+    }
+    int S0 = 0, S1 = 0, S2 = 0, S3 = 0;
+    if (active) {
+        for (int base = rpv[0]; base <= last; base += kEdgeChunk) {
+            if (base != rpv[0]) {
+#pragma unroll
+                for (int k = 0; k < kEdgeChunk; ++k) {
+                    const int e = min(base + k, last);
+                    cc[k] = gld<int32_t>(d.col[half], e);
+                    jj[k] = (int)gld<int8_t>(d.jw[half], e);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < kEdgeChunk; ++k) {
+                const int e = base + k;
+                const int sv = ((sh_sp[cc[k] >> 5] >> (cc[k] & 31)) & 1u) ? 1 : -1;
+                const int t = e <= last ? jj[k] * sv : 0;
+                S0 += e < rpv[1] ? t : 0;
+                S1 += (e >= rpv[1] && e < rpv[2]) ? t : 0;
+                S2 += (e >= rpv[2] && e < rpv[3]) ? t : 0;
+                S3 += (e >= rpv[3]) ? t : 0;
+            }
+        }
+    }
+    // 7. thresholds, the new spins and their packed copy
+    const int Sv[4] = {S0, S1, S2, S3};
+    uint32_t up = 0;
+    int e_acc = 0;
+    if (active) {
+        const uint32_t u[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int key = ((Sv[j] + smax) * 2 + (own[j] > 0)) * ncls + cl[j];
+            const uint64_t T = lut_lds ? sh_lut[key] : d.lut[key];
+            if (v0 + j < n && (uint64_t)u[j] < T) up |= 1u << j;
+            if (OBS && v0 + j < n) {
+                e_acc += own[j] * Sv[j];
+                if (own[j] > 0) atomicAdd(&sh_plus[cl[j]], 1);
+            }
+        }
+        up |= (fzw >> (v0 & 31)) & 0xFu;
+    }
+    if (!BP) graph_store4<false>(out, q4, n, up);
+    graph_store4<true>(bits_out, q4, n, up);
+    if (OBS) {
+        int64_t *lg = log_part(d, slot, blockIdx.x);
+        const int lane = tid & 63, wv = tid >> 6;
+        e_acc = wave_sum(e_acc);
+        if (lane == 0) sh_e[wv] = e_acc;
+        __syncthreads();
+        if (tid == 0) {
+            long long se = 0;
+            for (int i = 0; i < kLdsGraphBlock / 64; ++i) se += sh_e[i];
+            if (se) atomicAdd((unsigned long long *)&lg[0], (unsigned long long)se);
+        }
+        for (int i = tid; i < ncls; i += kLdsGraphBlock)
+            if (sh_plus[i]) atomicAdd((unsigned long long *)&lg[1 + i], (unsigned long long)sh_plus[i]);
+    }
+}
+
+// mirror[idx] = the configuration spin[idx] of an int8 graph chain, packed
+// (one word of 32 vertices per lane); chains without a mirror are skipped
+__global__ __launch_bounds__(256) void k_pack_mirror(const ChainDesc *__restrict__ descs, int idx) {
+    const ChainDesc &d = descs[blockIdx.y];
+    uint32_t *mir = d.mirror[idx];
+    if (!mir || d.format == FMT_BITPACKED) return;
+    const int w = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = d.n;
+    if (w >= ((n + 31) >> 5)) return;
+    const int8_t *sp = (const int8_t *)d.spin[idx];
+    uint32_t bits = 0;
+    const int v0 = 32 * w;
+    if (v0 + 31 < n) {
+        const uint4 *p = (const uint4 *)(sp + v0);
+        const uint4 a = p[0], b = p[1];
+        const uint32_t x[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bits |= (((x[k] >> (8 * j)) & 0xFFu) == 1u ? 1u : 0u) << (4 * k + j);
+    } else {
+        for (int j = 0; v0 + j < n; ++j) bits |= (sp[v0 + j] > 0 ? 1u : 0u) << j;
+    }
+    mir[w] = bits;
+}
+
 template <bool OBS, int K, bool BP>
 __global__ __launch_bounds__(256) void k_graph_ell(const ChainDesc *__restrict__ descs, StepArgs sa) {
     const ChainDesc &d = descs[blockIdx.y];
@@ -1033,8 +1227,15 @@ hipError_t launch_half_step_grid(const ChainDesc *dev_descs, const ChainDesc *ho
     const bool obs = log_on && even;
     const StepArgs sa{dstate, s_add, s_log0, log_on};
     const int b = block > 0 ? block : 256;
-    // the torus kernels split their tail queue over one, two or four wavefronts
-    if (b != 64 && b != 128 && b != 256) return hipErrorInvalidValue;
+    // the torus kernels split their tail queue over one, two or four
+    // wavefronts; 1024 selects the LDS-staged graph kernel
+    if (b == kLdsGraphBlock) {
+        if (h0.kind != KIND_GRAPH) return hipErrorInvalidValue;
+        for (int i = 0; i < nchains; ++i)
+            if (!graph_lds_fits(host_descs[i])) return hipErrorInvalidValue;
+    } else if (b != 64 && b != 128 && b != 256) {
+        return hipErrorInvalidValue;
+    }
     const dim3 grid((maxu + b - 1) / b, nchains);
     if (h0.kind == KIND_TORUS && h0.format == FMT_BITPACKED && h0.tri) {
         // the runtime groups triangular tori apart from square ones
@@ -1057,6 +1258,14 @@ hipError_t launch_half_step_grid(const ChainDesc *dev_descs, const ChainDesc *ho
     } else if (h0.kind == KIND_TORUS) {
         if (obs) hipLaunchKernelGGL((k_torus_i8<true>), grid, dim3(b), 0, stream, dev_descs, sa);
         else hipLaunchKernelGGL((k_torus_i8<false>), grid, dim3(b), 0, stream, dev_descs, sa);
+    } else if (b == kLdsGraphBlock) {
+        if (h0.format == FMT_BITPACKED) {
+            if (obs) hipLaunchKernelGGL((k_graph_lds<true, true>), grid, dim3(b), 0, stream, dev_descs, sa);
+            else hipLaunchKernelGGL((k_graph_lds<false, true>), grid, dim3(b), 0, stream, dev_descs, sa);
+        } else {
+            if (obs) hipLaunchKernelGGL((k_graph_lds<true, false>), grid, dim3(b), 0, stream, dev_descs, sa);
+            else hipLaunchKernelGGL((k_graph_lds<false, false>), grid, dim3(b), 0, stream, dev_descs, sa);
+        }
     } else {
         const size_t shm = obs ? sizeof(int) * (size_t)maxcls : 0;
         int ellk = host_descs[0].ell_k;
@@ -1077,6 +1286,24 @@ hipError_t launch_half_step_grid(const ChainDesc *dev_descs, const ChainDesc *ho
 #undef SHAKEN_GRAPH
 #undef SHAKEN_ELL
     }
+    return hipGetLastError();
+}
+
+bool graph_lds_fits(const ChainDesc &d) {
+    return d.kind == KIND_GRAPH && d.n <= 32 * kLdsGraphWords && (d.format == FMT_BITPACKED || d.mirror[0]);
+}
+
+int graph_lds_max_words() { return kLdsGraphWords; }
+
+hipError_t launch_pack_mirror(const ChainDesc *dev_descs, const ChainDesc *host_descs, int nchains, int idx,
+                              hipStream_t stream) {
+    int maxw = 0;
+    for (int i = 0; i < nchains; ++i)
+        if (host_descs[i].mirror[idx] && host_descs[i].format != FMT_BITPACKED)
+            maxw = maxw > ((host_descs[i].n + 31) >> 5) ? maxw : ((host_descs[i].n + 31) >> 5);
+    if (maxw == 0) return hipSuccess;
+    const int b = 256;
+    hipLaunchKernelGGL(k_pack_mirror, dim3((maxw + b - 1) / b, nchains), dim3(b), 0, stream, dev_descs, idx);
     return hipGetLastError();
 }
 

@@ -86,7 +86,26 @@ struct ChainDesc {
     uint32_t *best;
     int32_t lam2[16];
     int32_t csize[16];
+    // int8 graph chains small enough for the LDS-staged kernel: a bit-packed
+    // copy of spin[i] (one bit per vertex, layout of the bit-packed spins),
+    // written by that kernel beside its int8 output; null otherwise
+    uint32_t *mirror[2];
 };
+
+// workgroup size of the LDS-staged graph kernel; as a launch's block size it
+// selects that kernel
+constexpr int kLdsGraphBlock = 1024;
+
+// can chain d run in the LDS-staged graph kernel (graph, at most 1,179,648
+// vertices, bit-packed or with a packed mirror)?
+bool graph_lds_fits(const ChainDesc &d);
+
+// words of a packed mirror the LDS-staged kernel can hold (n <= 32 * this)
+int graph_lds_max_words();
+
+// mirror[idx] = spin[idx] packed, for every int8 chain with a mirror
+hipError_t launch_pack_mirror(const ChainDesc *dev_descs, const ChainDesc *host_descs, int nchains, int idx,
+                              hipStream_t stream);
 
 // ---------------------------------------------------------------- launchers
 // All launchers enqueue on `stream` and return the hipError_t of the launch.

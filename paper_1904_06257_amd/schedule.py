@@ -168,6 +168,14 @@ def load(path):
     return z["params"].astype(np.float32), meta
 
 
+def threshold_6_1(inst):
+    """max over the vertices of sum_{(x,y) in E^o} |J_xy| + |lambda_x| (the
+    reading of Theorem 6.1's condition with the out-half of x)"""
+    w = np.bincount(inst.src, weights=np.abs(inst.J.astype(np.float64)), minlength=inst.n)
+    lam = np.abs(np.asarray(inst.lam_values, dtype=np.float64))[inst.cls]
+    return float((w + lam).max())
+
+
 def compare(insts, seeds, mlp, geo, sweeps, chunk):
     """Learned and plain schedule on the same instances with the same Philox
     seeds (common random numbers), each run by the library's chunk loop;
@@ -189,6 +197,16 @@ def compare(insts, seeds, mlp, geo, sweeps, chunk):
                            if k.sum() > 1 else None,
                            wilcoxon_p_one_sided=float(stats.wilcoxon(ep, el, alternative="greater").pvalue)
                            if k.sum() > 1 and np.any(d != 0) else None)
+    # Theorem 6.1 (minimisers of the pair Hamiltonian on the diagonal) asks
+    # for q > max_x (sum over the out-half of |J_xy|) + |lambda_x|: the final
+    # q of each run against that threshold of its instance
+    thr = np.array([threshold_6_1(g) for g in insts])
+    for name, r in (("learned", rl), ("plain", rp)):
+        qf = r.q[-1]
+        out["theorem_6_1_" + name] = dict(
+            q_final_mean=float(qf.mean()), q_final_min=float(qf.min()), q_final_max=float(qf.max()),
+            threshold_mean=float(thr.mean()), feasible_fraction=float((qf > thr).mean()),
+            per_size={str(n): float((qf[ns == n] > thr[ns == n]).mean()) for n in sorted(set(ns.astype(int)))})
     d_all = (rp.best - rl.best) / ns
     out["all"] = dict(instances=len(insts), gain_mean=float(d_all.mean()),
                       win_rate=float((d_all > 0).mean()),
