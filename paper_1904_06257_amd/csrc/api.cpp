@@ -619,10 +619,17 @@ shaken_status init_device(shaken_ctx *c, const shaken_opts *o, HostLayout &hl) {
 
     // device buffers
     // whole 16-byte units (the LDS-staged graph kernel reads bit-packed
-    // configurations four words at a time)
-    const size_t sbytes = (c->spin_bytes() + 15) / 16 * 16;
-    CHK(dalloc((uint8_t **)&c->spin[0], sbytes));
-    CHK(dalloc((uint8_t **)&c->spin[1], sbytes));
+    // configurations four words at a time); a bit-packed torus has kRows
+    // more rows of zeros, so that the strip loads of the half-step kernels
+    // need no bounds test (rows past the side read as no sites)
+    size_t sbytes = (c->spin_bytes() + 15) / 16 * 16;
+    const size_t pad_bytes = (c->kind == KIND_TORUS && c->format == FMT_BITPACKED) ? (size_t)kRows * c->W * 4 : 0;
+    CHK(dalloc((uint8_t **)&c->spin[0], sbytes + pad_bytes));
+    CHK(dalloc((uint8_t **)&c->spin[1], sbytes + pad_bytes));
+    if (pad_bytes) {
+        HIPCHK(hipMemsetAsync((uint8_t *)c->spin[0] + c->spin_bytes(), 0, sbytes + pad_bytes - c->spin_bytes(), c->stream));
+        HIPCHK(hipMemsetAsync((uint8_t *)c->spin[1] + c->spin_bytes(), 0, sbytes + pad_bytes - c->spin_bytes(), c->stream));
+    }
     CHK(dalloc(&c->lut_dev, lut_entries));
     CHK(dalloc(&c->obs_dev, (size_t)c->stride()));
     CHK(dalloc(&c->dd, 1));
@@ -684,6 +691,7 @@ shaken_status init_device(shaken_ctx *c, const shaken_opts *o, HostLayout &hl) {
     d.format = c->format;
     d.L = c->L;
     d.W = c->W;
+    d.wdiv = c->W > 0 ? (uint32_t)((((uint64_t)1 << 32) + (uint64_t)c->W - 1) / (uint64_t)c->W) : 0u;
     d.n = c->n;
     d.J = c->J;
     d.lut = c->lut_dev;
@@ -1558,7 +1566,10 @@ shaken_status shaken_batch_create(shaken_batch **out, shaken_ctx *const *ctx, in
         delete b;
         return s;
     };
-    if (!b->stream && b->use_graph) {
+    // HIP graphs (and the autotuner's trial graphs) cannot be captured on the
+    // legacy null stream: such a batch gets a stream of its own (a blocking
+    // one, ordered with the null stream the chains may use on their own)
+    if (!b->stream && (b->use_graph || b->autotune)) {
         if (hipStreamCreate(&b->stream) != hipSuccess) return bail(fail(SHAKEN_EDEVICE, "hipStreamCreate failed"));
         b->own_stream = true;
     }

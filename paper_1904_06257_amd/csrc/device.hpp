@@ -134,6 +134,7 @@ constexpr int kT_and_or = bitop3_table([](int a, int b, int c) { return (a && b)
 constexpr int kT_xor3 = bitop3_table([](int a, int b, int c) { return a ^ b ^ c; });
 constexpr int kT_or_and = bitop3_table([](int a, int b, int c) { return a || (b && c); });
 constexpr int kT_bfi = bitop3_table([](int a, int b, int c) { return a ? b : c; });
+constexpr int kT_xor_and = bitop3_table([](int a, int b, int c) { return (a ^ b) & c; });
 
 // The eight level masks of the folded table's rest class (levels 0..7) in
 // vector registers: with one of the three masks of a level there, the class

@@ -151,9 +151,12 @@ __global__ __launch_bounds__(256) void k_torus_bp(const ChainDesc *__restrict__ 
     const int nwav = (int)(blockDim.x + 63) >> 6, wv = (int)threadIdx.x >> 6;
     const int qcap_w = kQCap >> (nwav == 4 ? 2 : (nwav == 2 ? 1 : 0)), qbase = wv * qcap_w;
     int wq = 0;  // entries this wavefront has queued (the same in every lane)
-    int e_acc = 0, p_acc = 0;
+    int dis_acc = 0, p_acc = 0;  // disagreeing in-half bonds and +1 sites
     const bool live = gid < total;
-    const int rb = live ? gid / W : 0, wd = live ? gid - rb * W : 0;
+    // row block and word column: gid / W as a multiply-high (W = 1: the
+    // reciprocal 2^32 does not fit, and gid is the row block itself)
+    const int rb = !live ? 0 : (W == 1 ? gid : (int)__umulhi((uint32_t)gid, d.wdiv));
+    const int wd = live ? gid - rb * W : 0;
     const int r0 = rb * kRows;
     const int nr = live ? min(kRows, L - r0) : 0;
     const uint32_t vm = bp_valid(L, W, wd);
@@ -164,16 +167,13 @@ __global__ __launch_bounds__(256) void k_torus_bp(const ChainDesc *__restrict__ 
     // (dl) or the bit it lands on (ur); 31 inside a row, the last valid bit at
     // the row's end
     const int csh = (phase == 0 ? wd > 0 : wd < W - 1) ? 31 : lastbits;
+    // rows past the side are the buffer's zero padding (no sites)
     uint32_t own[kRows], side[kRows];
+    const uint32_t obase = (uint32_t)(r0 * W + wd), sbase = (uint32_t)(r0 * W + wside);
 #pragma unroll
     for (int i = 0; i < kRows; ++i) {
-        if (i < nr) {
-            own[i] = gload(in, (uint32_t)((r0 + i) * W + wd));
-            side[i] = gload(in, (uint32_t)((r0 + i) * W + wside));
-        } else {
-            own[i] = 0u;
-            side[i] = 0u;
-        }
+        own[i] = gload(in, obase + (uint32_t)(i * W));
+        side[i] = gload(in, sbase + (uint32_t)(i * W));
     }
     uint32_t halo = 0;
     if (live) {
@@ -203,8 +203,9 @@ __global__ __launch_bounds__(256) void k_torus_bp(const ChainDesc *__restrict__ 
         }
         if (EXT && d.jneg && act) bp_jflip(d.jneg, L, W, r0 + i, wd, phase, a, b);
         if (OBS) {
-            e_acc += d.J * (2 * __popc(vmi) - 2 * __popc((own[i] ^ a) & vmi) -
-                            2 * __popc((own[i] ^ b) & vmi));
+            // disagreeing in-half bonds and +1 sites of the configuration read
+            dis_acc += __popc(__builtin_amdgcn_bitop3_b32(own[i], a, vmi, kT_xor_and));
+            dis_acc += __popc(__builtin_amdgcn_bitop3_b32(own[i], b, vmi, kT_xor_and));
             p_acc += __popc(own[i] & vmi);
         }
         // folded table: res = new spins of the sites decided; six classes:
@@ -304,8 +305,11 @@ __global__ __launch_bounds__(256) void k_torus_bp(const ChainDesc *__restrict__ 
                                              k1, ts, sgn) | (EXT ? frozen_word(d, (int)w) : 0u);
         }
     }
-    if (OBS && bx * (int)blockDim.x < total)
+    if (OBS && bx * (int)blockDim.x < total) {
+        // each site has two in-half bonds, J sigma sigma' = J (1 - 2 [disagree])
+        const int e_acc = d.J * (2 * nr * __popc(vm) - 2 * dis_acc);
         block_accumulate2(e_acc, p_acc, log_part(d, slot, bx));
+    }
 }
 
 // ------------------------------------------------ triangular bit-packed torus
@@ -362,7 +366,9 @@ __global__ __launch_bounds__(256) void k_tri_bp(const ChainDesc *__restrict__ de
     int wq = 0;  // entries this wavefront has queued (the same in every lane)
     int e_acc = 0, p_acc = 0;
     const bool live = gid < total;
-    const int rb = live ? gid / W : 0, wd = live ? gid - rb * W : 0;
+    // row block and word column (gid / W as a multiply-high, as in k_torus_bp)
+    const int rb = !live ? 0 : (W == 1 ? gid : (int)__umulhi((uint32_t)gid, d.wdiv));
+    const int wd = live ? gid - rb * W : 0;
     const int r0 = rb * kRows;
     const int nr = live ? min(kRows, L - r0) : 0;
     const uint32_t vm = bp_valid(L, W, wd);
@@ -372,11 +378,13 @@ __global__ __launch_bounds__(256) void k_tri_bp(const ChainDesc *__restrict__ de
     // (dl) or the bit it lands on (ur); 31 inside a row, the last valid bit at
     // the row's end
     const int csh = (phase == 0 ? wd > 0 : wd < W - 1) ? 31 : lastbits;
+    // rows past the side are the buffer's zero padding (no sites)
     uint32_t own[kRows], side[kRows];
+    const uint32_t obase = (uint32_t)(r0 * W + wd), sbase = (uint32_t)(r0 * W + wside);
 #pragma unroll
     for (int i = 0; i < kRows; ++i) {
-        own[i] = i < nr ? gload(in, (uint32_t)((r0 + i) * W + wd)) : 0u;
-        side[i] = i < nr ? gload(in, (uint32_t)((r0 + i) * W + wside)) : 0u;
+        own[i] = gload(in, obase + (uint32_t)(i * W));
+        side[i] = gload(in, sbase + (uint32_t)(i * W));
     }
     uint32_t halo = 0, halo_side = 0;
     if (live) {

@@ -35,6 +35,8 @@ struct ChainDesc {
     int32_t fold3;       // mirror classes share t and have opposite flips (3 classes
                          // after folding; 4 on the triangular torus)
     int32_t tri;         // triangular torus (section 4): third oriented edge (x, x + e1 + e2)
+    uint32_t wdiv;       // bit-packed torus: ceil(2^32 / W), so that g / W = umulhi(g, wdiv)
+                         // for every g with g W < 2^32 (g < rows * W / kRows here)
     int32_t J;           // uniform torus coupling
     // generic threshold table (int8 torus, graph): ((S+smax)*2 + (sigma>0))*ncls + cls
     const uint64_t *lut;
