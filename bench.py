@@ -301,7 +301,8 @@ def bench_torus4096(args, sk, triangular=False):
 
 def _graph_run(sk, inst, n, steps, warmup, reps=1, fmt="int8"):
     """grid batch of `reps` chains of the graph (own seeds), HIP graph replay;
-    returns (wall seconds, event seconds) of the timed call"""
+    returns (wall seconds, event seconds, workgroup size the autotuner chose)
+    of the timed call"""
     chains = [sk.Chain.graph(n, inst.src, inst.dst, J=inst.J, lam_values=inst.lam_values,
                              lam_class=inst.cls, q=1.5, beta=0.8, seed=1 + r, replica=r, layout="csr",
                              fmt=fmt) for r in range(reps)]
@@ -310,10 +311,11 @@ def _graph_run(sk, inst, n, steps, warmup, reps=1, fmt="int8"):
     batch.sweep(warmup)
     wall = timed_sweep(batch, steps)
     _, ev_ms = batch.info()
+    block = batch.launch_shape(0)
     batch.close()
     for c in chains:
         c.close()
-    return wall, ev_ms * 1e-3
+    return wall, ev_ms * 1e-3, block
 
 
 def bench_graph(args, sk):
@@ -322,7 +324,8 @@ def bench_graph(args, sk):
     import synth
     n = 1 << 20
     inst = synth.oriented_instance(n, 3, 3, lam_values=(-0.5, 0.0, 0.5), pm_j=True)
-    wall, ev_s = _graph_run(sk, inst, n, args.steps, args.warmup)
+    wall, ev_s, block = _graph_run(sk, inst, n, args.steps, args.warmup)
+    kernel = "k_graph_lds" if block == 1024 else "k_graph"
     value = 2.0 * n * args.steps / wall
     per_launch_s = ev_s / (2 * args.steps)
     m = inst.src.shape[0]
@@ -331,11 +334,12 @@ def bench_graph(args, sk):
     bytes_launch = 4 * (n + 1) + 5 * m + n + m + n + n
     achieved = bytes_launch / per_launch_s / 1e9
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": read_traffic("k_graph"),
-            "kernel": "k_graph", "launch_us": per_launch_s * 1e6}
+            "frac": achieved / HBM_PEAK_GBS, "traffic": read_traffic(kernel),
+            "kernel": kernel, "block": block, "launch_us": per_launch_s * 1e6,
+            "bytes_per_vertex_update": bytes_launch / n}
     extra_steps = max(1, args.steps // 2)
-    wall_bp, _ = _graph_run(sk, inst, n, extra_steps, args.warmup, fmt="bitpacked")
-    wall_8, _ = _graph_run(sk, inst, n, extra_steps, args.warmup, reps=8)
+    wall_bp, _, _ = _graph_run(sk, inst, n, extra_steps, args.warmup, fmt="bitpacked")
+    wall_8, _, _ = _graph_run(sk, inst, n, extra_steps, args.warmup, reps=8)
     cfg = {"workload": "random 3-regular +-J graph, n=2^20, coin orientation, CSR int32, int8 spins",
            "n": n, "q": 1.5, "beta": 0.8, "lambda": [-0.5, 0.0, 0.5],
            "bitpacked_spins_vertex_updates_per_s": 2.0 * n * extra_steps / wall_bp,
@@ -487,21 +491,24 @@ def bench_copycal(args):
     print(json.dumps({"copy_bytes": n, "copies": 3}), flush=True)
 
 
-def _counter_rows(path, grid=None):
+def _counter_rows(path, grid=None, counter=None):
     """counter values per kernel name; grid: keep only dispatches of that
-    grid size (work-items)"""
+    grid size (work-items); counter: keep only that counter (a pass may
+    collect several)"""
     import csv
     rows = list(csv.DictReader(open(path)))
     out = {}
     for r in rows:
         if grid is not None and int(r["Grid_Size"]) != grid:
             continue
+        if counter is not None and r.get("Counter_Name", counter) != counter:
+            continue
         name = r["Kernel_Name"]
         out.setdefault(name, []).append(float(r["Counter_Value"]))
     return out
 
 
-def summarize_traffic(cal_fetch_csv, cal_write_csv, workloads, out_path):
+def summarize_traffic(cal_fetch_csv, cal_write_csv, workloads, out_path, valu_workloads=()):
     """profiles/traffic.txt from rocprofv3 --pmc counter CSVs: FETCH_SIZE and
     WRITE_SIZE (KiB per dispatch) of the 1 GiB calibration copy, then per
     workload (kernel, fetch csv, write csv, full steps per timed launch or 0,
@@ -548,6 +555,23 @@ def summarize_traffic(cal_fetch_csv, cal_write_csv, workloads, out_path):
             raise SystemExit("kernel %s not found in %s" % (kernel, fetch_csv))
         key = "bytes_per_full_step" if steps else "bytes_per_launch"
         lines.append("%s.%s = %.0f" % (kernel, key, sum(fb_all) / len(fb_all) + sum(wb_all) / len(wb_all)))
+    for kernel, sq_csv, steps, grid, suffix in valu_workloads:
+        v = _counter_rows(sq_csv, grid, "SQ_INSTS_VALU")
+        vals = []
+        for k in sorted(v):
+            if short_name(k) != kernel or not k.split("(")[0].endswith(suffix):
+                continue
+            lv = [x * 64.0 for x in v[k]]
+            if steps:
+                lv = [max(lv) / steps]
+            lines.append("# %s%s: %.4g VALU lane-instructions per %s (SQ_INSTS_VALU x 64, %d dispatches)"
+                         % (k.split("(")[0], "" if grid is None else " grid %d" % grid, sum(lv) / len(lv),
+                            "full step" if steps else "launch", len(v[k])))
+            vals += lv
+        if not vals:
+            raise SystemExit("kernel %s not found in %s" % (kernel, sq_csv))
+        key = "valu_lane_instr_per_full_step" if steps else "valu_lane_instr_per_launch"
+        lines.append("%s.%s = %.0f" % (kernel, key, sum(vals) / len(vals)))
     with open(out_path, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("\n".join(lines))
@@ -596,15 +620,21 @@ def _line(metric, unit, value, steps, warmup, wall, cfg, roof, cpu, dtype):
 def main():
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-traffic":
         # bench.py --summarize-traffic CAL_FETCH CAL_WRITE KERNEL[@STEPS][#GRID][~SUFFIX]=FETCH,WRITE ...
-        wl = []
+        #          [valu:KERNEL[@STEPS][#GRID][~SUFFIX]=SQ_CSV ...]
+        wl, vl = [], []
         for arg in sys.argv[4:]:
             name, files = arg.split("=", 1)
+            is_valu = name.startswith("valu:")
+            name = name[5:] if is_valu else name
             name, _, suffix = name.partition("~")
             name, _, grid = name.partition("#")
             kernel, _, steps = name.partition("@")
-            fetch, write = files.split(",")
-            wl.append((kernel, fetch, write, int(steps or 0), int(grid) if grid else None, suffix))
-        summarize_traffic(sys.argv[2], sys.argv[3], wl, os.path.join(ROOT, "profiles", "traffic.txt"))
+            if is_valu:
+                vl.append((kernel, files, int(steps or 0), int(grid) if grid else None, suffix))
+            else:
+                fetch, write = files.split(",")
+                wl.append((kernel, fetch, write, int(steps or 0), int(grid) if grid else None, suffix))
+        summarize_traffic(sys.argv[2], sys.argv[3], wl, os.path.join(ROOT, "profiles", "traffic.txt"), vl)
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)

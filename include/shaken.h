@@ -422,6 +422,12 @@ typedef struct shaken_batch_counts {
 
 shaken_status shaken_batch_counters(shaken_batch *b, shaken_batch_counts *out);
 
+/* Launch shape chain i runs with (after autotuning, if any): the workgroup
+ * size of its group's half-step launches on the grid strategy -- 64, 128 or
+ * 256, or 1024 for the graph kernel that stages the configuration in LDS --
+ * and 0 on the persistent strategy.  SHAKEN_EINVAL for a bad index. */
+shaken_status shaken_batch_launch_shape(shaken_batch *b, int32_t i, int32_t *block);
+
 shaken_status shaken_batch_free(shaken_batch *b);
 
 

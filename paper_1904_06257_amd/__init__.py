@@ -131,6 +131,7 @@ _SIGS = {
     "shaken_batch_get_logs": [_vp, _i64p, _i64p, _i64p, ctypes.c_int64],
     "shaken_batch_info": [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)],
     "shaken_batch_counters": [_vp, ctypes.POINTER(shaken_batch_counts)],
+    "shaken_batch_launch_shape": [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
     "shaken_batch_free": [_vp],
     "shaken_batch_run": [ctypes.POINTER(_vp), ctypes.c_int32, ctypes.c_int64,
                          ctypes.POINTER(shaken_batch_opts), ctypes.POINTER(shaken_schedule),
@@ -486,6 +487,13 @@ class Batch:
         c = shaken_batch_counts()
         _check(_lib.shaken_batch_counters(self.handle, ctypes.byref(c)))
         return {k: int(getattr(c, k)) for k, _ in shaken_batch_counts._fields_}
+
+    def launch_shape(self, i):
+        """workgroup size of chain i's half-step launches (1024: the graph
+        kernel with the configuration in LDS; 0: persistent strategy)"""
+        v = ctypes.c_int32()
+        _check(_lib.shaken_batch_launch_shape(self.handle, int(i), ctypes.byref(v)))
+        return int(v.value)
 
     def close(self):
         if getattr(self, "handle", None) is not None:

@@ -1424,8 +1424,9 @@ shaken_status batch_build_pgraph(shaken_batch *b) {
 // bound, or one per compute unit) by timing eight full steps of the batch
 // with each; the occupancy bound stays unless the other is at least 3 %
 // faster (run-to-run noise is about that size).  Every chain's configuration
-// is saved before and restored after each trial, so tuning leaves the chains
-// as they were.
+// is saved before the trials and restored after the last one (a trial's
+// timing does not depend on which configuration it starts from), so tuning
+// leaves the chains as they were.
 shaken_status batch_autotune_persistent(shaken_batch *b) {
     const int n = (int)b->ctx.size();
     int ncu = 256;
@@ -1453,44 +1454,40 @@ shaken_status batch_autotune_persistent(shaken_batch *b) {
         return hipSuccess;
     };
     const uint32_t s0 = b->ctx[0]->s;
-    shaken_status st = SHAKEN_OK;
-    hipError_t e = copy_all(true);
-    // warm phase (steady clocks before the comparison): trial runs with the
-    // occupancy-bound grid, each followed by the restore
-    float warm = 0;
-    for (int k = 0; k < kWarmMaxTrials && warm < kWarmMs && e == hipSuccess; ++k) {
-        e = launch_set_state((uint32_t *)b->counter, 0u, 0u, b->stream);
+    // one trial: eight full steps with `grid` workgroups (GPU milliseconds)
+    auto trial = [&](int grid, float *ms) -> hipError_t {
+        hipError_t e = launch_set_state((uint32_t *)b->counter, 0u, 0u, b->stream);
         if (e == hipSuccess) e = hipEventRecord(b->ev0, b->stream);
         if (e == hipSuccess)
-            e = launch_persistent(b->pdescs, n, b->order, b->counter, s0, nullptr, 8, 0, 0, b->pblock, b->pgrid,
+            e = launch_persistent(b->pdescs, n, b->order, b->counter, s0, nullptr, 8, 0, 0, b->pblock, grid,
                                   b->stream);
         if (e == hipSuccess) e = hipEventRecord(b->ev1, b->stream);
-        if (e == hipSuccess) e = copy_all(false);
         if (e == hipSuccess) e = hipEventSynchronize(b->ev1);
+        if (e == hipSuccess) e = hipEventElapsedTime(ms, b->ev0, b->ev1);
+        return e;
+    };
+    shaken_status st = SHAKEN_OK;
+    hipError_t e = copy_all(true);
+    // warm phase (steady clocks before the comparison) with the occupancy-bound grid
+    float warm = 0;
+    for (int k = 0; k < kWarmMaxTrials && warm < kWarmMs && e == hipSuccess; ++k) {
         float ms = 0;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, b->ev0, b->ev1);
+        e = trial(b->pgrid, &ms);
         warm += ms;
     }
     float best = 1e30f;
     int best_g = b->pgrid;
     for (size_t k = 0; k < cands.size() && e == hipSuccess; ++k) {
         for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {  // the first run warms the caches
-            e = launch_set_state((uint32_t *)b->counter, 0u, 0u, b->stream);
-            if (e == hipSuccess) e = hipEventRecord(b->ev0, b->stream);
-            if (e == hipSuccess)
-                e = launch_persistent(b->pdescs, n, b->order, b->counter, s0, nullptr, 8, 0, 0, b->pblock,
-                                      cands[k], b->stream);
-            if (e == hipSuccess) e = hipEventRecord(b->ev1, b->stream);
-            if (e == hipSuccess) e = copy_all(false);
-            if (e == hipSuccess) e = hipEventSynchronize(b->ev1);
             float ms = 0;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, b->ev0, b->ev1);
+            e = trial(cands[k], &ms);
             if (e == hipSuccess && rep == 1 && (k == 0 || ms < 0.97f * best)) {
                 best = ms;
                 best_g = cands[k];
             }
         }
     }
+    if (e == hipSuccess) e = copy_all(false);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) st = fail(SHAKEN_EDEVICE, std::string("persistent autotune: ") + hipGetErrorString(e));
     dfree(save);
@@ -1887,6 +1884,15 @@ shaken_status shaken_batch_counters(shaken_batch *b, shaken_batch_counts *out) {
     out->log_allocs = b->n_log_allocs;
     out->autotunes = b->n_autotunes;
     out->uploads = b->n_uploads;
+    return SHAKEN_OK;
+}
+
+shaken_status shaken_batch_launch_shape(shaken_batch *b, int32_t i, int32_t *block) {
+    if (!b || !block || i < 0 || i >= (int32_t)b->ctx.size()) return fail(SHAKEN_EINVAL, "bad batch, index or output");
+    *block = 0;
+    for (const auto &g : b->groups)
+        for (int m : g.members)
+            if (m == i) *block = g.block;
     return SHAKEN_OK;
 }
 
