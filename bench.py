@@ -28,6 +28,7 @@ is touched, with the single-process rate beside the aggregate.
 from __future__ import annotations
 
 import argparse
+import csv
 import hashlib
 import json
 import os
@@ -577,6 +578,46 @@ def summarize_traffic(cal_fetch_csv, cal_write_csv, workloads, out_path, valu_wo
     print("\n".join(lines))
 
 
+def summarize_trace(trace_csv, stats_csv=None):
+    """Markdown tables from a rocprofv3 --kernel-trace run: per kernel and
+    launch shape (grid, workgroup, registers, LDS) the number of dispatches
+    and their average / min / max duration, then the tool's own per-kernel
+    statistics when its kernel_stats.csv is given."""
+    groups = {}
+    with open(trace_csv, newline="") as fh:
+        for r in csv.DictReader(fh):
+            name = r["Kernel_Name"].split("(")[0]
+            key = (name, int(r["Grid_Size_X"]), int(r["Grid_Size_Y"]), int(r["Workgroup_Size_X"]),
+                   int(r["VGPR_Count"]), int(r["LDS_Block_Size"]), int(r["Scratch_Size"]))
+            groups.setdefault(key, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    out = ["| kernel | grid x | grid y | block | VGPR | LDS B | scratch B | calls | avg us | min us | max us |",
+           "|---|---|---|---|---|---|---|---|---|---|---|"]
+    total = sum(sum(d) for d in groups.values())
+    shown = 0.0
+    rest = []
+    for key in sorted(groups, key=lambda k: -sum(groups[k])):
+        d = groups[key]
+        if sum(d) < 0.01 * total and len(out) > 2:   # shapes under 1 % each: counted below
+            rest.append(key)
+            continue
+        shown += sum(d)
+        out.append("| %s | %d | %d | %d | %d | %d | %d | %d | %.1f | %.1f | %.1f |"
+                   % (key + (len(d), sum(d) / len(d), min(d), max(d))))
+    if rest:
+        names = sorted({k[0] for k in rest})
+        out.append("| (%d more launch shapes of %s: %.2f %% of kernel time) | | | | | | | %d | | | |"
+                   % (len(rest), ", ".join(names), 100.0 * (total - shown) / total,
+                      sum(len(groups[k]) for k in rest)))
+    if stats_csv:
+        out += ["", "| kernel | calls | avg us | min us | max us | % time |", "|---|---|---|---|---|---|"]
+        with open(stats_csv, newline="") as fh:
+            for r in csv.DictReader(fh):
+                out.append("| %s | %s | %.1f | %.1f | %.1f | %.2f |"
+                           % (r["Name"].split("(")[0], r["Calls"], float(r["AverageNs"]) / 1e3,
+                              float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3, float(r["Percentage"])))
+    print("\n".join(out))
+
+
 def bench_mlp(sk, rows=512, reps=200):
     """Latency of the schedule network's calls at `rows` feature rows (one
     row per chain): forward; loss + backward (it returns the loss to the host,
@@ -618,6 +659,10 @@ def _line(metric, unit, value, steps, warmup, wall, cfg, roof, cpu, dtype):
 
 
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "--summarize-trace":
+        # bench.py --summarize-trace KERNEL_TRACE_CSV [KERNEL_STATS_CSV]
+        summarize_trace(sys.argv[2], sys.argv[3] if len(sys.argv) > 3 else None)
+        return
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-traffic":
         # bench.py --summarize-traffic CAL_FETCH CAL_WRITE KERNEL[@STEPS][#GRID][~SUFFIX]=FETCH,WRITE ...
         #          [valu:KERNEL[@STEPS][#GRID][~SUFFIX]=SQ_CSV ...]

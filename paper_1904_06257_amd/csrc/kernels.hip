@@ -207,6 +207,9 @@ __global__ __launch_bounds__(256) void k_torus_bp(const ChainDesc *__restrict__ 
             dis_acc += __popc(__builtin_amdgcn_bitop3_b32(own[i], a, vmi, kT_xor_and));
             dis_acc += __popc(__builtin_amdgcn_bitop3_b32(own[i], b, vmi, kT_xor_and));
             p_acc += __popc(own[i] & vmi);
+            // count here: left to the compiler, the counts sink to their use
+            // after the tail and keep every row's planes live across it
+            asm volatile("" : "+v"(dis_acc), "+v"(p_acc));
         }
         // folded table: res = new spins of the sites decided; six classes:
         // the sites decided with v < t (the flip plane applied at the store)
@@ -415,6 +418,7 @@ __global__ __launch_bounds__(256) void k_tri_bp(const ChainDesc *__restrict__ de
             e_acc += d.J * (3 * __popc(vmi) - 2 * __popc((own[i] ^ a) & vmi) -
                             2 * __popc((own[i] ^ b) & vmi) - 2 * __popc((own[i] ^ e) & vmi));
             p_acc += __popc(own[i] & vmi);
+            asm volatile("" : "+v"(e_acc), "+v"(p_acc));  // count here (as in k_torus_bp)
         }
         // folded table: res = new spins of the sites decided; eight classes:
         // the sites decided with v < t (the flip plane applied at the store)
