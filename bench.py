@@ -330,9 +330,12 @@ def bench_graph(args, sk):
     value = 2.0 * n * args.steps / wall
     per_launch_s = ev_s / (2 * args.steps)
     m = inst.src.shape[0]
-    # algorithmic bytes per half-step: rowptr (n+1) + col + J (m) + own spin,
-    # gathered spins (m), field class, written spin
-    bytes_launch = 4 * (n + 1) + 5 * m + n + m + n + n
+    # algorithmic bytes per half-step: rowptr (n+1), the edges (m; the
+    # LDS-staged kernel reads index and J as one 4-byte word, the plain one
+    # a 4-byte index and a 1-byte J), own spin, gathered spins (m), field
+    # class, written spin
+    edge_bytes = 4 if kernel == "k_graph_lds" else 5
+    bytes_launch = 4 * (n + 1) + edge_bytes * m + n + m + n + n
     achieved = bytes_launch / per_launch_s / 1e9
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": read_traffic(kernel),

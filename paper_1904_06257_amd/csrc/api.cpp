@@ -137,6 +137,7 @@ struct shaken_ctx {
     uint32_t *jneg_dev = nullptr;  // +-J torus sign planes (2 x L x W words)
     uint32_t *frozen_dev = nullptr;  // frozen set B as bits (layout of the bit-packed spins)
     uint32_t *mirror[2] = {nullptr, nullptr};  // packed copies of int8 graph spins (LDS-staged kernel)
+    int32_t *cj[2] = {nullptr, nullptr};       // index | J << 24 per CSR entry (LDS-staged kernel)
     bool tri = false;                // triangular torus
     std::vector<uint8_t> frozen_host;  // per site, nonzero = frozen
     int ell_k = 0;
@@ -175,6 +176,7 @@ void release(shaken_ctx *c) {
         dfree(c->rp[h]);
         dfree(c->col[h]);
         dfree(c->jw[h]);
+        dfree(c->cj[h]);
     }
     dfree(c->cls_dev);
     dfree(c->ell_dev);
@@ -672,10 +674,23 @@ shaken_status init_device(shaken_ctx *c, const shaken_opts *o, HostLayout &hl) {
         CHK(dalloc(&c->frozen_dev, hl.frozen.size()));
         HIPCHK(hipMemcpyAsync(c->frozen_dev, hl.frozen.data(), hl.frozen.size() * 4, hipMemcpyHostToDevice, c->stream));
     }
-    if (c->kind == KIND_GRAPH && c->format != FMT_BITPACKED && (c->n + 31) / 32 <= graph_lds_max_words()) {
-        const size_t mw = ((size_t)(c->n + 31) / 32 + 3) / 4 * 4;
-        CHK(dalloc(&c->mirror[0], mw));
-        CHK(dalloc(&c->mirror[1], mw));
+    if (c->kind == KIND_GRAPH && (c->n + 31) / 32 <= graph_lds_max_words()) {
+        if (c->format != FMT_BITPACKED) {
+            const size_t mw = ((size_t)(c->n + 31) / 32 + 3) / 4 * 4;
+            CHK(dalloc(&c->mirror[0], mw));
+            CHK(dalloc(&c->mirror[1], mw));
+        }
+        // the LDS-staged kernel's edge words: index (< 2^24) and J together,
+        // read four at a time from aligned positions
+        for (int h = 0; h < 2; ++h) {
+            const size_t mh = (size_t)rp[h][(size_t)c->n];
+            std::vector<int32_t> cj((mh + 3) / 4 * 4 + 16, 0);
+            for (size_t e = 0; e < mh; ++e)
+                cj[e] = (int32_t)(((uint32_t)col[h][e] & 0xFFFFFFu) | ((uint32_t)(uint8_t)jw[h][e] << 24));
+            CHK(dalloc(&c->cj[h], cj.size()));
+            HIPCHK(hipMemcpyAsync(c->cj[h], cj.data(), cj.size() * 4, hipMemcpyHostToDevice, c->stream));
+            HIPCHK(hipStreamSynchronize(c->stream));
+        }
     }
     if (!hl.jneg.empty()) {
         CHK(dalloc(&c->jneg_dev, hl.jneg.size()));
@@ -714,6 +729,8 @@ shaken_status init_device(shaken_ctx *c, const shaken_opts *o, HostLayout &hl) {
     d.frozen = c->frozen_dev;
     d.mirror[0] = c->mirror[0];
     d.mirror[1] = c->mirror[1];
+    d.cj[0] = c->cj[0];
+    d.cj[1] = c->cj[1];
     d.log_line = c->line();
     d.log_stride = c->stride();
     for (size_t k = 0; k < c->lam.size() && k < 16; ++k) {

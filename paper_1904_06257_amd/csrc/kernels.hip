@@ -789,6 +789,7 @@ __global__ __launch_bounds__(256) void k_graph(const ChainDesc *__restrict__ des
 constexpr int kLdsGraphWords = 36864;                 // 144 KiB: up to 1,179,648 vertices
 constexpr int kLdsGraphStage = kLdsGraphWords / 4 / kLdsGraphBlock;  // uint4 loads per lane
 constexpr int kLdsGraphClasses = 256;
+constexpr int kLdsEdgeChunk = 12;
 
 // Loads through the global address space (not flat), unconditional at
 // clamped indices: a load under a divergent branch makes the compiler wait
@@ -799,6 +800,35 @@ typedef int32_t gl_i32x4 __attribute__((ext_vector_type(4)));
 template <class T>
 __device__ __forceinline__ T gld(const void *base, int64_t i) {
     return ((const __attribute__((address_space(1))) T *)base)[i];
+}
+template <class T>
+__device__ __forceinline__ void gst(void *base, int64_t i, T v) {
+    ((__attribute__((address_space(1))) T *)base)[i] = v;
+}
+
+// The twelve edge words from position e0 on: four aligned 16-byte loads
+// from e0 rounded down to a multiple of four, then a shift by e0 & 3 in two
+// bitwise selects per word.  Entries past the half's last edge are padding or other
+// rows' edges; the caller masks them.
+__device__ __forceinline__ void lds_edge_window(const int32_t *cj, int e0, int (&ew)[kLdsEdgeChunk]) {
+    const int a = e0 >> 2, o = e0 & 3;
+    int w[16];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const gl_i32x4 v = gld<gl_i32x4>(cj, a + i);
+        w[4 * i] = v.x;
+        w[4 * i + 1] = v.y;
+        w[4 * i + 2] = v.z;
+        w[4 * i + 3] = v.w;
+    }
+    // bitwise selects (written as selects, they become a dynamically
+    // indexed array in scratch memory)
+    const int m2 = -((o >> 1) & 1), m1 = -(o & 1);
+    int w1[14];
+#pragma unroll
+    for (int i = 0; i < 14; ++i) w1[i] = (w[i + 2] & m2) | (w[i] & ~m2);
+#pragma unroll
+    for (int k = 0; k < kLdsEdgeChunk; ++k) ew[k] = (w1[k + 1] & m1) | (w1[k] & ~m1);
 }
 
 template <bool OBS, bool BP>
@@ -829,74 +859,86 @@ __global__ __launch_bounds__(kLdsGraphBlock) void k_graph_lds(const ChainDesc *_
                                       // to a multiple of four vertices
     const int nlut = (2 * smax + 1) * 2 * ncls;
     const bool lut_lds = nlut <= kLdsLut;
+    if (OBS)   // (first: later, its stores would wait for the loads below)
+        for (int i = tid; i < ncls; i += kLdsGraphBlock) sh_plus[i] = 0;
     // 1. row bounds, classes, the lane's threshold entry and frozen bits
+    // (every load of steps 1-3 unconditional, at clamped indices: a load
+    // under a branch makes the compiler wait for all loads before the next
+    // dependent one)
     const gl_i32x4 r4 = gld<gl_i32x4>(d.rowptr[half], va >> 2);
     const int rp4 = gld<int32_t>(d.rowptr[half], va + 4);
     const int rpv[5] = {r4.x, r4.y, r4.z, r4.w, rp4};
     const uint32_t c4 = gld<uint32_t>(d.cls, va >> 2);
-    const uint64_t lutv = lut_lds ? gld<uint64_t>(d.lut, min(tid, nlut - 1)) : 0;
-    const uint32_t fzw = d.frozen ? gld<uint32_t>(d.frozen, va >> 5) : 0u;
-    // 3. the first chunk of the lane's edges (needs the row bounds; arrays
-    // padded, indices clamped: every load valid)
-    const int last = rpv[4] - 1;
-    int cc[kEdgeChunk], jj[kEdgeChunk];
-#pragma unroll
-    for (int k = 0; k < kEdgeChunk; ++k) {
-        const int e = max(min(rpv[0] + k, last), 0);
-        cc[k] = gld<int32_t>(d.col[half], e);
-        jj[k] = (int)gld<int8_t>(d.jw[half], e);
-    }
-    // 4. the configuration, coalesced, straight into LDS (global_load_lds:
+    const uint64_t lutv = gld<uint64_t>(d.lut, min(tid, nlut - 1));
+    // (no frozen set: a valid word of the class bytes, discarded)
+    const uint32_t fzw0 = gld<uint32_t>(d.frozen ? (const void *)d.frozen : (const void *)d.cls, va >> 5);
+    const uint32_t fzw = d.frozen ? fzw0 : 0u;
+    // the lane's four uniforms while those loads are in flight
+    U4 r = {0u, 0u, 0u, 0u};
+    if (active)
+        r = philox10((uint32_t)q4, s, d.replica, kGraphStream, (uint32_t)d.seed, (uint32_t)(d.seed >> 32));
+    // (these loads stay ahead of the rest, and the row bounds are waited
+    // for here, before the loads into LDS are issued)
+    __builtin_amdgcn_sched_barrier(0);
+    const int e_first = rpv[0], last = rpv[4] - 1;
+    asm volatile("" ::"v"(e_first), "v"(last));
+    __builtin_amdgcn_sched_barrier(0);
+    // 2. the configuration, coalesced, straight into LDS (global_load_lds:
     // lane l of a wavefront loads 16 bytes into the wavefront's 1 KiB LDS
     // segment at 16 l, the same offset as in global memory).  Each group of
     // four words is loaded by exactly one lane, the last group with the
     // buffer's padding, so no other write to the array is needed -- a wait
     // on the vector memory counter covers only the waiting wavefront's own
-    // loads, and the barrier below is what orders them for everyone.
+    // loads, and the barrier below is what orders them for everyone.  Lanes
+    // past the last group load it again into LDS no vertex reads; wavefronts
+    // wholly past it load nothing.  Issued
+    // after the wait for the row bounds (with loads into LDS in flight the
+    // compiler no longer counts vector loads as returning in order, and that
+    // wait would cover these too) and before the edges (whose registers
+    // would otherwise be reused here, each reuse a wait for the edges).
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63;
 #pragma unroll
     for (int k = 0; k < kLdsGraphStage; ++k) {
         const int base = k * kLdsGraphBlock + wv * 64;
-        if (base < ng && base + lane < ng)
-            __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)(bits_in + 4 * (base + lane)),
+        const int g = min(base + lane, ng - 1);
+        if (base < ng)   // wave-uniform
+            __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)(bits_in + 4 * g),
                                              (__attribute__((address_space(3))) void *)(sh_sp4 + base), 16, 0, 0);
     }
-    if (OBS)
-        for (int i = tid; i < ncls; i += kLdsGraphBlock) sh_plus[i] = 0;
-    U4 r = {0u, 0u, 0u, 0u};
-    if (active)
-        r = philox10((uint32_t)q4, s, d.replica, kGraphStream, (uint32_t)d.seed, (uint32_t)(d.seed >> 32));
-    // 5. this wavefront's direct loads have landed (vector memory counter),
+    // 3. the first chunk of the lane's edges (needs the row bounds): twelve
+    // edge words, index | J << 24, from four aligned 16-byte loads (the
+    // array is padded past them), which covers four vertices of degree up
+    // to three in one round trip and few cache-line requests
+    __builtin_amdgcn_sched_barrier(0);
+    int ew[kLdsEdgeChunk];
+    lds_edge_window(d.cj[half], e_first, ew);
+    // 4. this wavefront's direct loads have landed (vector memory counter),
     // then the barrier: every lane sees the whole configuration
     __builtin_amdgcn_s_waitcnt(0);
     uint32_t *sh_sp = (uint32_t *)sh_sp4;
     if (lut_lds && tid < nlut) sh_lut[tid] = lutv;
     __syncthreads();
-    // 6. own spins and field sums from LDS
+    // 5. own spins and field sums from LDS
+    // (the lane's four vertices share one word; bits past n are padding
+    // and their results are discarded)
     int own[4], cl[4];
+    const uint32_t ow = sh_sp[min(v0, n - 1) >> 5] >> (v0 & 31);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        const int v = min(v0 + j, n - 1);
-        own[j] = ((sh_sp[v >> 5] >> (v & 31)) & 1u) ? 1 : -1;
+        own[j] = ((ow >> j) & 1u) ? 1 : -1;
         cl[j] = (int)((c4 >> (8 * j)) & 0xFFu);
     }
     int S0 = 0, S1 = 0, S2 = 0, S3 = 0;
     if (active) {
-        for (int base = rpv[0]; base <= last; base += kEdgeChunk) {
-            if (base != rpv[0]) {
+        for (int base = rpv[0]; base <= last; base += kLdsEdgeChunk) {
+            if (base != rpv[0]) lds_edge_window(d.cj[half], base, ew);
 #pragma unroll
-                for (int k = 0; k < kEdgeChunk; ++k) {
-                    const int e = min(base + k, last);
-                    cc[k] = gld<int32_t>(d.col[half], e);
-                    jj[k] = (int)gld<int8_t>(d.jw[half], e);
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < kEdgeChunk; ++k) {
+            for (int k = 0; k < kLdsEdgeChunk; ++k) {
                 const int e = base + k;
-                const int sv = ((sh_sp[cc[k] >> 5] >> (cc[k] & 31)) & 1u) ? 1 : -1;
-                const int t = e <= last ? jj[k] * sv : 0;
+                const int c = ew[k] & 0xFFFFFF;
+                const int sv = ((sh_sp[c >> 5] >> (c & 31)) & 1u) ? 1 : -1;
+                const int t = e <= last ? (ew[k] >> 24) * sv : 0;
                 S0 += e < rpv[1] ? t : 0;
                 S1 += (e >= rpv[1] && e < rpv[2]) ? t : 0;
                 S2 += (e >= rpv[2] && e < rpv[3]) ? t : 0;
@@ -904,7 +946,7 @@ __global__ __launch_bounds__(kLdsGraphBlock) void k_graph_lds(const ChainDesc *_
             }
         }
     }
-    // 7. thresholds, the new spins and their packed copy
+    // 6. thresholds, the new spins and their packed copy
     const int Sv[4] = {S0, S1, S2, S3};
     uint32_t up = 0;
     int e_acc = 0;
@@ -922,8 +964,27 @@ __global__ __launch_bounds__(kLdsGraphBlock) void k_graph_lds(const ChainDesc *_
         }
         up |= (fzw >> (v0 & 31)) & 0xFu;
     }
-    if (!BP) graph_store4<false>(out, q4, n, up);
-    graph_store4<true>(bits_out, q4, n, up);
+    // stores through the global address space (flat stores would also
+    // count against the LDS wait counter)
+    if (!BP && active) {
+        uint32_t packed = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) packed |= (((up >> j) & 1u) ? 0x01u : 0xFFu) << (8 * j);
+        if (v0 + 3 < n) {
+            gst<uint32_t>(out, q4, packed);
+        } else {
+            for (int j = 0; j < 4 && v0 + j < n; ++j) gst<int8_t>(out, v0 + j, (int8_t)(packed >> (8 * j)));
+        }
+    }
+    // packed word of 32 vertices: the eight lanes' 4-bit pieces OR-ed into
+    // the group's last lane by row shifts (DPP, no LDS traffic)
+    {
+        uint32_t val = (active ? up : 0u) << (4 * (q4 & 7));
+        val |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)val, 0x111, 0xF, 0xF, true);   // row_shr:1
+        val |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)val, 0x112, 0xF, 0xF, true);   // row_shr:2
+        val |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)val, 0x114, 0xF, 0xF, true);   // row_shr:4
+        if ((q4 & 7) == 7 && 4 * (q4 & ~7) < n) gst<uint32_t>(bits_out, q4 >> 3, val);
+    }
     if (OBS) {
         int64_t *lg = log_part(d, slot, blockIdx.x);
         const int lane = tid & 63, wv = tid >> 6;
@@ -1302,7 +1363,7 @@ hipError_t launch_half_step_grid(const ChainDesc *dev_descs, const ChainDesc *ho
 }
 
 bool graph_lds_fits(const ChainDesc &d) {
-    return d.kind == KIND_GRAPH && d.n <= 32 * kLdsGraphWords && (d.format == FMT_BITPACKED || d.mirror[0]);
+    return d.kind == KIND_GRAPH && d.n <= 32 * kLdsGraphWords && d.cj[0] && (d.format == FMT_BITPACKED || d.mirror[0]);
 }
 
 int graph_lds_max_words() { return kLdsGraphWords; }

@@ -92,6 +92,10 @@ struct ChainDesc {
     // copy of spin[i] (one bit per vertex, layout of the bit-packed spins),
     // written by that kernel beside its int8 output; null otherwise
     uint32_t *mirror[2];
+    // graphs the LDS-staged kernel takes (n < 2^24): each CSR entry as one
+    // word, (neighbour index) | J << 24, padded by 16 zero entries past a
+    // multiple of four; null otherwise
+    const int32_t *cj[2];
 };
 
 // workgroup size of the LDS-staged graph kernel; as a launch's block size it
