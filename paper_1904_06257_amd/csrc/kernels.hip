@@ -121,8 +121,10 @@ __device__ __forceinline__ int tail_slot(const int *cnt, int nwav, int qcap_w, i
 }
 
 // EXT: instantiation for chains with +-J sign planes or a frozen set (the
-// plain instantiation reads neither)
-template <bool OBS, bool FOLD3, bool EXT>
+// plain instantiation reads neither).  ALIGN: every chain's side is a
+// multiple of 32 (no padding bits, whole strips, the wrap-around bit always
+// at bit 31), which spares the per-row masks and selects.
+template <bool OBS, bool FOLD3, bool EXT, bool ALIGN = false>
 __global__ __launch_bounds__(256) void k_torus_bp(const ChainDesc *__restrict__ descs, StepArgs sa) {
     __shared__ uint32_t q_w[kQCap], q_a[kQCap], q_b[kQCap], q_c[kQCap], q_und[kQCap], q_res[kQCap];
     __shared__ int q_cnt[4];  // entries queued per wavefront region
@@ -158,15 +160,15 @@ __global__ __launch_bounds__(256) void k_torus_bp(const ChainDesc *__restrict__ 
     const int rb = !live ? 0 : (W == 1 ? gid : (int)__umulhi((uint32_t)gid, d.wdiv));
     const int wd = live ? gid - rb * W : 0;
     const int r0 = rb * kRows;
-    const int nr = live ? min(kRows, L - r0) : 0;
-    const uint32_t vm = bp_valid(L, W, wd);
+    const int nr = live ? (ALIGN ? kRows : min(kRows, L - r0)) : 0;
+    const uint32_t vm = ALIGN ? ~0u : bp_valid(L, W, wd);
     const int lastbits = (L - 1) & 31;
     // adjacent word supplying the carry bit: left word (dl) / right word (ur)
     const int wside = phase == 0 ? (wd > 0 ? wd - 1 : W - 1) : (wd < W - 1 ? wd + 1 : 0);
     // position of the wrap-around bit: the adjacent word's bit brought to bit 0
     // (dl) or the bit it lands on (ur); 31 inside a row, the last valid bit at
     // the row's end
-    const int csh = (phase == 0 ? wd > 0 : wd < W - 1) ? 31 : lastbits;
+    const int csh = (ALIGN || (phase == 0 ? wd > 0 : wd < W - 1)) ? 31 : lastbits;
     // rows past the side are the buffer's zero padding (no sites)
     uint32_t own[kRows], side[kRows];
     const uint32_t obase = (uint32_t)(r0 * W + wd), sbase = (uint32_t)(r0 * W + wside);
@@ -190,16 +192,16 @@ __global__ __launch_bounds__(256) void k_torus_bp(const ChainDesc *__restrict__ 
     for (int i = 0; i < kRows; ++i) {
         // rows past the strip (and lanes past the grid) are computed with no
         // valid sites: nothing undecided, nothing stored
-        const bool act = i < nr;
+        const bool act = ALIGN ? live : i < nr;
         const uint32_t vmi = act ? vm : 0u;
         const int widx = (r0 + i) * W + wd;
         uint32_t a, b;
         if (phase == 0) {
             a = (i == 0) ? halo : own[i > 0 ? i - 1 : 0];
-            b = (own[i] << 1) | ((side[i] >> csh) & 1u);
+            b = ALIGN ? __builtin_amdgcn_alignbit(own[i], side[i], 31) : (own[i] << 1) | ((side[i] >> csh) & 1u);
         } else {
-            a = (i == nr - 1) ? halo : own[i < kRows - 1 ? i + 1 : 0];
-            b = (own[i] >> 1) | ((side[i] & 1u) << csh);
+            a = (ALIGN ? i == kRows - 1 : i == nr - 1) ? halo : own[i < kRows - 1 ? i + 1 : 0];
+            b = ALIGN ? __builtin_amdgcn_alignbit(side[i], own[i], 1) : (own[i] >> 1) | ((side[i] & 1u) << csh);
         }
         if (EXT && d.jneg && act) bp_jflip(d.jneg, L, W, r0 + i, wd, phase, a, b);
         if (OBS) {
@@ -1290,10 +1292,11 @@ hipError_t launch_half_step_grid(const ChainDesc *dev_descs, const ChainDesc *ho
     if (nchains <= 0) return hipSuccess;
     // the chains of one launch share a kind and a format (the runtime groups them)
     const ChainDesc &h0 = host_descs[0];
-    int maxu = 0, fold = 1, maxcls = 1, jpl = 0;
+    int maxu = 0, fold = 1, maxcls = 1, jpl = 0, aligned = 1;
     for (int i = 0; i < nchains; ++i) {
         maxu = maxu > units_of(host_descs[i]) ? maxu : units_of(host_descs[i]);
         fold &= host_descs[i].fold3;
+        aligned &= host_descs[i].kind == KIND_TORUS && host_descs[i].L % 32 == 0;
         maxcls = maxcls > host_descs[i].ncls ? maxcls : host_descs[i].ncls;
         jpl |= host_descs[i].jneg != nullptr || host_descs[i].frozen != nullptr;
     }
@@ -1323,6 +1326,9 @@ hipError_t launch_half_step_grid(const ChainDesc *dev_descs, const ChainDesc *ho
             // launch skip them)
             if (obs) { if (fold) SHAKEN_BP(true, true, true); else SHAKEN_BP(true, false, true); }
             else { if (fold) SHAKEN_BP(false, true, true); else SHAKEN_BP(false, false, true); }
+        } else if (fold && aligned) {
+            if (obs) hipLaunchKernelGGL((k_torus_bp<true, true, false, true>), grid, dim3(b), 0, stream, dev_descs, sa);
+            else hipLaunchKernelGGL((k_torus_bp<false, true, false, true>), grid, dim3(b), 0, stream, dev_descs, sa);
         } else {
             if (obs) { if (fold) SHAKEN_BP(true, true, false); else SHAKEN_BP(true, false, false); }
             else { if (fold) SHAKEN_BP(false, true, false); else SHAKEN_BP(false, false, false); }
