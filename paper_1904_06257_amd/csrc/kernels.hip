@@ -339,7 +339,7 @@ __device__ __noinline__ uint32_t tri_finish(uint32_t a, uint32_t b, uint32_t e, 
     }
 }
 
-template <bool OBS, bool FOLD>
+template <bool OBS, bool FOLD, bool ALIGN = false>
 __global__ __launch_bounds__(256) void k_tri_bp(const ChainDesc *__restrict__ descs, StepArgs sa) {
     __shared__ uint32_t q_w[kQCap], q_a[kQCap], q_b[kQCap], q_e[kQCap], q_c[kQCap], q_und[kQCap],
         q_res[kQCap];
@@ -375,14 +375,14 @@ __global__ __launch_bounds__(256) void k_tri_bp(const ChainDesc *__restrict__ de
     const int rb = !live ? 0 : (W == 1 ? gid : (int)__umulhi((uint32_t)gid, d.wdiv));
     const int wd = live ? gid - rb * W : 0;
     const int r0 = rb * kRows;
-    const int nr = live ? min(kRows, L - r0) : 0;
-    const uint32_t vm = bp_valid(L, W, wd);
+    const int nr = live ? (ALIGN ? kRows : min(kRows, L - r0)) : 0;
+    const uint32_t vm = ALIGN ? ~0u : bp_valid(L, W, wd);
     const int lastbits = (L - 1) & 31;
     const int wside = phase == 0 ? (wd > 0 ? wd - 1 : W - 1) : (wd < W - 1 ? wd + 1 : 0);
     // position of the wrap-around bit: the adjacent word's bit brought to bit 0
     // (dl) or the bit it lands on (ur); 31 inside a row, the last valid bit at
     // the row's end
-    const int csh = (phase == 0 ? wd > 0 : wd < W - 1) ? 31 : lastbits;
+    const int csh = (ALIGN || (phase == 0 ? wd > 0 : wd < W - 1)) ? 31 : lastbits;
     // rows past the side are the buffer's zero padding (no sites)
     uint32_t own[kRows], side[kRows];
     const uint32_t obase = (uint32_t)(r0 * W + wd), sbase = (uint32_t)(r0 * W + wside);
@@ -401,20 +401,21 @@ __global__ __launch_bounds__(256) void k_tri_bp(const ChainDesc *__restrict__ de
     for (int i = 0; i < kRows; ++i) {
         // rows past the strip (and lanes past the grid) are computed with no
         // valid sites: nothing undecided, nothing stored
-        const bool act = i < nr;
+        const bool act = ALIGN ? live : i < nr;
         const uint32_t vmi = act ? vm : 0u;
         const int widx = (r0 + i) * W + wd;
         uint32_t a, b, e;
         if (phase == 0) {
             a = (i == 0) ? halo : own[i > 0 ? i - 1 : 0];
             const uint32_t as = (i == 0) ? halo_side : side[i > 0 ? i - 1 : 0];
-            b = (own[i] << 1) | ((side[i] >> csh) & 1u);
-            e = (a << 1) | ((as >> csh) & 1u);
+            b = ALIGN ? __builtin_amdgcn_alignbit(own[i], side[i], 31) : (own[i] << 1) | ((side[i] >> csh) & 1u);
+            e = ALIGN ? __builtin_amdgcn_alignbit(a, as, 31) : (a << 1) | ((as >> csh) & 1u);
         } else {
-            a = (i == nr - 1) ? halo : own[i < kRows - 1 ? i + 1 : 0];
-            const uint32_t as = (i == nr - 1) ? halo_side : side[i < kRows - 1 ? i + 1 : 0];
-            b = (own[i] >> 1) | ((side[i] & 1u) << csh);
-            e = (a >> 1) | ((as & 1u) << csh);
+            const bool top = ALIGN ? i == kRows - 1 : i == nr - 1;
+            a = top ? halo : own[i < kRows - 1 ? i + 1 : 0];
+            const uint32_t as = top ? halo_side : side[i < kRows - 1 ? i + 1 : 0];
+            b = ALIGN ? __builtin_amdgcn_alignbit(side[i], own[i], 1) : (own[i] >> 1) | ((side[i] & 1u) << csh);
+            e = ALIGN ? __builtin_amdgcn_alignbit(as, a, 1) : (a >> 1) | ((as & 1u) << csh);
         }
         if (OBS) {
             e_acc += d.J * (3 * __popc(vmi) - 2 * __popc((own[i] ^ a) & vmi) -
@@ -1315,7 +1316,10 @@ hipError_t launch_half_step_grid(const ChainDesc *dev_descs, const ChainDesc *ho
     const dim3 grid((maxu + b - 1) / b, nchains);
     if (h0.kind == KIND_TORUS && h0.format == FMT_BITPACKED && h0.tri) {
         // the runtime groups triangular tori apart from square ones
-        if (obs) { if (fold) hipLaunchKernelGGL((k_tri_bp<true, true>), grid, dim3(b), 0, stream, dev_descs, sa);
+        if (fold && aligned) {
+            if (obs) hipLaunchKernelGGL((k_tri_bp<true, true, true>), grid, dim3(b), 0, stream, dev_descs, sa);
+            else hipLaunchKernelGGL((k_tri_bp<false, true, true>), grid, dim3(b), 0, stream, dev_descs, sa);
+        } else if (obs) { if (fold) hipLaunchKernelGGL((k_tri_bp<true, true>), grid, dim3(b), 0, stream, dev_descs, sa);
                    else hipLaunchKernelGGL((k_tri_bp<true, false>), grid, dim3(b), 0, stream, dev_descs, sa); }
         else { if (fold) hipLaunchKernelGGL((k_tri_bp<false, true>), grid, dim3(b), 0, stream, dev_descs, sa);
                else hipLaunchKernelGGL((k_tri_bp<false, false>), grid, dim3(b), 0, stream, dev_descs, sa); }
