@@ -406,12 +406,12 @@ def bench_batch(args, sk):
     per_launch_s = ev_ms * 1e-3  # one persistent launch per sweep
     bytes_launch = adj_bytes_half * 2 * args.steps
     achieved = bytes_launch / per_launch_s / 1e9
-    traffic = read_traffic("k_persistent", per="full_step")
-    if traffic is not None:
-        traffic *= args.steps
+    # counters per full step; the timed launch covers args.steps of them
+    traffic_step = read_traffic("k_persistent", per="full_step")
+    traffic = traffic_step * args.steps if traffic_step is not None else None
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-            "kernel": "k_persistent", "launch_us": per_launch_s * 1e6,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_per_full_step": traffic_step,
+            "full_steps_per_launch": args.steps, "kernel": "k_persistent", "launch_us": per_launch_s * 1e6,
             "note": "graph adjacency streamed from HBM; tori are LDS-resident (0 B)"}
     cfg = {"workload": "2048 mixed chains in one persistent launch: 1024 tori L in {16..256}, "
                        "1024 3-regular +-J graphs n in [1024, 65536], own beta~U(0.2,1.2), "
