@@ -740,7 +740,8 @@ def main():
     else:
         value, wall, cfg, roof, dtype = bench_batch(args, sk)
         metric = "aggregate site updates/s (2048 mixed chains, persistent batch)"
-    out = {"metric": metric, "value": value, "unit": "site-updates/s", "n_gpus": 1,
+    unit = "vertex-updates/s" if args.workload == "graph" else "site-updates/s"
+    out = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": wall * 1e3 / args.steps, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic",

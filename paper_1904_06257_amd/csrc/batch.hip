@@ -440,11 +440,13 @@ __device__ __forceinline__ void graph_lds_half(const ChainDesc &d, const uint32_
             }
         }
         if (dst) {
+            // the eight lanes' 4-bit pieces OR-ed into the group's last lane
+            // (DPP row shifts; every lane of the workgroup is here)
             uint32_t val = bits << (4 * (q4 & 7));
-            val |= __shfl_xor(val, 1, 64);
-            val |= __shfl_xor(val, 2, 64);
-            val |= __shfl_xor(val, 4, 64);
-            if ((q4 & 7) == 0 && q4 < nq) dst[q4 >> 3] = val;
+            val |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)val, 0x111, 0xF, 0xF, true);   // row_shr:1
+            val |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)val, 0x112, 0xF, 0xF, true);   // row_shr:2
+            val |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)val, 0x114, 0xF, 0xF, true);   // row_shr:4
+            if ((q4 & 7) == 7 && (q4 & ~7) < nq) dst[q4 >> 3] = val;
         }
     }
     if (obs) {

@@ -77,10 +77,18 @@ __device__ __forceinline__ uint32_t bitmask(uint32_t v, int sh) {
 
 // ------------------------------------------------------------ reductions
 
+// Sum over the 64 lanes, returned in every lane: prefix sums within each
+// row of 16 lanes by row shifts, the row totals carried by the row
+// broadcasts of lanes 15 and 31, lane 63's total read out.  All DPP (VALU);
+// lane shuffles would be six dependent LDS round trips.
 __device__ __forceinline__ int wave_sum(int v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, true);   // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, true);   // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, true);   // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, true);   // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false);  // row_bcast:15 into rows 1, 3
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false);  // row_bcast:31 into rows 2, 3
+    return __builtin_amdgcn_readlane(v, 63);
 }
 
 // line of log slot `slot` that block `blk` adds into
