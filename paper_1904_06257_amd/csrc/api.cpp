@@ -137,7 +137,7 @@ struct shaken_ctx {
     uint32_t *jneg_dev = nullptr;  // +-J torus sign planes (2 x L x W words)
     uint32_t *frozen_dev = nullptr;  // frozen set B as bits (layout of the bit-packed spins)
     uint32_t *mirror[2] = {nullptr, nullptr};  // packed copies of int8 graph spins (LDS-staged kernel)
-    int32_t *cj[2] = {nullptr, nullptr};       // index | J << 24 per CSR entry (LDS-staged kernel)
+    int32_t *cj[2] = {nullptr, nullptr};       // edge words of the LDS-staged kernel (index, row slot, J)
     bool tri = false;                // triangular torus
     std::vector<uint8_t> frozen_host;  // per site, nonzero = frozen
     int ell_k = 0;
@@ -680,13 +680,16 @@ shaken_status init_device(shaken_ctx *c, const shaken_opts *o, HostLayout &hl) {
             CHK(dalloc(&c->mirror[0], mw));
             CHK(dalloc(&c->mirror[1], mw));
         }
-        // the LDS-staged kernel's edge words: index (< 2^24) and J together,
-        // read four at a time from aligned positions
+        // the LDS-staged kernel's edge words: index (< 2^21), the slot of the
+        // edge's row vertex in its group of four (v & 3) and J, read four at a
+        // time from aligned positions
         for (int h = 0; h < 2; ++h) {
             const size_t mh = (size_t)rp[h][(size_t)c->n];
             std::vector<int32_t> cj((mh + 3) / 4 * 4 + 16, 0);
-            for (size_t e = 0; e < mh; ++e)
-                cj[e] = (int32_t)(((uint32_t)col[h][e] & 0xFFFFFFu) | ((uint32_t)(uint8_t)jw[h][e] << 24));
+            for (int v = 0; v < c->n; ++v)
+                for (int32_t e = rp[h][(size_t)v]; e < rp[h][(size_t)v + 1]; ++e)
+                    cj[(size_t)e] = (int32_t)(((uint32_t)col[h][(size_t)e] & 0x1FFFFFu) | ((uint32_t)(v & 3) << 21) |
+                                              ((uint32_t)(uint8_t)jw[h][(size_t)e] << 24));
             CHK(dalloc(&c->cj[h], cj.size()));
             HIPCHK(hipMemcpyAsync(c->cj[h], cj.data(), cj.size() * 4, hipMemcpyHostToDevice, c->stream));
             HIPCHK(hipStreamSynchronize(c->stream));

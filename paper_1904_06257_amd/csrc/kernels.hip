@@ -793,6 +793,7 @@ constexpr int kLdsGraphWords = 36864;                 // 144 KiB: up to 1,179,64
 constexpr int kLdsGraphStage = kLdsGraphWords / 4 / kLdsGraphBlock;  // uint4 loads per lane
 constexpr int kLdsGraphClasses = 256;
 constexpr int kLdsEdgeChunk = 12;
+static_assert(32 * kLdsGraphWords <= (1 << 21), "edge words hold 21-bit vertex indices");
 
 // Loads through the global address space (not flat), unconditional at
 // clamped indices: a load under a divergent branch makes the compiler wait
@@ -910,7 +911,7 @@ __global__ __launch_bounds__(kLdsGraphBlock) void k_graph_lds(const ChainDesc *_
                                              (__attribute__((address_space(3))) void *)(sh_sp4 + base), 16, 0, 0);
     }
     // 3. the first chunk of the lane's edges (needs the row bounds): twelve
-    // edge words, index | J << 24, from four aligned 16-byte loads (the
+    // edge words (index, row slot, J) from four aligned 16-byte loads (the
     // array is padded past them), which covers four vertices of degree up
     // to three in one round trip and few cache-line requests
     __builtin_amdgcn_sched_barrier(0);
@@ -933,13 +934,36 @@ __global__ __launch_bounds__(kLdsGraphBlock) void k_graph_lds(const ChainDesc *_
         cl[j] = (int)((c4 >> (8 * j)) & 0xFFu);
     }
     int S0 = 0, S1 = 0, S2 = 0, S3 = 0;
-    if (active) {
+    const int cnt = last + 1 - e_first;   // the lane's edges
+    if (active && cnt <= kLdsEdgeChunk) {
+        // all of them in the window: each edge adds J sigma_y + 128 into the
+        // 16-bit field of its row vertex (the slot in the word), so the four
+        // sums cost one shift and one add per edge; no field can carry (at
+        // most twelve terms below 2^9)
+        uint64_t acc = 0;
+#pragma unroll
+        for (int k = 0; k < kLdsEdgeChunk; ++k) {
+            if (k < cnt) {
+                const uint32_t w = (uint32_t)ew[k];
+                const uint32_t c = w & 0x1FFFFFu;
+                const int jv = (int)w >> 24;
+                const int t = ((sh_sp[c >> 5] >> (c & 31)) & 1u) ? jv : -jv;
+                acc += (uint64_t)(uint32_t)(t + 128) << ((w >> 17) & 0x30u);
+            }
+        }
+        S0 = (int)(acc & 0xFFFFu) - 128 * (rpv[1] - rpv[0]);
+        S1 = (int)((acc >> 16) & 0xFFFFu) - 128 * (rpv[2] - rpv[1]);
+        S2 = (int)((acc >> 32) & 0xFFFFu) - 128 * (rpv[3] - rpv[2]);
+        S3 = (int)((acc >> 48) & 0xFFFFu) - 128 * (rpv[4] - rpv[3]);
+    } else if (active) {
+        // longer edge ranges: window after window, each edge assigned to its
+        // vertex by the row bounds
         for (int base = rpv[0]; base <= last; base += kLdsEdgeChunk) {
             if (base != rpv[0]) lds_edge_window(d.cj[half], base, ew);
 #pragma unroll
             for (int k = 0; k < kLdsEdgeChunk; ++k) {
                 const int e = base + k;
-                const int c = ew[k] & 0xFFFFFF;
+                const int c = ew[k] & 0x1FFFFF;
                 const int sv = ((sh_sp[c >> 5] >> (c & 31)) & 1u) ? 1 : -1;
                 const int t = e <= last ? (ew[k] >> 24) * sv : 0;
                 S0 += e < rpv[1] ? t : 0;

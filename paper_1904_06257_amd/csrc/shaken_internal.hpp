@@ -92,9 +92,9 @@ struct ChainDesc {
     // copy of spin[i] (one bit per vertex, layout of the bit-packed spins),
     // written by that kernel beside its int8 output; null otherwise
     uint32_t *mirror[2];
-    // graphs the LDS-staged kernel takes (n < 2^24): each CSR entry as one
-    // word, (neighbour index) | J << 24, padded by 16 zero entries past a
-    // multiple of four; null otherwise
+    // graphs the LDS-staged kernel takes (n < 2^21): each CSR entry as one
+    // word, index | (v & 3) << 21 | J << 24 with v the entry's row vertex,
+    // padded by 16 zero entries past a multiple of four; null otherwise
     const int32_t *cj[2];
 };
 
