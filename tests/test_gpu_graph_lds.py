@@ -193,3 +193,26 @@ def test_lds_kernel_noalloc_sweep(sk):
     assert np.array_equal(a.spins(), b.spins())
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("fmt", ["int8", "bitpacked"])
+def test_lds_kernel_extreme_couplings(sk, fmt):
+    """Couplings at the ends of the int8 range (-128 and 127 included) on a
+    3-regular graph (every lane's edges in one window: the packed per-vertex
+    sums) and on an Erdos-Renyi graph of mean degree 12 (lanes with more
+    edges than one window); the threshold table is then too large for LDS."""
+    rng = np.random.Generator(np.random.PCG64(17))
+    vals = np.array([-128, -127, -64, -1, 1, 63, 126, 127], dtype=np.int8)
+    for inst, T in [(_instance(100_002, 41), 8),
+                    (synth.random_oriented_graph(2001, 0.006, 43, jmax=1, n_classes=3, lam_scale=0.5), 12)]:
+        _print_case("graph lds extreme J", inst.n, fmt)
+        J = rng.choice(vals, size=inst.J.shape[0]).astype(np.int8)
+        g = oracle.Graph(inst.n, inst.src, inst.dst, J, inst.cls, inst.lam_values)
+        ch = sk.Chain.graph(inst.n, inst.src, inst.dst, J=J, lam_values=inst.lam_values, lam_class=inst.cls,
+                            q=2.0, beta=0.01, seed=6, replica=1, fmt=fmt, graph_kernel="lds")
+        want, ej, plus = oracle.graph_run(g, oracle.graph_init_random(inst.n, 6, 1), 2.0, 0.01, 6, 1, T)
+        H, M = ch.sweep(T, log=True)
+        assert np.array_equal(ch.spins(), want)
+        Hw, Mw = _H_M(inst, ej, plus)
+        assert np.array_equal(H, Hw) and np.array_equal(M, Mw)
+        ch.close()
