@@ -105,19 +105,28 @@ constexpr int kQ2Cap = 128;
 constexpr uint32_t kLastWord = 0x80000000u;
 
 // Tail queue in wavefront regions of qcap_w entries, cnt[r] of them used:
-// the total, and the slot of the it-th entry in region order.
-__device__ __forceinline__ int tail_total(const int *cnt, int nwav) {
-    int t = 0;
-    for (int r = 0; r < nwav; ++r) t += cnt[r];
-    return t;
+// the entries in region order.  The region boundaries are read once (the
+// same in every lane); the slot of the it-th entry is then three compares
+// and adds, with no loop and no LDS read per entry.
+struct TailMap {
+    int total;             // entries queued in all regions
+    int b1, b2, b3;        // first entry of regions 1, 2, 3 (past the total if absent)
+    int d1, d2, d3;        // slot offset added on entering regions 1, 2, 3
+};
+__device__ __forceinline__ TailMap tail_map(const int *cnt, int nwav, int qcap_w) {
+    const int c0 = cnt[0], c1 = nwav > 1 ? cnt[1] : 0, c2 = nwav > 2 ? cnt[2] : 0, c3 = nwav > 3 ? cnt[3] : 0;
+    TailMap m;
+    m.total = c0 + c1 + c2 + c3;
+    m.b1 = nwav > 1 ? c0 : m.total;
+    m.b2 = nwav > 2 ? c0 + c1 : m.total;
+    m.b3 = nwav > 3 ? c0 + c1 + c2 : m.total;
+    m.d1 = qcap_w - c0;
+    m.d2 = qcap_w - c1;
+    m.d3 = qcap_w - c2;
+    return m;
 }
-__device__ __forceinline__ int tail_slot(const int *cnt, int nwav, int qcap_w, int it) {
-    int r = 0;
-    while (r < nwav - 1 && it >= cnt[r]) {
-        it -= cnt[r];
-        ++r;
-    }
-    return r * qcap_w + it;
+__device__ __forceinline__ int tail_slot(const TailMap &m, int it) {
+    return it + (it >= m.b1 ? m.d1 : 0) + (it >= m.b2 ? m.d2 : 0) + (it >= m.b3 ? m.d3 : 0);
 }
 
 // EXT: instantiation for chains with +-J sign planes or a frozen set (the
@@ -263,12 +272,13 @@ __global__ __launch_bounds__(256) void k_torus_bp(const ChainDesc *__restrict__ 
     if ((threadIdx.x & 63) == 0) q_cnt[wv] = min(wq, qcap_w);
     if (FOLD3 && threadIdx.x == 0) q2_cnt = 0;
     __syncthreads();
-    const int Q = tail_total(q_cnt, nwav);
+    const TailMap tm = tail_map(q_cnt, nwav, qcap_w);
+    const int Q = tm.total;
     const uint32_t vlast = bp_valid(L, W, W - 1);
     if constexpr (FOLD3) {
         // stage 1: level group 2 of every queued word
         for (int it = threadIdx.x; it < Q; it += blockDim.x) {
-            const int qs = tail_slot(q_cnt, nwav, qcap_w, it);
+            const int qs = tail_slot(tm, it);
             const uint32_t wf = q_w[qs], w = wf & ~kLastWord;
             const uint32_t vw = (wf & kLastWord) ? vlast : ~0u;
             const uint32_t a = q_a[qs], b = q_b[qs], c = q_c[qs];
@@ -303,7 +313,7 @@ __global__ __launch_bounds__(256) void k_torus_bp(const ChainDesc *__restrict__ 
         }
     } else {
         for (int it = threadIdx.x; it < Q; it += blockDim.x) {
-            const int qs = tail_slot(q_cnt, nwav, qcap_w, it);
+            const int qs = tail_slot(tm, it);
             const uint32_t wf = q_w[qs], w = wf & ~kLastWord;
             const uint32_t vw = (wf & kLastWord) ? vlast : ~0u;
             gword(out, w) = bp_finish<false>(q_a[qs], q_b[qs], q_c[qs], q_und[qs], q_res[qs], vw, w, s, rep, k0,
@@ -470,13 +480,14 @@ __global__ __launch_bounds__(256) void k_tri_bp(const ChainDesc *__restrict__ de
     if ((threadIdx.x & 63) == 0) q_cnt[wv] = min(wq, qcap_w);
     if (FOLD && threadIdx.x == 0) q2_cnt = 0;
     __syncthreads();
-    const int Q = tail_total(q_cnt, nwav);
+    const TailMap tm = tail_map(q_cnt, nwav, qcap_w);
+    const int Q = tm.total;
     const uint32_t vlast = bp_valid(L, W, W - 1);
     if constexpr (FOLD) {
         // stage 1: level group 2 of every queued word; the words still
         // undecided move to the second queue
         for (int it = threadIdx.x; it < Q; it += blockDim.x) {
-            const int qs = tail_slot(q_cnt, nwav, qcap_w, it);
+            const int qs = tail_slot(tm, it);
             const uint32_t wf = q_w[qs], w = wf & ~kLastWord;
             const uint32_t vw = (wf & kLastWord) ? vlast : ~0u;
             const uint32_t a = q_a[qs], b = q_b[qs], e = q_e[qs], c = q_c[qs];
@@ -512,7 +523,7 @@ __global__ __launch_bounds__(256) void k_tri_bp(const ChainDesc *__restrict__ de
         }
     } else {
         for (int it = threadIdx.x; it < Q; it += blockDim.x) {
-            const int qs = tail_slot(q_cnt, nwav, qcap_w, it);
+            const int qs = tail_slot(tm, it);
             const uint32_t wf = q_w[qs], w = wf & ~kLastWord;
             const uint32_t vw = (wf & kLastWord) ? vlast : ~0u;
             gword(out, w) = tri_finish<false>(q_a[qs], q_b[qs], q_e[qs], q_c[qs], q_und[qs], q_res[qs], vw, w, s,
