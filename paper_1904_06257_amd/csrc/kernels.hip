@@ -181,10 +181,14 @@ __global__ __launch_bounds__(256) void k_torus_bp(const ChainDesc *__restrict__ 
     // rows past the side are the buffer's zero padding (no sites)
     uint32_t own[kRows], side[kRows];
     const uint32_t obase = (uint32_t)(r0 * W + wd), sbase = (uint32_t)(r0 * W + wside);
+    // row i of the strip: a scalar base (row offsets are the same in every
+    // lane) plus the lane's byte offsets, so no address arithmetic per load
+    const uint32_t ob4 = obase << 2, sb4 = sbase << 2;
 #pragma unroll
     for (int i = 0; i < kRows; ++i) {
-        own[i] = gload(in, obase + (uint32_t)(i * W));
-        side[i] = gload(in, sbase + (uint32_t)(i * W));
+        const gmem_char *rowb = (const gmem_char *)in + (size_t)i * (size_t)W * 4u;
+        own[i] = *(const gmem_u32 *)(rowb + ob4);
+        side[i] = *(const gmem_u32 *)(rowb + sb4);
     }
     uint32_t halo = 0;
     if (live) {
@@ -396,10 +400,14 @@ __global__ __launch_bounds__(256) void k_tri_bp(const ChainDesc *__restrict__ de
     // rows past the side are the buffer's zero padding (no sites)
     uint32_t own[kRows], side[kRows];
     const uint32_t obase = (uint32_t)(r0 * W + wd), sbase = (uint32_t)(r0 * W + wside);
+    // row i of the strip: a scalar base (row offsets are the same in every
+    // lane) plus the lane's byte offsets, so no address arithmetic per load
+    const uint32_t ob4 = obase << 2, sb4 = sbase << 2;
 #pragma unroll
     for (int i = 0; i < kRows; ++i) {
-        own[i] = gload(in, obase + (uint32_t)(i * W));
-        side[i] = gload(in, sbase + (uint32_t)(i * W));
+        const gmem_char *rowb = (const gmem_char *)in + (size_t)i * (size_t)W * 4u;
+        own[i] = *(const gmem_u32 *)(rowb + ob4);
+        side[i] = *(const gmem_u32 *)(rowb + sb4);
     }
     uint32_t halo = 0, halo_side = 0;
     if (live) {
