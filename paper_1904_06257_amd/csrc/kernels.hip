@@ -1010,6 +1010,22 @@ __global__ __launch_bounds__(kLdsGraphBlock) void k_graph_lds(const ChainDesc *_
         }
         up |= (fzw >> (v0 & 31)) & 0xFu;
     }
+    // the observables first: their atomics are then in flight with the
+    // stores instead of after them
+    if (OBS) {
+        int64_t *lg = log_part(d, slot, blockIdx.x);
+        const int lane = tid & 63, wv = tid >> 6;
+        e_acc = wave_sum(e_acc);
+        if (lane == 0) sh_e[wv] = e_acc;
+        __syncthreads();
+        if (tid == 0) {
+            long long se = 0;
+            for (int i = 0; i < kLdsGraphBlock / 64; ++i) se += sh_e[i];
+            if (se) atomicAdd((unsigned long long *)&lg[0], (unsigned long long)se);
+        }
+        for (int i = tid; i < ncls; i += kLdsGraphBlock)
+            if (sh_plus[i]) atomicAdd((unsigned long long *)&lg[1 + i], (unsigned long long)sh_plus[i]);
+    }
     // stores through the global address space (flat stores would also
     // count against the LDS wait counter)
     if (!BP && active) {
@@ -1030,20 +1046,6 @@ __global__ __launch_bounds__(kLdsGraphBlock) void k_graph_lds(const ChainDesc *_
         val |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)val, 0x112, 0xF, 0xF, true);   // row_shr:2
         val |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)val, 0x114, 0xF, 0xF, true);   // row_shr:4
         if ((q4 & 7) == 7 && 4 * (q4 & ~7) < n) gst<uint32_t>(bits_out, q4 >> 3, val);
-    }
-    if (OBS) {
-        int64_t *lg = log_part(d, slot, blockIdx.x);
-        const int lane = tid & 63, wv = tid >> 6;
-        e_acc = wave_sum(e_acc);
-        if (lane == 0) sh_e[wv] = e_acc;
-        __syncthreads();
-        if (tid == 0) {
-            long long se = 0;
-            for (int i = 0; i < kLdsGraphBlock / 64; ++i) se += sh_e[i];
-            if (se) atomicAdd((unsigned long long *)&lg[0], (unsigned long long)se);
-        }
-        for (int i = tid; i < ncls; i += kLdsGraphBlock)
-            if (sh_plus[i]) atomicAdd((unsigned long long *)&lg[1 + i], (unsigned long long)sh_plus[i]);
     }
 }
 
