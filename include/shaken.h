@@ -322,7 +322,12 @@ typedef struct shaken_batch_opts {
                               on the first call and keep the fastest (grid:
                               the block size of every group; persistent: the
                               number of resident workgroups, on trial runs
-                              after which every configuration is restored)   */
+                              after which every configuration is restored);
+                              2: as 1, but a batch of the same shape (device,
+                              and every chain's kind, format, sizes, table,
+                              couplings, field classes and layout) measured
+                              earlier in this process reuses that result
+                              without measuring; other values: SHAKEN_EINVAL */
     int32_t record;        /* log H and M of every chain at every full step  */
     void *stream;          /* hipStream_t; NULL = the first chain's stream   */
     int32_t track;         /* persistent strategy: keep, per chain, H of the
@@ -407,7 +412,8 @@ shaken_status shaken_batch_info(shaken_batch *b, int32_t *strategy, double *last
  *               that serves every later call whatever its n_full);
  *   log_allocs: device allocations of log space (a recorded sweep longer than
  *               any before it, beyond opts.log_reserve);
- *   autotunes:  autotuning passes (the first sweep with opts.autotune);
+ *   autotunes:  autotuning passes that measured (the first sweep with
+ *               opts.autotune; none when autotune = 2 found the shape);
  *   uploads:    refreshes of the device chain descriptors (log space moved,
  *               parameters changed, or a member's spin buffers swapped by
  *               shaken_set_half_step).

@@ -415,7 +415,7 @@ class Batch:
     def __init__(self, chains, strategy="auto", use_hipgraph=False, autotune=False,
                  record=False, stream=None, track=False, log_reserve=0):
         self.chains = list(chains)
-        o = shaken_batch_opts(_STRAT[strategy], int(use_hipgraph), int(autotune), int(record),
+        o = shaken_batch_opts(_STRAT[strategy], int(use_hipgraph), _autotune(autotune), int(record),
                               _stream_handle(stream), int(track), int(log_reserve))
         arr = (_vp * len(self.chains))(*[c.handle.value for c in self.chains])
         h = _vp()
@@ -516,6 +516,15 @@ class RunOutput:
         self.__dict__.update(kw)
 
 
+def _autotune(a):
+    """False / True / "cached" -> 0 / 1 / 2 (opts.autotune)"""
+    if a == "cached":
+        return 2
+    if isinstance(a, str):
+        raise ValueError("autotune: False, True or 'cached'")
+    return int(bool(a))
+
+
 def batch_run(chains, n_full, schedule="none", chunk_sweeps=0, beta0=1.0, beta1=1.0, q=1.0, mlp=None,
               strategy="auto", use_hipgraph=False, autotune=False, best_spins=False, energies=True,
               stream=None):
@@ -527,7 +536,7 @@ def batch_run(chains, n_full, schedule="none", chunk_sweeps=0, beta0=1.0, beta1=
     kind = _SCHED[schedule]
     if n < 1:
         raise ValueError("batch_run needs at least one chain")
-    o = shaken_batch_opts(_STRAT[strategy], int(use_hipgraph), int(autotune), 0, _stream_handle(stream), 0, 0)
+    o = shaken_batch_opts(_STRAT[strategy], int(use_hipgraph), _autotune(autotune), 0, _stream_handle(stream), 0, 0)
     sc = shaken_schedule(kind, int(chunk_sweeps), float(beta0), float(beta1), float(q),
                          None if mlp is None else mlp.handle)
     chunks = 0 if schedule == "none" or chunk_sweeps < 1 else int(n_full) // int(chunk_sweeps)

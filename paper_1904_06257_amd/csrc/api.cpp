@@ -11,8 +11,10 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <new>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 using namespace shaken;
@@ -1347,11 +1349,66 @@ shaken_status time_replay(shaken_batch *b, TrialGraph &t, float *ms) {
 constexpr float kWarmMs = 40.0f;
 constexpr int kWarmMaxTrials = 400;
 
+// Launch shapes the autotuners measured, kept for the process (opts.autotune
+// = 2 reuses them).  The key is the device and every chain's shape: kind,
+// format, lattice, sizes, table folding, sign planes, frozen set, field
+// classes, graph layout and the kernel the chain may run on.
+std::mutex g_tune_mu;
+std::unordered_map<std::string, int> g_tune_cache;
+
+std::string chain_shape(const shaken_ctx *c, const ChainDesc &d) {
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "%d.%d.%d.%d.%d.%lld.%d.%d.%d.%d.%d.%d.%d.%d.%d;", d.kind, d.format, d.tri, d.L,
+                  d.n, (long long)c->m, d.fold3, d.jneg != nullptr, d.frozen != nullptr, d.ncls, d.smax, d.ell_k,
+                  d.pell != nullptr, d.cj != nullptr, c->block);
+    return buf;
+}
+
+std::string tune_key(const shaken_batch *b, const char *what, const std::vector<int> &members) {
+    std::string k = std::string(what) + "@" + std::to_string(b->device) + ":";
+    for (int i : members) k += chain_shape(b->ctx[(size_t)i], b->ctx[(size_t)i]->hd);
+    return k;
+}
+
+bool tune_lookup(const std::string &key, int *out) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it == g_tune_cache.end()) return false;
+    *out = it->second;
+    return true;
+}
+
+void tune_store(const std::string &key, int v) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = v;
+}
+
 shaken_status batch_autotune(shaken_batch *b) {
     const uint32_t s = b->ctx[0]->s;
+    // shapes already measured in this process (autotune = 2)
+    std::vector<std::string> keys;
+    bool all_cached = true;
+    for (auto &g : b->groups) {
+        keys.push_back(tune_key(b, "grid", g.members));
+        int blk = 0;
+        if (b->autotune == 2 && tune_lookup(keys.back(), &blk)) continue;
+        all_cached = false;
+    }
+    if (all_cached) {
+        for (size_t k = 0; k < b->groups.size(); ++k) (void)tune_lookup(keys[k], &b->groups[k].block);
+        b->tuned = true;
+        return SHAKEN_OK;
+    }
     CHK(batch_pack_mirrors(b, s, true));
     const int reps = 10;
+    size_t gi = 0;
     for (auto &g : b->groups) {
+        const std::string &key = keys[gi++];
+        int cached = 0;
+        if (b->autotune == 2 && tune_lookup(key, &cached)) {
+            g.block = cached;
+            continue;
+        }
         std::vector<int> cands{64, 128, 256};
         if (group_lds_fits(g)) cands.push_back(kLdsGraphBlock);
         std::vector<TrialGraph> tg(cands.size());
@@ -1380,6 +1437,7 @@ shaken_status batch_autotune(shaken_batch *b) {
             }
         }
         g.block = best_b;
+        tune_store(key, best_b);
     }
     b->tuned = true;
     b->n_autotunes += 1;
@@ -1449,6 +1507,15 @@ shaken_status batch_build_pgraph(shaken_batch *b) {
 // leaves the chains as they were.
 shaken_status batch_autotune_persistent(shaken_batch *b) {
     const int n = (int)b->ctx.size();
+    std::vector<int> all(n);
+    for (int i = 0; i < n; ++i) all[(size_t)i] = i;
+    const std::string key = tune_key(b, "persistent", all);
+    int cached = 0;
+    if (b->autotune == 2 && tune_lookup(key, &cached)) {
+        b->pgrid = cached;
+        b->ptuned = true;
+        return SHAKEN_OK;
+    }
     int ncu = 256;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, b->device) == hipSuccess) ncu = prop.multiProcessorCount;
@@ -1515,6 +1582,7 @@ shaken_status batch_autotune_persistent(shaken_batch *b) {
     b->pgrid = best_g;
     b->ptuned = true;
     b->n_autotunes += 1;
+    tune_store(key, best_g);
     return SHAKEN_OK;
 }
 
@@ -1567,6 +1635,7 @@ shaken_status shaken_batch_create(shaken_batch **out, shaken_ctx *const *ctx, in
     if (o.strategy < SHAKEN_BATCH_AUTO || o.strategy > SHAKEN_BATCH_PERSISTENT)
         return fail(SHAKEN_EINVAL, "unknown batch strategy");
     if (o.log_reserve < 0) return fail(SHAKEN_EINVAL, "log_reserve must be >= 0");
+    if (o.autotune < 0 || o.autotune > 2) return fail(SHAKEN_EINVAL, "autotune must be 0, 1 or 2");
     shaken_batch *b = new (std::nothrow) shaken_batch();
     if (!b) return fail(SHAKEN_ENOMEM, "host allocation failed");
     b->ctx.assign(ctx, ctx + n);

@@ -655,3 +655,47 @@ def test_persistent_hipgraph_and_autotune_equal_eager(sk):
     bc.close()
     for x in a + c:
         x.close()
+
+
+@pytest.mark.parametrize("strategy", ["grid", "persistent"])
+def test_autotune_cached_shapes(sk, strategy):
+    """autotune="cached": the first batch of a shape measures, a second batch
+    of the same shape (fresh chains, same seeds) reuses the result without
+    measuring and runs bit for bit like the first and the oracle; a batch of
+    another shape measures again; autotune values other than 0, 1, 2 are
+    rejected."""
+    T = 6
+    _print_case("autotune cached", strategy)
+    specs = _mixed_specs(T, [16, 100], [1024], seed0=91)
+    a = [_make(sk, sp) for sp in specs]
+    c = [_make(sk, sp) for sp in specs]
+    ba = sk.Batch(a, strategy=strategy, record=True, use_hipgraph=True, autotune="cached")
+    ba.sweep(T)
+    bc = sk.Batch(c, strategy=strategy, record=True, use_hipgraph=True, autotune="cached")
+    bc.sweep(T)
+    assert ba.counters()["autotunes"] <= 1 and bc.counters()["autotunes"] == 0
+    assert ba.launch_shape(0) == bc.launch_shape(0)
+    _, Ma, EJa = ba.logs()
+    _, Mc, EJc = bc.logs()
+    assert np.array_equal(Ma, Mc) and np.array_equal(EJa, EJc)
+    for i, sp in enumerate(specs):
+        assert np.array_equal(c[i].spins().reshape(sp["want"].shape), sp["want"]), i
+        assert np.array_equal(Mc[i], sp["M"]) and np.array_equal(EJc[i], sp["EJ"]), i
+    # another shape measures
+    specs2 = _mixed_specs(2, [48], [1030], seed0=93)
+    d = [_make(sk, sp) for sp in specs2]
+    bd = sk.Batch(d, strategy=strategy, record=True, use_hipgraph=True, autotune="cached")
+    bd.sweep(2)
+    assert bd.counters()["autotunes"] == 1
+    for b in (ba, bc, bd):
+        b.close()
+    import ctypes
+    o = sk.shaken_batch_opts(sk._STRAT[strategy], 0, 3, 0, None, 0, 0)
+    arr = (ctypes.c_void_p * len(a))(*[x.handle.value for x in a])
+    h = ctypes.c_void_p()
+    assert sk._lib.shaken_batch_create(ctypes.byref(h), arr, len(a), ctypes.byref(o)) == sk.SHAKEN_EINVAL
+    assert not h.value
+    with pytest.raises(ValueError):
+        sk.Batch(a, autotune="sometimes")
+    for x in a + c + d:
+        x.close()
