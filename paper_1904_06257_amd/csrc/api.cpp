@@ -140,6 +140,8 @@ struct shaken_ctx {
     uint32_t *frozen_dev = nullptr;  // frozen set B as bits (layout of the bit-packed spins)
     uint32_t *mirror[2] = {nullptr, nullptr};  // packed copies of int8 graph spins (LDS-staged kernel)
     int32_t *cj[2] = {nullptr, nullptr};       // edge words of the LDS-staged kernel (index, row slot, J)
+    uint32_t *e3[2] = {nullptr, nullptr};      // its three slots per vertex (half-degrees <= 3, one |J|)
+    int j0 = 0;                                // that common |J|
     bool tri = false;                // triangular torus
     std::vector<uint8_t> frozen_host;  // per site, nonzero = frozen
     int ell_k = 0;
@@ -179,6 +181,7 @@ void release(shaken_ctx *c) {
         dfree(c->col[h]);
         dfree(c->jw[h]);
         dfree(c->cj[h]);
+        dfree(c->e3[h]);
     }
     dfree(c->cls_dev);
     dfree(c->ell_dev);
@@ -303,7 +306,6 @@ void unpack_rows(const std::vector<uint32_t> &in, int rows, int cols, int W, int
             out[(size_t)r * cols + c] = ((in[(size_t)r * W + (c >> 5)] >> (c & 31)) & 1u) ? 1 : -1;
 }
 
-void pack_torus(const int8_t *in, int L, int W, std::vector<uint32_t> &out) { pack_rows(in, L, L, W, out); }
 void unpack_torus(const std::vector<uint32_t> &in, int L, int W, int8_t *out) { unpack_rows(in, L, L, W, out); }
 
 // the spins of a context as bit-packed rows: (rows, cols, words per row)
@@ -696,6 +698,37 @@ shaken_status init_device(shaken_ctx *c, const shaken_opts *o, HostLayout &hl) {
             HIPCHK(hipMemcpyAsync(c->cj[h], cj.data(), cj.size() * 4, hipMemcpyHostToDevice, c->stream));
             HIPCHK(hipStreamSynchronize(c->stream));
         }
+        // three slots per vertex where every half-degree is at most three and
+        // every coupling has one magnitude: the kernel then needs no row
+        // bounds, no window shift and no masks (empty slots read a zero word)
+        int j0 = 0;
+        bool e3ok = c->maxdeg <= 3;
+        for (int h = 0; h < 2 && e3ok; ++h)
+            for (int32_t e = 0; e < rp[h][(size_t)c->n] && e3ok; ++e) {
+                const int a = std::abs((int)jw[h][(size_t)e]);
+                if (j0 == 0) j0 = a;
+                e3ok = a > 0 && a == j0;
+            }
+        if (e3ok) {
+            const uint32_t zw = (uint32_t)graph_lds_max_words() << 7;  // the zero word, bit 0
+            const size_t nq = ((size_t)c->n + 3) / 4;
+            for (int h = 0; h < 2; ++h) {
+                std::vector<uint32_t> e3(nq * 12, zw);
+                for (int v = 0; v < c->n; ++v) {
+                    const int32_t e0 = rp[h][(size_t)v], deg = rp[h][(size_t)v + 1] - e0;
+                    for (int k = 0; k < deg; ++k) {
+                        const uint32_t cv = (uint32_t)col[h][(size_t)(e0 + k)];
+                        e3[(size_t)3 * v + k] = (cv & 31u) | ((cv >> 5) << 7) |
+                                                (jw[h][(size_t)(e0 + k)] < 0 ? 0x80000000u : 0u);
+                    }
+                    e3[(size_t)3 * v] |= (uint32_t)deg << 23;
+                }
+                CHK(dalloc(&c->e3[h], e3.size()));
+                HIPCHK(hipMemcpyAsync(c->e3[h], e3.data(), e3.size() * 4, hipMemcpyHostToDevice, c->stream));
+                HIPCHK(hipStreamSynchronize(c->stream));
+            }
+            c->j0 = j0 > 0 ? j0 : 1;
+        }
     }
     if (!hl.jneg.empty()) {
         CHK(dalloc(&c->jneg_dev, hl.jneg.size()));
@@ -736,6 +769,9 @@ shaken_status init_device(shaken_ctx *c, const shaken_opts *o, HostLayout &hl) {
     d.mirror[1] = c->mirror[1];
     d.cj[0] = c->cj[0];
     d.cj[1] = c->cj[1];
+    d.e3[0] = c->e3[0];
+    d.e3[1] = c->e3[1];
+    d.j0 = c->j0;
     d.log_line = c->line();
     d.log_stride = c->stride();
     for (size_t k = 0; k < c->lam.size() && k < 16; ++k) {
@@ -1358,9 +1394,9 @@ std::unordered_map<std::string, int> g_tune_cache;
 
 std::string chain_shape(const shaken_ctx *c, const ChainDesc &d) {
     char buf[160];
-    std::snprintf(buf, sizeof buf, "%d.%d.%d.%d.%d.%lld.%d.%d.%d.%d.%d.%d.%d.%d.%d;", d.kind, d.format, d.tri, d.L,
+    std::snprintf(buf, sizeof buf, "%d.%d.%d.%d.%d.%lld.%d.%d.%d.%d.%d.%d.%d.%d.%d.%d;", d.kind, d.format, d.tri, d.L,
                   d.n, (long long)c->m, d.fold3, d.jneg != nullptr, d.frozen != nullptr, d.ncls, d.smax, d.ell_k,
-                  d.pell != nullptr, d.cj != nullptr, c->block);
+                  d.pell != nullptr, d.cj[0] != nullptr, d.e3[0] != nullptr, c->block);
     return buf;
 }
 

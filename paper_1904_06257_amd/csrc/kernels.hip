@@ -789,11 +789,6 @@ __global__ __launch_bounds__(256) void k_graph(const ChainDesc *__restrict__ des
     }
 }
 
-// ELL variant (couplings +-1, at most 4 neighbours): a lane loads the slot
-// records of its 4 vertices as one 16-byte load per slot, gathers every
-// neighbour spin at once (empty slots point to the vertex itself) and keeps
-// those of the half being updated.  Two dependent memory levels instead of
-// three (no row pointers).
 // ------------------------------------------- graph, gathers served from LDS
 //
 // Every edge of a half-step gathers one neighbour spin.  From global memory a
@@ -813,6 +808,7 @@ constexpr int kLdsGraphStage = kLdsGraphWords / 4 / kLdsGraphBlock;  // uint4 lo
 constexpr int kLdsGraphClasses = 256;
 constexpr int kLdsEdgeChunk = 12;
 static_assert(32 * kLdsGraphWords <= (1 << 21), "edge words hold 21-bit vertex indices");
+static_assert(kLdsGraphWords < (1 << 16), "three-slot words hold 16-bit word indices");
 
 // Loads through the global address space (not flat), unconditional at
 // clamped indices: a load under a divergent branch makes the compiler wait
@@ -854,9 +850,13 @@ __device__ __forceinline__ void lds_edge_window(const int32_t *cj, int e0, int (
     for (int k = 0; k < kLdsEdgeChunk; ++k) ew[k] = (w1[k + 1] & m1) | (w1[k] & ~m1);
 }
 
-template <bool OBS, bool BP>
+// E3: the three-slot layout (half-degrees at most three, couplings of one
+// magnitude): each lane loads its twelve slots from a fixed position, and a
+// slot costs one LDS read and four instructions with no edge test.
+template <bool OBS, bool BP, bool E3>
 __global__ __launch_bounds__(kLdsGraphBlock) void k_graph_lds(const ChainDesc *__restrict__ descs, StepArgs sa) {
-    __shared__ gl_u32x4 sh_sp4[kLdsGraphWords / 4];
+    // the configuration, and one group of zero words past it (E3's empty slots)
+    __shared__ gl_u32x4 sh_sp4[kLdsGraphWords / 4 + 1];
     __shared__ uint64_t sh_lut[kLdsLut];
     __shared__ int sh_plus[kLdsGraphClasses];
     __shared__ int sh_e[kLdsGraphBlock / 64];
@@ -884,13 +884,25 @@ __global__ __launch_bounds__(kLdsGraphBlock) void k_graph_lds(const ChainDesc *_
     const bool lut_lds = nlut <= kLdsLut;
     if (OBS)   // (first: later, its stores would wait for the loads below)
         for (int i = tid; i < ncls; i += kLdsGraphBlock) sh_plus[i] = 0;
-    // 1. row bounds, classes, the lane's threshold entry and frozen bits
-    // (every load of steps 1-3 unconditional, at clamped indices: a load
-    // under a branch makes the compiler wait for all loads before the next
-    // dependent one)
-    const gl_i32x4 r4 = gld<gl_i32x4>(d.rowptr[half], va >> 2);
-    const int rp4 = gld<int32_t>(d.rowptr[half], va + 4);
-    const int rpv[5] = {r4.x, r4.y, r4.z, r4.w, rp4};
+    if (E3 && tid == 0) sh_sp4[kLdsGraphWords / 4] = gl_u32x4{0u, 0u, 0u, 0u};
+    // 1. row bounds (E3: the lane's twelve slots), classes, the lane's
+    // threshold entry and frozen bits (every load of steps 1-3
+    // unconditional, at clamped indices: a load under a branch makes the
+    // compiler wait for all loads before the next dependent one)
+    int rpv[5] = {0, 0, 0, 0, 0};
+    gl_u32x4 sl[3];
+    if constexpr (E3) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) sl[i] = gld<gl_u32x4>(d.e3[half], 3 * (int64_t)(va >> 2) + i);
+    } else {
+        const gl_i32x4 r4 = gld<gl_i32x4>(d.rowptr[half], va >> 2);
+        const int rp4 = gld<int32_t>(d.rowptr[half], va + 4);
+        rpv[0] = r4.x;
+        rpv[1] = r4.y;
+        rpv[2] = r4.z;
+        rpv[3] = r4.w;
+        rpv[4] = rp4;
+    }
     const uint32_t c4 = gld<uint32_t>(d.cls, va >> 2);
     const uint64_t lutv = gld<uint64_t>(d.lut, min(tid, nlut - 1));
     // (no frozen set: a valid word of the class bytes, discarded)
@@ -904,7 +916,7 @@ __global__ __launch_bounds__(kLdsGraphBlock) void k_graph_lds(const ChainDesc *_
     // for here, before the loads into LDS are issued)
     __builtin_amdgcn_sched_barrier(0);
     const int e_first = rpv[0], last = rpv[4] - 1;
-    asm volatile("" ::"v"(e_first), "v"(last));
+    if constexpr (!E3) asm volatile("" ::"v"(e_first), "v"(last));
     __builtin_amdgcn_sched_barrier(0);
     // 2. the configuration, coalesced, straight into LDS (global_load_lds:
     // lane l of a wavefront loads 16 bytes into the wavefront's 1 KiB LDS
@@ -935,7 +947,7 @@ __global__ __launch_bounds__(kLdsGraphBlock) void k_graph_lds(const ChainDesc *_
     // to three in one round trip and few cache-line requests
     __builtin_amdgcn_sched_barrier(0);
     int ew[kLdsEdgeChunk];
-    lds_edge_window(d.cj[half], e_first, ew);
+    if constexpr (!E3) lds_edge_window(d.cj[half], e_first, ew);
     // 4. this wavefront's direct loads have landed (vector memory counter),
     // then the barrier: every lane sees the whole configuration
     __builtin_amdgcn_s_waitcnt(0);
@@ -954,7 +966,32 @@ __global__ __launch_bounds__(kLdsGraphBlock) void k_graph_lds(const ChainDesc *_
     }
     int S0 = 0, S1 = 0, S2 = 0, S3 = 0;
     const int cnt = last + 1 - e_first;   // the lane's edges
-    if (active && cnt <= kLdsEdgeChunk) {
+    if constexpr (E3) {
+        // all twelve LDS reads first (every slot names a word: a vertex's or
+        // the zero word), then per slot the neighbour's bit xor the sign of
+        // J: the count of edges with J sigma_y > 0, so that the field is
+        // j0 (2 count - degree); vertices past n have only empty slots.  The
+        // bit extract reads the low five bits of its offset operand only, so
+        // the slot word itself is the offset.
+        const uint32_t w[12] = {sl[0].x, sl[0].y, sl[0].z, sl[0].w, sl[1].x, sl[1].y,
+                                sl[1].z, sl[1].w, sl[2].x, sl[2].y, sl[2].z, sl[2].w};
+        uint32_t x[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k)
+            x[k] = *(const uint32_t *)((const char *)sh_sp4 + __builtin_amdgcn_ubfe(w[k], 5u, 18u));
+        int Sj[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            uint32_t pc = 0;
+#pragma unroll
+            for (int k = 3 * j; k < 3 * j + 3; ++k) pc += __builtin_amdgcn_ubfe(x[k], w[k], 1u) ^ (w[k] >> 31);
+            Sj[j] = __mul24(d.j0, 2 * (int)pc - (int)__builtin_amdgcn_ubfe(w[3 * j], 23u, 2u));
+        }
+        S0 = Sj[0];
+        S1 = Sj[1];
+        S2 = Sj[2];
+        S3 = Sj[3];
+    } else if (active && cnt <= kLdsEdgeChunk) {
         // all of them in the window: each edge adds J sigma_y + 128 into the
         // 16-bit field of its row vertex (the slot in the word), so the four
         // sums cost one shift and one add per edge; no field can carry (at
@@ -1075,6 +1112,11 @@ __global__ __launch_bounds__(256) void k_pack_mirror(const ChainDesc *__restrict
     mir[w] = bits;
 }
 
+// ELL variant (couplings +-1, at most 4 neighbours): a lane loads the slot
+// records of its 4 vertices as one 16-byte load per slot, gathers every
+// neighbour spin at once (empty slots point to the vertex itself) and keeps
+// those of the half being updated.  Two dependent memory levels instead of
+// three (no row pointers).
 template <bool OBS, int K, bool BP>
 __global__ __launch_bounds__(256) void k_graph_ell(const ChainDesc *__restrict__ descs, StepArgs sa) {
     const ChainDesc &d = descs[blockIdx.y];
@@ -1387,13 +1429,18 @@ hipError_t launch_half_step_grid(const ChainDesc *dev_descs, const ChainDesc *ho
         if (obs) hipLaunchKernelGGL((k_torus_i8<true>), grid, dim3(b), 0, stream, dev_descs, sa);
         else hipLaunchKernelGGL((k_torus_i8<false>), grid, dim3(b), 0, stream, dev_descs, sa);
     } else if (b == kLdsGraphBlock) {
+        // the three-slot layout where every chain of the launch has it
+        bool e3 = true;
+        for (int i = 0; i < nchains; ++i) e3 = e3 && host_descs[i].e3[0] != nullptr;
+#define SHAKEN_LDS(O, BPF, E) hipLaunchKernelGGL((k_graph_lds<O, BPF, E>), grid, dim3(b), 0, stream, dev_descs, sa)
         if (h0.format == FMT_BITPACKED) {
-            if (obs) hipLaunchKernelGGL((k_graph_lds<true, true>), grid, dim3(b), 0, stream, dev_descs, sa);
-            else hipLaunchKernelGGL((k_graph_lds<false, true>), grid, dim3(b), 0, stream, dev_descs, sa);
+            if (e3) { if (obs) SHAKEN_LDS(true, true, true); else SHAKEN_LDS(false, true, true); }
+            else { if (obs) SHAKEN_LDS(true, true, false); else SHAKEN_LDS(false, true, false); }
         } else {
-            if (obs) hipLaunchKernelGGL((k_graph_lds<true, false>), grid, dim3(b), 0, stream, dev_descs, sa);
-            else hipLaunchKernelGGL((k_graph_lds<false, false>), grid, dim3(b), 0, stream, dev_descs, sa);
+            if (e3) { if (obs) SHAKEN_LDS(true, false, true); else SHAKEN_LDS(false, false, true); }
+            else { if (obs) SHAKEN_LDS(true, false, false); else SHAKEN_LDS(false, false, false); }
         }
+#undef SHAKEN_LDS
     } else {
         const size_t shm = obs ? sizeof(int) * (size_t)maxcls : 0;
         int ellk = host_descs[0].ell_k;

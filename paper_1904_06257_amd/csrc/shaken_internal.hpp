@@ -96,6 +96,15 @@ struct ChainDesc {
     // word, index | (v & 3) << 21 | J << 24 with v the entry's row vertex,
     // padded by 16 zero entries past a multiple of four; null otherwise
     const int32_t *cj[2];
+    // graphs the LDS-staged kernel takes whose half-degrees are at most three
+    // and whose couplings share one magnitude j0: three slots per vertex
+    // (vertex v at 3v .. 3v+2), each (index & 31) | (index >> 5) << 7 | J < 0
+    // << 31, so that bits 5-22 are the byte offset of the index's word in
+    // LDS and bits 0-4 its bit; slot 0 also holds the vertex's degree in the
+    // half (bits 23-24); empty slots point at a zero word past the
+    // configuration (word graph_lds_max_words()); null otherwise
+    const uint32_t *e3[2];
+    int32_t j0;
 };
 
 // workgroup size of the LDS-staged graph kernel; as a launch's block size it

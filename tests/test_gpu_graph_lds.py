@@ -216,3 +216,77 @@ def test_lds_kernel_extreme_couplings(sk, fmt):
         Hw, Mw = _H_M(inst, ej, plus)
         assert np.array_equal(H, Hw) and np.array_equal(M, Mw)
         ch.close()
+
+
+def _max_half_degree(inst):
+    return max(np.bincount(inst.dst, minlength=inst.n).max(), np.bincount(inst.src, minlength=inst.n).max())
+
+
+@pytest.mark.parametrize("fmt", ["int8", "bitpacked"])
+def test_lds_kernel_three_slot_layout(sk, fmt):
+    """Graphs whose half-degrees are at most three and whose couplings share
+    one magnitude run on the three-slot layout (twelve slots per lane, empty
+    slots reading a zero word, the field j0 (2 count - degree)): magnitudes
+    2, 127 and 128 with both signs, ragged n, reversed order and a frozen
+    set; then grid batches where every chain has the layout and where one
+    chain lacks it (the launch then takes the row-bound layout for all)."""
+    rng = np.random.Generator(np.random.PCG64(23))
+    base = synth.oriented_instance(100_002, 3, 61, lam_values=(-0.5, 0.0, 0.5), pm_j=True)
+    assert _max_half_degree(base) <= 3
+    m = base.J.shape[0]
+    cases = [(2 * base.J).astype(np.int8),
+             np.where(rng.integers(0, 2, m) == 1, 127, -127).astype(np.int8),
+             np.full(m, -128, dtype=np.int8)]
+    for k, J in enumerate(cases):
+        _print_case("graph lds three-slot", k, fmt)
+        g = oracle.Graph(base.n, base.src, base.dst, J, base.cls, base.lam_values)
+        ch = sk.Chain.graph(base.n, base.src, base.dst, J=J, lam_values=base.lam_values, lam_class=base.cls,
+                            q=1.5, beta=0.05 if k else 0.4, seed=30 + k, replica=k, fmt=fmt, graph_kernel="lds")
+        T = 12
+        want, ej, plus = oracle.graph_run(g, oracle.graph_init_random(base.n, 30 + k, k), 1.5,
+                                          0.05 if k else 0.4, 30 + k, k, T)
+        H, M = ch.sweep(T, log=True)
+        assert np.array_equal(ch.spins(), want), k
+        Hw, Mw = _H_M(base, ej, plus)
+        assert np.array_equal(H, Hw) and np.array_equal(M, Mw), k
+        ch.close()
+    J = cases[0]
+    # reversed order and a frozen set on the same layout
+    _print_case("graph lds three-slot reversed/frozen", fmt)
+    gr = oracle.Graph(base.n, base.dst, base.src, J, base.cls, base.lam_values)
+    ch = sk.Chain.graph(base.n, base.src, base.dst, J=J, lam_values=base.lam_values, lam_class=base.cls,
+                        q=1.5, beta=0.4, seed=40, reversed=True, fmt=fmt, graph_kernel="lds")
+    want, _, _ = oracle.graph_run(gr, oracle.graph_init_random(base.n, 40, 0), 1.5, 0.4, 40, 0, 8, log=False)
+    ch.sweep(8)
+    assert np.array_equal(ch.spins(), want)
+    ch.close()
+    fz = (np.arange(base.n) % 5) == 2
+    g = oracle.Graph(base.n, base.src, base.dst, J, base.cls, base.lam_values)
+    ch = sk.Chain.graph(base.n, base.src, base.dst, J=J, lam_values=base.lam_values, lam_class=base.cls,
+                        q=1.5, beta=0.4, seed=41, frozen=fz, fmt=fmt, graph_kernel="lds")
+    want, ej, plus = oracle.graph_run_frozen(g, oracle.graph_init_random(base.n, 41, 0), fz, 1.5, 0.4, 41, 0, 8)
+    H, M = ch.sweep(8, log=True)
+    assert np.array_equal(ch.spins(), want)
+    Hw, Mw = _H_M(base, ej, plus)
+    assert np.array_equal(H, Hw) and np.array_equal(M, Mw)
+    ch.close()
+    # grid batches: all on the three-slot layout, then mixed with a graph of
+    # mean degree 6 (half-degrees above three)
+    other = synth.random_oriented_graph(3001, 0.002, 45, jmax=1, n_classes=3, lam_scale=0.5)
+    assert _max_half_degree(other) > 3
+    small = synth.oriented_instance(2_050, 3, 62, lam_values=(-0.5, 0.0, 0.5), pm_j=True)
+    for members in ([base, small], [base, other, small]):
+        _print_case("graph lds three-slot batch", len(members), fmt)
+        chains = [_chain(sk, x, 50 + i, replica=i, fmt=fmt, graph_kernel="lds") for i, x in enumerate(members)]
+        b = sk.Batch(chains, strategy="grid", use_hipgraph=True, record=True)
+        b.sweep(10)
+        for i, x in enumerate(members):
+            want, ej, plus = oracle.graph_run(_oracle_graph(x), oracle.graph_init_random(x.n, 50 + i, i), 1.5,
+                                              0.8, 50 + i, i, 10)
+            assert np.array_equal(chains[i].spins(), want), i
+            H, M = b.log(i)
+            Hw, Mw = _H_M(x, ej, plus)
+            assert np.array_equal(H, Hw) and np.array_equal(M, Mw), i
+        b.close()
+        for c in chains:
+            c.close()
