@@ -311,10 +311,13 @@ __device__ __forceinline__ void graph_lds_half(const ChainDesc &d, const uint32_
         __syncthreads();
     }
     int e_acc = 0;
-    // +1 counts per field class: in registers for up to four classes (one LDS
-    // atomic per wavefront and class at the end), else LDS atomics per vertex
-    int pc[4] = {0, 0, 0, 0};
+    // +1 counts per field class: for up to four classes one byte each of a
+    // register (a lane counts at most 4 kPWords * 32 / (4 kPBlock) vertices),
+    // summed per wavefront and class at the end; else LDS atomics per vertex
+    uint32_t pcb = 0;
+    static_assert(kPWords * 32 / kPBlock < 256, "a lane's class counts fit a byte");
     const bool pc_reg = ncls <= 4;
+    const PhiloxShared ps = philox10_shared(s, d.replica, kGraphStream, k0, k1);
     for (int q4 = threadIdx.x; q4 < nq_pad; q4 += kPBlock) {
         uint32_t bits = 0;
         if (q4 < nq) {
@@ -406,36 +409,32 @@ __device__ __forceinline__ void graph_lds_half(const ChainDesc &d, const uint32_
                     for (int j = 0; j < 4; ++j) cl[j] = v0 + j < n ? d.cls[v0 + j] : 0;
                 }
             }
-            // own spins of the four vertices: bits (v0 & 31) .. +3 of one word
-            const uint32_t ownw = src[v0 >> 5] >> (v0 & 31);
+            // own spins of the four vertices: bits (v0 & 31) .. +3 of one word.
+            // Vertices past n (the last group's padding) have no edges in any
+            // layout (S = 0, class 0): they are computed like the others and
+            // their bits masked, with no test per vertex
+            const uint32_t vmask = n - v0 >= 4 ? 0xFu : (1u << (n - v0)) - 1u;
+            const uint32_t ownw = (src[v0 >> 5] >> (v0 & 31)) & vmask;
             if (dst) {
-                const U4 r = philox10((uint32_t)q4, s, d.replica, kGraphStream, k0, k1);
+                const U4 r = philox10_c0((uint32_t)q4, ps, k0, k1);
                 const uint32_t u[4] = {r.x, r.y, r.z, r.w};
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    if (v0 + j < n) {
-                        const int own = (int)((ownw >> j) & 1u);
-                        const uint64_t T = lut[((Sv[j] + smax) * 2 + own) * ncls + cl[j]];
-                        if ((uint64_t)u[j] < T) bits |= 1u << j;
-                    }
+                    const int own = (int)((ownw >> j) & 1u);
+                    const uint64_t T = lut[__mul24((Sv[j] + smax) * 2 + own, ncls) + cl[j]];
+                    bits |= (uint32_t)((uint64_t)u[j] < T) << j;
                 }
-                bits |= frozen4(d, v0);
+                bits = (bits | frozen4(d, v0)) & vmask;
             }
             if (obs) {
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    if (v0 + j < n) {
-                        const bool up = (ownw >> j) & 1u;
-                        e_acc += up ? Sv[j] : -Sv[j];
-                        if (up) {
-                            if (pc_reg) {
-#pragma unroll
-                                for (int k = 0; k < 4; ++k) pc[k] += cl[j] == k;
-                            } else {
-                                atomicAdd(&sh_plus[cl[j]], 1);
-                            }
-                        }
-                    }
+                    const bool up = (ownw >> j) & 1u;
+                    e_acc += up ? Sv[j] : -Sv[j];
+                    if (pc_reg)
+                        pcb += (uint32_t)up << (8 * cl[j]);
+                    else if (up)
+                        atomicAdd(&sh_plus[cl[j]], 1);
                 }
             }
         }
@@ -452,10 +451,9 @@ __device__ __forceinline__ void graph_lds_half(const ChainDesc &d, const uint32_
     if (obs) {
         if (pc_reg) {
             const int lane = threadIdx.x & 63;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int t = wave_sum(pc[k]);
-                if (lane == 0 && k < ncls && t) atomicAdd(&sh_plus[k], t);
+            for (int k = 0; k < ncls; ++k) {
+                const int t = wave_sum((int)((pcb >> (8 * k)) & 0xFFu));
+                if (lane == 0 && t) atomicAdd(&sh_plus[k], t);
             }
         }
         int dummy = 0;

@@ -45,6 +45,57 @@ __device__ __forceinline__ U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, ui
     return U4{c0, c1, c2, c3};
 }
 
+// The same call when c1, c2, c3 and the key are the same in every lane and
+// only c0 varies (the graph kernels' (vertex group, s, replica, stream)):
+// what rounds one and two compute from the shared words alone -- round one's
+// product of c2, round two's product of the new c0 -- is done once per call
+// site with plain integer arithmetic, which the compiler keeps on the scalar
+// unit (philox10_shared), and each lane finishes from its c0 (philox10_c0):
+// two products and three xors for the first two rounds instead of four and
+// four.  philox10_c0(c0, philox10_shared(c1, c2, c3, k0, k1), k0, k1) equals
+// philox10(c0, c1, c2, c3, k0, k1).
+struct PhiloxShared {
+    uint32_t x3;  // c3 ^ k1: round one's xor into the new c2
+    uint32_t x0;  // round one's low c2 product ^ round two's k0: into round two's new c0
+    uint32_t x2;  // high half of round two's c0 product ^ its k1: into round two's new c2
+    uint32_t c3;  // round two's new c3 (low half of that product)
+};
+
+__device__ __forceinline__ PhiloxShared philox10_shared(uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                                        uint32_t k1) {
+    const uint64_t b0 = (uint64_t)c2 * 0xCD9E8D57u;
+    const uint32_t c0r1 = (uint32_t)(b0 >> 32) ^ c1 ^ k0;
+    const uint64_t a1 = (uint64_t)c0r1 * 0xD2511F53u;
+    PhiloxShared p;
+    p.x3 = c3 ^ k1;
+    p.x0 = (uint32_t)b0 ^ (k0 + 0x9E3779B9u);
+    p.x2 = (uint32_t)(a1 >> 32) ^ (k1 + 0xBB67AE85u);
+    p.c3 = (uint32_t)a1;
+    return p;
+}
+
+__device__ __forceinline__ U4 philox10_c0(uint32_t c0, const PhiloxShared &p, uint32_t k0, uint32_t k1) {
+    const uint64_t a0 = (uint64_t)c0 * 0xD2511F53u;
+    const uint64_t b1 = (uint64_t)((uint32_t)(a0 >> 32) ^ p.x3) * 0xCD9E8D57u;
+    uint32_t x0 = (uint32_t)(b1 >> 32) ^ p.x0, x1 = (uint32_t)b1, x2 = (uint32_t)a0 ^ p.x2, x3 = p.c3;
+    k0 += 2u * 0x9E3779B9u;
+    k1 += 2u * 0xBB67AE85u;
+#pragma unroll
+    for (int i = 2; i < 10; ++i) {
+        const uint64_t a = (uint64_t)x0 * 0xD2511F53u;
+        const uint64_t b = (uint64_t)x2 * 0xCD9E8D57u;
+        const uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(b >> 32), x1, k0, 0x96);
+        const uint32_t n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(a >> 32), x3, k1, 0x96);
+        x1 = (uint32_t)b;
+        x3 = (uint32_t)a;
+        x0 = n0;
+        x2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return U4{x0, x1, x2, x3};
+}
+
 // The same call with words x and z of the result xored with a per-lane word
 // v: the last round's key xor takes (k ^ v) in their place, so the xor costs
 // nothing there.  kx0, kx1 = the tenth round's keys xor v.

@@ -725,8 +725,9 @@ __global__ __launch_bounds__(256) void k_graph(const ChainDesc *__restrict__ des
 #pragma unroll
             for (int j = 0; j < 4; ++j) cl[j] = v0 + j < n ? cls[v0 + j] : 0;
         }
-        r = philox10((uint32_t)q4, s, d.replica, kGraphStream, (uint32_t)d.seed,
-                     (uint32_t)(d.seed >> 32));
+        r = philox10_c0((uint32_t)q4,
+                        philox10_shared(s, d.replica, kGraphStream, (uint32_t)d.seed, (uint32_t)(d.seed >> 32)),
+                        (uint32_t)d.seed, (uint32_t)(d.seed >> 32));
         int S0 = 0, S1 = 0, S2 = 0, S3 = 0;
         const int last = rpv[4] - 1;
         for (int base = rpv[0]; base <= last; base += kEdgeChunk) {
@@ -911,7 +912,9 @@ __global__ __launch_bounds__(kLdsGraphBlock) void k_graph_lds(const ChainDesc *_
     // the lane's four uniforms while those loads are in flight
     U4 r = {0u, 0u, 0u, 0u};
     if (active)
-        r = philox10((uint32_t)q4, s, d.replica, kGraphStream, (uint32_t)d.seed, (uint32_t)(d.seed >> 32));
+        r = philox10_c0((uint32_t)q4,
+                        philox10_shared(s, d.replica, kGraphStream, (uint32_t)d.seed, (uint32_t)(d.seed >> 32)),
+                        (uint32_t)d.seed, (uint32_t)(d.seed >> 32));
     // (these loads stay ahead of the rest, and the row bounds are waited
     // for here, before the loads into LDS are issued)
     __builtin_amdgcn_sched_barrier(0);
@@ -1162,8 +1165,10 @@ __global__ __launch_bounds__(256) void k_graph_ell(const ChainDesc *__restrict__
 #pragma unroll
             for (int j = 0; j < 4; ++j) cl[j] = v0 + j < n ? cls[v0 + j] : 0;
         }
-        const U4 r = philox10((uint32_t)q4, s, d.replica, kGraphStream, (uint32_t)d.seed,
-                              (uint32_t)(d.seed >> 32));
+        const U4 r = philox10_c0((uint32_t)q4,
+                                 philox10_shared(s, d.replica, kGraphStream, (uint32_t)d.seed,
+                                                 (uint32_t)(d.seed >> 32)),
+                                 (uint32_t)d.seed, (uint32_t)(d.seed >> 32));
         int sv[K][4];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
