@@ -58,36 +58,50 @@ struct Obs {
     int plus[kPClasses];
 };
 
-// Neighbour planes of word w read in half `phase` (0 = dl, 1 = ur): a the
-// vertical neighbours, b the horizontal ones, e (triangular lattice) the
-// diagonal ones, flipped by the coupling signs where there are any.
+// Row of word w: w / W as a multiply-high by the descriptor's reciprocal
+// wdiv (W = 1: the row is w itself).
+__device__ __forceinline__ int torus_row(int W, uint32_t wdiv, int w) {
+    return W == 1 ? w : (int)__umulhi((uint32_t)w, wdiv);
+}
+
+// Neighbour planes of word w (row r, word column wd) read in half `phase`
+// (0 = dl, 1 = ur): a the vertical neighbours, b the horizontal ones, e
+// (triangular lattice) the diagonal ones, flipped by the coupling signs where
+// there are any.  Every index is selected first and each word then read
+// unconditionally (a read inside a select becomes a branch and a wait).
 template <bool TRI, bool EXT>
-__device__ __forceinline__ void lds_planes(const ChainDesc &d, const uint32_t *src, int w, int phase,
-                                           uint32_t &a, uint32_t &b, uint32_t &e) {
+__device__ __forceinline__ void lds_planes(const ChainDesc &d, const uint32_t *src, int w, int r, int wd,
+                                           int phase, uint32_t &a, uint32_t &b, uint32_t &e) {
     const int L = d.L, W = d.W;
-    const int r = w / W, wd = w - r * W;
     const uint32_t own = src[w];
     const int lastbits = (L - 1) & 31;
     e = 0;
     if (phase == 0) {
-        // down and left neighbours (the in-half); triangular: down-left too
-        const int rd = r == 0 ? L - 1 : r - 1;
-        a = src[rd * W + wd];
-        const uint32_t carry = wd > 0 ? (src[r * W + wd - 1] >> 31)
-                                      : ((src[r * W + W - 1] >> lastbits) & 1u);
-        b = (own << 1) | carry;
+        // down and left neighbours (the in-half); triangular: down-left too.
+        // The left carry is bit 31 of the word to the left, or at the row's
+        // start the last valid bit of the row's last word
+        const int ia = (r == 0 ? L - 1 : r - 1) * W + wd;
+        const int sh = wd > 0 ? 31 : lastbits;
+        a = src[ia];
+        const uint32_t sw = src[wd > 0 ? w - 1 : w + W - 1];
+        b = (own << 1) | ((sw >> sh) & 1u);
         if (TRI) {
-            const uint32_t as = wd > 0 ? src[rd * W + wd - 1] : src[rd * W + W - 1];
-            e = (a << 1) | (wd > 0 ? (as >> 31) : ((as >> lastbits) & 1u));
+            const uint32_t as = src[wd > 0 ? ia - 1 : ia + W - 1];
+            e = (a << 1) | ((as >> sh) & 1u);
         }
     } else {
-        const int ru = r == L - 1 ? 0 : r + 1;
-        a = src[ru * W + wd];
-        b = wd < W - 1 ? ((own >> 1) | (src[r * W + wd + 1] << 31))
-                       : ((own >> 1) | ((src[r * W] & 1u) << lastbits));
-        if (TRI)
-            e = wd < W - 1 ? ((a >> 1) | (src[ru * W + wd + 1] << 31))
-                           : ((a >> 1) | ((src[ru * W] & 1u) << lastbits));
+        // up and right: the right carry is bit 0 of the word to the right
+        // (to bit 31), or at the row's end bit 0 of the row's first word (to
+        // the last valid bit)
+        const int ia = (r == L - 1 ? 0 : r + 1) * W + wd;
+        const int sh = wd < W - 1 ? 31 : lastbits;
+        a = src[ia];
+        const uint32_t sw = src[wd < W - 1 ? w + 1 : w - wd];
+        b = (own >> 1) | ((sw & 1u) << sh);
+        if (TRI) {
+            const uint32_t as = src[wd < W - 1 ? ia + 1 : ia - wd];
+            e = (a >> 1) | ((as & 1u) << sh);
+        }
     }
     if (EXT && !TRI && d.jneg) bp_jflip(d.jneg, L, W, r, wd, phase, a, b);
 }
@@ -108,21 +122,23 @@ template <bool FOLD3, bool TRI, bool EXT>
 __device__ __forceinline__ void torus_lds_half(const ChainDesc &d, const uint32_t *src, uint32_t *dst, uint32_t s,
                                                bool obs, int *sh_red, Obs *o, TailQ *tq) {
     const int L = d.L, W = d.W, nw = L * W;
+    const uint32_t wdiv = d.wdiv;
     const int phase = (int)(s & 1u) ^ d.rev;  // half read: 0 = dl, 1 = ur
     const uint32_t k0 = (uint32_t)d.seed, k1 = (uint32_t)(d.seed >> 32);
     int e_acc = 0, p_acc = 0;
     for (int w = threadIdx.x; w < nw; w += kPBlock) {
         const uint32_t own = src[w];
-        const uint32_t vm = bp_valid(L, W, w - (w / W) * W);
+        const int r = torus_row(W, wdiv, w), wd = w - __mul24(r, W);
+        const uint32_t vm = bp_valid(L, W, wd);
         uint32_t a, b, e;
         if (obs) {
-            lds_planes<TRI, EXT>(d, src, w, 0, a, b, e);
+            lds_planes<TRI, EXT>(d, src, w, r, wd, 0, a, b, e);
             e_acc += d.J * (2 * __popc(vm) - 2 * __popc((own ^ a) & vm) - 2 * __popc((own ^ b) & vm));
             if (TRI) e_acc += d.J * (__popc(vm) - 2 * __popc((own ^ e) & vm));
             p_acc += __popc(own & vm);
         }
         if (!dst) continue;
-        if (!obs || phase == 1) lds_planes<TRI, EXT>(d, src, w, phase, a, b, e);
+        if (!obs || phase == 1) lds_planes<TRI, EXT>(d, src, w, r, wd, phase, a, b, e);
         uint32_t nw_bits;
         if constexpr (FOLD3) {
             uint32_t ob = 0, eq = ~0u;
@@ -165,7 +181,7 @@ __device__ __forceinline__ void torus_lds_half(const ChainDesc &d, const uint32_
         for (int it = threadIdx.x; it < Q; it += kPBlock) {
             const int w = (int)tq->w[it];
             const uint32_t own = src[w];
-            const uint32_t vm = bp_valid(L, W, w - (w / W) * W);
+            const uint32_t vm = bp_valid(L, W, w - __mul24(torus_row(W, wdiv, w), W));
             const uint32_t a = tq->a[it], b = tq->b[it], e = TRI ? tq->e[it] : 0u;
             uint32_t nw_bits;
             if constexpr (TRI)

@@ -579,11 +579,11 @@ __device__ __forceinline__ void bp_jflip(const uint32_t *__restrict__ jn, int L,
     const uint32_t *__restrict__ up = jn;
     const uint32_t *__restrict__ rt = jn + (size_t)L * W;
     if (phase == 0) {
+        // (the indices selected first, each word read unconditionally)
         const int rd = (r == 0) ? L - 1 : r - 1;
         a ^= up[rd * W + wd];
-        const uint32_t carry = wd > 0 ? (rt[r * W + wd - 1] >> 31)
-                                      : ((rt[r * W + W - 1] >> ((L - 1) & 31)) & 1u);
-        b ^= (rt[r * W + wd] << 1) | carry;
+        const uint32_t cw = rt[r * W + (wd > 0 ? wd - 1 : W - 1)];
+        b ^= (rt[r * W + wd] << 1) | ((cw >> (wd > 0 ? 31 : ((L - 1) & 31))) & 1u);
     } else {
         a ^= up[r * W + wd];
         b ^= rt[r * W + wd];
