@@ -70,8 +70,8 @@ __device__ __forceinline__ int torus_row(int W, uint32_t wdiv, int w) {
 // there are any.  Every index is selected first and each word then read
 // unconditionally (a read inside a select becomes a branch and a wait).
 template <bool TRI, bool EXT>
-__device__ __forceinline__ void lds_planes(const ChainDesc &d, const uint32_t *src, int w, int r, int wd,
-                                           int phase, uint32_t &a, uint32_t &b, uint32_t &e) {
+__device__ __forceinline__ void lds_planes(const ChainDesc &d, const uint32_t *src, const uint32_t *jn, int w,
+                                           int r, int wd, int phase, uint32_t &a, uint32_t &b, uint32_t &e) {
     const int L = d.L, W = d.W;
     const uint32_t own = src[w];
     const int lastbits = (L - 1) & 31;
@@ -103,7 +103,7 @@ __device__ __forceinline__ void lds_planes(const ChainDesc &d, const uint32_t *s
             e = (a >> 1) | ((as & 1u) << sh);
         }
     }
-    if (EXT && !TRI && d.jneg) bp_jflip(d.jneg, L, W, r, wd, phase, a, b);
+    if (EXT && !TRI && jn) bp_jflip(jn, L, W, r, wd, phase, a, b);
 }
 
 // Words of a torus half-step whose top eight levels left sites undecided,
@@ -120,7 +120,7 @@ struct TailQ {
 // L x L bit-packed torus held in LDS.
 template <bool FOLD3, bool TRI, bool EXT>
 __device__ __forceinline__ void torus_lds_half(const ChainDesc &d, const uint32_t *src, uint32_t *dst, uint32_t s,
-                                               bool obs, int *sh_red, Obs *o, TailQ *tq) {
+                                               bool obs, int *sh_red, Obs *o, TailQ *tq, const uint32_t *jn) {
     const int L = d.L, W = d.W, nw = L * W;
     const uint32_t wdiv = d.wdiv;
     const int phase = (int)(s & 1u) ^ d.rev;  // half read: 0 = dl, 1 = ur
@@ -132,13 +132,13 @@ __device__ __forceinline__ void torus_lds_half(const ChainDesc &d, const uint32_
         const uint32_t vm = bp_valid(L, W, wd);
         uint32_t a, b, e;
         if (obs) {
-            lds_planes<TRI, EXT>(d, src, w, r, wd, 0, a, b, e);
+            lds_planes<TRI, EXT>(d, src, jn, w, r, wd, 0, a, b, e);
             e_acc += d.J * (2 * __popc(vm) - 2 * __popc((own ^ a) & vm) - 2 * __popc((own ^ b) & vm));
             if (TRI) e_acc += d.J * (__popc(vm) - 2 * __popc((own ^ e) & vm));
             p_acc += __popc(own & vm);
         }
         if (!dst) continue;
-        if (!obs || phase == 1) lds_planes<TRI, EXT>(d, src, w, r, wd, phase, a, b, e);
+        if (!obs || phase == 1) lds_planes<TRI, EXT>(d, src, jn, w, r, wd, phase, a, b, e);
         uint32_t nw_bits;
         if constexpr (FOLD3) {
             uint32_t ob = 0, eq = ~0u;
@@ -260,7 +260,8 @@ __device__ __forceinline__ int64_t uniform_i64(int64_t x) { return (int64_t)unif
 template <bool FOLD3, bool TRI, bool EXT>
 __device__ __attribute__((noinline)) void run_torus(const ChainDesc &d_arg, uint32_t (*buf)[kPWords], uint32_t s0_arg,
                                                     int64_t n_full_arg, int record_arg, int track_arg,
-                                                    int *sh_red, int *sh_flag, Obs &o, TailQ *tq) {
+                                                    int *sh_red, int *sh_flag, Obs &o, TailQ *tq,
+                                                    uint32_t *jn_lds) {
     const ChainDesc &d = uniform_desc(d_arg);
     const uint32_t s0 = (uint32_t)__builtin_amdgcn_readfirstlane(s0_arg);
     const int64_t n_full = uniform_i64(n_full_arg);
@@ -270,21 +271,27 @@ __device__ __attribute__((noinline)) void run_torus(const ChainDesc &d_arg, uint
     const bool obs = record || track;
     const uint32_t *g = (const uint32_t *)d.spin[0];
     for (int w = threadIdx.x; w < nw; w += kPBlock) buf[0][w] = g[w];
+    // +-J: the two coupling-sign planes copied into LDS once for the whole run
+    const uint32_t *jn = nullptr;
+    if (EXT && !TRI && d.jneg) {
+        for (int w = threadIdx.x; w < 2 * nw; w += kPBlock) jn_lds[w] = d.jneg[w];
+        jn = jn_lds;
+    }
     if (threadIdx.x == 0) tq->n = 0;
     __syncthreads();
     int64_t best_h = INT64_MAX, last_h = 0;
     for (int64_t t = 0; t < n_full; ++t) {
         const uint32_t s = s0 + 2u * (uint32_t)t;
-        torus_lds_half<FOLD3, TRI, EXT>(d, buf[0], buf[1], s, obs, sh_red, &o, tq);
+        torus_lds_half<FOLD3, TRI, EXT>(d, buf[0], buf[1], s, obs, sh_red, &o, tq, jn);
         if (obs)
             observe_step(d, o, record ? d.log + t * d.log_stride : nullptr, track, &best_h, &last_h,
                          buf[0], nw, sh_flag);
         __syncthreads();
-        torus_lds_half<FOLD3, TRI, EXT>(d, buf[1], buf[0], s + 1u, false, sh_red, nullptr, tq);
+        torus_lds_half<FOLD3, TRI, EXT>(d, buf[1], buf[0], s + 1u, false, sh_red, nullptr, tq, jn);
         __syncthreads();
     }
     if (obs) {
-        torus_lds_half<FOLD3, TRI, EXT>(d, buf[0], nullptr, s0, true, sh_red, &o, tq);
+        torus_lds_half<FOLD3, TRI, EXT>(d, buf[0], nullptr, s0, true, sh_red, &o, tq, jn);
         observe_step(d, o, record ? d.log + n_full * d.log_stride : nullptr, track, &best_h, &last_h,
                      buf[0], nw, sh_flag);
         if (track && threadIdx.x == 0) {
@@ -572,6 +579,7 @@ __global__ __launch_bounds__(kPBlock, SHAKEN_PWAVES) void k_persistent(const Cha
     __shared__ uint64_t sh_lut[kPLut];
     __shared__ Obs sh_obs;  // observables of the current configuration (thread 0)
     __shared__ TailQ sh_tail;
+    __shared__ uint32_t sh_jn[2 * kPWords];  // +-J torus: its coupling-sign planes
     for (;;) {
         if (threadIdx.x == 0) {
             const int k = atomicAdd(counter, 1);
@@ -587,18 +595,18 @@ __global__ __launch_bounds__(kPBlock, SHAKEN_PWAVES) void k_persistent(const Cha
             const bool ext = d.jneg || d.frozen;
             if (d.tri) {
                 if (d.fold3)
-                    run_torus<true, true, true>(d, buf, s0, n_full, record, track, sh_red, &sh_flag, sh_obs, &sh_tail);
+                    run_torus<true, true, true>(d, buf, s0, n_full, record, track, sh_red, &sh_flag, sh_obs, &sh_tail, sh_jn);
                 else
-                    run_torus<false, true, true>(d, buf, s0, n_full, record, track, sh_red, &sh_flag, sh_obs, &sh_tail);
+                    run_torus<false, true, true>(d, buf, s0, n_full, record, track, sh_red, &sh_flag, sh_obs, &sh_tail, sh_jn);
             } else if (ext) {
                 if (d.fold3)
-                    run_torus<true, false, true>(d, buf, s0, n_full, record, track, sh_red, &sh_flag, sh_obs, &sh_tail);
+                    run_torus<true, false, true>(d, buf, s0, n_full, record, track, sh_red, &sh_flag, sh_obs, &sh_tail, sh_jn);
                 else
-                    run_torus<false, false, true>(d, buf, s0, n_full, record, track, sh_red, &sh_flag, sh_obs, &sh_tail);
+                    run_torus<false, false, true>(d, buf, s0, n_full, record, track, sh_red, &sh_flag, sh_obs, &sh_tail, sh_jn);
             } else if (d.fold3) {
-                run_torus<true, false, false>(d, buf, s0, n_full, record, track, sh_red, &sh_flag, sh_obs, &sh_tail);
+                run_torus<true, false, false>(d, buf, s0, n_full, record, track, sh_red, &sh_flag, sh_obs, &sh_tail, sh_jn);
             } else {
-                run_torus<false, false, false>(d, buf, s0, n_full, record, track, sh_red, &sh_flag, sh_obs, &sh_tail);
+                run_torus<false, false, false>(d, buf, s0, n_full, record, track, sh_red, &sh_flag, sh_obs, &sh_tail, sh_jn);
             }
         } else {
             if (d.pell)
