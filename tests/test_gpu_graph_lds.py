@@ -290,3 +290,35 @@ def test_lds_kernel_three_slot_layout(sk, fmt):
         b.close()
         for c in chains:
             c.close()
+
+
+@pytest.mark.parametrize("fmt", ["int8", "bitpacked"])
+def test_lds_kernel_three_slot_degenerate(sk, fmt):
+    """The three-slot layout with every slot empty (graphs without edges, n = 1
+    and a ragged n) and with half-degrees of at most one (a perfect matching,
+    each pair one coin-oriented edge of coupling +-2): the field is q sigma +
+    lambda alone, or one neighbour's."""
+    rng = np.random.Generator(np.random.PCG64(29))
+    cases = []
+    for n in (1, 4099):
+        cases.append(synth.random_oriented_graph(n, 0.0, 30 + n, jmax=1, n_classes=3, lam_scale=0.5))
+    n = 10_002
+    perm = rng.permutation(n).astype(np.int32)
+    u, v = perm[0::2], perm[1::2]
+    flip = rng.integers(0, 2, n // 2).astype(bool)
+    src, dst = np.where(flip, v, u).astype(np.int32), np.where(flip, u, v).astype(np.int32)
+    J = np.where(rng.integers(0, 2, n // 2) == 1, 2, -2).astype(np.int8)
+    cls = rng.integers(0, 3, n).astype(np.uint8)
+    cases.append(synth.Instance(n, src, dst, J, cls, np.array([-0.5, 0.0, 0.5])))
+    for k, inst in enumerate(cases):
+        _print_case("graph lds three-slot degenerate", inst.n, inst.src.shape[0], fmt)
+        assert inst.src.shape[0] == 0 or _max_half_degree(inst) <= 1
+        g = _oracle_graph(inst)
+        ch = _chain(sk, inst, 70 + k, replica=k, fmt=fmt, graph_kernel="lds")
+        T = 15
+        want, ej, plus = oracle.graph_run(g, oracle.graph_init_random(inst.n, 70 + k, k), 1.5, 0.8, 70 + k, k, T)
+        H, M = ch.sweep(T, log=True)
+        assert np.array_equal(ch.spins(), want), k
+        Hw, Mw = _H_M(inst, ej, plus)
+        assert np.array_equal(H, Hw) and np.array_equal(M, Mw), k
+        ch.close()
