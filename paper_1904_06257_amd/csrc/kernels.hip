@@ -807,6 +807,7 @@ __global__ __launch_bounds__(256) void k_graph(const ChainDesc *__restrict__ des
 constexpr int kLdsGraphWords = 36864;                 // 144 KiB: up to 1,179,648 vertices
 constexpr int kLdsGraphStage = kLdsGraphWords / 4 / kLdsGraphBlock;  // uint4 loads per lane
 constexpr int kLdsGraphClasses = 256;
+constexpr int kPlusCopies = 8;
 constexpr int kLdsEdgeChunk = 12;
 static_assert(32 * kLdsGraphWords <= (1 << 21), "edge words hold 21-bit vertex indices");
 static_assert(kLdsGraphWords < (1 << 16), "three-slot words hold 16-bit word indices");
@@ -882,9 +883,12 @@ __global__ __launch_bounds__(kLdsGraphBlock) void k_graph_lds(const ChainDesc *_
     const int va = active ? v0 : 0;   // row pointers and classes are padded
                                       // to a multiple of four vertices
     const int nlut = (2 * smax + 1) * 2 * ncls;
+    // +1 counts per class in kPlusCopies copies (lane & 7 picks one) where
+    // they fit, so that the lanes of one LDS atomic meet on fewer addresses
+    const int pcopies = ncls * kPlusCopies <= kLdsGraphClasses ? kPlusCopies : 1;
     const bool lut_lds = nlut <= kLdsLut;
     if (OBS)   // (first: later, its stores would wait for the loads below)
-        for (int i = tid; i < ncls; i += kLdsGraphBlock) sh_plus[i] = 0;
+        for (int i = tid; i < ncls * pcopies; i += kLdsGraphBlock) sh_plus[i] = 0;
     if (E3 && tid == 0) sh_sp4[kLdsGraphWords / 4] = gl_u32x4{0u, 0u, 0u, 0u};
     // 1. row bounds (E3: the lane's twelve slots), classes, the lane's
     // threshold entry and frozen bits (every load of steps 1-3
@@ -1045,7 +1049,7 @@ __global__ __launch_bounds__(kLdsGraphBlock) void k_graph_lds(const ChainDesc *_
             if (v0 + j < n && (uint64_t)u[j] < T) up |= 1u << j;
             if (OBS && v0 + j < n) {
                 e_acc += own[j] * Sv[j];
-                if (own[j] > 0) atomicAdd(&sh_plus[cl[j]], 1);
+                if (own[j] > 0) atomicAdd(&sh_plus[cl[j] * pcopies + (tid & (pcopies - 1))], 1);
             }
         }
         up |= (fzw >> (v0 & 31)) & 0xFu;
@@ -1063,8 +1067,11 @@ __global__ __launch_bounds__(kLdsGraphBlock) void k_graph_lds(const ChainDesc *_
             for (int i = 0; i < kLdsGraphBlock / 64; ++i) se += sh_e[i];
             if (se) atomicAdd((unsigned long long *)&lg[0], (unsigned long long)se);
         }
-        for (int i = tid; i < ncls; i += kLdsGraphBlock)
-            if (sh_plus[i]) atomicAdd((unsigned long long *)&lg[1 + i], (unsigned long long)sh_plus[i]);
+        for (int i = tid; i < ncls; i += kLdsGraphBlock) {
+            int v = 0;
+            for (int c = 0; c < pcopies; ++c) v += sh_plus[i * pcopies + c];
+            if (v) atomicAdd((unsigned long long *)&lg[1 + i], (unsigned long long)v);
+        }
     }
     // stores through the global address space (flat stores would also
     // count against the LDS wait counter)
