@@ -347,6 +347,7 @@ __device__ __forceinline__ void graph_lds_half(const ChainDesc &d, const uint32_
             const int v0 = 4 * q4;
             int S0 = 0, S1 = 0, S2 = 0, S3 = 0;
             int cl[4];
+            uint32_t pq[4] = {0u, 0u, 0u, 0u};  // packed: the table index's (p, q) bits
             if constexpr (LAY == GL_PACKED) {
                 // packed: one 8-byte record per vertex holds neighbours, the
                 // slots of each half, signs and class (two 16-byte loads per
@@ -364,12 +365,18 @@ __device__ __forceinline__ void graph_lds_half(const ChainDesc &d, const uint32_
                     const uint32_t w0 = src[(lo[j] & 0xFFFFu) >> 5];
                     const uint32_t w1 = src[lo[j] >> 21];
                     const uint32_t w2 = src[(hi[j] & 0xFFFFu) >> 5];
-                    const uint32_t x = ((w0 >> (lo[j] & 31u)) & 1u) |
-                                       (((w1 >> ((lo[j] >> 16) & 31u)) & 1u) << 1) |
-                                       (((w2 >> (hi[j] & 31u)) & 1u) << 2);
+                    // the bit extracts read the low five bits of their offset
+                    // operand only: the record words themselves are the offsets
+                    // of slots 0 and 2
+                    const uint32_t b0 = __builtin_amdgcn_ubfe(w0, lo[j], 1u);
+                    const uint32_t b2 = __builtin_amdgcn_ubfe(w2, hi[j], 1u);
+                    const uint32_t t1 = w1 >> ((lo[j] >> 16) & 31u);
+                    const uint32_t x = (b2 << 2) | (((t1 & 1u) << 1) | b0);
                     const uint32_t sel = (hi[j] >> selsh) & 7u;
                     const uint32_t y = (x ^ (hi[j] >> 22)) & sel;
-                    t[j] = 2 * (int)__popc(y) - (int)__popc(sel);
+                    const uint32_t pc = __popc(y), qc = __popc(sel);
+                    t[j] = 2 * (int)pc - (int)qc;
+                    pq[j] = (pc << 7) | (qc << 5);
                     cl[j] = (int)((hi[j] >> 25) & 15u);
                 }
                 S0 = t[0];
@@ -444,7 +451,11 @@ __device__ __forceinline__ void graph_lds_half(const ChainDesc &d, const uint32_
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const int own = (int)((ownw >> j) & 1u);
-                    const uint64_t T = lut[__mul24((Sv[j] + smax) * 2 + own, ncls) + cl[j]];
+                    // packed: the table is indexed by (p, q, own, class) with
+                    // power-of-two strides (built by run_graph), no multiply
+                    const uint64_t T = LAY == GL_PACKED
+                                           ? lut[pq[j] | ((uint32_t)own << 4) | (uint32_t)cl[j]]
+                                           : lut[__mul24((Sv[j] + smax) * 2 + own, ncls) + cl[j]];
                     bits |= (uint32_t)((uint64_t)u[j] < T) << j;
                 }
                 bits = (bits | frozen4(d, v0)) & vmask;
@@ -503,7 +514,22 @@ __device__ __attribute__((noinline)) void run_graph(const ChainDesc &d_arg, uint
     // the chain's threshold table in LDS when it fits (constant during the call)
     const int nlut = (2 * d.smax + 1) * 2 * d.ncls;
     const uint64_t *lut = d.lut;
-    if (LAY != GL_CSR || nlut <= kPLut) {
+    if constexpr (LAY == GL_PACKED) {
+        // re-indexed for the packed record (couplings +-1, at most three
+        // slots, at most 16 classes): entry ((p * 4 + q) * 2 + own) * 16 +
+        // class holds the threshold of the field S = 2p - q, p of the q slots
+        // of the half having J sigma_y = +1; combinations that cannot occur
+        // (p > q, or |S| beyond the table) stay 0
+        static_assert(kPLut == 4 * 4 * 2 * 16, "the packed table fills the LDS table");
+        for (int i = threadIdx.x; i < kPLut; i += kPBlock) {
+            const int cl = i & 15, own = (i >> 4) & 1, q = (i >> 5) & 3, p = (i >> 7) & 3;
+            const int S = 2 * p - q;
+            uint64_t T = 0;
+            if (cl < d.ncls && p <= q && S >= -d.smax && S <= d.smax)
+                T = d.lut[((S + d.smax) * 2 + own) * d.ncls + cl];
+            sh_lut[i] = T;
+        }
+    } else if (LAY != GL_CSR || nlut <= kPLut) {
         for (int i = threadIdx.x; i < nlut; i += kPBlock) sh_lut[i] = d.lut[i];
         lut = sh_lut;
     }
