@@ -1384,6 +1384,8 @@ shaken_status time_replay(shaken_batch *b, TrialGraph &t, float *ms) {
 // comparison made while the clocks rise favours whichever candidate runs last.
 constexpr float kWarmMs = 40.0f;
 constexpr int kWarmMaxTrials = 400;
+// timed replays per candidate of the grid autotuner (the fastest counts)
+constexpr int kTimedRounds = 3;
 
 // Launch shapes the autotuners measured, kept for the process (opts.autotune
 // = 2 reuses them).  The key is the device and every chain's shape: kind,
@@ -1453,25 +1455,35 @@ shaken_status batch_autotune(shaken_batch *b) {
             CHK(trial_graph(b, g, cands[k], s, reps, tg[k]));
             if (cands[k] == g.block) def = k;
         }
-        // warm phase with the default shape, then one untimed and one timed
-        // replay per candidate
+        // warm phase with the default shape, one untimed replay per
+        // candidate, then kTimedRounds rounds of one timed replay each, the
+        // candidates in turn; each keeps its fastest.  (A replay of a
+        // microsecond-scale launch lasts tens of microseconds, so one
+        // disturbed replay could otherwise decide.)
         float warm = 0;
         for (int k = 0; k < kWarmMaxTrials && warm < kWarmMs; ++k) {
             float ms = 0;
             CHK(time_replay(b, tg[def], &ms));
             warm += ms;
         }
-        float best = 1e30f;
-        int best_b = g.block;
+        std::vector<float> tmin(cands.size(), 1e30f);
         for (size_t k = 0; k < cands.size(); ++k) {
             float ms = 0;
             CHK(time_replay(b, tg[k], &ms));
-            CHK(time_replay(b, tg[k], &ms));
-            if (ms < best) {
-                best = ms;
+        }
+        for (int round = 0; round < kTimedRounds; ++round)
+            for (size_t k = 0; k < cands.size(); ++k) {
+                float ms = 0;
+                CHK(time_replay(b, tg[k], &ms));
+                tmin[k] = std::min(tmin[k], ms);
+            }
+        int best_b = g.block;
+        float best = 1e30f;
+        for (size_t k = 0; k < cands.size(); ++k)
+            if (tmin[k] < best) {
+                best = tmin[k];
                 best_b = cands[k];
             }
-        }
         g.block = best_b;
         tune_store(key, best_b);
     }

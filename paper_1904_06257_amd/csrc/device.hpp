@@ -416,6 +416,44 @@ __device__ __forceinline__ uint32_t fold_finish(const S &sl, uint32_t und, uint3
     return out & vm;
 }
 
+// Groups 3..7 of one word by a quad of lanes (qlane = the lane's place in
+// it, 0..3; all four lanes active, the same word in each): lane i evaluates
+// level group 3 + i for every site in und at once, and the quad's first lane
+// combines the four -- a site takes the outcome of the lowest group that
+// decides it --, finishes the rare sites still undecided after group 6 and
+// passes the word's new spins (masked by vm) to store.  One group's latency
+// instead of a chain of five.
+template <class S, class F>
+__device__ __forceinline__ void fold_quad_finish(const S &sl, uint32_t und, uint32_t res, int qlane,
+                                                 uint32_t vm, uint32_t w, uint32_t s, uint32_t rep,
+                                                 uint32_t k0, uint32_t k1, uint32_t sgn, F &&store) {
+    const int g = 3 + qlane;
+    const U4 r = philox10(w, s, rep, (uint32_t)g, k0, k1);
+    const uint32_t rr[4] = {r.x, r.y, r.z, r.w};
+    uint32_t ug = und, og = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t dd = __builtin_amdgcn_bitop3_b32(rr[k], sl.c(), sl.sel(4 * g + k), kT_xor3);  // u != y
+        og = __builtin_amdgcn_bitop3_b32(og, ug & dd, rr[k], kT_or_andn);
+        ug &= ~dd;
+    }
+    const uint32_t dg = und & ~ug;  // decided within group g
+    // lanes 1..3 of the quad (groups 4..6) to lane 0
+    const uint32_t d4 = (uint32_t)__builtin_amdgcn_mov_dpp((int)dg, 0x55, 0xF, 0xF, false);
+    const uint32_t o4 = (uint32_t)__builtin_amdgcn_mov_dpp((int)og, 0x55, 0xF, 0xF, false);
+    const uint32_t d5 = (uint32_t)__builtin_amdgcn_mov_dpp((int)dg, 0xAA, 0xF, 0xF, false);
+    const uint32_t o5 = (uint32_t)__builtin_amdgcn_mov_dpp((int)og, 0xAA, 0xF, 0xF, false);
+    const uint32_t d6 = (uint32_t)__builtin_amdgcn_mov_dpp((int)dg, 0xFF, 0xF, 0xF, false);
+    const uint32_t o6 = (uint32_t)__builtin_amdgcn_mov_dpp((int)og, 0xFF, 0xF, 0xF, false);
+    if (qlane == 0) {
+        const uint32_t d34 = dg | d4, d345 = d34 | d5;
+        res |= og | (o4 & ~dg) | (o5 & ~d34) | (o6 & ~d345);
+        const uint32_t left = und & ~(d345 | d6);
+        if (left) res = fold_finish<S, 7>(sl, left, res, vm, w, s, rep, k0, k1, sgn);
+        store(res & vm);
+    }
+}
+
 // a whole word on a folded table
 template <class S>
 __device__ __forceinline__ uint32_t fold_word(const S &sl, uint32_t vm, uint32_t w, uint32_t s, uint32_t rep,

@@ -306,45 +306,16 @@ __global__ __launch_bounds__(256) void k_torus_bp(const ChainDesc *__restrict__ 
             }
         }
         __syncthreads();
-        // stage 2: groups 3..6 of the words still undecided, four lanes per
-        // word, each lane one group for all the word's undecided sites at
-        // once (a site takes the result of the first group that decides it);
-        // the quad's first lane combines the four and finishes the rare
-        // sites still undecided with group 7.  One group's latency instead of
-        // a chain of groups in one lane.
+        // stage 2: groups 3..7 of the words still undecided, four lanes per
+        // word (whole quads: 4 Q2 and the block size are multiples of four)
         const int Q2 = min(q2_cnt, kQ2Cap);
-        for (int it = threadIdx.x; it < 4 * Q2; it += blockDim.x) {   // whole quads
-            const int wi = it >> 2, g = 3 + (it & 3);
+        for (int it = threadIdx.x; it < 4 * Q2; it += blockDim.x) {
+            const int wi = it >> 2;
             const uint32_t wf = q2_w[wi], w = wf & ~kLastWord;
-            const uint32_t a = q2_a[wi], b = q2_b[wi], c = q2_c[wi], und = q2_und[wi];
-            const FoldPlanes fp = fold_planes(a, b, c);
-            const U4 r = philox10(w, s, rep, (uint32_t)g, k0, k1);
-            const uint32_t rr[4] = {r.x, r.y, r.z, r.w};
-            uint32_t ug = und, og = 0;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                // level 4g + k, the class words' bit 31 - (4g + k) (per lane)
-                const uint32_t t = fold_select(fp, ft, 31 - (4 * g + k));
-                const uint32_t dd = __builtin_amdgcn_bitop3_b32(rr[k], c, t, kT_xor3);  // u != y
-                og = __builtin_amdgcn_bitop3_b32(og, ug & dd, rr[k], kT_or_andn);
-                ug &= ~dd;
-            }
-            const uint32_t dg = und & ~ug;  // decided within group g
-            // the quad's lanes 1..3 (groups 4..6) to lane 0
-            const uint32_t d4 = (uint32_t)__builtin_amdgcn_mov_dpp((int)dg, 0x55, 0xF, 0xF, false);
-            const uint32_t o4 = (uint32_t)__builtin_amdgcn_mov_dpp((int)og, 0x55, 0xF, 0xF, false);
-            const uint32_t d5 = (uint32_t)__builtin_amdgcn_mov_dpp((int)dg, 0xAA, 0xF, 0xF, false);
-            const uint32_t o5 = (uint32_t)__builtin_amdgcn_mov_dpp((int)og, 0xAA, 0xF, 0xF, false);
-            const uint32_t d6 = (uint32_t)__builtin_amdgcn_mov_dpp((int)dg, 0xFF, 0xF, 0xF, false);
-            const uint32_t o6 = (uint32_t)__builtin_amdgcn_mov_dpp((int)og, 0xFF, 0xF, 0xF, false);
-            if ((it & 3) == 0) {
-                const uint32_t vw = (wf & kLastWord) ? vlast : ~0u;
-                const uint32_t d34 = dg | d4, d345 = d34 | d5;
-                uint32_t res = q2_res[wi] | og | (o4 & ~dg) | (o5 & ~d34) | (o6 & ~d345);
-                const uint32_t left = und & ~(d345 | d6);
-                if (left) res = fold_finish<SqSel, 7>(SqSel{fp, ft}, left, res, vw, w, s, rep, k0, k1, sgn);
-                gword(out, w) = (res & vw) | (EXT ? frozen_word(d, (int)w) : 0u);
-            }
+            const uint32_t vw = (wf & kLastWord) ? vlast : ~0u;
+            fold_quad_finish(SqSel{fold_planes(q2_a[wi], q2_b[wi], q2_c[wi]), ft}, q2_und[wi], q2_res[wi], it & 3, vw,
+                             w, s, rep, k0, k1, sgn,
+                             [&](uint32_t word) { gword(out, w) = word | (EXT ? frozen_word(d, (int)w) : 0u); });
         }
     } else {
         for (int it = threadIdx.x; it < Q; it += blockDim.x) {
@@ -551,14 +522,15 @@ __global__ __launch_bounds__(256) void k_tri_bp(const ChainDesc *__restrict__ de
             }
         }
         __syncthreads();
-        // stage 2: groups 3..7 of the words still undecided
+        // stage 2: groups 3..7 of the words still undecided, four lanes per
+        // word as on the square lattice
         const int Q2 = min(q2_cnt, kQ2Cap);
-        for (int it = threadIdx.x; it < Q2; it += blockDim.x) {
-            const uint32_t wf = q2_w[it], w = wf & ~kLastWord;
+        for (int it = threadIdx.x; it < 4 * Q2; it += blockDim.x) {
+            const int wi = it >> 2;
+            const uint32_t wf = q2_w[wi], w = wf & ~kLastWord;
             const uint32_t vw = (wf & kLastWord) ? vlast : ~0u;
-            gword(out, w) = tri_finish<true, 3>(q2_a[it], q2_b[it], q2_e[it], q2_c[it], q2_und[it], q2_res[it], vw,
-                                                w, s, rep, k0, k1, ts, sgn) |
-                            frozen_word(d, (int)w);
+            fold_quad_finish(tri_sel(q2_a[wi], q2_b[wi], q2_e[wi], q2_c[wi], ts, sgn), q2_und[wi], q2_res[wi], it & 3,
+                             vw, w, s, rep, k0, k1, sgn, [&](uint32_t word) { gword(out, w) = word | frozen_word(d, (int)w); });
         }
     } else {
         for (int it = threadIdx.x; it < Q; it += blockDim.x) {
