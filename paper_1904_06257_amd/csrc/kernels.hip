@@ -98,7 +98,8 @@ __device__ __noinline__ uint32_t bp_finish(uint32_t a, uint32_t b, uint32_t c, u
 constexpr int kQCap = 512;
 // Folded table: words still undecided after level group 2 of the tail move to
 // a second, short queue (about 1 in 15 of the first queue's), so that the rare
-// deeper groups run in one wavefront instead of in all of them.
+// deeper groups run in the few wavefronts those words fill (four lanes per
+// word, one level group each) instead of in all of them.
 constexpr int kQ2Cap = 128;
 // A queued word index carries this flag where the word is the last of its row
 // with bits past the side (its valid-bit mask is the row end's).
