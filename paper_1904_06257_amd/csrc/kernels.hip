@@ -208,7 +208,8 @@ __global__ __launch_bounds__(256) void k_torus_bp(const ChainDesc *__restrict__ 
         // valid sites: nothing undecided, nothing stored
         const bool act = ALIGN ? live : i < nr;
         const uint32_t vmi = act ? vm : 0u;
-        const int widx = (r0 + i) * W + wd;
+        // i * W on the scalar unit (EXT: the sign planes' index shares (r0 + i) * W)
+        const int widx = EXT ? (r0 + i) * W + wd : (int)obase + i * W;
         uint32_t a, b;
         if (phase == 0) {
             a = (i == 0) ? halo : own[i > 0 ? i - 1 : 0];
@@ -424,7 +425,7 @@ __global__ __launch_bounds__(256) void k_tri_bp(const ChainDesc *__restrict__ de
         // valid sites: nothing undecided, nothing stored
         const bool act = ALIGN ? live : i < nr;
         const uint32_t vmi = act ? vm : 0u;
-        const int widx = (r0 + i) * W + wd;
+        const int widx = (int)obase + i * W;   // i * W on the scalar unit
         uint32_t a, b, e;
         if (phase == 0) {
             a = (i == 0) ? halo : own[i > 0 ? i - 1 : 0];
