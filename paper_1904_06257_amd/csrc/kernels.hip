@@ -16,6 +16,8 @@
 // the class masks, and a site drops out of the comparison as soon as its
 // uniform bit differs from its threshold bit.  Thresholds are folded by the
 // sign of h (u < 2^32 - t  <=>  not(~u < t)), so only t <= 2^31 is compared.
+#include <climits>
+
 #include "device.hpp"
 
 namespace shaken {
@@ -133,9 +135,12 @@ __device__ __forceinline__ int tail_slot(const TailMap &m, int it) {
 // EXT: instantiation for chains with +-J sign planes or a frozen set (the
 // plain instantiation reads neither).  ALIGN: every chain's side is a
 // multiple of 32 (no padding bits, whole strips, the wrap-around bit always
-// at bit 31), which spares the per-row masks and selects.
-template <bool OBS, bool FOLD3, bool EXT, bool ALIGN = false>
+// at bit 31), which spares the per-row masks and selects.  FULL (with ALIGN):
+// every chain has exactly as many strips as the grid has lanes, so every
+// lane is live and no row needs its activity select.
+template <bool OBS, bool FOLD3, bool EXT, bool ALIGN = false, bool FULL = false>
 __global__ __launch_bounds__(256) void k_torus_bp(const ChainDesc *__restrict__ descs, StepArgs sa) {
+    static_assert(ALIGN || !FULL, "FULL grids are aligned ones");
     __shared__ uint32_t q_w[kQCap], q_a[kQCap], q_b[kQCap], q_c[kQCap], q_und[kQCap], q_res[kQCap];
     __shared__ int q_cnt[4];  // entries queued per wavefront region
     __shared__ uint32_t q2_w[FOLD3 ? kQ2Cap : 1], q2_a[FOLD3 ? kQ2Cap : 1], q2_b[FOLD3 ? kQ2Cap : 1],
@@ -164,7 +169,7 @@ __global__ __launch_bounds__(256) void k_torus_bp(const ChainDesc *__restrict__ 
     const int qcap_w = kQCap >> (nwav == 4 ? 2 : (nwav == 2 ? 1 : 0)), qbase = wv * qcap_w;
     int wq = 0;  // entries this wavefront has queued (the same in every lane)
     int dis_acc = 0, p_acc = 0;  // disagreeing in-half bonds and +1 sites
-    const bool live = gid < total;
+    const bool live = FULL || gid < total;
     // row block and word column: gid / W as a multiply-high (W = 1: the
     // reciprocal 2^32 does not fit, and gid is the row block itself)
     const int rb = !live ? 0 : (W == 1 ? gid : (int)__umulhi((uint32_t)gid, d.wdiv));
@@ -1397,9 +1402,10 @@ hipError_t launch_half_step_grid(const ChainDesc *dev_descs, const ChainDesc *ho
     if (nchains <= 0) return hipSuccess;
     // the chains of one launch share a kind and a format (the runtime groups them)
     const ChainDesc &h0 = host_descs[0];
-    int maxu = 0, fold = 1, maxcls = 1, jpl = 0, aligned = 1;
+    int maxu = 0, minu = INT_MAX, fold = 1, maxcls = 1, jpl = 0, aligned = 1;
     for (int i = 0; i < nchains; ++i) {
         maxu = maxu > units_of(host_descs[i]) ? maxu : units_of(host_descs[i]);
+        minu = minu < units_of(host_descs[i]) ? minu : units_of(host_descs[i]);
         fold &= host_descs[i].fold3;
         aligned &= host_descs[i].kind == KIND_TORUS && host_descs[i].L % 32 == 0;
         maxcls = maxcls > host_descs[i].ncls ? maxcls : host_descs[i].ncls;
@@ -1434,6 +1440,10 @@ hipError_t launch_half_step_grid(const ChainDesc *dev_descs, const ChainDesc *ho
             // launch skip them)
             if (obs) { if (fold) SHAKEN_BP(true, true, true); else SHAKEN_BP(true, false, true); }
             else { if (fold) SHAKEN_BP(false, true, true); else SHAKEN_BP(false, false, true); }
+        } else if (fold && aligned && minu == maxu && maxu % b == 0) {
+            // every lane of the grid is a strip of every chain
+            if (obs) hipLaunchKernelGGL((k_torus_bp<true, true, false, true, true>), grid, dim3(b), 0, stream, dev_descs, sa);
+            else hipLaunchKernelGGL((k_torus_bp<false, true, false, true, true>), grid, dim3(b), 0, stream, dev_descs, sa);
         } else if (fold && aligned) {
             if (obs) hipLaunchKernelGGL((k_torus_bp<true, true, false, true>), grid, dim3(b), 0, stream, dev_descs, sa);
             else hipLaunchKernelGGL((k_torus_bp<false, true, false, true>), grid, dim3(b), 0, stream, dev_descs, sa);
