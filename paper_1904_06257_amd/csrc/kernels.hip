@@ -362,8 +362,9 @@ __device__ __noinline__ uint32_t tri_finish(uint32_t a, uint32_t b, uint32_t e, 
     }
 }
 
-template <bool OBS, bool FOLD, bool ALIGN = false>
+template <bool OBS, bool FOLD, bool ALIGN = false, bool FULL = false>
 __global__ __launch_bounds__(256) void k_tri_bp(const ChainDesc *__restrict__ descs, StepArgs sa) {
+    static_assert(ALIGN || !FULL, "FULL grids are aligned ones");  // as in k_torus_bp
     __shared__ uint32_t q_w[kQCap], q_a[kQCap], q_b[kQCap], q_e[kQCap], q_c[kQCap], q_und[kQCap],
         q_res[kQCap];
     __shared__ int q_cnt[4];  // entries queued per wavefront region
@@ -393,7 +394,7 @@ __global__ __launch_bounds__(256) void k_tri_bp(const ChainDesc *__restrict__ de
     const int qcap_w = kQCap >> (nwav == 4 ? 2 : (nwav == 2 ? 1 : 0)), qbase = wv * qcap_w;
     int wq = 0;  // entries this wavefront has queued (the same in every lane)
     int e_acc = 0, p_acc = 0;
-    const bool live = gid < total;
+    const bool live = FULL || gid < total;
     // row block and word column (gid / W as a multiply-high, as in k_torus_bp)
     const int rb = !live ? 0 : (W == 1 ? gid : (int)__umulhi((uint32_t)gid, d.wdiv));
     const int wd = live ? gid - rb * W : 0;
@@ -1426,7 +1427,10 @@ hipError_t launch_half_step_grid(const ChainDesc *dev_descs, const ChainDesc *ho
     const dim3 grid((maxu + b - 1) / b, nchains);
     if (h0.kind == KIND_TORUS && h0.format == FMT_BITPACKED && h0.tri) {
         // the runtime groups triangular tori apart from square ones
-        if (fold && aligned) {
+        if (fold && aligned && minu == maxu && maxu % b == 0) {
+            if (obs) hipLaunchKernelGGL((k_tri_bp<true, true, true, true>), grid, dim3(b), 0, stream, dev_descs, sa);
+            else hipLaunchKernelGGL((k_tri_bp<false, true, true, true>), grid, dim3(b), 0, stream, dev_descs, sa);
+        } else if (fold && aligned) {
             if (obs) hipLaunchKernelGGL((k_tri_bp<true, true, true>), grid, dim3(b), 0, stream, dev_descs, sa);
             else hipLaunchKernelGGL((k_tri_bp<false, true, true>), grid, dim3(b), 0, stream, dev_descs, sa);
         } else if (obs) { if (fold) hipLaunchKernelGGL((k_tri_bp<true, true>), grid, dim3(b), 0, stream, dev_descs, sa);

@@ -76,20 +76,23 @@ def test_torus_ragged_and_parameters(sk, L, fmt, lam, q, beta, J):
     assert ob.E_J == ej[-1]
 
 
+@pytest.mark.parametrize("tri", [False, True])
 @pytest.mark.parametrize("sizes,autotune", [
     ((256,), False),          # every lane of the grid a strip of the chain
     ((512, 512), True),       # the same for two chains, blocks autotuned
     ((256, 512), False),      # aligned sides of two sizes: the smaller leaves lanes idle
     ((96, 32), False),        # aligned sides whose strips do not fill a block
 ])
-def test_torus_aligned_full_and_partial_grids(sk, sizes, autotune):
+def test_torus_aligned_full_and_partial_grids(sk, sizes, autotune, tri):
     """Sides that are multiples of 32 in grid batches with fused
-    observables: grids where every lane is a strip of every chain (all
-    chains one size, strips a multiple of the block) and grids with idle
-    lanes; every chain's configuration and H, M logs bit-exact."""
+    observables, square and triangular lattices: grids where every lane is
+    a strip of every chain (all chains one size, strips a multiple of the
+    block) and grids with idle lanes; every chain's configuration and H, M
+    logs bit-exact."""
     T, q, beta = 6, 1.0, 0.44
-    _print_case("torus aligned grid", sizes, autotune)
-    chains = [sk.Chain.torus(L, q=q, beta=beta, seed=70 + i, replica=i) for i, L in enumerate(sizes)]
+    _print_case("torus aligned grid", sizes, autotune, tri)
+    make = sk.Chain.triangular if tri else sk.Chain.torus
+    chains = [make(L, q=q, beta=beta, seed=70 + i, replica=i) for i, L in enumerate(sizes)]
     starts = [c.spins() for c in chains]
     b = sk.Batch(chains, strategy="grid", use_hipgraph=True, record=True, autotune=autotune, log_reserve=T)
     b.sweep(T)
@@ -101,7 +104,7 @@ def test_torus_aligned_full_and_partial_grids(sk, sizes, autotune):
     for i, L in enumerate(sizes):
         init = oracle.torus_init_random(L, 70 + i, i)
         assert np.array_equal(starts[i], init)
-        want, ej, mm = oracle.torus_run(init, 1, 0.0, q, beta, 70 + i, i, T)
+        want, ej, mm = oracle.torus_run(init, 1, 0.0, q, beta, 70 + i, i, T, tri=tri)
         assert np.array_equal(got[i], want), "chain %d (L = %d)" % (i, L)
         assert np.array_equal(H[i], -ej) and np.array_equal(M[i], mm), "chain %d logs" % i
 
