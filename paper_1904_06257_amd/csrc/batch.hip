@@ -143,10 +143,10 @@ __device__ __forceinline__ void torus_lds_half(const ChainDesc &d, const uint32_
         if constexpr (FOLD3) {
             uint32_t ob = 0, eq = ~0u;
             if constexpr (TRI)
-                fold_top8(tri_sel(a, b, e, own, d.tsmall, d.sgn), ob, eq, (uint32_t)w, s, d.replica, k0, k1);
+                fold_top8<true>(tri_sel(a, b, e, own, d.tsmall, d.sgn), ob, eq, (uint32_t)w, s, d.replica, k0, k1);
             else
-                fold_top8(SqSel{fold_planes(a, b, own), fold_t(d.tsmall, d.sgn)}, ob, eq, (uint32_t)w, s,
-                          d.replica, k0, k1);
+                fold_top8<true>(SqSel{fold_planes(a, b, own), fold_t(d.tsmall, d.sgn)}, ob, eq, (uint32_t)w, s,
+                                d.replica, k0, k1);
             const uint32_t und = eq & vm;
             nw_bits = ob & vm;
             if (und != 0) {

@@ -98,14 +98,21 @@ __device__ __forceinline__ U4 philox10_c0(uint32_t c0, const PhiloxShared &p, ui
 
 // The same call with words x and z of the result xored with a per-lane word
 // v: the last round's key xor takes (k ^ v) in their place, so the xor costs
-// nothing there.  kx0, kx1 = the tenth round's keys xor v.
+// nothing there.  kx0, kx1 = the tenth round's keys xor v.  SH: c2 is the
+// same in every lane, so round two's c1 (the low half of round one's c2
+// product) is too, and c1 ^ k0 there is one scalar operand (one instruction
+// per call fewer; faster in the triangular and persistent kernels, slower
+// in the square-lattice grid kernel, which keeps the plain form).
+template <bool SH = false>
 __device__ __forceinline__ U4 philox10_xv(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                           uint32_t k0, uint32_t k1, uint32_t kx0, uint32_t kx1) {
 #pragma unroll
     for (int i = 0; i < 10; ++i) {
         const uint64_t a = (uint64_t)c0 * 0xD2511F53u;
         const uint64_t b = (uint64_t)c2 * 0xCD9E8D57u;
-        const uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(b >> 32), c1, i == 9 ? kx0 : k0, 0x96);
+        const uint32_t n0 = (SH && i == 1)
+                                ? (uint32_t)(b >> 32) ^ (c1 ^ k0)
+                                : __builtin_amdgcn_bitop3_b32((uint32_t)(b >> 32), c1, i == 9 ? kx0 : k0, 0x96);
         const uint32_t n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(a >> 32), c3, i == 9 ? kx1 : k1, 0x96);
         c1 = (uint32_t)b;
         c3 = (uint32_t)a;
@@ -354,7 +361,7 @@ struct SqSelV : SqSel {  // rest-class words of levels 0..7 in vector registers
 // The levels run on x = u ^ c against tf: u and y differ where x and tf do,
 // and the state kept is o ^ c, whose update is then `tf where x != tf`.  Two
 // of the four words of each Philox call come out already xored with c.
-template <class S>
+template <bool SH = false, class S>
 __device__ __forceinline__ void fold_top8(const S &sl, uint32_t &o, uint32_t &eq, uint32_t w, uint32_t s,
                                           uint32_t rep, uint32_t k0, uint32_t k1) {
 #define SHAKEN_FLEVEL(K, X)                                                                       \
@@ -367,12 +374,12 @@ __device__ __forceinline__ void fold_top8(const S &sl, uint32_t &o, uint32_t &eq
     const uint32_t c = sl.c();
     const uint32_t kx0 = (k0 + 9u * 0x9E3779B9u) ^ c, kx1 = (k1 + 9u * 0xBB67AE85u) ^ c;
     uint32_t oc = 0;
-    const U4 r1 = philox10_xv(w, s, rep, 1u, k0, k1, kx0, kx1);
+    const U4 r1 = philox10_xv<SH>(w, s, rep, 1u, k0, k1, kx0, kx1);
     SHAKEN_FLEVEL(7, r1.w ^ c)
     SHAKEN_FLEVEL(6, r1.z)
     SHAKEN_FLEVEL(5, r1.y ^ c)
     SHAKEN_FLEVEL(4, r1.x)
-    const U4 r0 = philox10_xv(w, s, rep, 0u, k0, k1, kx0, kx1);
+    const U4 r0 = philox10_xv<SH>(w, s, rep, 0u, k0, k1, kx0, kx1);
     SHAKEN_FLEVEL(3, r0.w ^ c)
     SHAKEN_FLEVEL(2, r0.z)
     SHAKEN_FLEVEL(1, r0.y ^ c)

@@ -456,7 +456,7 @@ __global__ __launch_bounds__(256) void k_tri_bp(const ChainDesc *__restrict__ de
         uint32_t und, res, smask = 0;
         if constexpr (FOLD) {
             uint32_t o = 0, eq = ~0u;
-            fold_top8(tri_sel(a, b, e, own[i], ts, sgn), o, eq, (uint32_t)widx, s, rep, k0, k1);
+            fold_top8<true>(tri_sel(a, b, e, own[i], ts, sgn), o, eq, (uint32_t)widx, s, rep, k0, k1);
             und = eq & vmi;
             res = o & ~eq;
         } else {
